@@ -1,0 +1,108 @@
+"""Pins for the oracle's random-walk MH move and exchange move."""
+
+import itertools
+import math
+
+import numpy as np
+
+from oracle import evidence, gmm, smc
+from oracle.gmm import Model
+from workloads import make_mixture_data, pt_betas
+
+
+def test_rwmh_leaves_k1_tempered_posterior_invariant():
+    """Start from exact draws of p0 L^beta (Gaussian for k = 1); after RW-MH
+    moves the mean and variance still match the closed form."""
+    y = make_mixture_data(50, np.array([2.0]), 0.55, seed=3)
+    m = Model.equal_weights(1, 1, 0.55)
+    beta = 0.3
+    mean, var = evidence.posterior_k1(y, 0.55, beta)
+    rng = np.random.default_rng(5)
+    N = 1 << 15
+    th = rng.normal(mean, math.sqrt(var), size=(1, N))
+    l = gmm.loglik(th, y, m)
+    acc = 0
+    for mv in range(4):
+        th, l, a = smc.rwmh_move(th, l, y, m, beta, 0.5, seed=77, step=1, move=mv)
+        acc += a.sum()
+    assert 0.05 < acc / (4 * N) < 0.95
+    se_mean = math.sqrt(var / N)
+    assert abs(th.mean() - mean) < 5 * se_mean * 3        # moves correlate draws mildly
+    assert abs(th.var() / var - 1.0) < 5 * math.sqrt(2.0 / N) * 3
+
+
+def test_rwmh_drifts_away_from_wrong_distribution():
+    """Counter-check: started off-target, the sampler moves toward the posterior
+    (a sign error in log alpha would push it away)."""
+    y = make_mixture_data(50, np.array([2.0]), 0.55, seed=3)
+    m = Model.equal_weights(1, 1, 0.55)
+    mean, var = evidence.posterior_k1(y, 0.55, 1.0)
+    th = np.full((1, 4096), mean + 2.0)
+    l = gmm.loglik(th, y, m)
+    for mv in range(150):
+        th, l, _ = smc.rwmh_move(th, l, y, m, 1.0, 0.15, seed=1, step=2, move=mv)
+    assert abs(th.mean() - mean) < 0.1
+
+
+def test_exchange_log_alpha_properties():
+    assert smc.exchange_log_alpha(0.3, 0.3, -5.0, -100.0) == 0.0
+    for ba, bb, la, lb in ((0.1, 0.4, -10.0, -3.0), (0.9, 0.2, -1e4, -5e3)):
+        # the reverse move (states already swapped) has the reciprocal ratio
+        assert smc.exchange_log_alpha(ba, bb, la, lb) + smc.exchange_log_alpha(ba, bb, lb, la) == 0.0
+        # relabelling the pair does not change the ratio
+        assert smc.exchange_log_alpha(ba, bb, la, lb) == smc.exchange_log_alpha(bb, ba, lb, la)
+
+
+def test_exchange_detailed_balance_discrete_target():
+    """Two chains on a 3-state space with targets pi_b(x) ~ exp(b * E(x)): the
+    exchange kernel built from exchange_log_alpha leaves the product target
+    invariant (its transition matrix has it as a stationary vector)."""
+    E = np.array([-1.0, -4.0, -0.2])
+    ba, bb = 0.25, 1.0
+    pa = np.exp(ba * E) / np.exp(ba * E).sum()
+    pb = np.exp(bb * E) / np.exp(bb * E).sum()
+    states = list(itertools.product(range(3), range(3)))
+    P = np.zeros((9, 9))
+    for s, (xa, xb) in enumerate(states):
+        la = smc.exchange_log_alpha(ba, bb, E[xa], E[xb])
+        acc = min(1.0, math.exp(la))
+        t = states.index((xb, xa))
+        P[s, t] += acc
+        P[s, s] += 1.0 - acc
+    pi = np.array([pa[xa] * pb[xb] for xa, xb in states])
+    np.testing.assert_allclose(pi @ P, pi, atol=1e-15)
+
+
+def test_exchange_pairs_partitions():
+    assert smc.exchange_pairs(6, 0, False) == [(0, 1), (2, 3), (4, 5)]
+    assert smc.exchange_pairs(6, 1, False) == [(1, 2), (3, 4)]
+    assert smc.exchange_pairs(6, 1, True) == [(1, 2), (3, 4), (5, 0)]
+    assert smc.exchange_pairs(7, 0, False) == [(0, 1), (2, 3), (4, 5)]
+    # pairs are disjoint
+    for M in (2, 5, 8, 9):
+        for par in (0, 1):
+            flat = [i for p in smc.exchange_pairs(M, par, True) for i in p]
+            assert len(flat) == len(set(flat))
+
+
+def test_pt_exchange_equal_betas_always_swap():
+    M = 8
+    th = np.arange(4 * M, dtype=np.float64).reshape(4, M)
+    l = -np.arange(M, dtype=np.float64)
+    th2, l2, n = smc.pt_exchange(th, l, np.full(M, 0.5), 0, False, seed=3, it=0)
+    assert n == M // 2
+    assert np.array_equal(l2, l.reshape(-1, 2)[:, ::-1].reshape(-1))
+    assert np.array_equal(th2[:, 0], th[:, 1])
+
+
+def test_pt_run_small_moves_hot_chain_between_modes():
+    """A short population-MCMC run on a 2-component posterior: the beta = 1 chain
+    ends near a mode (log-likelihood close to the best one)."""
+    mu = np.array([-2.0, 2.0])
+    y = make_mixture_data(40, mu, 0.55, seed=9)
+    m = Model.equal_weights(2, 1, 0.55)
+    betas = pt_betas(16, power=2)
+    out = smc.pt_run(y, m, betas, 200, 0.5, seed=5)
+    lbest = gmm.loglik(mu[:, None], y, m)[0]
+    assert out["l"][-1] > lbest - 15.0
+    assert out["swaps"] > 0
