@@ -1,0 +1,229 @@
+/*
+ * smc.h -- C ABI of libsmcgpu: the data-parallel hot path of tempered
+ * Gaussian-mixture SMC samplers and population MCMC on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * What is computed (Lee, Yau, Giles, Doucet & Holmes, "On the utility of
+ * graphics cards to perform massively parallel simulation of advanced Monte
+ * Carlo methods"):
+ *   - the per-particle mixture log-likelihood over all observations
+ *     (Mixture Modelling section);
+ *   - the random-walk Metropolis-Hastings move targeting a tempered posterior
+ *     p0 * L^beta (Population-Based MCMC and SMC Sampler subsections);
+ *   - the incremental reweight, log-sum-exp normalisation and effective sample
+ *     size, and systematic resampling by prefix sum and search (Sequential Monte
+ *     Carlo and SMC Samplers subsections; importance weights as in the
+ *     Importance Sampling equations);
+ *   - the exchange move between adjacent tempered chains on disjoint pairs
+ *     (Population-Based MCMC: exchange ratio alpha_ij and partitions I_1..I_R).
+ *
+ * Conventions (every entry point):
+ *   - Array arguments are DEVICE pointers on the context's GPU, owned by the
+ *     caller; the library never frees or keeps them beyond the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *     enqueue work asynchronously on it unless marked [sync].
+ *   - Return value: SMC_OK (0) or a negative SMC_ERR_* code. On an argument
+ *     error nothing is enqueued. No C++ exception crosses the ABI.
+ *     smc_last_error() returns a thread-local description of the last failure.
+ *   - Numeric degeneracy found on the device (NaN log-likelihood, all weights
+ *     zero) cannot be returned by an asynchronous call: kernels raise a device
+ *     status flag that smc_check() reports as SMC_ERR_NUMERIC.
+ *   - Particle parameters theta are FP64, structure-of-arrays [k*d][N]: element
+ *     (i*d + c)*N + p is coordinate c of mean i of particle p.
+ *   - Observations y are FP32, row-major [n][d].
+ *   - Random numbers come from Philox4x32-10 (Salmon et al., SC'11) with
+ *     counter (index, block, step, purpose<<24 | move) and key = seed; the same
+ *     words are produced on the CPU for the same counter.
+ *   - A context must not be used from two host threads at the same time; calls
+ *     on one context that overlap on different streams share its scratch and
+ *     race.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMC_KMAX 8            /* most mixture components supported */
+#define SMC_DMAX 8            /* most dimensions supported */
+#define SMC_KDMAX 64          /* SMC_KMAX * SMC_DMAX */
+
+enum {
+    SMC_OK = 0,
+    SMC_ERR_INVALID_ARG = -1, /* bad pointer, size or parameter */
+    SMC_ERR_UNSUPPORTED = -2, /* (k, d, precision) combination not compiled */
+    SMC_ERR_HIP = -3,         /* a HIP runtime call failed */
+    SMC_ERR_NUMERIC = -4,     /* device status flag: NaN or all-zero weights */
+    SMC_ERR_NOMEM = -5,       /* device allocation failed */
+    SMC_ERR_CAPTURE = -6      /* scratch would have to grow during stream capture */
+};
+
+typedef enum {
+    SMC_PREC_FP64 = 0,        /* plain FP64 arithmetic with device-library exp/log */
+    SMC_PREC_FP32 = 1,        /* FP32 + hardware exp2, compensated FP64 accumulation */
+    SMC_PREC_BF16X3 = 2       /* d-dim: split-BF16 MFMA cross term, FP32 accumulation */
+} smc_prec;
+
+typedef enum { SMC_PRIOR_GAUSS = 0, SMC_PRIOR_BOX = 1 } smc_prior_kind;
+
+/* The mixture model: k components in d dimensions with known covariance
+ * sigma2 * I and known natural-log weights log_w[0..k-1] (summing to one in
+ * probability); the unknowns are the k means. Prior on every coordinate of
+ * every mean: N(prior_a, prior_b^2) (SMC_PRIOR_GAUSS) or uniform on
+ * [prior_a, prior_b] (SMC_PRIOR_BOX, the paper's hypercube prior). */
+typedef struct {
+    int32_t k, d;
+    double sigma2;
+    double log_w[SMC_KMAX];
+    int32_t prior;
+    double prior_a, prior_b;
+} smc_gmm;
+
+typedef struct smc_ctx_s* smc_ctx;
+
+/* [sync] Create a context on HIP device `device` (it becomes current while
+ * the context allocates its scratch). */
+int smc_create(smc_ctx* out, int device);
+
+/* [sync] Destroy a context and free its scratch. NULL is accepted. */
+int smc_destroy(smc_ctx ctx);
+
+/* [sync] Size the context scratch for up to N particles of up to kd = k*d
+ * parameters each, so that later calls (in particular inside hipGraph stream
+ * capture) never allocate. */
+int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd);
+
+/* [sync] Synchronise `stream`, then read and clear the device status flag:
+ * SMC_OK, or SMC_ERR_NUMERIC if a kernel saw a NaN log-likelihood or weights
+ * that were all zero since the last check. */
+int smc_check(smc_ctx ctx, void* stream);
+
+const char* smc_last_error(void);
+
+/* Override the number of data slices (waves per workgroup that split the
+ * observations of the same 64 particles) used by the likelihood kernels;
+ * 0 restores the built-in choice. Range 0..16. */
+int smc_set_slices(smc_ctx ctx, int32_t slices);
+
+/* Per-particle log-likelihood (Mixture Modelling section):
+ *   loglik[p] = sum_j log sum_i w_i N_d(y_j; mu_{p,i}, sigma2 I).
+ * y: [n][d] FP32; theta: [k*d][N] FP64; loglik: [N] FP64 out.
+ * prec FP64: plain form; FP32: FP32 arithmetic with hardware exp2 and a
+ * compensated FP64 sum (relative error below 1e-6); BF16X3 requires d > 1. */
+int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
+               const double* theta, int64_t N, smc_prec prec, double* loglik,
+               void* stream);
+
+/* Draw theta_0 from the prior: [k*d][N] out. Gaussian coordinates use the
+ * Box-Muller normals of stream (p, block, step 0, PRIOR, move 0); the box prior
+ * maps the same words to (a, b) by a + (b - a) (w + 1/2) 2^-32. */
+int smc_prior_init(smc_ctx ctx, const smc_gmm* model, int64_t N, uint64_t seed,
+                   double* theta, void* stream);
+
+/* One random-walk Metropolis-Hastings move of every particle, in place.
+ * Proposal theta' = theta + step_sd * xi, xi ~ N(0, I_{kd}) jointly (normal c
+ * of stream (p, c/4, step, PROP, move)). Accept iff log alpha >= 0 or
+ * log u < log alpha, with log alpha = b_p (l' - l) + log p0(theta') - log p0(theta),
+ * b_p = beta_vec[p] if beta_vec is non-NULL (one beta per chain) else beta,
+ * u = (w0 + 1/2) 2^-32 from stream (p, 0, step, ACC, move).
+ * theta, loglik: in/out (loglik must hold l(theta) on entry).
+ * n_accept: nullable device u64 counter, incremented by the accepted count. */
+int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
+                  double* theta, double* loglik, int64_t N, const double* beta_vec,
+                  double beta, double step_sd, uint64_t seed, uint64_t step,
+                  uint32_t move, smc_prec prec, unsigned long long* n_accept,
+                  void* stream);
+
+/* Incremental reweight of a tempering step (SMC Sampler subsection: with a
+ * pi_t-invariant move the incremental weight is pi_t/pi_{t-1} = L^dbeta):
+ *   logw[p] += dbeta * loglik[p]            (in/out, FP64)
+ *   W[p] = exp(logw[p] - m) / sum_q exp(logw[q] - m)   (out, nullable)
+ *   *logZ += lse(logw_new) - lse(logw_old)  (device scalar in/out, nullable)
+ *   *ess = 1 / sum W^2                      (device scalar out, nullable;
+ *                                            requires W)  */
+int smc_reweight(smc_ctx ctx, double* logw, const double* loglik, int64_t N, double dbeta,
+                 double* W, double* logZ, double* ess, void* stream);
+
+/* Effective sample size 1 / sum_p W[p]^2 of normalised weights W [N]. */
+int smc_ess(smc_ctx ctx, const double* W, int64_t N, double* ess, void* stream);
+
+/* Systematic resampling (Sequential Monte Carlo subsection: build the
+ * empirical CDF of the normalised weights and sample N times from it).
+ * C_j is the correctly rounded prefix sum W_0 + ... + W_j (double-double scan,
+ * rounded once); U_i = (i + u)/N with u = w0 2^-32 from stream
+ * (0, 0, step, RESAMP, 0), or *u_override if non-NULL (device scalar in [0,1));
+ * idx[i] = min{j : U_i < C_j}, or the first j with C_j = C_{N-1} if none.
+ * If `ess` is non-NULL the step runs only when *ess < ess_threshold; when
+ * skipped idx is the identity and theta_out/l_out are copies of the inputs.
+ * idx: [N] int32 out (nullable). theta_in/theta_out: [kd][N] (nullable pair;
+ * must not alias). l_in/l_out: [N] (nullable pair). logw: [N], set to 0 when
+ * resampling happened (nullable). Bit-exact for N <= 2^20. */
+int smc_resample_systematic(smc_ctx ctx, const double* W, int64_t N, uint64_t seed,
+                            uint64_t step, const double* u_override, const double* ess,
+                            double ess_threshold, int32_t* idx, const double* theta_in,
+                            double* theta_out, int32_t kd, const double* l_in,
+                            double* l_out, double* logw, void* stream);
+
+/* Exchange moves between adjacent chains (Population-Based MCMC subsection).
+ * Pairs (a, a+1) with a = parity, parity+2, ... < M-1; with `wrap` and
+ * parity 1 (M even) also (M-1, 0). log alpha = (beta[a] - beta[b]) (l_b - l_a);
+ * swap the states and log-likelihoods iff log alpha >= 0 or log u < log alpha,
+ * u = (w0 + 1/2) 2^-32 from stream (a, 0, iter, EXCH, 0).
+ * theta: [kd][M] in/out; loglik, beta: [M]; n_swap: nullable device u32 counter. */
+int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, int64_t M,
+                int32_t kd, int32_t parity, int32_t wrap, uint64_t seed, uint64_t iter,
+                unsigned int* n_swap, void* stream);
+
+/* One whole tempering step of the SMC sampler with every per-step value read on
+ * the device, so the same enqueued work can be captured once in a hipGraph and
+ * replayed T times:
+ *   t = *t_dev clamped to 1..T; dbeta = beta[t] - beta[t-1];
+ *   reweight (logw, W, *logZ, *ess) -> if *ess < ess_frac*N: systematic
+ *   resampling with u from step t, gather into context scratch, logw = 0 ->
+ *   n_moves RW-MH moves at beta[t] (move m uses stream move m) -> *t_dev = t+1.
+ * beta: [T+1] device FP64 (beta[0..T]). theta/loglik/logw/W: [kd][N], [N], [N], [N] in/out.
+ * stats: device FP64 [4] = {logZ (accumulated), last ESS, resample count,
+ * unused}. n_accept: nullable device u64 counter. */
+int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
+             double* theta, double* loglik, double* logw, double* W, const double* beta,
+             int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed,
+             double ess_frac, smc_prec prec, double* stats, unsigned long long* n_accept,
+             void* stream);
+
+/* One population-MCMC iteration with the iteration index read on the device
+ * (graph-replayable): it = *it_dev; one RW-MH move per chain at its own
+ * beta[i] with step = it; exchanges on partition parity (it & 1 when
+ * parity_mode = 0; a Philox bit from stream (0, 0, it, PARITY, 0) when 1), with
+ * the wrap pair if `wrap`; then *it_dev = it + 1. */
+int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
+                 double* theta, double* loglik, const double* beta, int32_t* it_dev,
+                 double step_sd, uint64_t seed, int32_t parity_mode, int32_t wrap,
+                 smc_prec prec, unsigned long long* n_accept, unsigned int* n_swap,
+                 void* stream);
+
+/* Graph helpers: capture `reps` calls of smc_step (or pt_iteration) enqueued by
+ * the caller between smc_graph_begin and smc_graph_end on `stream` into one
+ * executable hipGraph, then launch it. */
+typedef struct smc_graph_s* smc_graph;
+int smc_graph_begin(smc_ctx ctx, void* stream);
+int smc_graph_end(smc_ctx ctx, void* stream, smc_graph* out);
+int smc_graph_launch(smc_graph g, void* stream);
+int smc_graph_destroy(smc_graph g);
+
+/* Diagnostics used by the CPU/GPU bit-identity tests: Philox words and
+ * Box-Muller normals for indices 0..count-1 of one stream.
+ * rng_words out: [count][4] u32 for counter (i, block, step, purpose<<24|move).
+ * rng_normals out: [per_index][count] FP64, normal c of index i at c*count + i. */
+int smc_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
+                  uint32_t purpose, uint32_t move, uint32_t* out, void* stream);
+int smc_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t step,
+                    uint32_t purpose, uint32_t move, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMC_H */

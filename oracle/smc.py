@@ -215,8 +215,34 @@ def rwmh_move(theta, l, y, model: Model, beta, step_sd, seed, step, move):
 # ---------------------------------------------------------------------------
 # SMC sampler
 
+def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
+             ess_frac=0.5, resample=True):
+    """Tempering step t >= 1: reweight by L^(beta_t - beta_{t-1}); if
+    ESS < ess_frac * N resample systematically (offset from stream (seed, t)) and
+    reset the log-weights; then n_moves RW-MH moves at beta_t (move m uses
+    stream move m). Returns (theta, l, logw, W, logZ_increment, info)."""
+    N = l.size
+    dbeta = betas[t] - betas[t - 1]
+    logw, W, inc, e = reweight(logw, l, dbeta)
+    did = bool(resample and e < ess_frac * N)
+    u = None
+    if did:
+        u = resample_offset(seed, t)
+        idx = systematic_resample(W, u)
+        theta = theta[:, idx]
+        l = l[idx]
+        logw = np.zeros(N)
+        W = np.full(N, 1.0 / N)
+    accepted = []
+    for m in range(n_moves):
+        theta, l, a = rwmh_move(theta, l, y, model, betas[t], step_sd, seed, t, m)
+        accepted.append(a)
+    info = dict(ess=e, resampled=did, u=u, accepted=accepted)
+    return theta, l, logw, W, inc, info
+
+
 def smc_run(y, model: Model, betas, N, step_sd, n_moves, seed, ess_frac=0.5,
-            resample=True, record=False):
+            resample=True):
     """Tempered SMC sampler from beta_0 = 0 to beta_T = 1.
 
     Returns a dict with theta, l, logw, W, logZ and per-step traces (ESS,
@@ -230,28 +256,16 @@ def smc_run(y, model: Model, betas, N, step_sd, n_moves, seed, ess_frac=0.5,
     logZ = 0.0
     tr = dict(ess=[], resampled=[], accepted=[], logZ_inc=[], u=[])
     for t in range(1, T + 1):
-        dbeta = betas[t] - betas[t - 1]
-        logw, W, inc, e = reweight(logw, l, dbeta)
+        theta, l, logw, W, inc, info = smc_step(theta, l, logw, y, model, betas, t, step_sd,
+                                                n_moves, seed, ess_frac, resample)
         logZ += inc
-        did = bool(resample and e < ess_frac * N)
-        if did:
-            u = resample_offset(seed, t)
-            idx = systematic_resample(W, u)
-            theta = theta[:, idx]
-            l = l[idx]
-            logw = np.zeros(N)
-            W = np.full(N, 1.0 / N)
-            tr["u"].append(u)
-        acc = 0
-        for m in range(n_moves):
-            theta, l, a = rwmh_move(theta, l, y, model, betas[t], step_sd, seed, t, m)
-            acc += int(a.sum())
-        tr["ess"].append(e)
-        tr["resampled"].append(did)
-        tr["accepted"].append(acc)
+        tr["ess"].append(info["ess"])
+        tr["resampled"].append(info["resampled"])
+        tr["accepted"].append(int(sum(int(a.sum()) for a in info["accepted"])))
         tr["logZ_inc"].append(inc)
-    out = dict(theta=theta, l=l, logw=logw, W=W, logZ=logZ, trace=tr)
-    return out
+        if info["resampled"]:
+            tr["u"].append(info["u"])
+    return dict(theta=theta, l=l, logw=logw, W=W, logZ=logZ, trace=tr)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,107 @@
+"""ctypes loader for libsmcgpu.so (built in-tree by ``paper_0905_2441_amd.build``).
+
+There is no fallback: if the shared library is missing or fails to load, this
+module raises, and so does everything that imports it.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int64, c_uint32,
+                    c_uint64, c_void_p)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmcgpu.so")
+
+SMC_KMAX = 8
+SMC_DMAX = 8
+SMC_KDMAX = 64
+
+SMC_OK = 0
+SMC_ERR_INVALID_ARG = -1
+SMC_ERR_UNSUPPORTED = -2
+SMC_ERR_HIP = -3
+SMC_ERR_NUMERIC = -4
+SMC_ERR_NOMEM = -5
+SMC_ERR_CAPTURE = -6
+
+SMC_PREC_FP64 = 0
+SMC_PREC_FP32 = 1
+SMC_PREC_BF16X3 = 2
+
+SMC_PRIOR_GAUSS = 0
+SMC_PRIOR_BOX = 1
+
+
+class SmcGmm(Structure):
+    _fields_ = [("k", c_int32), ("d", c_int32), ("sigma2", c_double),
+                ("log_w", c_double * SMC_KMAX), ("prior", c_int32),
+                ("prior_a", c_double), ("prior_b", c_double)]
+
+
+_P = c_void_p
+_GP = POINTER(SmcGmm)
+
+# name -> (restype, argtypes); every function declared in include/smc.h.
+SIGNATURES = {
+    "smc_create": (c_int, [POINTER(c_void_p), c_int]),
+    "smc_destroy": (c_int, [_P]),
+    "smc_reserve": (c_int, [_P, c_int64, c_int32]),
+    "smc_check": (c_int, [_P, _P]),
+    "smc_last_error": (c_char_p, []),
+    "smc_set_slices": (c_int, [_P, c_int32]),
+    "smc_loglik": (c_int, [_P, _GP, _P, c_int64, _P, c_int64, c_int, _P, _P]),
+    "smc_prior_init": (c_int, [_P, _GP, c_int64, c_uint64, _P, _P]),
+    "smc_rwmh_move": (c_int, [_P, _GP, _P, c_int64, _P, _P, c_int64, _P, c_double, c_double,
+                              c_uint64, c_uint64, c_uint32, c_int, _P, _P]),
+    "smc_reweight": (c_int, [_P, _P, _P, c_int64, c_double, _P, _P, _P, _P]),
+    "smc_ess": (c_int, [_P, _P, c_int64, _P, _P]),
+    "smc_resample_systematic": (c_int, [_P, _P, c_int64, c_uint64, c_uint64, _P, _P, c_double,
+                                        _P, _P, _P, c_int32, _P, _P, _P, _P]),
+    "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
+                            c_uint64, _P, _P]),
+    "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, c_int32, _P, c_double,
+                         c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
+    "pt_iteration": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_double, c_uint64,
+                             c_int32, c_int32, c_int, _P, _P, _P]),
+    "smc_graph_begin": (c_int, [_P, _P]),
+    "smc_graph_end": (c_int, [_P, _P, POINTER(c_void_p)]),
+    "smc_graph_launch": (c_int, [_P, _P]),
+    "smc_graph_destroy": (c_int, [_P]),
+    "smc_rng_words": (c_int, [c_uint64, c_int64, c_uint32, c_uint32, c_uint32, c_uint32, _P, _P]),
+    "smc_rng_normals": (c_int, [c_uint64, c_int64, c_int32, c_uint32, c_uint32, c_uint32, _P,
+                                _P]),
+}
+
+
+class SmcError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libsmcgpu error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsmcgpu.so once; raise ImportError if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_0905_2441_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> None:
+    if code != SMC_OK:
+        msg = load().smc_last_error()
+        raise SmcError(code, msg.decode() if msg else "")

@@ -1,0 +1,285 @@
+"""Thin Python binding of the C ABI: same names, torch tensors in, no arithmetic.
+
+Every function checks tensor placement, dtype, shape and contiguity, passes raw
+device pointers and the current (or given) HIP stream to libsmcgpu, and raises
+``SmcError`` on a non-zero return code. Nothing here computes any part of the
+sampler.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+PREC = {"fp64": L.SMC_PREC_FP64, "fp32": L.SMC_PREC_FP32, "bf16x3": L.SMC_PREC_BF16X3}
+PURPOSE = {"prior": 1, "prop": 2, "acc": 3, "resamp": 4, "exch": 5, "parity": 6}
+
+
+@dataclasses.dataclass(frozen=True)
+class Gmm:
+    """Mixture model of the C ABI's smc_gmm (known weights and covariance sigma2*I)."""
+    k: int
+    d: int
+    sigma2: float
+    log_w: Sequence[float]
+    prior: str = "gauss"        # "gauss": N(prior_a, prior_b^2); "box": U[prior_a, prior_b]
+    prior_a: float = 0.0
+    prior_b: float = 10.0
+
+    @staticmethod
+    def equal_weights(k: int, d: int, sigma2: float, **kw) -> "Gmm":
+        return Gmm(k=k, d=d, sigma2=sigma2, log_w=tuple([math.log(1.0 / k)] * k), **kw)
+
+    @property
+    def kd(self) -> int:
+        return self.k * self.d
+
+    def struct(self) -> L.SmcGmm:
+        s = L.SmcGmm()
+        s.k = self.k
+        s.d = self.d
+        s.sigma2 = float(self.sigma2)
+        for i in range(L.SMC_KMAX):
+            s.log_w[i] = float(self.log_w[i]) if i < self.k else float("-inf")
+        s.prior = {"gauss": L.SMC_PRIOR_GAUSS, "box": L.SMC_PRIOR_BOX}[self.prior]
+        s.prior_a = float(self.prior_a)
+        s.prior_b = float(self.prior_b)
+        return s
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor, dtype, name: str, numel: Optional[int] = None) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, name, numel=None):
+    return None if t is None else _ptr(t, dtype, name, numel)
+
+
+def _data_shape(model: Gmm, y: torch.Tensor) -> int:
+    if y.dim() == 1 and model.d == 1:
+        return y.shape[0]
+    if y.dim() == 2 and y.shape[1] == model.d:
+        return y.shape[0]
+    raise ValueError(f"y must be [n] (d = 1) or [n, {model.d}]")
+
+
+def _theta_shape(model: Gmm, theta: torch.Tensor) -> int:
+    if theta.dim() != 2 or theta.shape[0] != model.kd:
+        raise ValueError(f"theta must be [k*d = {model.kd}, N]")
+    return theta.shape[1]
+
+
+class Context:
+    """Owns an smc_ctx (device scratch and launch choices) on one GPU."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        h = ctypes.c_void_p()
+        L.check(self._lib.smc_create(ctypes.byref(h), int(device)))
+        self.handle = h
+        self.device = device
+
+    def reserve(self, N: int, kd: int = 8) -> None:
+        L.check(self._lib.smc_reserve(self.handle, int(N), int(kd)))
+
+    def check(self, stream=None) -> None:
+        L.check(self._lib.smc_check(self.handle, _stream(stream)))
+
+    def set_slices(self, slices: int) -> None:
+        L.check(self._lib.smc_set_slices(self.handle, int(slices)))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.smc_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def smc_loglik(ctx: Context, model: Gmm, y, theta, prec="fp32", out=None, stream=None):
+    n = _data_shape(model, y)
+    N = _theta_shape(model, theta)
+    if out is None:
+        out = torch.empty(N, dtype=torch.float64, device=theta.device)
+    L.check(ctx._lib.smc_loglik(ctx.handle, ctypes.byref(model.struct()),
+                                _ptr(y, torch.float32, "y"), n,
+                                _ptr(theta, torch.float64, "theta"), N, _prec(prec),
+                                _ptr(out, torch.float64, "loglik", N), _stream(stream)))
+    return out
+
+
+def smc_prior_init(ctx: Context, model: Gmm, N: int, seed: int, out=None, stream=None):
+    if out is None:
+        out = torch.empty((model.kd, N), dtype=torch.float64, device="cuda")
+    L.check(ctx._lib.smc_prior_init(ctx.handle, ctypes.byref(model.struct()), int(N),
+                                    int(seed), _ptr(out, torch.float64, "theta", model.kd * N),
+                                    _stream(stream)))
+    return out
+
+
+def smc_rwmh_move(ctx: Context, model: Gmm, y, theta, loglik, beta, step_sd, seed, step,
+                  move=0, prec="fp32", n_accept=None, beta_vec=None, stream=None):
+    n = _data_shape(model, y)
+    N = _theta_shape(model, theta)
+    L.check(ctx._lib.smc_rwmh_move(
+        ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n,
+        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", N), N,
+        _opt(beta_vec, torch.float64, "beta_vec", N), float(beta), float(step_sd), int(seed),
+        int(step), int(move), _prec(prec), _opt(n_accept, torch.int64, "n_accept", 1),
+        _stream(stream)))
+
+
+def smc_reweight(ctx: Context, logw, loglik, dbeta, W=None, logZ=None, ess=None, stream=None):
+    N = logw.numel()
+    L.check(ctx._lib.smc_reweight(ctx.handle, _ptr(logw, torch.float64, "logw"),
+                                  _ptr(loglik, torch.float64, "loglik", N), N, float(dbeta),
+                                  _opt(W, torch.float64, "W", N),
+                                  _opt(logZ, torch.float64, "logZ", 1),
+                                  _opt(ess, torch.float64, "ess", 1), _stream(stream)))
+
+
+def smc_ess(ctx: Context, W, ess, stream=None):
+    L.check(ctx._lib.smc_ess(ctx.handle, _ptr(W, torch.float64, "W"), W.numel(),
+                             _ptr(ess, torch.float64, "ess", 1), _stream(stream)))
+
+
+def smc_resample_systematic(ctx: Context, W, seed, step, u_override=None, ess=None,
+                            ess_threshold=0.0, idx=None, theta_in=None, theta_out=None,
+                            l_in=None, l_out=None, logw=None, stream=None):
+    N = W.numel()
+    kd = 0
+    if theta_in is not None:
+        if theta_in.dim() != 2 or theta_in.shape[1] != N:
+            raise ValueError("theta_in must be [kd, N]")
+        kd = theta_in.shape[0]
+    L.check(ctx._lib.smc_resample_systematic(
+        ctx.handle, _ptr(W, torch.float64, "W"), N, int(seed), int(step),
+        _opt(u_override, torch.float64, "u_override", 1), _opt(ess, torch.float64, "ess", 1),
+        float(ess_threshold), _opt(idx, torch.int32, "idx", N),
+        _opt(theta_in, torch.float64, "theta_in", kd * N),
+        _opt(theta_out, torch.float64, "theta_out", kd * N), kd,
+        _opt(l_in, torch.float64, "l_in", N), _opt(l_out, torch.float64, "l_out", N),
+        _opt(logw, torch.float64, "logw", N), _stream(stream)))
+
+
+def pt_exchange(ctx: Context, theta, loglik, beta, parity, wrap, seed, iteration, n_swap=None,
+                stream=None):
+    M = loglik.numel()
+    if theta.dim() != 2 or theta.shape[1] != M:
+        raise ValueError("theta must be [kd, M]")
+    L.check(ctx._lib.pt_exchange(ctx.handle, _ptr(theta, torch.float64, "theta"),
+                                 _ptr(loglik, torch.float64, "loglik"),
+                                 _ptr(beta, torch.float64, "beta", M), M, theta.shape[0],
+                                 int(parity), int(bool(wrap)), int(seed), int(iteration),
+                                 _opt(n_swap, torch.int32, "n_swap", 1), _stream(stream)))
+
+
+def smc_step(ctx: Context, model: Gmm, y, theta, loglik, logw, W, beta, t_dev, step_sd,
+             n_moves, seed, ess_frac, prec, stats, n_accept=None, stream=None):
+    n = _data_shape(model, y)
+    N = _theta_shape(model, theta)
+    L.check(ctx._lib.smc_step(
+        ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n, N,
+        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", N),
+        _ptr(logw, torch.float64, "logw", N), _ptr(W, torch.float64, "W", N),
+        _ptr(beta, torch.float64, "beta"), beta.numel() - 1, _ptr(t_dev, torch.int32, "t_dev", 1),
+        float(step_sd), int(n_moves), int(seed), float(ess_frac), _prec(prec),
+        _ptr(stats, torch.float64, "stats", 4), _opt(n_accept, torch.int64, "n_accept", 1),
+        _stream(stream)))
+
+
+def pt_iteration(ctx: Context, model: Gmm, y, theta, loglik, beta, it_dev, step_sd, seed,
+                 parity_mode=0, wrap=False, prec="fp32", n_accept=None, n_swap=None,
+                 stream=None):
+    n = _data_shape(model, y)
+    M = _theta_shape(model, theta)
+    L.check(ctx._lib.pt_iteration(
+        ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n, M,
+        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", M),
+        _ptr(beta, torch.float64, "beta", M), _ptr(it_dev, torch.int32, "it_dev", 1),
+        float(step_sd), int(seed), int(parity_mode), int(bool(wrap)), _prec(prec),
+        _opt(n_accept, torch.int64, "n_accept", 1), _opt(n_swap, torch.int32, "n_swap", 1),
+        _stream(stream)))
+
+
+def smc_rng_words(seed, count, block, step, purpose, move=0, out=None, stream=None):
+    if out is None:
+        out = torch.empty((count, 4), dtype=torch.int32, device="cuda")
+    pur = PURPOSE[purpose] if isinstance(purpose, str) else int(purpose)
+    L.check(L.load().smc_rng_words(int(seed), int(count), int(block), int(step), pur, int(move),
+                                   _ptr(out, torch.int32, "out", 4 * count), _stream(stream)))
+    return out
+
+
+def smc_rng_normals(seed, count, per_index, step, purpose, move=0, out=None, stream=None):
+    if out is None:
+        out = torch.empty((per_index, count), dtype=torch.float64, device="cuda")
+    pur = PURPOSE[purpose] if isinstance(purpose, str) else int(purpose)
+    L.check(L.load().smc_rng_normals(int(seed), int(count), int(per_index), int(step), pur,
+                                     int(move), _ptr(out, torch.float64, "out",
+                                                     per_index * count), _stream(stream)))
+    return out
+
+
+class Graph:
+    """An executable hipGraph captured from calls enqueued on ``stream``."""
+
+    def __init__(self, ctx: Context, stream: torch.cuda.Stream):
+        self.ctx = ctx
+        self.stream = stream
+        self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        L.check(self.ctx._lib.smc_graph_begin(self.ctx.handle, _stream(self.stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        rc = self.ctx._lib.smc_graph_end(self.ctx.handle, _stream(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            L.check(rc)
+            self.handle = h
+        return False
+
+    def launch(self):
+        L.check(self.ctx._lib.smc_graph_launch(self.handle, _stream(self.stream)))
+
+    def close(self):
+        if self.handle.value:
+            self.ctx._lib.smc_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

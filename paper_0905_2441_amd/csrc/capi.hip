@@ -1,0 +1,540 @@
+// C ABI of libsmcgpu: argument checking, context scratch, launch choices,
+// tempering-step orchestration and hipGraph capture helpers.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+#include "wave.hpp"
+
+using namespace smc;
+
+struct smc_ctx_s {
+    int device = 0;
+    int slices_override = 0;
+    Scratch sc{};
+    void* fixed = nullptr;       // partials, tickets, status, state
+    void* grow = nullptr;        // cdf, dd partials, l_tmp, theta_tmp
+    int64_t grow_kd = 0;
+};
+
+struct smc_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(SMC_ERR_HIP, m);
+}
+
+#define SMC_CHECK_HIP(call, what)                 \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+int check_model(const smc_gmm* m, GmmDev* out) {
+    if (!m) return fail(SMC_ERR_INVALID_ARG, "model is NULL");
+    if (m->k < 1 || m->k > SMC_KMAX) return fail(SMC_ERR_INVALID_ARG, "k must be in 1..8");
+    if (m->d < 1 || m->d > SMC_DMAX) return fail(SMC_ERR_INVALID_ARG, "d must be in 1..8");
+    if (!(m->sigma2 > 0.0) || !isfinite(m->sigma2))
+        return fail(SMC_ERR_INVALID_ARG, "sigma2 must be positive and finite");
+    bool any_finite = false;
+    for (int i = 0; i < m->k; ++i) {
+        if (m->log_w[i] != m->log_w[i] || m->log_w[i] == INFINITY)
+            return fail(SMC_ERR_INVALID_ARG, "log_w must not be NaN or +inf");
+        any_finite = any_finite || isfinite(m->log_w[i]);
+    }
+    if (!any_finite) return fail(SMC_ERR_INVALID_ARG, "every mixture weight is zero");
+    if (m->prior == SMC_PRIOR_GAUSS) {
+        if (!(m->prior_b > 0.0) || !isfinite(m->prior_a) || !isfinite(m->prior_b))
+            return fail(SMC_ERR_INVALID_ARG, "Gaussian prior needs finite mean and sd > 0");
+    } else if (m->prior == SMC_PRIOR_BOX) {
+        if (!(m->prior_b > m->prior_a) || !isfinite(m->prior_a) || !isfinite(m->prior_b))
+            return fail(SMC_ERR_INVALID_ARG, "box prior needs finite a < b");
+    } else {
+        return fail(SMC_ERR_INVALID_ARG, "unknown prior kind");
+    }
+    GmmDev g{};
+    g.k = m->k;
+    g.d = m->d;
+    const double log2e = 1.4426950408889634;
+    g.s32 = static_cast<float>(sqrt(log2e / (2.0 * m->sigma2)));
+    for (int i = 0; i < SMC_KMAX; ++i) {
+        const double lw = (i < m->k) ? m->log_w[i] : -INFINITY;
+        g.lw[i] = lw;
+        g.lw2[i] = static_cast<float>(lw * log2e);
+    }
+    g.inv2s2 = 1.0 / (2.0 * m->sigma2);
+    g.cst = -0.5 * static_cast<double>(m->d) * log(2.0 * M_PI * m->sigma2);
+    g.prior = m->prior;
+    g.pa = m->prior_a;
+    g.pb = m->prior_b;
+    g.lp_const = (m->prior == SMC_PRIOR_GAUSS) ? -0.5 * log(2.0 * M_PI * m->prior_b * m->prior_b)
+                                               : 0.0;
+    *out = g;
+    return SMC_OK;
+}
+
+int check_prec(const GmmDev& g, int prec) {
+    if (prec != SMC_PREC_FP64 && prec != SMC_PREC_FP32 && prec != SMC_PREC_BF16X3)
+        return fail(SMC_ERR_INVALID_ARG, "unknown precision");
+    if (!supported_kd(g.k, g.d, prec))
+        return fail(SMC_ERR_UNSUPPORTED, "(k, d, precision) combination is not compiled");
+    return SMC_OK;
+}
+
+int check_sizes(int64_t n, int64_t N) {
+    if (n < 1 || n > (int64_t{1} << 30)) return fail(SMC_ERR_INVALID_ARG, "n must be in 1..2^30");
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    return SMC_OK;
+}
+
+// Data slices per 64-particle workgroup: enough waves to fill 256 CUs several
+// times over, at least 32 observations per slice, and a grid within 2^32 threads.
+int choose_slices(const smc_ctx_s* ctx, int64_t n, int64_t N) {
+    const int64_t tiles = (N + kWave - 1) / kWave;
+    int64_t S = ctx->slices_override;
+    if (S <= 0) {
+        S = (8192 + tiles - 1) / tiles;
+        if (S > kMaxSlices) S = kMaxSlices;
+        while (S > 1 && n / S < 32) --S;
+    }
+    if (S > n) S = n;
+    if (S < 1) S = 1;
+    while (S > 1 && tiles * kWave * S >= (int64_t{1} << 32)) --S;
+    return static_cast<int>(S);
+}
+
+int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
+    if (ctx->sc.cap >= N && ctx->grow_kd >= kd) return SMC_OK;
+    if (capturing(s))
+        return fail(SMC_ERR_CAPTURE, "scratch must grow; call smc_reserve before capture");
+    const int64_t cap = ctx->sc.cap >= N ? ctx->sc.cap : N;
+    const int64_t kdc = ctx->grow_kd >= kd ? ctx->grow_kd : (kd < 8 ? 8 : kd);
+    const int64_t chunks = (cap + kScanChunk - 1) / kScanChunk + 1;
+    const size_t b_cdf = align_up(sizeof(double) * cap);
+    const size_t b_dd = align_up(sizeof(double) * 2 * chunks);
+    const size_t b_l = align_up(sizeof(double) * cap);
+    const size_t b_th = align_up(sizeof(double) * cap * kdc);
+    SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    SMC_CHECK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize before scratch growth");
+    if (ctx->grow) {
+        SMC_CHECK_HIP(hipFree(ctx->grow), "hipFree");
+        ctx->grow = nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, b_cdf + b_dd + b_l + b_th) != hipSuccess) {
+        ctx->sc.cap = 0;
+        ctx->grow_kd = 0;
+        return fail(SMC_ERR_NOMEM, "device allocation of context scratch failed");
+    }
+    char* c = static_cast<char*>(p);
+    ctx->grow = p;
+    ctx->sc.cdf = reinterpret_cast<double*>(c);
+    ctx->sc.dd_part = reinterpret_cast<double*>(c + b_cdf);
+    ctx->sc.l_tmp = reinterpret_cast<double*>(c + b_cdf + b_dd);
+    ctx->sc.theta_tmp = reinterpret_cast<double*>(c + b_cdf + b_dd + b_l);
+    ctx->sc.cap = cap;
+    ctx->grow_kd = kdc;
+    return SMC_OK;
+}
+
+int enter(smc_ctx ctx) {
+    if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return SMC_OK;
+}
+
+StepSrc host_src(int t, double beta, double dbeta) {
+    StepSrc s{};
+    s.t_dev = nullptr;
+    s.beta_dev = nullptr;
+    s.t_host = t;
+    s.beta_host = beta;
+    s.dbeta_host = dbeta;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* smc_last_error(void) { return g_last_error.c_str(); }
+
+int smc_create(smc_ctx* out, int device) {
+    if (!out) return fail(SMC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    SMC_CHECK_HIP(hipGetDeviceCount(&count), "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(SMC_ERR_INVALID_ARG, "no such device");
+    SMC_CHECK_HIP(hipSetDevice(device), "hipSetDevice");
+    smc_ctx ctx = new (std::nothrow) smc_ctx_s();
+    if (!ctx) return fail(SMC_ERR_NOMEM, "host allocation failed");
+    ctx->device = device;
+    const size_t b_part = align_up(sizeof(LsePair) * kMaxRedBlocks);
+    const size_t b_sq = align_up(sizeof(double) * kMaxRedBlocks);
+    const size_t b_tk = align_up(sizeof(unsigned) * 8);
+    const size_t b_st = align_up(sizeof(int));
+    const size_t b_state = align_up(sizeof(StepState));
+    const size_t total = 2 * b_part + b_sq + b_tk + b_st + b_state;
+    void* p = nullptr;
+    if (hipMalloc(&p, total) != hipSuccess) {
+        delete ctx;
+        return fail(SMC_ERR_NOMEM, "device allocation of context scratch failed");
+    }
+    if (hipMemset(p, 0, total) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p);
+        delete ctx;
+        return fail(SMC_ERR_HIP, "clearing context scratch failed");
+    }
+    char* c = static_cast<char*>(p);
+    ctx->fixed = p;
+    ctx->sc.part_old = reinterpret_cast<LsePair*>(c);
+    ctx->sc.part_new = reinterpret_cast<LsePair*>(c + b_part);
+    ctx->sc.part_sq = reinterpret_cast<double*>(c + 2 * b_part);
+    ctx->sc.tickets = reinterpret_cast<unsigned*>(c + 2 * b_part + b_sq);
+    ctx->sc.status = reinterpret_cast<int*>(c + 2 * b_part + b_sq + b_tk);
+    ctx->sc.state = reinterpret_cast<StepState*>(c + 2 * b_part + b_sq + b_tk + b_st);
+    *out = ctx;
+    return SMC_OK;
+}
+
+int smc_destroy(smc_ctx ctx) {
+    if (!ctx) return SMC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->grow) (void)hipFree(ctx->grow);
+    if (ctx->fixed) (void)hipFree(ctx->fixed);
+    delete ctx;
+    return SMC_OK;
+}
+
+int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (kd < 1 || kd > SMC_KDMAX) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
+    return ensure_scratch(ctx, N, kd, nullptr);
+}
+
+int smc_check(smc_ctx ctx, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    SMC_CHECK_HIP(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");
+    int flag = 0;
+    SMC_CHECK_HIP(hipMemcpy(&flag, ctx->sc.status, sizeof(int), hipMemcpyDeviceToHost),
+                  "hipMemcpy status");
+    if (flag) {
+        const int zero = 0;
+        SMC_CHECK_HIP(hipMemcpy(ctx->sc.status, &zero, sizeof(int), hipMemcpyHostToDevice),
+                      "hipMemcpy status");
+        std::string m = "device status:";
+        if (flag & kStatusNaN) m += " NaN or +inf in log-likelihoods or log-weights;";
+        if (flag & kStatusAllZeroWeight) m += " every weight is zero;";
+        return fail(SMC_ERR_NUMERIC, m);
+    }
+    return SMC_OK;
+}
+
+int smc_set_slices(smc_ctx ctx, int32_t slices) {
+    if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
+    if (slices < 0 || slices > kMaxSlices) return fail(SMC_ERR_INVALID_ARG, "slices in 0..16");
+    ctx->slices_override = slices;
+    return SMC_OK;
+}
+
+int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
+               const double* theta, int64_t N, smc_prec prec, double* loglik, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, N))) return r;
+    if (!y || !theta || !loglik) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    const hipError_t e = launch_loglik(g, y, n, theta, N, prec, loglik,
+                                       choose_slices(ctx, n, N), ctx->sc.status,
+                                       as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "loglik launch");
+    return SMC_OK;
+}
+
+int smc_prior_init(smc_ctx ctx, const smc_gmm* model, int64_t N, uint64_t seed,
+                   double* theta, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!theta) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    const hipError_t e = launch_prior(g, N, seed, theta, as_stream(stream));
+    if (e == hipErrorInvalidValue) return fail(SMC_ERR_UNSUPPORTED, "k*d not compiled for prior");
+    if (e != hipSuccess) return hip_fail(e, "prior launch");
+    return SMC_OK;
+}
+
+int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
+                  double* theta, double* loglik, int64_t N, const double* beta_vec,
+                  double beta, double step_sd, uint64_t seed, uint64_t step, uint32_t move,
+                  smc_prec prec, unsigned long long* n_accept, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, N))) return r;
+    if (!y || !theta || !loglik) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    if (!beta_vec && (!(beta >= 0.0) || !isfinite(beta)))
+        return fail(SMC_ERR_INVALID_ARG, "beta must be finite and >= 0");
+    if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
+    if (move > 0xFFFFFFu) return fail(SMC_ERR_INVALID_ARG, "move must fit in 24 bits");
+    const hipError_t e = launch_rwmh(g, y, n, theta, loglik, N, beta_vec,
+                                     host_src(static_cast<int>(step), beta, 0.0), step_sd, seed,
+                                     move, prec, n_accept, choose_slices(ctx, n, N),
+                                     ctx->sc.status, nullptr, nullptr, nullptr,
+                                     as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+    return SMC_OK;
+}
+
+int smc_reweight(smc_ctx ctx, double* logw, const double* loglik, int64_t N, double dbeta,
+                 double* W, double* logZ, double* ess, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!logw || !loglik) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (ess && !W) return fail(SMC_ERR_INVALID_ARG, "ess requires W");
+    if (!isfinite(dbeta)) return fail(SMC_ERR_INVALID_ARG, "dbeta must be finite");
+    const hipError_t e = launch_reweight(ctx->sc, logw, loglik, N, host_src(0, 0.0, dbeta), W,
+                                         logZ, ess, 0.0, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "reweight launch");
+    return SMC_OK;
+}
+
+int smc_ess(smc_ctx ctx, const double* W, int64_t N, double* ess, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!W || !ess) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    const hipError_t e = launch_ess(ctx->sc, W, N, ess, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "ess launch");
+    return SMC_OK;
+}
+
+int smc_resample_systematic(smc_ctx ctx, const double* W, int64_t N, uint64_t seed,
+                            uint64_t step, const double* u_override, const double* ess,
+                            double ess_threshold, int32_t* idx, const double* theta_in,
+                            double* theta_out, int32_t kd, const double* l_in, double* l_out,
+                            double* logw, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!W) return fail(SMC_ERR_INVALID_ARG, "W is NULL");
+    if ((theta_in == nullptr) != (theta_out == nullptr))
+        return fail(SMC_ERR_INVALID_ARG, "theta_in and theta_out go together");
+    if (theta_in && (kd < 1 || kd > SMC_KDMAX)) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
+    if (theta_in && theta_in == theta_out) return fail(SMC_ERR_INVALID_ARG, "theta_out aliases theta_in");
+    if ((l_in == nullptr) != (l_out == nullptr))
+        return fail(SMC_ERR_INVALID_ARG, "l_in and l_out go together");
+    if (l_in && l_in == l_out) return fail(SMC_ERR_INVALID_ARG, "l_out aliases l_in");
+    if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
+    if ((r = ensure_scratch(ctx, N, 1, as_stream(stream)))) return r;
+    const hipError_t e = launch_resample(ctx->sc, W, N, seed, host_src(static_cast<int>(step), 0, 0),
+                                         u_override, ess, ess_threshold, nullptr, idx, theta_in,
+                                         theta_out, theta_in ? kd : 0, l_in, l_out, logw,
+                                         as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "resample launch");
+    return SMC_OK;
+}
+
+int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, int64_t M,
+                int32_t kd, int32_t parity, int32_t wrap, uint64_t seed, uint64_t iter,
+                unsigned int* n_swap, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (M < 2 || M > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "M must be in 2..2^31-1");
+    if (!theta || !loglik || !beta) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (kd < 1 || kd > SMC_KDMAX) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
+    if (parity != 0 && parity != 1) return fail(SMC_ERR_INVALID_ARG, "parity is 0 or 1");
+    if (iter > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "iter must fit in 32 bits");
+    const hipError_t e = launch_exchange(theta, loglik, beta, M, kd, 2, parity, wrap ? 1 : 0,
+                                         seed, host_src(static_cast<int>(iter), 0, 0), n_swap,
+                                         as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "exchange launch");
+    return SMC_OK;
+}
+
+int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
+             double* theta, double* loglik, double* logw, double* W, const double* beta,
+             int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed, double ess_frac,
+             smc_prec prec, double* stats, unsigned long long* n_accept, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, N))) return r;
+    if (!y || !theta || !loglik || !logw || !W || !beta || !t_dev || !stats)
+        return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (n_moves < 0) return fail(SMC_ERR_INVALID_ARG, "n_moves must be >= 0");
+    if (T < 1) return fail(SMC_ERR_INVALID_ARG, "T must be >= 1");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
+    const hipStream_t s = as_stream(stream);
+    const int kd = g.k * g.d;
+    if ((r = ensure_scratch(ctx, N, kd, s))) return r;
+    StepSrc src{};
+    src.t_dev = t_dev;
+    src.beta_dev = beta;
+    src.t_max = T;
+    hipError_t e = launch_reweight_step(ctx->sc, logw, loglik, N, src, W, stats, ess_frac, s);
+    if (e != hipSuccess) return hip_fail(e, "reweight launch");
+    e = launch_resample(ctx->sc, W, N, seed, src, nullptr, nullptr, 0.0, ctx->sc.state, nullptr,
+                        theta, ctx->sc.theta_tmp, kd, loglik, ctx->sc.l_tmp, logw, s);
+    if (e != hipSuccess) return hip_fail(e, "resample launch");
+    const int S = choose_slices(ctx, n, N);
+    if (n_moves == 0) {
+        e = launch_copy_back(ctx->sc, theta, loglik, N, kd, s);
+        if (e != hipSuccess) return hip_fail(e, "copy-back launch");
+    }
+    for (int m = 0; m < n_moves; ++m) {
+        const bool first = (m == 0);
+        e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, src, step_sd, seed,
+                        static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status,
+                        first ? ctx->sc.theta_tmp : nullptr, first ? ctx->sc.l_tmp : nullptr,
+                        first ? ctx->sc.state : nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+    }
+    e = launch_counter_inc(t_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "counter launch");
+    return SMC_OK;
+}
+
+int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
+                 double* theta, double* loglik, const double* beta, int32_t* it_dev,
+                 double step_sd, uint64_t seed, int32_t parity_mode, int32_t wrap, smc_prec prec,
+                 unsigned long long* n_accept, unsigned int* n_swap, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, M))) return r;
+    if (M < 2) return fail(SMC_ERR_INVALID_ARG, "M must be >= 2");
+    if (!y || !theta || !loglik || !beta || !it_dev) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (parity_mode != 0 && parity_mode != 1) return fail(SMC_ERR_INVALID_ARG, "parity_mode 0 or 1");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    const hipStream_t s = as_stream(stream);
+    StepSrc src{};
+    src.t_dev = it_dev;
+    hipError_t e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec,
+                               n_accept, choose_slices(ctx, n, M), ctx->sc.status, nullptr,
+                               nullptr, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+    e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed, src,
+                        n_swap, s);
+    if (e != hipSuccess) return hip_fail(e, "exchange launch");
+    e = launch_counter_inc(it_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "counter launch");
+    return SMC_OK;
+}
+
+int smc_graph_begin(smc_ctx ctx, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!stream) return fail(SMC_ERR_INVALID_ARG, "the null stream cannot be captured");
+    SMC_CHECK_HIP(hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal),
+                  "hipStreamBeginCapture");
+    return SMC_OK;
+}
+
+int smc_graph_end(smc_ctx ctx, void* stream, smc_graph* out) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!out) return fail(SMC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hipGraph_t graph = nullptr;
+    SMC_CHECK_HIP(hipStreamEndCapture(as_stream(stream), &graph), "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    smc_graph g = new (std::nothrow) smc_graph_s();
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(SMC_ERR_NOMEM, "host allocation failed");
+    }
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return SMC_OK;
+}
+
+int smc_graph_launch(smc_graph g, void* stream) {
+    if (!g) return fail(SMC_ERR_INVALID_ARG, "graph is NULL");
+    SMC_CHECK_HIP(hipGraphLaunch(g->exec, as_stream(stream)), "hipGraphLaunch");
+    return SMC_OK;
+}
+
+int smc_graph_destroy(smc_graph g) {
+    if (!g) return SMC_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return SMC_OK;
+}
+
+int smc_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step, uint32_t purpose,
+                  uint32_t move, uint32_t* out, void* stream) {
+    if (count < 1 || count > INT32_MAX || !out) return fail(SMC_ERR_INVALID_ARG, "bad count or out");
+    if (purpose > 255 || move > 0xFFFFFFu) return fail(SMC_ERR_INVALID_ARG, "purpose/move range");
+    const hipError_t e = launch_rng_words(seed, count, block, step, purpose, move, out,
+                                          as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "rng launch");
+    return SMC_OK;
+}
+
+int smc_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t step,
+                    uint32_t purpose, uint32_t move, double* out, void* stream) {
+    if (count < 1 || count > INT32_MAX || !out || per_index < 1 || per_index > SMC_KDMAX)
+        return fail(SMC_ERR_INVALID_ARG, "bad count, per_index or out");
+    if (purpose > 255 || move > 0xFFFFFFu) return fail(SMC_ERR_INVALID_ARG, "purpose/move range");
+    const hipError_t e = launch_rng_normals(seed, count, per_index, step, purpose, move, out,
+                                            as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "rng launch");
+    return SMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP translation units of libsmcgpu.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/smc.h"
+
+namespace smc {
+
+constexpr int kMaxSlices = 16;          // waves per workgroup in the likelihood kernels
+constexpr int kRedBlock = 256;          // threads per block in the weight/resample kernels
+constexpr int kMaxRedBlocks = 1024;     // grid cap of the grid-stride weight kernels
+constexpr int kScanPerThread = 8;       // W elements per thread in the CDF scan
+constexpr int kScanChunk = kRedBlock * kScanPerThread;
+
+// Status bits raised by kernels and reported by smc_check.
+enum StatusBits : int { kStatusNaN = 1, kStatusAllZeroWeight = 2 };
+
+// Model constants in the form the kernels consume (built on the host once per call).
+struct GmmDev {
+    int k, d;
+    float s32;                 // sqrt(log2(e) / (2 sigma2)), rounded to FP32
+    float lw2[SMC_KMAX];       // log2 w_i, FP32
+    double lw[SMC_KMAX];       // ln w_i, FP64
+    double inv2s2;             // 1 / (2 sigma2)
+    double cst;                // per-datum constant -(d/2) ln(2 pi sigma2)
+    int prior;                 // SMC_PRIOR_GAUSS or SMC_PRIOR_BOX
+    double pa, pb;
+    double lp_const;           // Gaussian prior: -(1/2) ln(2 pi pb^2) per coordinate
+};
+
+// Per-step values one kernel computes and later kernels of the same step read.
+struct StepState {
+    double M;                  // max log-weight after the reweight
+    double S;                  // sum exp(logw - M)
+    double lse_old, lse_new;
+    double ess;
+    int resampled;             // 1 when the ESS test fired this step
+    int pad;
+};
+
+struct alignas(16) LsePair {
+    double m, s;
+};
+
+// Device scratch owned by a context.
+struct Scratch {
+    LsePair* part_old;         // [kMaxRedBlocks]
+    LsePair* part_new;         // [kMaxRedBlocks]
+    double* part_sq;           // [kMaxRedBlocks]
+    double* dd_part;           // [2 * max scan blocks]
+    unsigned* tickets;         // [8], zero between launches
+    int* status;               // [1]
+    StepState* state;          // [1]
+    double* cdf;               // [cap]
+    double* theta_tmp;         // [SMC_KDMAX * cap]
+    double* l_tmp;             // [cap]
+    int64_t cap;
+};
+
+// How kernels obtain the step / iteration index and the inverse temperature:
+// from host scalars, or (graph replay) from a device counter and beta array.
+struct StepSrc {
+    const int* t_dev;          // nullable: device step counter
+    const double* beta_dev;    // nullable: device beta[0..t_max]
+    int t_max;                 // with beta_dev: steps index beta[1..t_max]; t is clamped
+    int t_host;
+    double beta_host;
+    double dbeta_host;
+};
+
+// Step index of the current call: the device counter (clamped to 1..t_max when a
+// beta array is indexed with it) or the host value.
+__device__ __forceinline__ int step_index(const StepSrc& src) {
+    if (!src.t_dev) return src.t_host;
+    int t = *src.t_dev;
+    if (src.beta_dev) t = t < 1 ? 1 : (t > src.t_max ? src.t_max : t);
+    return t;
+}
+
+hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
+                         int64_t N, int prec, double* out, int slices, int* status,
+                         hipStream_t s);
+hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
+                       int64_t N, const double* beta_vec, StepSrc src, double sd,
+                       uint64_t seed, uint32_t move, int prec,
+                       unsigned long long* n_accept, int slices, int* status,
+                       const double* theta_alt, const double* l_alt,
+                       const StepState* alt_flag, hipStream_t s);
+hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,
+                        hipStream_t s);
+bool supported_kd(int k, int d, int prec);
+
+hipError_t launch_reweight(const Scratch& sc, double* logw, const double* l, int64_t N,
+                           StepSrc src, double* W, double* logZ, double* ess,
+                           double ess_threshold_frac, hipStream_t s);
+hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess,
+                      hipStream_t s);
+hipError_t launch_resample(const Scratch& sc, const double* W, int64_t N, uint64_t seed,
+                           StepSrc src, const double* u_override, const double* ess,
+                           double ess_threshold, const StepState* pred_state,
+                           int32_t* idx, const double* theta_in, double* theta_out,
+                           int32_t kd, const double* l_in, double* l_out, double* logw,
+                           hipStream_t s);
+hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
+                           int32_t kd, int parity_mode, int parity_host, int wrap,
+                           uint64_t seed, StepSrc src, unsigned* n_swap, hipStream_t s);
+hipError_t launch_reweight_step(const Scratch& sc, double* logw, const double* l, int64_t N,
+                                StepSrc src, double* W, double* stats, double ess_frac,
+                                hipStream_t s);
+hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, int64_t N, int kd,
+                            hipStream_t s);
+hipError_t launch_counter_inc(int* counter, hipStream_t s);
+hipError_t launch_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
+                            uint32_t purpose, uint32_t move, uint32_t* out, hipStream_t s);
+hipError_t launch_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t step,
+                              uint32_t purpose, uint32_t move, double* out, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,102 @@
+// Philox4x32-10 counter-based generator for gfx950, with exact uniform maps
+// and Box-Muller normals.
+//
+// Generator: Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as
+// 1, 2, 3" (SC'11). Ten rounds of a 4-word bijection keyed by two words; each
+// round multiplies words 0 and 2 by fixed odd constants, keeps both halves of
+// the 64-bit products, mixes the high halves into the other two words with the
+// round key, and the key advances by two Weyl increments between rounds.
+//
+// The paper's own generators (MRG32k3a and xorshift with skip-ahead, Parallel
+// Random Number Generation subsection) keep per-thread state; a counter-based
+// generator needs none: every draw is a pure function of (seed, counter), so
+// the CPU and GPU produce the same words for the same draw.
+//
+// Counter layout used by every kernel:
+//   c0 = index (particle, chain or pair), c1 = block of four words,
+//   c2 = step (tempering step or PT iteration), c3 = purpose << 24 | move;
+//   key = (seed low word, seed high word).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+enum Purpose : uint32_t { kPrior = 1, kProp = 2, kAcc = 3, kResamp = 4, kExch = 5, kParity = 6 };
+
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u;   // multiplies word 0
+    constexpr uint32_t kMulB = 0xCD9E8D57u;   // multiplies word 2
+    constexpr uint32_t kBumpA = 0x9E3779B9u;  // golden-ratio Weyl step
+    constexpr uint32_t kBumpB = 0xBB67AE85u;  // sqrt(3) - 1 Weyl step
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += kBumpA;
+            k1 += kBumpB;
+        }
+        const uint32_t hiA = __umulhi(kMulA, c0);
+        const uint32_t loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2);
+        const uint32_t loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0;
+        const uint32_t n2 = hiA ^ c3 ^ k1;
+        c0 = n0;
+        c1 = loB;
+        c2 = n2;
+        c3 = loA;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Words4 draw(uint64_t seed, uint32_t index, uint32_t block,
+                                       uint32_t step, uint32_t purpose, uint32_t move) {
+    return philox4x32_10(index, block, step, (purpose << 24) | (move & 0xFFFFFFu),
+                         static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+}
+
+// (w + 1/2) 2^-32: strictly inside (0, 1), exact in FP64.
+__device__ __forceinline__ double u01_open(uint32_t w) {
+    return (static_cast<double>(w) + 0.5) * 0x1p-32;
+}
+
+// w 2^-32: in [0, 1), exact in FP64.
+__device__ __forceinline__ double u01_left_closed(uint32_t w) {
+    return static_cast<double>(w) * 0x1p-32;
+}
+
+// Box & Muller (1958): two independent standard normals from two uniforms.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& z0, double& z1) {
+    constexpr double kTwoPi = 6.283185307179586;
+    const double r = sqrt(-2.0 * log(u01_open(wa)));
+    const double ang = kTwoPi * u01_open(wb);
+    double s, c;
+    sincos(ang, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Standard normal number c of the stream (index, step, purpose, move):
+// block c/4, words (0,1) -> c%4 in {0,1}, words (2,3) -> c%4 in {2,3}.
+template <int COUNT>
+__device__ __forceinline__ void normals(uint64_t seed, uint32_t index, uint32_t step,
+                                        uint32_t purpose, uint32_t move, double* z) {
+#pragma unroll
+    for (int b = 0; b < (COUNT + 3) / 4; ++b) {
+        const Words4 w = draw(seed, index, b, step, purpose, move);
+        double a0, a1, a2, a3;
+        box_muller(w.w0, w.w1, a0, a1);
+        box_muller(w.w2, w.w3, a2, a3);
+        if (4 * b + 0 < COUNT) z[4 * b + 0] = a0;
+        if (4 * b + 1 < COUNT) z[4 * b + 1] = a1;
+        if (4 * b + 2 < COUNT) z[4 * b + 2] = a2;
+        if (4 * b + 3 < COUNT) z[4 * b + 3] = a3;
+    }
+}
+
+}  // namespace smc

@@ -1,0 +1,160 @@
+"""Sampler drivers: device-resident state plus one enqueued (or graph-replayed)
+call per tempering step or PT iteration. All arithmetic runs in libsmcgpu.
+
+SMCSampler: tempered SMC sampler (SMC Samplers and SMC Sampler subsections):
+prior draws, then for t = 1..T one smc_step (reweight, ESS test and systematic
+resampling on the device, RW-MH moves at beta_t). The step reads t from a
+device counter, so a single captured hipGraph is replayed T times and the host
+never waits inside the run.
+
+PTSampler: population MCMC with tempered chains (Population-Based MCMC
+subsection): per iteration one RW-MH move per chain at its own beta, then
+exchange moves on one partition of adjacent pairs.
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .api import (Context, Gmm, Graph, pt_iteration, smc_loglik, smc_prior_init, smc_step)
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+class SMCSampler:
+    def __init__(self, ctx: Context, model: Gmm, y, N: int, betas, step_sd: float,
+                 n_moves: int, seed: int, ess_frac: float = 0.5, prec: str = "fp32",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.ctx, self.model, self.N = ctx, model, int(N)
+        self.step_sd, self.n_moves, self.seed = float(step_sd), int(n_moves), int(seed)
+        self.ess_frac, self.prec = float(ess_frac), prec
+        self.T = len(betas) - 1
+        self.stream = stream or torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.y = _dev(y, torch.float32)
+            self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
+            kd = model.kd
+            self.theta = torch.empty((kd, self.N), dtype=torch.float64, device="cuda")
+            self.loglik = torch.empty(self.N, dtype=torch.float64, device="cuda")
+            self.logw = torch.zeros(self.N, dtype=torch.float64, device="cuda")
+            self.W = torch.full((self.N,), 1.0 / self.N, dtype=torch.float64, device="cuda")
+            self.t = torch.ones(1, dtype=torch.int32, device="cuda")
+            self.stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+            self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ctx.reserve(self.N, model.kd)
+        self.graph: Optional[Graph] = None
+
+    def init(self):
+        """theta_0 from the prior, l(theta_0), logw = 0, t = 1, statistics cleared."""
+        with torch.cuda.stream(self.stream):
+            smc_prior_init(self.ctx, self.model, self.N, self.seed, out=self.theta,
+                           stream=self.stream)
+            smc_loglik(self.ctx, self.model, self.y, self.theta, self.prec, out=self.loglik,
+                       stream=self.stream)
+            self.logw.zero_()
+            self.W.fill_(1.0 / self.N)
+            self.t.fill_(1)
+            self.stats.zero_()
+            self.n_accept.zero_()
+
+    def enqueue_step(self):
+        smc_step(self.ctx, self.model, self.y, self.theta, self.loglik, self.logw, self.W,
+                 self.beta, self.t, self.step_sd, self.n_moves, self.seed, self.ess_frac,
+                 self.prec, self.stats, self.n_accept, stream=self.stream)
+
+    def capture(self) -> Graph:
+        """Capture one tempering step into a hipGraph (replayable for every t)."""
+        if self.graph is None:
+            g = Graph(self.ctx, self.stream)
+            with g:
+                self.enqueue_step()
+            self.graph = g
+        return self.graph
+
+    def step(self, graph: bool = True):
+        if graph:
+            self.capture().launch()
+        else:
+            self.enqueue_step()
+
+    def run(self, graph: bool = True, steps: Optional[int] = None):
+        self.init()
+        for _ in range(self.T if steps is None else steps):
+            self.step(graph)
+        self.stream.synchronize()
+        self.ctx.check(self.stream)
+        return self.results()
+
+    def results(self):
+        self.stream.synchronize()
+        st = self.stats.cpu().numpy()
+        return dict(logZ=float(st[0]), ess=float(st[1]), resamples=int(st[2]),
+                    accepted=int(self.n_accept.cpu().item()), t=int(self.t.cpu().item()),
+                    theta=self.theta.cpu().numpy(), l=self.loglik.cpu().numpy(),
+                    logw=self.logw.cpu().numpy(), W=self.W.cpu().numpy())
+
+
+class PTSampler:
+    def __init__(self, ctx: Context, model: Gmm, y, betas, step_sd: float, seed: int,
+                 parity_mode: int = 0, wrap: bool = False, prec: str = "fp32",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.ctx, self.model = ctx, model
+        self.M = len(betas)
+        self.step_sd, self.seed = float(step_sd), int(seed)
+        self.parity_mode, self.wrap, self.prec = int(parity_mode), bool(wrap), prec
+        self.stream = stream or torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.y = _dev(y, torch.float32)
+            self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
+            self.theta = torch.empty((model.kd, self.M), dtype=torch.float64, device="cuda")
+            self.loglik = torch.empty(self.M, dtype=torch.float64, device="cuda")
+            self.it = torch.zeros(1, dtype=torch.int32, device="cuda")
+            self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
+            self.n_swap = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.graph: Optional[Graph] = None
+
+    def init(self):
+        with torch.cuda.stream(self.stream):
+            smc_prior_init(self.ctx, self.model, self.M, self.seed, out=self.theta,
+                           stream=self.stream)
+            smc_loglik(self.ctx, self.model, self.y, self.theta, self.prec, out=self.loglik,
+                       stream=self.stream)
+            self.it.zero_()
+            self.n_accept.zero_()
+            self.n_swap.zero_()
+
+    def enqueue_iteration(self):
+        pt_iteration(self.ctx, self.model, self.y, self.theta, self.loglik, self.beta, self.it,
+                     self.step_sd, self.seed, self.parity_mode, self.wrap, self.prec,
+                     self.n_accept, self.n_swap, stream=self.stream)
+
+    def capture(self, iterations: int = 1) -> Graph:
+        if self.graph is None:
+            g = Graph(self.ctx, self.stream)
+            with g:
+                for _ in range(iterations):
+                    self.enqueue_iteration()
+            self.graph = g
+        return self.graph
+
+    def run(self, iterations: int, graph: bool = True):
+        self.init()
+        for _ in range(iterations):
+            if graph:
+                self.capture().launch()
+            else:
+                self.enqueue_iteration()
+        self.stream.synchronize()
+        self.ctx.check(self.stream)
+        return self.results()
+
+    def results(self):
+        self.stream.synchronize()
+        return dict(theta=self.theta.cpu().numpy(), l=self.loglik.cpu().numpy(),
+                    accepted=int(self.n_accept.cpu().item()),
+                    swaps=int(self.n_swap.cpu().item()), it=int(self.it.cpu().item()))

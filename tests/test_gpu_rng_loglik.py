@@ -1,0 +1,180 @@
+"""GPU parity: Philox words, Box-Muller normals, prior draws and the mixture
+log-likelihood against the FP64 oracle."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce, oracle_model, rel_err
+from oracle import gmm as ogmm
+from oracle import philox as opx
+from oracle import smc as osmc
+from workloads import (CONFIGS, make_data, make_mixture_data, theta_near_posterior,
+                       theta_prior_draws)
+from workloads.data import true_means_for
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-6       # per-particle relative error bound for the FP32 likelihood
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import paper_0905_2441_amd as smc
+    return smc
+
+
+@pytest.fixture(scope="module")
+def ctx(smc):
+    return smc.Context(0)
+
+
+def test_philox_words_bit_identical(smc):
+    for (seed, count, block, step, purpose, move) in ((0, 1, 0, 0, 1, 0),
+                                                      (123456789012345, 1 << 20, 3, 77, 2, 5),
+                                                      (2 ** 64 - 1, 4097, 0, 2 ** 32 - 1, 4, 0)):
+        announce(f"philox seed={seed} count={count}")
+        got = smc.smc_rng_words(seed, count, block, step, purpose, move)
+        torch.cuda.synchronize()
+        g = got.cpu().numpy().view(np.uint32).astype(np.uint64)
+        w = opx.words(seed, np.arange(count, dtype=np.uint64), block, step, purpose, move)
+        ref = np.stack(w, axis=1)
+        assert np.array_equal(g, ref)
+
+
+def test_box_muller_normals_match(smc):
+    announce("normals")
+    count, per = 1 << 16, 7
+    got = smc.smc_rng_normals(42, count, per, 9, "prop", 3).cpu().numpy()
+    ref = opx.normals(42, np.arange(count, dtype=np.uint64), 9, opx.PROP, 3, per)
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("prior", ["gauss", "box"])
+def test_prior_init_matches(smc, ctx, prior):
+    announce(f"prior {prior}")
+    g = smc.Gmm.equal_weights(4, 1, 0.55, prior=prior,
+                              prior_a=0.0 if prior == "gauss" else -10.0, prior_b=10.0)
+    th = smc.smc_prior_init(ctx, g, 3000, 77).cpu().numpy()
+    ref = osmc.prior_init(oracle_model(g), 3000, 77)
+    assert np.max(np.abs(th - ref)) < 1e-12
+
+
+def _check_loglik(smc, ctx, g, y, theta, prec, tol):
+    got = smc.smc_loglik(ctx, g, torch.as_tensor(y).cuda(), torch.as_tensor(theta).cuda(), prec)
+    ctx.check()
+    ref = ogmm.loglik(theta, y, oracle_model(g))
+    err = rel_err(got.cpu().numpy(), ref)
+    assert err.max() <= tol, (prec, float(err.max()))
+    return err
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("fp64", FP64_TOL)])
+@pytest.mark.parametrize("n,N", [(100, 1024), (1000, 777), (37, 65), (1, 3), (5000, 200)])
+def test_loglik_1d_parity(smc, ctx, prec, tol, n, N):
+    announce(f"loglik 1d {prec} n={n} N={N}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(n, mu, 0.55, seed=n)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    th = np.hstack([theta_prior_draws(N // 2, 4, 1, seed=N),
+                    theta_near_posterior(N - N // 2, mu, seed=N + 1)])
+    _check_loglik(smc, ctx, g, y, th, prec, tol)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 6, 7, 8])
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("fp64", FP64_TOL)])
+def test_loglik_1d_every_k(smc, ctx, k, prec, tol):
+    announce(f"loglik k={k} {prec}")
+    rng = np.random.default_rng(k)
+    mu = np.sort(rng.uniform(-8, 8, size=k))
+    w = rng.dirichlet(np.ones(k))
+    y = make_mixture_data(333, mu, 0.4, seed=k, weights=w)
+    g = smc.Gmm(k=k, d=1, sigma2=0.4, log_w=tuple(np.log(w)))
+    th = np.hstack([theta_prior_draws(100, k, 1, seed=k), theta_near_posterior(91, mu, seed=k)])
+    _check_loglik(smc, ctx, g, y, th, prec, tol)
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("fp64", FP64_TOL)])
+def test_loglik_ddim_parity(smc, ctx, k, prec, tol):
+    announce(f"loglik d=8 k={k} {prec}")
+    rng = np.random.default_rng(10 + k)
+    mu = 3.0 * rng.standard_normal((k, 8))
+    y = make_mixture_data(700, mu, 1.0, seed=k)
+    g = smc.Gmm.equal_weights(k, 8, 1.0)
+    th = np.hstack([theta_prior_draws(70, k, 8, seed=k), theta_near_posterior(60, mu, seed=k)])
+    _check_loglik(smc, ctx, g, y, th, prec, tol)
+
+
+@pytest.mark.parametrize("slices", [1, 2, 5, 16])
+def test_loglik_slice_counts(smc, ctx, slices):
+    """Every split of the data over waves gives the oracle's value."""
+    announce(f"loglik slices={slices}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(999, mu, 0.55, seed=3)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    th = theta_near_posterior(300, mu, seed=4)
+    ctx.set_slices(slices)
+    try:
+        _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
+        _check_loglik(smc, ctx, g, y, th, "fp64", FP64_TOL)
+    finally:
+        ctx.set_slices(0)
+
+
+def test_loglik_headline_size_sampled(smc, ctx):
+    """At the headline size (n = 1000, N = 131072) compare a sample of particles."""
+    cfg = CONFIGS["gmm1d_k4_n1000_N131072"]
+    announce("loglik headline size")
+    y = make_data(cfg)
+    mu = true_means_for(cfg)
+    N = cfg.N
+    th = np.hstack([theta_prior_draws(N // 2, 4, 1, seed=5), theta_near_posterior(N // 2, mu, seed=6)])
+    g = smc.Gmm.equal_weights(4, 1, cfg.sigma2)
+    yt = torch.as_tensor(y).cuda()
+    tt = torch.as_tensor(th).cuda()
+    sample = np.unique(np.concatenate([np.arange(0, N, 509), [N - 1]]))
+    for prec, tol in (("fp32", FP32_TOL), ("fp64", FP64_TOL)):
+        got = smc.smc_loglik(ctx, g, yt, tt, prec).cpu().numpy()
+        ref = ogmm.loglik(th[:, sample], y, oracle_model(g))
+        assert rel_err(got[sample], ref).max() <= tol
+        assert np.all(np.isfinite(got))
+
+
+def test_loglik_long_data_fp32(smc, ctx):
+    """n = 10^5 observations (the longest data of the batched workload)."""
+    announce("loglik n=1e5")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(100000, mu, 0.55, seed=8)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    th = np.hstack([theta_prior_draws(64, 4, 1, seed=8), theta_near_posterior(64, mu, seed=9)])
+    _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
+
+
+def test_loglik_nan_raises_status(smc, ctx):
+    announce("loglik NaN status")
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    y = torch.tensor([0.0, float("nan"), 1.0], dtype=torch.float32).cuda()
+    th = torch.zeros((4, 64), dtype=torch.float64).cuda()
+    smc.smc_loglik(ctx, g, y, th, "fp64")
+    with pytest.raises(smc.SmcError):
+        ctx.check()
+    ctx.check()  # cleared
+
+
+def test_argument_errors(smc, ctx):
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    y = torch.zeros(10, dtype=torch.float32).cuda()
+    th = torch.zeros((3, 8), dtype=torch.float64).cuda()
+    with pytest.raises(ValueError):
+        smc.smc_loglik(ctx, g, y, th, "fp32")
+    bad = smc.Gmm(k=9, d=1, sigma2=1.0, log_w=tuple([0.0] * 9))
+    with pytest.raises(Exception):
+        smc.smc_loglik(ctx, bad, y, torch.zeros((9, 8), dtype=torch.float64).cuda(), "fp32")
+    g3 = smc.Gmm.equal_weights(3, 8, 1.0)   # (k=3, d=8) is not compiled
+    with pytest.raises(smc.SmcError):
+        smc.smc_loglik(ctx, g3, torch.zeros((10, 8), dtype=torch.float32).cuda(),
+                       torch.zeros((24, 8), dtype=torch.float64).cuda(), "fp32")

@@ -1,0 +1,152 @@
+"""GPU parity of whole runs under matched randomness: the tempered SMC sampler
+(small workload, FP64 and FP32) and population MCMC, eager and graph-replayed."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce, oracle_model, rel_err
+from oracle import gmm as ogmm
+from oracle import smc as osmc
+from workloads import CONFIGS, beta_schedule, make_data, pt_betas, make_mixture_data
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import paper_0905_2441_amd as smc
+    return smc
+
+
+@pytest.fixture(scope="module")
+def ctx(smc):
+    return smc.Context(0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    cfg = CONFIGS["gmm1d_k4_n100_N1024"]
+    y = make_data(cfg)
+    betas = beta_schedule(cfg.T, cfg.schedule)
+    return cfg, y, betas
+
+
+@pytest.fixture(scope="module")
+def small_oracle(small):
+    cfg, y, betas = small
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                             prior_b=cfg.prior_b)
+    return osmc.smc_run(y, om, betas, cfg.N, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                        ess_frac=cfg.ess_frac)
+
+
+def _sampler(smc, ctx, cfg, y, betas, prec):
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    return smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                          ess_frac=cfg.ess_frac, prec=prec)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph):
+    cfg, y, betas = small
+    announce(f"smc small fp64 graph={graph}")
+    s = _sampler(smc, ctx, cfg, y, betas, "fp64")
+    r = s.run(graph=graph)
+    ref = small_oracle
+    assert r["t"] == cfg.T + 1
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"]))
+    assert abs(r["logZ"] - ref["logZ"]) <= 1e-3
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+    assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+
+
+def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
+    cfg, y, betas = small
+    announce("smc graph vs eager")
+    a = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=False)
+    b = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True)
+    assert a["logZ"] == b["logZ"]
+    assert np.array_equal(a["theta"], b["theta"])
+    # repeated replays of the same sampler give the same answer again
+    s = _sampler(smc, ctx, cfg, y, betas, "fp32")
+    c = s.run(graph=True)
+    d = s.run(graph=True)
+    assert c["logZ"] == d["logZ"] and np.array_equal(c["theta"], d["theta"])
+
+
+def _snapshot(s):
+    s.stream.synchronize()
+    return (s.theta.cpu().numpy().copy(), s.loglik.cpu().numpy().copy(),
+            s.logw.cpu().numpy().copy(), float(s.stats[0].item()))
+
+
+def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
+    """FP32 run checked step by step: the oracle takes every step from the GPU's
+    own state, so reweight/ESS/resampling must agree to FP64 rounding and the
+    moves may differ only by FP32 near-tie accept flips, which are counted."""
+    cfg, y, betas = small
+    announce("smc small fp32 stepwise")
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                             prior_b=cfg.prior_b)
+    s = _sampler(smc, ctx, cfg, y, betas, "fp32")
+    s.init()
+    th, l, lw, z = _snapshot(s)
+    l_ref0 = ogmm.loglik(th, y, om)
+    assert rel_err(l, l_ref0).max() <= 1e-6
+    flips = decisions = 0
+    sum_gpu = sum_ref = 0.0
+    for t in range(1, cfg.T + 1):
+        s.step(graph=False)
+        th1, l1, lw1, z1 = _snapshot(s)
+        rth, rl, rlw, _, inc, info = osmc.smc_step(th, l, lw, y, om, betas, t, cfg.step_sd,
+                                                   cfg.n_moves, cfg.run_seed, cfg.ess_frac)
+        assert abs((z1 - z) - inc) <= 1e-10 * max(1.0, abs(inc))
+        assert np.array_equal(lw1, rlw) or np.max(np.abs(lw1 - rlw)) <= 1e-12
+        same = np.all(th1 == rth, axis=0) | np.all(np.abs(th1 - rth) <= 1e-12, axis=0)
+        flips += int(np.sum(~same))
+        decisions += cfg.N * cfg.n_moves
+        assert rel_err(l1[same], rl[same]).max() <= 1e-6
+        sum_gpu += z1 - z
+        sum_ref += inc
+        th, l, lw, z = th1, l1, lw1, z1
+    assert flips <= max(3, decisions // 1000), flips
+    assert abs(sum_gpu - sum_ref) <= 1e-3
+    print(f"fp32 flipped decisions: {flips} of {decisions}")
+
+
+def test_pt_matches_oracle(smc, ctx):
+    announce("pt small fp64")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(300, mu, 0.55, seed=3)
+    M, iters = 128, 25
+    betas = pt_betas(M, 4)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
+    s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=103, parity_mode=0, wrap=False, prec="fp64")
+    r = s.run(iters, graph=True)
+    ref = osmc.pt_run(y, om, betas, iters, 0.5, 103, parity_mode="alternate", wrap=False)
+    assert r["it"] == iters
+    assert r["swaps"] == ref["swaps"]
+    assert r["accepted"] == ref["accepted"]
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+
+
+def test_pt_paper_mode_random_parity_wrap(smc, ctx):
+    announce("pt paper mode")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(100, mu, 0.3025, seed=1)
+    M, iters = 32, 15
+    betas = pt_betas(M, 2)
+    g = smc.Gmm.equal_weights(4, 1, 0.3025, prior="box", prior_a=-10.0, prior_b=10.0)
+    om = oracle_model(g)
+    s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64")
+    r = s.run(iters, graph=False)
+    ref = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True)
+    assert r["swaps"] == ref["swaps"]
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9

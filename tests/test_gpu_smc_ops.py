@@ -1,0 +1,206 @@
+"""GPU parity: reweight / LSE / ESS, systematic resampling, RW-MH move and the
+exchange move against the FP64 oracle on the same inputs."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce, oracle_model, rel_err
+from oracle import gmm as ogmm
+from oracle import philox as opx
+from oracle import smc as osmc
+from workloads import lognormal_logw, make_mixture_data, pt_betas, theta_near_posterior, theta_prior_draws
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import paper_0905_2441_amd as smc
+    return smc
+
+
+@pytest.fixture(scope="module")
+def ctx(smc):
+    return smc.Context(0)
+
+
+def _cuda(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+# ------------------------------------------------------------------ reweight / ESS
+
+@pytest.mark.parametrize("N", [1, 5, 1000, 4097, 131072, 1 << 20])
+def test_reweight_matches_oracle(smc, ctx, N):
+    announce(f"reweight N={N}")
+    logw0 = lognormal_logw(N, seed=N, spread=2.0)
+    l = -500.0 + 30.0 * lognormal_logw(N, seed=N + 1)
+    dbeta = 0.0123
+    lw = _cuda(logw0)
+    W = torch.empty(N, dtype=torch.float64).cuda()
+    logZ = torch.full((1,), 1.5, dtype=torch.float64).cuda()
+    ess = torch.zeros(1, dtype=torch.float64).cuda()
+    smc.smc_reweight(ctx, lw, _cuda(l), dbeta, W=W, logZ=logZ, ess=ess)
+    ctx.check()
+    lw_ref, W_ref, inc_ref, ess_ref = osmc.reweight(logw0, l, dbeta)
+    assert np.array_equal(lw.cpu().numpy(), lw_ref)                 # one mul + one add each
+    assert np.max(np.abs(W.cpu().numpy() - W_ref)) <= 1e-14
+    assert abs(logZ.item() - (1.5 + inc_ref)) <= 1e-12 * max(1.0, abs(inc_ref))
+    assert abs(ess.item() - ess_ref) <= 1e-12 * ess_ref
+    # standalone ESS of the oracle's weights
+    e2 = torch.zeros(1, dtype=torch.float64).cuda()
+    smc.smc_ess(ctx, _cuda(W_ref), e2)
+    assert abs(e2.item() - osmc.ess(W_ref)) <= 1e-12 * ess_ref
+
+
+def test_reweight_special_cases(smc, ctx):
+    announce("reweight special")
+    N = 1 << 12
+    W = torch.empty(N, dtype=torch.float64).cuda()
+    ess = torch.zeros(1, dtype=torch.float64).cuda()
+    smc.smc_reweight(ctx, _cuda(np.zeros(N)), _cuda(np.full(N, -3.0)), 0.5, W=W, ess=ess)
+    assert ess.item() == N
+    assert np.all(W.cpu().numpy() == 1.0 / N)
+    lw = np.full(N, -np.inf)
+    lw[17] = 0.0
+    smc.smc_reweight(ctx, _cuda(lw), _cuda(np.zeros(N)), 0.1, W=W, ess=ess)
+    assert ess.item() == 1.0
+    ctx.check()
+    smc.smc_reweight(ctx, _cuda(np.full(N, -np.inf)), _cuda(np.zeros(N)), 0.1, W=W, ess=ess)
+    with pytest.raises(smc.SmcError):
+        ctx.check()
+
+
+# ------------------------------------------------------------------ resampling
+
+def _resample_gpu(smc, ctx, W, u, theta=None, l=None):
+    N = W.size
+    idx = torch.empty(N, dtype=torch.int32).cuda()
+    kw = {}
+    if theta is not None:
+        kw.update(theta_in=_cuda(theta), theta_out=torch.empty(theta.shape, dtype=torch.float64).cuda(),
+                  l_in=_cuda(l), l_out=torch.empty(N, dtype=torch.float64).cuda())
+    smc.smc_resample_systematic(ctx, _cuda(W), seed=0, step=0,
+                                u_override=_cuda(np.array([u])), idx=idx, **kw)
+    return idx, kw
+
+
+@pytest.mark.parametrize("N", [1, 2, 7, 1000, 2049, 131072, 1 << 20])
+def test_resample_bit_exact(smc, ctx, N):
+    announce(f"resample N={N}")
+    W = osmc.normalise(lognormal_logw(N, seed=N + 5, spread=3.0))
+    rng = np.random.default_rng(N)
+    for trial in range(2):
+        u = float(rng.integers(0, 2 ** 32)) * 2.0 ** -32
+        idx, _ = _resample_gpu(smc, ctx, W, u)
+        ref = osmc.systematic_resample(W, u)
+        assert np.array_equal(idx.cpu().numpy(), ref)
+
+
+def test_resample_degenerate_weights(smc, ctx):
+    announce("resample degenerate")
+    N = 5000
+    for W in (np.full(N, 1.0 / N), np.eye(1, N, 4321).ravel(),
+              np.where(np.arange(N) % 3 == 0, 1.0, 0.0) / (N // 3 + 1)):
+        W = W / W.sum()
+        for u in (0.0, 0.5, 1.0 - 2.0 ** -32):
+            idx, _ = _resample_gpu(smc, ctx, W, u)
+            assert np.array_equal(idx.cpu().numpy(), osmc.systematic_resample(W, u))
+
+
+def test_resample_gather_and_predicate(smc, ctx):
+    announce("resample gather")
+    N, kd = 3000, 4
+    W = osmc.normalise(lognormal_logw(N, seed=1))
+    theta = np.random.default_rng(0).normal(size=(kd, N))
+    l = np.random.default_rng(1).normal(size=N)
+    idx, kw = _resample_gpu(smc, ctx, W, 0.25, theta, l)
+    ref = osmc.systematic_resample(W, 0.25)
+    assert np.array_equal(kw["theta_out"].cpu().numpy(), theta[:, ref])
+    assert np.array_equal(kw["l_out"].cpu().numpy(), l[ref])
+    # ESS predicate: not fired -> identity and copies
+    idx2 = torch.empty(N, dtype=torch.int32).cuda()
+    th_out = torch.empty((kd, N), dtype=torch.float64).cuda()
+    ess = _cuda(np.array([osmc.ess(W)]))
+    smc.smc_resample_systematic(ctx, _cuda(W), 3, 4, ess=ess, ess_threshold=1.0, idx=idx2,
+                                theta_in=_cuda(theta), theta_out=th_out)
+    assert np.array_equal(idx2.cpu().numpy(), np.arange(N))
+    assert np.array_equal(th_out.cpu().numpy(), theta)
+    # fired, with the offset drawn from the Philox stream of (seed, step)
+    smc.smc_resample_systematic(ctx, _cuda(W), 3, 4, ess=ess, ess_threshold=float(N), idx=idx2)
+    assert np.array_equal(idx2.cpu().numpy(), osmc.systematic_resample(W, osmc.resample_offset(3, 4)))
+
+
+# ------------------------------------------------------------------ RW-MH move
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rwmh_move_matches_oracle(smc, ctx, prec):
+    announce(f"rwmh {prec}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(200, mu, 0.55, seed=2)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
+    N = 4000
+    th = np.hstack([theta_prior_draws(N // 2, 4, 1, seed=3), theta_near_posterior(N // 2, mu, seed=4)])
+    l = ogmm.loglik(th, y, om)
+    tt, lt = _cuda(th), _cuda(l)
+    acc = torch.zeros(1, dtype=torch.int64).cuda()
+    beta = 0.37
+    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, beta, 0.5, seed=11, step=6,
+                      move=2, prec=prec, n_accept=acc)
+    ctx.check()
+    th_ref, l_ref, a_ref = osmc.rwmh_move(th, l, y, om, beta, 0.5, 11, 6, 2)
+    got_th, got_l = tt.cpu().numpy(), lt.cpu().numpy()
+    a_got = np.any(got_th != th, axis=0)
+    flips = int(np.sum(a_got != a_ref))
+    if prec == "fp64":
+        assert flips == 0
+    else:
+        assert flips <= 2          # FP32 log-likelihood error can flip a near-tie decision
+    same = a_got == a_ref
+    assert acc.item() == int(a_got.sum())
+    assert np.max(np.abs(got_th[:, same] - th_ref[:, same])) <= 1e-13 * 30
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert rel_err(got_l[same], l_ref[same]).max() <= tol
+
+
+def test_rwmh_per_chain_beta_and_box_prior(smc, ctx):
+    announce("rwmh beta_vec box")
+    mu = np.array([-2.0, 2.0])
+    y = make_mixture_data(80, mu, 0.3, seed=5)
+    g = smc.Gmm.equal_weights(2, 1, 0.3, prior="box", prior_a=-10.0, prior_b=10.0)
+    om = oracle_model(g)
+    M = 512
+    betas = pt_betas(M, 4)
+    th = osmc.prior_init(om, M, 9)
+    th[:, :5] = 9.95                           # proposals near the edge leave the box
+    l = ogmm.loglik(th, y, om)
+    tt, lt = _cuda(th), _cuda(l)
+    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, 0.0, 1.0, seed=5, step=1,
+                      prec="fp64", beta_vec=_cuda(betas))
+    th_ref, l_ref, a_ref = osmc.rwmh_move(th, l, y, om, betas, 1.0, 5, 1, 0)
+    assert np.max(np.abs(tt.cpu().numpy() - th_ref)) <= 1e-12
+    assert rel_err(lt.cpu().numpy(), l_ref).max() <= 1e-12
+    assert np.all(tt.cpu().numpy() <= 10.0) and np.all(tt.cpu().numpy() >= -10.0)
+
+
+# ------------------------------------------------------------------ exchange
+
+@pytest.mark.parametrize("M,parity,wrap", [(8192, 0, False), (8192, 1, False), (64, 1, True),
+                                           (7, 0, False), (7, 1, True), (2, 0, False)])
+def test_exchange_matches_oracle(smc, ctx, M, parity, wrap):
+    announce(f"exchange M={M} parity={parity} wrap={wrap}")
+    rng = np.random.default_rng(M + parity)
+    betas = pt_betas(M, 4)
+    th = rng.normal(size=(4, M))
+    l = -1000.0 + 50.0 * rng.normal(size=M)
+    tt, lt = _cuda(th), _cuda(l)
+    ns = torch.zeros(1, dtype=torch.int32).cuda()
+    smc.pt_exchange(ctx, tt, lt, _cuda(betas), parity, wrap, seed=17, iteration=33, n_swap=ns)
+    th_ref, l_ref, n_ref = osmc.pt_exchange(th, l, betas, parity, wrap, 17, 33)
+    assert np.array_equal(lt.cpu().numpy(), l_ref)
+    assert np.array_equal(tt.cpu().numpy(), th_ref)
+    assert ns.item() == n_ref
