@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the tempered-SMC hot path on one MI355X.
+
+A step is one whole tempering step of the SMC sampler (incremental reweight,
+log-sum-exp normalisation, ESS, ESS-triggered systematic resampling, one
+RW-MH move whose proposal log-likelihood is the mixture likelihood over all
+observations) on the headline workload: 1-D k = 4 mixture, n = 1000
+observations, N = 131072 particles, 100 quadratic tempering steps. The step
+is captured once in a hipGraph and replayed; inputs are resident in HBM.
+
+value = particle x datum log-likelihood evaluations per second over whole
+steps (FP32 path). The same run times the plain FP64 GPU form and reports the
+FP32/FP64 step-time ratio, the dominant kernel's roofline position (its
+average launch time from HIP events on its own stream) and the FP64 CPU
+oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 5]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "gmm1d_k4_n1000_N131072"
+
+# Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
+# 3.93e13 non-packed FP32 VALU lane-operations per second. A transcendental
+# (v_exp_f32) issues at half that rate on CDNA4, i.e. it occupies TRANS_SLOTS = 2
+# slots (an issue-rate probe measured 1.5-1.8 slot equivalents when mixed with FMAs).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+TRANS_SLOTS = 2.0
+HBM_PEAK_GBS = 8000.0
+
+
+def ops_per_eval(k: int) -> float:
+    """Algorithmic VALU work of one particle x datum evaluation in the FP32 form:
+    per component a distance FMA, a square-and-weight FMA, a shift subtract and
+    one exp2; per datum k-1 max, k-1 adds, the product update and the max
+    accumulation."""
+    return 5.0 * k + TRANS_SLOTS * k
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, y, betas, budget_s=12.0):
+    """The FP64 oracle on a bounded sample: whole tempering steps of the same
+    workload (same n, data, schedule) on fewer particles, timed on host cores."""
+    from oracle import gmm as ogmm
+    from oracle import smc as osmc
+    from oracle.gmm import Model
+    import numpy as np
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                             prior_b=cfg.prior_b)
+    Ns = 4096
+    theta = osmc.prior_init(om, Ns, cfg.run_seed)
+    l = ogmm.loglik(theta, y, om)
+    logw = np.zeros(Ns)
+    t = 1
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        theta, l, logw, _, _, _ = osmc.smc_step(theta, l, logw, y, om, betas, t, cfg.step_sd,
+                                                cfg.n_moves, cfg.run_seed, cfg.ess_frac)
+        steps += 1
+        t = min(t + 1, cfg.T)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    evals = steps * Ns * cfg.n * cfg.n_moves
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": evals / dt,
+        "unit": "evals/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{steps} whole tempering steps (reweight, ESS, resampling, RW-MH move) "
+                   f"of the {cfg.name} workload on {Ns} particles (n = {cfg.n}), {dt:.1f} s, "
+                   f"NumPy FP64 single-threaded on {cpu}; "
+                   f"{len(os.sched_getaffinity(0))} host cores visible"),
+        "ms_per_step_scaled_to_N": dt / steps * 1e3 * cfg.N / Ns,
+    }
+
+
+def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
+    s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac, prec=prec)
+    s.init()
+    graph = s.capture()
+    for _ in range(warmup):
+        graph.launch()
+    s.stream.synchronize()
+    s.init()                               # a fresh run from the prior for the timed steps
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    s.stream.synchronize()
+    t1 = time.perf_counter()
+    ctx.check(s.stream)
+    res = s.results()
+    ms_step = (t1 - t0) * 1e3 / steps
+    # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept),
+    # timed with HIP events recorded on the stream it runs on
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(10, steps)
+    e0.record(s.stream)
+    for i in range(reps):
+        smc.smc_rwmh_move(ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed,
+                          cfg.T + 1 + i, 0, prec, stream=s.stream)
+    e1.record(s.stream)
+    e1.synchronize()
+    ctx.check(s.stream)
+    kern_ms = e0.elapsed_time(e1) / reps
+    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, resamples=res["resamples"],
+                accepted=res["accepted"], logZ=res["logZ"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process on one GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0905_2441_amd as smc
+    from workloads import CONFIGS, beta_schedule, make_data
+
+    cfg = CONFIGS[WORKLOAD]
+    y = make_data(cfg)
+    betas = beta_schedule(cfg.T, cfg.schedule)
+    torch.cuda.set_device(0)
+    ctx = smc.Context(0)
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    evals_per_step = cfg.N * cfg.n * cfg.n_moves
+
+    log(f"[bench] {WORKLOAD}: fp32 {args.steps} steps after {args.warmup} warm-up")
+    r32 = time_precision(smc, torch, ctx, cfg, g, y, betas, "fp32", args.steps, args.warmup)
+    log(f"[bench] fp32 {r32['ms_per_step']:.4f} ms/step, move kernel {r32['kernel_ms']:.4f} ms")
+    r64 = None
+    if not args.no_fp64:
+        r64 = time_precision(smc, torch, ctx, cfg, g, y, betas, "fp64", args.steps, args.warmup)
+        log(f"[bench] fp64 {r64['ms_per_step']:.4f} ms/step, move kernel {r64['kernel_ms']:.4f} ms")
+
+    kern_evals = evals_per_step / (r32["kernel_ms"] * 1e-3)
+    achieved = kern_evals * ops_per_eval(cfg.k)
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_LANE_OPS / 1e12,
+        "unit": "Tlane-op/s",
+        "frac": achieved / PEAK_LANE_OPS,
+        "traffic": None,
+        "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
+        "ops_per_eval": ops_per_eval(cfg.k),
+        "kernel_ms": r32["kernel_ms"],
+        "kernel_evals_per_s": kern_evals,
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(cfg, y, betas)
+        log(f"[bench] oracle {cpu['value']:.3e} evals/s")
+
+    value = evals_per_step / (r32["ms_per_step"] * 1e-3)
+    out = {
+        "metric": "particle×datum loglik evals/s; ms per SMC tempering step, FP32/batched vs FP64",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N,
+                   "T": cfg.T, "schedule": "(t/T)^2", "moves_per_step": cfg.n_moves,
+                   "ess_threshold": "N/2", "graph": "one hipGraph per step, replayed"},
+        "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
+        "fp32_over_fp64_speedup": (r64["ms_per_step"] / r32["ms_per_step"]) if r64 else None,
+        "fp64_move_kernel_ms": r64["kernel_ms"] if r64 else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -142,8 +142,9 @@ int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
  *   logw[p] += dbeta * loglik[p]            (in/out, FP64)
  *   W[p] = exp(logw[p] - m) / sum_q exp(logw[q] - m)   (out, nullable)
  *   *logZ += lse(logw_new) - lse(logw_old)  (device scalar in/out, nullable)
- *   *ess = 1 / sum W^2                      (device scalar out, nullable;
- *                                            requires W)  */
+ *   *ess = 1 / sum W^2                      (device scalar out, nullable)
+ * All three come out of one pass over (logw, loglik) plus a one-workgroup
+ * combine in a fixed order (bit-reproducible). */
 int smc_reweight(smc_ctx ctx, double* logw, const double* loglik, int64_t N, double dbeta,
                  double* W, double* logZ, double* ess, void* stream);
 

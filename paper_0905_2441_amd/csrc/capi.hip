@@ -16,7 +16,7 @@ struct smc_ctx_s {
     int device = 0;
     int slices_override = 0;
     Scratch sc{};
-    void* fixed = nullptr;       // partials, tickets, status, state
+    void* fixed = nullptr;       // partials, chunk totals, status, state
     void* grow = nullptr;        // cdf, dd partials, l_tmp, theta_tmp
     int64_t grow_kd = 0;
 };
@@ -135,9 +135,7 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
         return fail(SMC_ERR_CAPTURE, "scratch must grow; call smc_reserve before capture");
     const int64_t cap = ctx->sc.cap >= N ? ctx->sc.cap : N;
     const int64_t kdc = ctx->grow_kd >= kd ? ctx->grow_kd : (kd < 8 ? 8 : kd);
-    const int64_t chunks = (cap + kScanChunk - 1) / kScanChunk + 1;
     const size_t b_cdf = align_up(sizeof(double) * cap);
-    const size_t b_dd = align_up(sizeof(double) * 2 * chunks);
     const size_t b_l = align_up(sizeof(double) * cap);
     const size_t b_th = align_up(sizeof(double) * cap * kdc);
     SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -147,17 +145,17 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
         ctx->grow = nullptr;
     }
     void* p = nullptr;
-    if (hipMalloc(&p, b_cdf + b_dd + b_l + b_th) != hipSuccess) {
+    if (hipMalloc(&p, 2 * b_cdf + b_l + b_th) != hipSuccess) {
         ctx->sc.cap = 0;
         ctx->grow_kd = 0;
         return fail(SMC_ERR_NOMEM, "device allocation of context scratch failed");
     }
     char* c = static_cast<char*>(p);
     ctx->grow = p;
-    ctx->sc.cdf = reinterpret_cast<double*>(c);
-    ctx->sc.dd_part = reinterpret_cast<double*>(c + b_cdf);
-    ctx->sc.l_tmp = reinterpret_cast<double*>(c + b_cdf + b_dd);
-    ctx->sc.theta_tmp = reinterpret_cast<double*>(c + b_cdf + b_dd + b_l);
+    ctx->sc.cdf_hi = reinterpret_cast<double*>(c);
+    ctx->sc.cdf_lo = reinterpret_cast<double*>(c + b_cdf);
+    ctx->sc.l_tmp = reinterpret_cast<double*>(c + 2 * b_cdf);
+    ctx->sc.theta_tmp = reinterpret_cast<double*>(c + 2 * b_cdf + b_l);
     ctx->sc.cap = cap;
     ctx->grow_kd = kdc;
     return SMC_OK;
@@ -196,12 +194,12 @@ int smc_create(smc_ctx* out, int device) {
     smc_ctx ctx = new (std::nothrow) smc_ctx_s();
     if (!ctx) return fail(SMC_ERR_NOMEM, "host allocation failed");
     ctx->device = device;
-    const size_t b_part = align_up(sizeof(LsePair) * kMaxRedBlocks);
+    const size_t b_part = align_up(sizeof(RwPartial) * kMaxRedBlocks);
     const size_t b_sq = align_up(sizeof(double) * kMaxRedBlocks);
-    const size_t b_tk = align_up(sizeof(unsigned) * 8);
+    const size_t b_dd = align_up(sizeof(double) * 2 * kMaxChunks);
     const size_t b_st = align_up(sizeof(int));
     const size_t b_state = align_up(sizeof(StepState));
-    const size_t total = 2 * b_part + b_sq + b_tk + b_st + b_state;
+    const size_t total = b_part + b_sq + b_dd + b_st + b_state;
     void* p = nullptr;
     if (hipMalloc(&p, total) != hipSuccess) {
         delete ctx;
@@ -214,12 +212,11 @@ int smc_create(smc_ctx* out, int device) {
     }
     char* c = static_cast<char*>(p);
     ctx->fixed = p;
-    ctx->sc.part_old = reinterpret_cast<LsePair*>(c);
-    ctx->sc.part_new = reinterpret_cast<LsePair*>(c + b_part);
-    ctx->sc.part_sq = reinterpret_cast<double*>(c + 2 * b_part);
-    ctx->sc.tickets = reinterpret_cast<unsigned*>(c + 2 * b_part + b_sq);
-    ctx->sc.status = reinterpret_cast<int*>(c + 2 * b_part + b_sq + b_tk);
-    ctx->sc.state = reinterpret_cast<StepState*>(c + 2 * b_part + b_sq + b_tk + b_st);
+    ctx->sc.rw_part = reinterpret_cast<RwPartial*>(c);
+    ctx->sc.sq_part = reinterpret_cast<double*>(c + b_part);
+    ctx->sc.dd_part = reinterpret_cast<double*>(c + b_part + b_sq);
+    ctx->sc.status = reinterpret_cast<int*>(c + b_part + b_sq + b_dd);
+    ctx->sc.state = reinterpret_cast<StepState*>(c + b_part + b_sq + b_dd + b_st);
     *out = ctx;
     return SMC_OK;
 }
@@ -318,8 +315,7 @@ int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
     const hipError_t e = launch_rwmh(g, y, n, theta, loglik, N, beta_vec,
                                      host_src(static_cast<int>(step), beta, 0.0), step_sd, seed,
                                      move, prec, n_accept, choose_slices(ctx, n, N),
-                                     ctx->sc.status, nullptr, nullptr, nullptr,
-                                     as_stream(stream));
+                                     ctx->sc.status, MoveStep{}, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     return SMC_OK;
 }
@@ -330,11 +326,15 @@ int smc_reweight(smc_ctx ctx, double* logw, const double* loglik, int64_t N, dou
     if (r) return r;
     if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
     if (!logw || !loglik) return fail(SMC_ERR_INVALID_ARG, "NULL array");
-    if (ess && !W) return fail(SMC_ERR_INVALID_ARG, "ess requires W");
     if (!isfinite(dbeta)) return fail(SMC_ERR_INVALID_ARG, "dbeta must be finite");
-    const hipError_t e = launch_reweight(ctx->sc, logw, loglik, N, host_src(0, 0.0, dbeta), W,
-                                         logZ, ess, 0.0, as_stream(stream));
+    const hipStream_t s = as_stream(stream);
+    hipError_t e = launch_reweight(ctx->sc, logw, loglik, N, host_src(0, 0.0, dbeta), nullptr,
+                                   logZ, ess, 0.0, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "reweight launch");
+    if (W) {
+        e = launch_weights(ctx->sc, logw, N, W, s);
+        if (e != hipSuccess) return hip_fail(e, "weights launch");
+    }
     return SMC_OK;
 }
 
@@ -366,9 +366,10 @@ int smc_resample_systematic(smc_ctx ctx, const double* W, int64_t N, uint64_t se
     if (l_in && l_in == l_out) return fail(SMC_ERR_INVALID_ARG, "l_out aliases l_in");
     if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
     if ((r = ensure_scratch(ctx, N, 1, as_stream(stream)))) return r;
-    const hipError_t e = launch_resample(ctx->sc, W, N, seed, host_src(static_cast<int>(step), 0, 0),
+    WeightSrc ws{W, nullptr, nullptr};
+    const hipError_t e = launch_resample(ctx->sc, ws, N, seed, host_src(static_cast<int>(step), 0, 0),
                                          u_override, ess, ess_threshold, nullptr, idx, theta_in,
-                                         theta_out, theta_in ? kd : 0, l_in, l_out, logw,
+                                         theta_out, theta_in ? kd : 0, l_in, l_out, logw, 1,
                                          as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "resample launch");
     return SMC_OK;
@@ -411,30 +412,40 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     const hipStream_t s = as_stream(stream);
     const int kd = g.k * g.d;
     if ((r = ensure_scratch(ctx, N, kd, s))) return r;
+    // the reweight pass reads t from the caller's counter; its finaliser records t
+    // in the step state and advances the counter, and every later kernel of the
+    // step reads t from the state
     StepSrc src{};
     src.t_dev = t_dev;
     src.beta_dev = beta;
     src.t_max = T;
-    hipError_t e = launch_reweight_step(ctx->sc, logw, loglik, N, src, W, stats, ess_frac, s);
+    StepSrc later = src;
+    later.t_dev = &ctx->sc.state->t;
+    hipError_t e = launch_reweight(ctx->sc, logw, loglik, N, src, t_dev, stats, stats + 1,
+                                   ess_frac, stats + 2, s);
     if (e != hipSuccess) return hip_fail(e, "reweight launch");
-    e = launch_resample(ctx->sc, W, N, seed, src, nullptr, nullptr, 0.0, ctx->sc.state, nullptr,
-                        theta, ctx->sc.theta_tmp, kd, loglik, ctx->sc.l_tmp, logw, s);
+    WeightSrc ws{nullptr, logw, ctx->sc.state};
+    e = launch_resample(ctx->sc, ws, N, seed, later, nullptr, nullptr, 0.0, ctx->sc.state,
+                        nullptr, theta, ctx->sc.theta_tmp, kd, loglik, ctx->sc.l_tmp, logw, 0, s);
     if (e != hipSuccess) return hip_fail(e, "resample launch");
     const int S = choose_slices(ctx, n, N);
     if (n_moves == 0) {
-        e = launch_copy_back(ctx->sc, theta, loglik, N, kd, s);
+        e = launch_copy_back(ctx->sc, theta, loglik, W, logw, N, kd, s);
         if (e != hipSuccess) return hip_fail(e, "copy-back launch");
     }
     for (int m = 0; m < n_moves; ++m) {
-        const bool first = (m == 0);
-        e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, src, step_sd, seed,
-                        static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status,
-                        first ? ctx->sc.theta_tmp : nullptr, first ? ctx->sc.l_tmp : nullptr,
-                        first ? ctx->sc.state : nullptr, s);
+        MoveStep ms{};
+        if (m == 0) {
+            ms.theta_alt = ctx->sc.theta_tmp;
+            ms.l_alt = ctx->sc.l_tmp;
+            ms.state = ctx->sc.state;
+            ms.W_out = W;
+            ms.logw = logw;
+        }
+        e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, later, step_sd, seed,
+                        static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status, ms, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }
-    e = launch_counter_inc(t_dev, s);
-    if (e != hipSuccess) return hip_fail(e, "counter launch");
     return SMC_OK;
 }
 
@@ -457,8 +468,7 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
     StepSrc src{};
     src.t_dev = it_dev;
     hipError_t e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec,
-                               n_accept, choose_slices(ctx, n, M), ctx->sc.status, nullptr,
-                               nullptr, nullptr, s);
+                               n_accept, choose_slices(ctx, n, M), ctx->sc.status, MoveStep{}, s);
     if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed, src,
                         n_swap, s);

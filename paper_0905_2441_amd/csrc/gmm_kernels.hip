@@ -191,8 +191,7 @@ template <int K, int D, int PREC>
 __global__ void __launch_bounds__(1024)
 k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        const double* __restrict__ beta_vec, StepSrc src, double sd, uint64_t seed,
-       uint32_t move, GmmDev g, unsigned long long* n_acc, int* status,
-       const double* theta_alt, const double* l_alt, const StepState* alt_flag) {
+       uint32_t move, GmmDev g, unsigned long long* n_acc, int* status, MoveStep ms) {
     constexpr int KD = K * D;
     __shared__ double red[kMaxSlices][kWave];
     const int S = wave_uniform(blockDim.x / kWave);
@@ -203,9 +202,9 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
     const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
     const uint32_t step = static_cast<uint32_t>(step_index(src));
-    const bool use_alt = (alt_flag != nullptr) && (alt_flag->resampled != 0);
-    const double* th_src = use_alt ? theta_alt : theta;
-    const double* l_src = use_alt ? l_alt : l;
+    const bool use_alt = (ms.state != nullptr) && (ms.state->resampled != 0);
+    const double* th_src = use_alt ? ms.theta_alt : theta;
+    const double* l_src = use_alt ? ms.l_alt : l;
 
     double pr[KD];
     {
@@ -244,6 +243,10 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
             l[p] = l_cur;
         }
         if (l_prop != l_prop) atomicOr(status, kStatusNaN);
+        if (ms.W_out) {
+            ms.W_out[p] = use_alt ? 1.0 / static_cast<double>(N)
+                                  : exp(ms.logw[p] - ms.state->M) / ms.state->S;
+        }
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
@@ -313,9 +316,8 @@ hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const doubl
 hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
                        int64_t N, const double* beta_vec, StepSrc src, double sd,
                        uint64_t seed, uint32_t move, int prec,
-                       unsigned long long* n_accept, int slices, int* status,
-                       const double* theta_alt, const double* l_alt,
-                       const StepState* alt_flag, hipStream_t s) {
+                       unsigned long long* n_accept, int slices, int* status, MoveStep ms,
+                       hipStream_t s) {
     const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
     const dim3 block(static_cast<unsigned>(kWave * slices));
 #define SMC_CASE(K, D)                                                                        \
@@ -323,13 +325,11 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
         if (prec == SMC_PREC_FP32)                                                            \
             hipLaunchKernelGGL((k_rwmh<K, D, SMC_PREC_FP32>), grid, block, 0, s, y,           \
                                static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,  \
-                               src, sd, seed, move, g, n_accept, status, theta_alt, l_alt,    \
-                               alt_flag);                                                     \
+                               src, sd, seed, move, g, n_accept, status, ms);                 \
         else                                                                                  \
             hipLaunchKernelGGL((k_rwmh<K, D, SMC_PREC_FP64>), grid, block, 0, s, y,           \
                                static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,  \
-                               src, sd, seed, move, g, n_accept, status, theta_alt, l_alt,    \
-                               alt_flag);                                                     \
+                               src, sd, seed, move, g, n_accept, status, ms);                 \
         return hipGetLastError();                                                             \
     }
     SMC_KD_CASES(SMC_CASE)

@@ -33,27 +33,31 @@ struct GmmDev {
 struct StepState {
     double M;                  // max log-weight after the reweight
     double S;                  // sum exp(logw - M)
+    double S2;                 // sum exp(2 (logw - M))
     double lse_old, lse_new;
     double ess;
     int resampled;             // 1 when the ESS test fired this step
-    int pad;
+    int t;                     // step index of the current device-driven step
 };
 
-struct alignas(16) LsePair {
-    double m, s;
+// Per-block partial of the reweight pass: running log-sum-exp of the old
+// log-weights (mo, so) and of the new ones with the sum of squares (mn, s1, s2).
+struct alignas(16) RwPartial {
+    double mo, so, mn, s1, s2, pad;
 };
+
+constexpr int kMaxChunks = 1024;        // CDF chunks (one per scan block)
 
 // Device scratch owned by a context.
 struct Scratch {
-    LsePair* part_old;         // [kMaxRedBlocks]
-    LsePair* part_new;         // [kMaxRedBlocks]
-    double* part_sq;           // [kMaxRedBlocks]
-    double* dd_part;           // [2 * max scan blocks]
-    unsigned* tickets;         // [8], zero between launches
+    RwPartial* rw_part;        // [kMaxRedBlocks]
+    double* sq_part;           // [kMaxRedBlocks]
+    double* dd_part;           // [2 * kMaxChunks] chunk totals (hi, lo)
     int* status;               // [1]
     StepState* state;          // [1]
-    double* cdf;               // [cap]
-    double* theta_tmp;         // [SMC_KDMAX * cap]
+    double* cdf_hi;            // [cap] within-chunk inclusive prefix, high part
+    double* cdf_lo;            // [cap] low part
+    double* theta_tmp;         // [kd * cap]
     double* l_tmp;             // [cap]
     int64_t cap;
 };
@@ -78,38 +82,59 @@ __device__ __forceinline__ int step_index(const StepSrc& src) {
     return t;
 }
 
+// Extra duties of the first RW-MH move of a fused tempering step: start from
+// the resampled population when the ESS test fired, and publish the
+// normalised weights of the step (1/N after resampling).
+struct MoveStep {
+    const double* theta_alt;   // gathered population (scratch)
+    const double* l_alt;
+    const StepState* state;    // nullable: no step duties
+    double* W_out;             // nullable
+    const double* logw;        // log-weights after the reweight
+};
+
+// How the CDF kernels obtain the normalised weights: read W, or form
+// exp(logw - M) / S from the step state.
+struct WeightSrc {
+    const double* W;           // nullable
+    const double* logw;
+    const StepState* state;
+};
+
 hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
                          int64_t N, int prec, double* out, int slices, int* status,
                          hipStream_t s);
 hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
                        int64_t N, const double* beta_vec, StepSrc src, double sd,
                        uint64_t seed, uint32_t move, int prec,
-                       unsigned long long* n_accept, int slices, int* status,
-                       const double* theta_alt, const double* l_alt,
-                       const StepState* alt_flag, hipStream_t s);
+                       unsigned long long* n_accept, int slices, int* status, MoveStep ms,
+                       hipStream_t s);
 hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,
                         hipStream_t s);
 bool supported_kd(int k, int d, int prec);
 
+// Reweight pass and its one-block finalisation. With t_dev set (fused step)
+// the finaliser also records t in the step state and advances the counter.
 hipError_t launch_reweight(const Scratch& sc, double* logw, const double* l, int64_t N,
-                           StepSrc src, double* W, double* logZ, double* ess,
-                           double ess_threshold_frac, hipStream_t s);
+                           StepSrc src, int* t_advance, double* logZ, double* ess,
+                           double ess_frac, double* resample_count, hipStream_t s);
+hipError_t launch_weights(const Scratch& sc, const double* logw, int64_t N, double* W,
+                          hipStream_t s);
 hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess,
                       hipStream_t s);
-hipError_t launch_resample(const Scratch& sc, const double* W, int64_t N, uint64_t seed,
-                           StepSrc src, const double* u_override, const double* ess,
+// Systematic resampling: CDF of the weights, then search and gather. pred_ess /
+// pred_state make both kernels no-ops unless the ESS test fired.
+hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t seed,
+                           StepSrc src, const double* u_override, const double* pred_ess,
                            double ess_threshold, const StepState* pred_state,
                            int32_t* idx, const double* theta_in, double* theta_out,
                            int32_t kd, const double* l_in, double* l_out, double* logw,
-                           hipStream_t s);
+                           int copy_when_skipped, hipStream_t s);
 hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
                            int32_t kd, int parity_mode, int parity_host, int wrap,
                            uint64_t seed, StepSrc src, unsigned* n_swap, hipStream_t s);
-hipError_t launch_reweight_step(const Scratch& sc, double* logw, const double* l, int64_t N,
-                                StepSrc src, double* W, double* stats, double ess_frac,
-                                hipStream_t s);
-hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, int64_t N, int kd,
-                            hipStream_t s);
+hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, double* W,
+                            const double* logw, int64_t N, int kd, hipStream_t s);
 hipError_t launch_counter_inc(int* counter, hipStream_t s);
 hipError_t launch_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
                             uint32_t purpose, uint32_t move, uint32_t* out, hipStream_t s);

@@ -1,17 +1,25 @@
 // Weight, resampling and exchange kernels (FP64) for gfx950.
 //
-// Reweight and ESS are HBM-bound streaming passes; their grid-wide reductions
-// use the "last block finishes" pattern: every block writes a partial, fences,
-// takes a ticket, and the block that takes the last ticket combines all
-// partials in block order (so results are bit-reproducible) and resets the
-// ticket. Device-scope fences make the partials visible across the eight XCDs,
-// whose L2 caches are not coherent with each other.
+// Grid-wide reductions never communicate between workgroups inside a kernel:
+// a streaming kernel writes one partial per workgroup and a one-workgroup
+// kernel combines them in block order. On MI355X a device-scope fence inside a
+// kernel writes back and invalidates the L2 of the issuing XCD, so per-block
+// "last block finishes" tickets cost far more than the kernel boundary they
+// would save. Combining in a fixed order keeps every result bit-reproducible.
 //
-// Systematic resampling builds the correctly rounded empirical CDF of the
-// weights with a double-double scan in three phases (block totals; per-block
-// scan with the block's offset; search and gather). Every phase can be
-// predicated on a device-side ESS test, so a tempering step never returns to
-// the host.
+// Reweight (SMC Sampler subsection: incremental weight L^dbeta) is one pass
+// over (logw, l) that keeps three running sums per thread: the log-sum-exp of
+// the old log-weights, and of the new ones together with the sum of their
+// squares, so the normalising constant, the log-evidence increment and the ESS
+// 1/sum W^2 = S1^2/S2 all come out of the same pass.
+//
+// Systematic resampling (Sequential Monte Carlo subsection: the empirical CDF
+// of the weights, sampled N times) builds the CDF with a double-double scan:
+// each chunk's workgroup stores within-chunk inclusive prefixes and the chunk
+// total; the search kernel forms the chunk offsets once per workgroup in LDS
+// and rounds offset + prefix once, so every C_j is the correctly rounded
+// prefix sum (up to double-double error, about 2^-104 relative). Both kernels
+// can be predicated on the device-side ESS test.
 #include "internal.hpp"
 #include "philox.hpp"
 #include "wave.hpp"
@@ -19,25 +27,58 @@
 namespace smc {
 namespace {
 
-__device__ __forceinline__ bool take_last_ticket(unsigned* ticket) {
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
+// ---------------------------------------------------------------- helpers
+
+struct Lse3 {
+    double m, s1, s2;          // sum exp(x - m), sum exp(2 (x - m))
+};
+
+__device__ __forceinline__ Lse3 lse3_empty() { return Lse3{-INFINITY, 0.0, 0.0}; }
+
+__device__ __forceinline__ Lse3 lse3_push(Lse3 a, double x) {
+    if (x == -INFINITY) return a;
+    if (x > a.m) {
+        const double r = (a.m == -INFINITY) ? 0.0 : exp(a.m - x);
+        return Lse3{x, a.s1 * r + 1.0, a.s2 * (r * r) + 1.0};
+    }
+    const double e = exp(x - a.m);
+    return Lse3{a.m, a.s1 + e, a.s2 + e * e};
+}
+
+__device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
+    if (b.m == -INFINITY) return a;
+    if (a.m == -INFINITY) return b;
+    if (a.m >= b.m) {
+        const double r = exp(b.m - a.m);
+        return Lse3{a.m, a.s1 + b.s1 * r, a.s2 + b.s2 * (r * r)};
+    }
+    const double r = exp(a.m - b.m);
+    return Lse3{b.m, b.s1 + a.s1 * r, b.s2 + a.s2 * (r * r)};
+}
+
+__device__ __forceinline__ Lse3 wave_lse3(Lse3 v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        Lse3 o{__shfl_xor(v.m, off, kWave), __shfl_xor(v.s1, off, kWave),
+               __shfl_xor(v.s2, off, kWave)};
+        v = (lane_id() & off) ? lse3_merge(o, v) : lse3_merge(v, o);
+    }
+    return v;
 }
 
 // Block (kRedBlock threads) reductions; the result is valid in thread 0.
-__device__ LseAcc block_lse(LseAcc v) {
-    __shared__ LsePair sh[kRedBlock / kWave];
-    v = wave_lse(v);
-    if (lane_id() == 0) sh[wave_id()] = LsePair{v.m, v.s};
+__device__ Lse3 block_lse3(Lse3 v) {
+    __shared__ double sm[kRedBlock / kWave], s1[kRedBlock / kWave], s2[kRedBlock / kWave];
+    v = wave_lse3(v);
+    if (lane_id() == 0) {
+        sm[wave_id()] = v.m;
+        s1[wave_id()] = v.s1;
+        s2[wave_id()] = v.s2;
+    }
     __syncthreads();
-    LseAcc r = lse_empty();
+    Lse3 r = lse3_empty();
     if (threadIdx.x == 0)
-        for (int w = 0; w < kRedBlock / kWave; ++w) r = lse_merge(r, LseAcc{sh[w].m, sh[w].s});
+        for (int w = 0; w < kRedBlock / kWave; ++w) r = lse3_merge(r, Lse3{sm[w], s1[w], s2[w]});
     __syncthreads();
     return r;
 }
@@ -54,114 +95,116 @@ __device__ double block_sum(double v) {
     return r;
 }
 
-__device__ dd block_dd_sum(dd v) {
-    __shared__ double shh[kRedBlock / kWave], shl[kRedBlock / kWave];
-    v = wave_sum(v);
-    if (lane_id() == 0) {
-        shh[wave_id()] = v.hi;
-        shl[wave_id()] = v.lo;
+// Exclusive scan of one dd value per thread over the block (thread order);
+// also returns the block total in `total` (valid in every thread).
+__device__ dd block_dd_exclusive_scan(dd v, dd& total) {
+    __shared__ double wh[kRedBlock / kWave], wl[kRedBlock / kWave];
+    const int lane = lane_id();
+    dd inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const dd up{__shfl_up(inc.hi, o, kWave), __shfl_up(inc.lo, o, kWave)};
+        if (lane >= o) inc = dd_add(up, inc);
     }
+    if (lane == kWave - 1) {
+        wh[wave_id()] = inc.hi;
+        wl[wave_id()] = inc.lo;
+    }
+    dd excl{__shfl_up(inc.hi, 1, kWave), __shfl_up(inc.lo, 1, kWave)};
+    if (lane == 0) excl = dd_zero();
     __syncthreads();
-    dd r = dd_zero();
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kRedBlock / kWave; ++w) r = dd_add(r, dd{shh[w], shl[w]});
+    dd off = dd_zero();
+    for (int w = 0; w < wave_id(); ++w) off = dd_add(off, dd{wh[w], wl[w]});
+    dd tot = dd_zero();
+    for (int w = 0; w < kRedBlock / kWave; ++w) tot = dd_add(tot, dd{wh[w], wl[w]});
+    total = tot;
     __syncthreads();
-    return r;
+    return dd_add(off, excl);
 }
 
 // ---------------------------------------------------------------- reweight
 
 __global__ void __launch_bounds__(kRedBlock)
-k_reweight_a(double* __restrict__ logw, const double* __restrict__ l, int N, StepSrc src,
-             Scratch sc, double* logZ) {
+k_reweight_partial(double* __restrict__ logw, const double* __restrict__ l, int N, StepSrc src,
+                   Scratch sc) {
     double dbeta = src.dbeta_host;
     if (src.beta_dev) {
         const int t = step_index(src);
         dbeta = src.beta_dev[t] - src.beta_dev[t - 1];
     }
-    LseAcc old_acc = lse_empty(), new_acc = lse_empty();
+    Lse3 o = lse3_empty(), nw = lse3_empty();
     bool bad = false;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
         const double lo = logw[p];
         const double ln = lo + dbeta * l[p];
         logw[p] = ln;
         bad = bad || (ln != ln) || (ln == INFINITY);
-        old_acc = lse_push(old_acc, lo);
-        new_acc = lse_push(new_acc, ln);
+        o = lse3_push(o, lo);
+        nw = lse3_push(nw, ln);
     }
     if (bad) atomicOr(sc.status, kStatusNaN);
-    const LseAcc bo = block_lse(old_acc);
-    const LseAcc bn = block_lse(new_acc);
-    if (threadIdx.x == 0) {
-        sc.part_old[blockIdx.x] = LsePair{bo.m, bo.s};
-        sc.part_new[blockIdx.x] = LsePair{bn.m, bn.s};
+    o = block_lse3(o);
+    nw = block_lse3(nw);
+    if (threadIdx.x == 0) sc.rw_part[blockIdx.x] = RwPartial{o.m, o.s1, nw.m, nw.s1, nw.s2, 0.0};
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+k_reweight_final(int parts, int N, StepSrc src, int* t_advance, Scratch sc, double* logZ,
+                 double* ess_out, double ess_frac, double* resample_count) {
+    Lse3 o = lse3_empty(), nw = lse3_empty();
+    for (int b = threadIdx.x; b < parts; b += blockDim.x) {
+        const RwPartial q = sc.rw_part[b];
+        o = lse3_merge(o, Lse3{q.mo, q.so, 0.0});
+        nw = lse3_merge(nw, Lse3{q.mn, q.s1, q.s2});
     }
-    if (!take_last_ticket(&sc.tickets[0])) return;
-    LseAcc o = lse_empty(), nw = lse_empty();
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += blockDim.x) {
-        const LsePair po = sc.part_old[b], pn = sc.part_new[b];
-        o = lse_merge(o, LseAcc{po.m, po.s});
-        nw = lse_merge(nw, LseAcc{pn.m, pn.s});
-    }
-    o = block_lse(o);
-    nw = block_lse(nw);
-    if (threadIdx.x == 0) {
-        StepState* st = sc.state;
-        st->M = nw.m;
-        st->S = nw.s;
-        st->lse_old = lse_value(o);
-        st->lse_new = lse_value(nw);
-        if (nw.m == -INFINITY) atomicOr(sc.status, kStatusAllZeroWeight);
-        if (logZ) *logZ += st->lse_new - st->lse_old;
-        sc.tickets[0] = 0u;
+    o = block_lse3(o);
+    nw = block_lse3(nw);
+    if (threadIdx.x != 0) return;
+    StepState* st = sc.state;
+    st->M = nw.m;
+    st->S = nw.s1;
+    st->S2 = nw.s2;
+    st->lse_old = (o.m == -INFINITY) ? -INFINITY : o.m + log(o.s1);
+    st->lse_new = (nw.m == -INFINITY) ? -INFINITY : nw.m + log(nw.s1);
+    const double e = (nw.s1 * nw.s1) / nw.s2;
+    st->ess = e;
+    const int fire = (ess_frac > 0.0) && (e < ess_frac * static_cast<double>(N));
+    st->resampled = fire;
+    if (nw.m == -INFINITY || !(e == e)) atomicOr(sc.status, kStatusAllZeroWeight);
+    if (logZ) *logZ += st->lse_new - st->lse_old;
+    if (ess_out) *ess_out = e;
+    if (resample_count && fire) *resample_count += 1.0;
+    if (t_advance) {
+        const int t = step_index(src);
+        st->t = t;
+        *t_advance = t + 1;
     }
 }
 
 __global__ void __launch_bounds__(kRedBlock)
-k_reweight_b(const double* __restrict__ logw, int N, double* __restrict__ W, Scratch sc,
-             double* ess_out, double ess_frac, double* resample_count) {
-    const double M = sc.state->M;
-    const double S = sc.state->S;
-    double sq = 0.0;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
-        const double w = exp(logw[p] - M) / S;
-        W[p] = w;
-        sq += w * w;
-    }
-    const double bs = block_sum(sq);
-    if (threadIdx.x == 0) sc.part_sq[blockIdx.x] = bs;
-    if (!take_last_ticket(&sc.tickets[1])) return;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += blockDim.x) acc += sc.part_sq[b];
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) {
-        const double e = 1.0 / acc;
-        sc.state->ess = e;
-        const int fire = (ess_frac > 0.0) && (e < ess_frac * static_cast<double>(N));
-        sc.state->resampled = fire;
-        if (ess_out) *ess_out = e;
-        if (resample_count && fire) *resample_count += 1.0;
-        sc.tickets[1] = 0u;
-    }
+k_weights(const double* __restrict__ logw, int N, Scratch sc, double* __restrict__ W) {
+    const double M = sc.state->M, S = sc.state->S;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x)
+        W[p] = exp(logw[p] - M) / S;
 }
 
 __global__ void __launch_bounds__(kRedBlock)
-k_ess(const double* __restrict__ W, int N, Scratch sc, double* ess_out) {
+k_sq_partial(const double* __restrict__ W, int N, Scratch sc) {
     double sq = 0.0;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
         const double w = W[p];
         sq += w * w;
     }
     const double bs = block_sum(sq);
-    if (threadIdx.x == 0) sc.part_sq[blockIdx.x] = bs;
-    if (!take_last_ticket(&sc.tickets[2])) return;
+    if (threadIdx.x == 0) sc.sq_part[blockIdx.x] = bs;
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+k_sq_final(int parts, Scratch sc, double* ess_out) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < static_cast<int>(gridDim.x); b += blockDim.x) acc += sc.part_sq[b];
+    for (int b = threadIdx.x; b < parts; b += blockDim.x) acc += sc.sq_part[b];
     acc = block_sum(acc);
-    if (threadIdx.x == 0) {
-        *ess_out = 1.0 / acc;
-        sc.tickets[2] = 0u;
-    }
+    if (threadIdx.x == 0) *ess_out = 1.0 / acc;
 }
 
 // ---------------------------------------------------------------- resampling
@@ -178,82 +221,59 @@ __device__ __forceinline__ bool should_fire(const ResamplePred& pr) {
     return true;
 }
 
-// Phase 1: double-double total of each chunk of kScanChunk weights.
+__device__ __forceinline__ double weight_at(const WeightSrc& w, int j) {
+    if (w.W) return w.W[j];
+    return exp(w.logw[j] - w.state->M) / w.state->S;
+}
+
+// Phase 1: within-chunk inclusive prefixes (double-double) and chunk totals.
+// Chunk b covers [b*chunk, min(N, (b+1)*chunk)), processed kScanChunk at a time.
 __global__ void __launch_bounds__(kRedBlock)
-k_cdf_totals(const double* __restrict__ W, int N, Scratch sc, ResamplePred pred) {
+k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
     if (!should_fire(pred)) return;
-    const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
-    dd acc = dd_zero();
+    const int begin = blockIdx.x * chunk;
+    const int end = min(N, begin + chunk);
+    dd carry = dd_zero();
+    for (int piece = begin; piece < end; piece += kScanChunk) {
+        const int base = piece + threadIdx.x * kScanPerThread;
+        dd pre[kScanPerThread];
+        dd run = dd_zero();
 #pragma unroll
-    for (int e = 0; e < kScanPerThread; ++e)
-        if (base + e < N) acc = dd_add(acc, W[base + e]);
-    acc = block_dd_sum(acc);
+        for (int e = 0; e < kScanPerThread; ++e) {
+            if (base + e < end) run = dd_add(run, weight_at(w, base + e));
+            pre[e] = run;
+        }
+        dd total;
+        const dd excl = block_dd_exclusive_scan(run, total);
+        const dd lead = dd_add(carry, excl);
+#pragma unroll
+        for (int e = 0; e < kScanPerThread; ++e) {
+            if (base + e < end) {
+                const dd c = dd_add(lead, pre[e]);
+                sc.cdf_hi[base + e] = c.hi;
+                sc.cdf_lo[base + e] = c.lo;
+            }
+        }
+        carry = dd_add(carry, total);
+    }
     if (threadIdx.x == 0) {
-        sc.dd_part[2 * blockIdx.x] = acc.hi;
-        sc.dd_part[2 * blockIdx.x + 1] = acc.lo;
+        sc.dd_part[2 * blockIdx.x] = carry.hi;
+        sc.dd_part[2 * blockIdx.x + 1] = carry.lo;
     }
 }
 
-// Phase 2: per-chunk inclusive scan plus the sum of all earlier chunks; each
-// prefix is rounded once from double-double to double.
-__global__ void __launch_bounds__(kRedBlock)
-k_cdf_scan(const double* __restrict__ W, int N, Scratch sc, ResamplePred pred) {
-    if (!should_fire(pred)) return;
-    __shared__ double wh[kRedBlock / kWave], wl[kRedBlock / kWave];
-    __shared__ double oh, ol;
-    // offset = sum of the totals of chunks 0..b-1, in chunk order per thread
-    dd off = dd_zero();
-    for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += blockDim.x)
-        off = dd_add(off, dd{sc.dd_part[2 * b], sc.dd_part[2 * b + 1]});
-    off = block_dd_sum(off);
-    if (threadIdx.x == 0) {
-        oh = off.hi;
-        ol = off.lo;
-    }
-    // this thread's inclusive prefixes
-    const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
-    dd pre[kScanPerThread];
-    dd run = dd_zero();
-#pragma unroll
-    for (int e = 0; e < kScanPerThread; ++e) {
-        if (base + e < N) run = dd_add(run, W[base + e]);
-        pre[e] = run;
-    }
-    // inclusive scan of thread totals within the wave (earlier + later)
-    dd inc = run;
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const dd up{__shfl_up(inc.hi, o, kWave), __shfl_up(inc.lo, o, kWave)};
-        if (lane >= o) inc = dd_add(up, inc);
-    }
-    if (lane == kWave - 1) {
-        wh[wave_id()] = inc.hi;
-        wl[wave_id()] = inc.lo;
-    }
-    dd excl{__shfl_up(inc.hi, 1, kWave), __shfl_up(inc.lo, 1, kWave)};
-    if (lane == 0) excl = dd_zero();
-    __syncthreads();
-    dd wave_off{oh, ol};
-    for (int w = 0; w < wave_id(); ++w) wave_off = dd_add(wave_off, dd{wh[w], wl[w]});
-    const dd lead = dd_add(wave_off, excl);
-#pragma unroll
-    for (int e = 0; e < kScanPerThread; ++e)
-        if (base + e < N) sc.cdf[base + e] = dd_add(lead, pre[e]).hi;
-}
-
-// Phase 3: U_i = (i + u)/N, idx_i = min{j : U_i < C_j} (or the first j with
+// Phase 2: chunk offsets (exclusive scan of the chunk totals, once per block in
+// LDS), then U_i = (i + u)/N, idx_i = min{j : U_i < C_j} (or the first j with
 // C_j = C_{N-1} when U_i >= C_{N-1}), then gather.
 __global__ void __launch_bounds__(kRedBlock)
-k_search_gather(int N, Scratch sc, ResamplePred pred, uint64_t seed, StepSrc src,
-                const double* u_override, int32_t* idx_out, const double* __restrict__ theta_in,
-                double* __restrict__ theta_out, int kd, const double* __restrict__ l_in,
-                double* __restrict__ l_out, double* logw, double* W_reset,
+k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, uint64_t seed,
+                StepSrc src, const double* u_override, int32_t* idx_out,
+                const double* __restrict__ theta_in, double* __restrict__ theta_out, int kd,
+                const double* __restrict__ l_in, double* __restrict__ l_out, double* logw,
                 int copy_when_skipped) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     if (!should_fire(pred)) {
-        if (!copy_when_skipped) return;
+        if (!copy_when_skipped || i >= N) return;
         if (idx_out) idx_out[i] = i;
         if (theta_in && theta_out)
             for (int c = 0; c < kd; ++c)
@@ -261,7 +281,33 @@ k_search_gather(int N, Scratch sc, ResamplePred pred, uint64_t seed, StepSrc src
         if (l_in && l_out) l_out[i] = l_in[i];
         return;
     }
-    const double* C = sc.cdf;
+    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
+    {
+        constexpr int per = kMaxChunks / kRedBlock;
+        const int c0 = threadIdx.x * per;
+        dd loc[per];
+        dd run = dd_zero();
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            loc[q] = run;
+            if (c0 + q < nchunks)
+                run = dd_add(run, dd{sc.dd_part[2 * (c0 + q)], sc.dd_part[2 * (c0 + q) + 1]});
+        }
+        dd total;
+        const dd lead = block_dd_exclusive_scan(run, total);
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            const dd o = dd_add(lead, loc[q]);
+            offh[c0 + q] = o.hi;
+            offl[c0 + q] = o.lo;
+        }
+        __syncthreads();
+    }
+    if (i >= N) return;
+    auto cdf = [&](int j) -> double {
+        const int b = j / chunk;
+        return dd_add(dd{offh[b], offl[b]}, dd{sc.cdf_hi[j], sc.cdf_lo[j]}).hi;
+    };
     double u;
     if (u_override) {
         u = *u_override;
@@ -270,18 +316,18 @@ k_search_gather(int N, Scratch sc, ResamplePred pred, uint64_t seed, StepSrc src
         u = u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
     }
     const double U = (static_cast<double>(i) + u) / static_cast<double>(N);
-    const double clast = C[N - 1];
+    const double clast = cdf(N - 1);
     int lo = 0, hi = N - 1;
     if (U < clast) {
         while (lo < hi) {
             const int mid = lo + ((hi - lo) >> 1);
-            if (U < C[mid]) hi = mid;
+            if (U < cdf(mid)) hi = mid;
             else lo = mid + 1;
         }
     } else {
         while (lo < hi) {
             const int mid = lo + ((hi - lo) >> 1);
-            if (C[mid] >= clast) hi = mid;
+            if (cdf(mid) >= clast) hi = mid;
             else lo = mid + 1;
         }
     }
@@ -292,7 +338,6 @@ k_search_gather(int N, Scratch sc, ResamplePred pred, uint64_t seed, StepSrc src
             theta_out[static_cast<size_t>(c) * N + i] = theta_in[static_cast<size_t>(c) * N + j];
     if (l_in && l_out) l_out[i] = l_in[j];
     if (logw) logw[i] = 0.0;
-    if (W_reset) W_reset[i] = 1.0 / static_cast<double>(N);
 }
 
 // ---------------------------------------------------------------- exchange
@@ -334,14 +379,22 @@ k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __r
     }
 }
 
-// After a step whose moves were all skipped: adopt the resampled population.
+// A step whose moves were all skipped: adopt the resampled population and
+// publish the step's weights.
 __global__ void __launch_bounds__(kRedBlock)
-k_copy_back(double* __restrict__ theta, double* __restrict__ l, int N, int kd, Scratch sc) {
+k_copy_back(double* __restrict__ theta, double* __restrict__ l, double* __restrict__ W,
+            const double* __restrict__ logw, int N, int kd, Scratch sc) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || sc.state->resampled == 0) return;
-    for (int c = 0; c < kd; ++c)
-        theta[static_cast<size_t>(c) * N + i] = sc.theta_tmp[static_cast<size_t>(c) * N + i];
-    l[i] = sc.l_tmp[i];
+    if (i >= N) return;
+    const StepState* st = sc.state;
+    if (st->resampled) {
+        for (int c = 0; c < kd; ++c)
+            theta[static_cast<size_t>(c) * N + i] = sc.theta_tmp[static_cast<size_t>(c) * N + i];
+        l[i] = sc.l_tmp[i];
+        W[i] = 1.0 / static_cast<double>(N);
+    } else {
+        W[i] = exp(logw[i] - st->M) / st->S;
+    }
 }
 
 __global__ void k_counter_inc(int* c) {
@@ -379,75 +432,64 @@ int red_grid(int64_t N) {
     return static_cast<int>(g);
 }
 
+// Elements per CDF chunk: a multiple of kScanChunk, so that at most kMaxChunks chunks cover N.
+int cdf_chunk(int64_t N) {
+    int64_t per = (N + kMaxChunks - 1) / kMaxChunks;
+    per = ((per + kScanChunk - 1) / kScanChunk) * kScanChunk;
+    if (per < kScanChunk) per = kScanChunk;
+    return static_cast<int>(per);
+}
+
 }  // namespace
 
 hipError_t launch_reweight(const Scratch& sc, double* logw, const double* l, int64_t N,
-                           StepSrc src, double* W, double* logZ, double* ess,
-                           double ess_threshold_frac, hipStream_t s) {
+                           StepSrc src, int* t_advance, double* logZ, double* ess,
+                           double ess_frac, double* resample_count, hipStream_t s) {
     const int g = red_grid(N);
-    hipLaunchKernelGGL(k_reweight_a, dim3(g), dim3(kRedBlock), 0, s, logw, l,
-                       static_cast<int>(N), src, sc, logZ);
+    hipLaunchKernelGGL(k_reweight_partial, dim3(g), dim3(kRedBlock), 0, s, logw, l,
+                       static_cast<int>(N), src, sc);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || W == nullptr) return e;
-    hipLaunchKernelGGL(k_reweight_b, dim3(g), dim3(kRedBlock), 0, s, logw,
-                       static_cast<int>(N), W, sc, ess, ess_threshold_frac,
-                       static_cast<double*>(nullptr));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reweight_final, dim3(1), dim3(kRedBlock), 0, s, g, static_cast<int>(N),
+                       src, t_advance, sc, logZ, ess, ess_frac, resample_count);
     return hipGetLastError();
 }
 
-hipError_t launch_reweight_step(const Scratch& sc, double* logw, const double* l, int64_t N,
-                                StepSrc src, double* W, double* stats, double ess_frac,
-                                hipStream_t s) {
-    const int g = red_grid(N);
-    hipLaunchKernelGGL(k_reweight_a, dim3(g), dim3(kRedBlock), 0, s, logw, l,
-                       static_cast<int>(N), src, sc, stats);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reweight_b, dim3(g), dim3(kRedBlock), 0, s, logw,
-                       static_cast<int>(N), W, sc, stats + 1, ess_frac, stats + 2);
+hipError_t launch_weights(const Scratch& sc, const double* logw, int64_t N, double* W,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_weights, dim3(red_grid(N)), dim3(kRedBlock), 0, s, logw,
+                       static_cast<int>(N), sc, W);
     return hipGetLastError();
 }
 
 hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_ess, dim3(red_grid(N)), dim3(kRedBlock), 0, s, W,
-                       static_cast<int>(N), sc, ess);
-    return hipGetLastError();
-}
-
-static hipError_t launch_resample_impl(const Scratch& sc, const double* W, int64_t N,
-                                       uint64_t seed, StepSrc src, const double* u_override,
-                                       ResamplePred pred, int32_t* idx, const double* theta_in,
-                                       double* theta_out, int32_t kd, const double* l_in,
-                                       double* l_out, double* logw, double* W_reset,
-                                       int copy_when_skipped, hipStream_t s) {
-    const int chunks = static_cast<int>((N + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_cdf_totals, dim3(chunks), dim3(kRedBlock), 0, s, W,
-                       static_cast<int>(N), sc, pred);
+    const int g = red_grid(N);
+    hipLaunchKernelGGL(k_sq_partial, dim3(g), dim3(kRedBlock), 0, s, W, static_cast<int>(N), sc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cdf_scan, dim3(chunks), dim3(kRedBlock), 0, s, W,
-                       static_cast<int>(N), sc, pred);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
-    hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N),
-                       sc, pred, seed, src, u_override, idx, theta_in, theta_out, kd, l_in,
-                       l_out, logw, W_reset, copy_when_skipped);
+    hipLaunchKernelGGL(k_sq_final, dim3(1), dim3(kRedBlock), 0, s, g, sc, ess);
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const Scratch& sc, const double* W, int64_t N, uint64_t seed,
-                           StepSrc src, const double* u_override, const double* ess,
+hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t seed,
+                           StepSrc src, const double* u_override, const double* pred_ess,
                            double ess_threshold, const StepState* pred_state,
                            int32_t* idx, const double* theta_in, double* theta_out,
                            int32_t kd, const double* l_in, double* l_out, double* logw,
-                           hipStream_t s) {
-    ResamplePred pred{ess, ess_threshold, pred_state};
-    const int copy = pred_state ? 0 : 1;
-    double* W_reset = pred_state ? const_cast<double*>(W) : nullptr;
-    return launch_resample_impl(sc, W, N, seed, src, u_override, pred, idx, theta_in,
-                                theta_out, kd, l_in, l_out, logw, W_reset, copy, s);
+                           int copy_when_skipped, hipStream_t s) {
+    ResamplePred pred{pred_ess, ess_threshold, pred_state};
+    const int chunk = cdf_chunk(N);
+    const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_cdf_local, dim3(nchunks), dim3(kRedBlock), 0, s, w,
+                       static_cast<int>(N), chunk, sc, pred);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
+    hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N),
+                       chunk, nchunks, sc, pred, seed, src, u_override, idx, theta_in,
+                       theta_out, kd, l_in, l_out, logw, copy_when_skipped);
+    return hipGetLastError();
 }
 
 hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
@@ -461,10 +503,10 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, int64_t N, int kd,
-                            hipStream_t s) {
+hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, double* W,
+                            const double* logw, int64_t N, int kd, hipStream_t s) {
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
-    hipLaunchKernelGGL(k_copy_back, dim3(g), dim3(kRedBlock), 0, s, theta, l,
+    hipLaunchKernelGGL(k_copy_back, dim3(g), dim3(kRedBlock), 0, s, theta, l, W, logw,
                        static_cast<int>(N), kd, sc);
     return hipGetLastError();
 }
