@@ -92,9 +92,10 @@ int smc_create(smc_ctx* out, int device);
 int smc_destroy(smc_ctx ctx);
 
 /* [sync] Size the context scratch for up to N particles of up to kd = k*d
- * parameters each, so that later calls (in particular inside hipGraph stream
- * capture) never allocate. */
-int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd);
+ * parameters each and, when n > 0, for the MFMA form over up to n observations,
+ * so that later calls (in particular inside hipGraph stream capture) never
+ * allocate. */
+int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd, int64_t n);
 
 /* [sync] Synchronise `stream`, then read and clear the device status flag:
  * SMC_OK, or SMC_ERR_NUMERIC if a kernel saw a NaN log-likelihood or weights
@@ -112,7 +113,10 @@ int smc_set_slices(smc_ctx ctx, int32_t slices);
  *   loglik[p] = sum_j log sum_i w_i N_d(y_j; mu_{p,i}, sigma2 I).
  * y: [n][d] FP32; theta: [k*d][N] FP64; loglik: [N] FP64 out.
  * prec FP64: plain form; FP32: FP32 arithmetic with hardware exp2 and a
- * compensated FP64 sum (relative error below 1e-6); BF16X3 requires d > 1. */
+ * compensated FP64 sum (relative error below 1e-6); BF16X3: d = 8, k in
+ * {1,2,4,8}: the quadratic forms as one K = 64 BF16 MFMA contraction of
+ * three-way (hi/mid/lo) split operands with FP32 accumulation, then the same
+ * FP32 epilogue (relative error below 1e-6). */
 int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
                const double* theta, int64_t N, smc_prec prec, double* loglik,
                void* stream);

@@ -46,7 +46,7 @@ _GP = POINTER(SmcGmm)
 SIGNATURES = {
     "smc_create": (c_int, [POINTER(c_void_p), c_int]),
     "smc_destroy": (c_int, [_P]),
-    "smc_reserve": (c_int, [_P, c_int64, c_int32]),
+    "smc_reserve": (c_int, [_P, c_int64, c_int32, c_int64]),
     "smc_check": (c_int, [_P, _P]),
     "smc_last_error": (c_char_p, []),
     "smc_set_slices": (c_int, [_P, c_int32]),

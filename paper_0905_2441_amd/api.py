@@ -104,8 +104,8 @@ class Context:
         self.handle = h
         self.device = device
 
-    def reserve(self, N: int, kd: int = 8) -> None:
-        L.check(self._lib.smc_reserve(self.handle, int(N), int(kd)))
+    def reserve(self, N: int, kd: int = 8, n: int = 0) -> None:
+        L.check(self._lib.smc_reserve(self.handle, int(N), int(kd), int(n)))
 
     def check(self, stream=None) -> None:
         L.check(self._lib.smc_check(self.handle, _stream(stream)))

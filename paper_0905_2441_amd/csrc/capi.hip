@@ -19,6 +19,7 @@ struct smc_ctx_s {
     void* fixed = nullptr;       // partials, chunk totals, status, state
     void* grow = nullptr;        // cdf, dd partials, l_tmp, theta_tmp
     int64_t grow_kd = 0;
+    void* mm = nullptr;          // MFMA form: data rows, columns, proposals, partials
 };
 
 struct smc_graph_s {
@@ -161,6 +162,42 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
     return SMC_OK;
 }
 
+// Scratch of the MFMA form: data rows [n_pad][64] bf16, particle-component
+// columns [N*8][64] bf16, proposals [64][N] and slice partials [16][N] FP64.
+int ensure_mm_scratch(smc_ctx ctx, int64_t n, int64_t N, hipStream_t s) {
+    const int64_t rows = dd_padded_rows(n);
+    if (ctx->sc.mm_rows_cap >= rows && ctx->sc.mm_n_cap >= N) return SMC_OK;
+    if (capturing(s))
+        return fail(SMC_ERR_CAPTURE, "scratch must grow; call smc_reserve before capture");
+    const int64_t rc = ctx->sc.mm_rows_cap >= rows ? ctx->sc.mm_rows_cap : rows;
+    const int64_t nc = ctx->sc.mm_n_cap >= N ? ctx->sc.mm_n_cap : N;
+    const size_t b_rows = align_up(static_cast<size_t>(rc) * 128);
+    const size_t b_cols = align_up(static_cast<size_t>(nc) * SMC_KMAX * 128);
+    const size_t b_prop = align_up(sizeof(double) * nc * SMC_KDMAX);
+    const size_t b_part = align_up(sizeof(double) * nc * kMaxSlices);
+    SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    SMC_CHECK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize before scratch growth");
+    if (ctx->mm) {
+        SMC_CHECK_HIP(hipFree(ctx->mm), "hipFree");
+        ctx->mm = nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, b_rows + b_cols + b_prop + b_part) != hipSuccess) {
+        ctx->sc.mm_rows_cap = 0;
+        ctx->sc.mm_n_cap = 0;
+        return fail(SMC_ERR_NOMEM, "device allocation of MFMA scratch failed");
+    }
+    char* c = static_cast<char*>(p);
+    ctx->mm = p;
+    ctx->sc.mm_rows = reinterpret_cast<__bf16*>(c);
+    ctx->sc.mm_cols = reinterpret_cast<__bf16*>(c + b_rows);
+    ctx->sc.mm_prop = reinterpret_cast<double*>(c + b_rows + b_cols);
+    ctx->sc.mm_part = reinterpret_cast<double*>(c + b_rows + b_cols + b_prop);
+    ctx->sc.mm_rows_cap = rc;
+    ctx->sc.mm_n_cap = nc;
+    return SMC_OK;
+}
+
 int enter(smc_ctx ctx) {
     if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
     hipError_t e = hipSetDevice(ctx->device);
@@ -226,17 +263,21 @@ int smc_destroy(smc_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->grow) (void)hipFree(ctx->grow);
+    if (ctx->mm) (void)hipFree(ctx->mm);
     if (ctx->fixed) (void)hipFree(ctx->fixed);
     delete ctx;
     return SMC_OK;
 }
 
-int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd) {
+int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd, int64_t n) {
     int r = enter(ctx);
     if (r) return r;
     if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
     if (kd < 1 || kd > SMC_KDMAX) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
-    return ensure_scratch(ctx, N, kd, nullptr);
+    if (n < 0 || n > (int64_t{1} << 30)) return fail(SMC_ERR_INVALID_ARG, "n in 0..2^30");
+    if ((r = ensure_scratch(ctx, N, kd, nullptr))) return r;
+    if (n > 0) return ensure_mm_scratch(ctx, n, N, nullptr);
+    return SMC_OK;
 }
 
 int smc_check(smc_ctx ctx, void* stream) {
@@ -274,9 +315,18 @@ int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
     if ((r = check_prec(g, prec))) return r;
     if ((r = check_sizes(n, N))) return r;
     if (!y || !theta || !loglik) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    const hipStream_t s = as_stream(stream);
+    if (prec == SMC_PREC_BF16X3) {
+        if ((r = ensure_mm_scratch(ctx, n, N, s))) return r;
+        hipError_t e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
+        if (e == hipSuccess)
+            e = launch_dd_loglik(g, ctx->sc.mm_rows, n, theta, N, ctx->sc.mm_cols, ctx->sc.mm_part,
+                                 dd_slices(n, N), loglik, ctx->sc.status, s);
+        if (e != hipSuccess) return hip_fail(e, "MFMA loglik launch");
+        return SMC_OK;
+    }
     const hipError_t e = launch_loglik(g, y, n, theta, N, prec, loglik,
-                                       choose_slices(ctx, n, N), ctx->sc.status,
-                                       as_stream(stream));
+                                       choose_slices(ctx, n, N), ctx->sc.status, s);
     if (e != hipSuccess) return hip_fail(e, "loglik launch");
     return SMC_OK;
 }
@@ -312,6 +362,18 @@ int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
         return fail(SMC_ERR_INVALID_ARG, "beta must be finite and >= 0");
     if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
     if (move > 0xFFFFFFu) return fail(SMC_ERR_INVALID_ARG, "move must fit in 24 bits");
+    if (prec == SMC_PREC_BF16X3) {
+        const hipStream_t s = as_stream(stream);
+        if ((r = ensure_mm_scratch(ctx, n, N, s))) return r;
+        hipError_t e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
+        if (e == hipSuccess)
+            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, N, beta_vec,
+                               host_src(static_cast<int>(step), beta, 0.0), step_sd, seed, move,
+                               n_accept, ctx->sc.mm_cols, ctx->sc.mm_prop, ctx->sc.mm_part,
+                               dd_slices(n, N), ctx->sc.status, MoveStep{}, s);
+        if (e != hipSuccess) return hip_fail(e, "MFMA rwmh launch");
+        return SMC_OK;
+    }
     const hipError_t e = launch_rwmh(g, y, n, theta, loglik, N, beta_vec,
                                      host_src(static_cast<int>(step), beta, 0.0), step_sd, seed,
                                      move, prec, n_accept, choose_slices(ctx, n, N),
@@ -429,6 +491,12 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
                         nullptr, theta, ctx->sc.theta_tmp, kd, loglik, ctx->sc.l_tmp, logw, 0, s);
     if (e != hipSuccess) return hip_fail(e, "resample launch");
     const int S = choose_slices(ctx, n, N);
+    const bool mfma = (prec == SMC_PREC_BF16X3);
+    if (mfma) {
+        if ((r = ensure_mm_scratch(ctx, n, N, s))) return r;
+        e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
+        if (e != hipSuccess) return hip_fail(e, "MFMA prep launch");
+    }
     if (n_moves == 0) {
         e = launch_copy_back(ctx->sc, theta, loglik, W, logw, N, kd, s);
         if (e != hipSuccess) return hip_fail(e, "copy-back launch");
@@ -442,8 +510,14 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
             ms.W_out = W;
             ms.logw = logw;
         }
-        e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, later, step_sd, seed,
-                        static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status, ms, s);
+        if (mfma)
+            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, N, nullptr, later, step_sd,
+                               seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
+                               ctx->sc.mm_prop, ctx->sc.mm_part, dd_slices(n, N), ctx->sc.status,
+                               ms, s);
+        else
+            e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, later, step_sd, seed,
+                            static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status, ms, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }
     return SMC_OK;
@@ -467,8 +541,18 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
     const hipStream_t s = as_stream(stream);
     StepSrc src{};
     src.t_dev = it_dev;
-    hipError_t e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec,
-                               n_accept, choose_slices(ctx, n, M), ctx->sc.status, MoveStep{}, s);
+    hipError_t e;
+    if (prec == SMC_PREC_BF16X3) {
+        if ((r = ensure_mm_scratch(ctx, n, M, s))) return r;
+        e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
+        if (e == hipSuccess)
+            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, M, beta, src, step_sd, seed, 0,
+                               n_accept, ctx->sc.mm_cols, ctx->sc.mm_prop, ctx->sc.mm_part,
+                               dd_slices(n, M), ctx->sc.status, MoveStep{}, s);
+    } else {
+        e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec, n_accept,
+                        choose_slices(ctx, n, M), ctx->sc.status, MoveStep{}, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed, src,
                         n_swap, s);

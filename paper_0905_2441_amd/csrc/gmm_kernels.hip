@@ -26,16 +26,10 @@
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.
-#include "internal.hpp"
-#include "philox.hpp"
-#include "wave.hpp"
+#include "gmm_common.hpp"
 
 namespace smc {
 namespace {
-
-constexpr double kLn2 = 0.6931471805599453;
-
-__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij} (FP32 arithmetic, FP64 result).
 template <int K, int D>
@@ -139,27 +133,6 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
     }
 }
 
-template <int PREC>
-__device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev& g) {
-    const double body = (PREC == SMC_PREC_FP32) ? kLn2 * acc : acc;
-    return static_cast<double>(n) * g.cst + body;
-}
-
-__device__ __forceinline__ double log_prior(const double* pr, int kd, const GmmDev& g) {
-    if (g.prior == SMC_PRIOR_GAUSS) {
-        double lp = 0.0;
-        const double den = 2.0 * g.pb * g.pb;
-        for (int c = 0; c < kd; ++c) {
-            const double z = pr[c] - g.pa;
-            lp += g.lp_const - (z * z) / den;
-        }
-        return lp;
-    }
-    bool inside = true;
-    for (int c = 0; c < kd; ++c) inside = inside && (pr[c] >= g.pa) && (pr[c] <= g.pb);
-    return inside ? -static_cast<double>(kd) * log(g.pb - g.pa) : -INFINITY;
-}
-
 template <int K, int D, int PREC>
 __global__ void __launch_bounds__(1024)
 k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, int N,
@@ -204,7 +177,6 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     const bool use_alt = (ms.state != nullptr) && (ms.state->resampled != 0);
     const double* th_src = use_alt ? ms.theta_alt : theta;
-    const double* l_src = use_alt ? ms.l_alt : l;
 
     double pr[KD];
     {
@@ -222,31 +194,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         double tot = red[0][lane];
         for (int s = 1; s < S; ++s) tot += red[s][lane];
         const double l_prop = finish_loglik<PREC>(tot, n, g);
-        const double l_cur = l_src[p];
-        double cur[KD];
-#pragma unroll
-        for (int c = 0; c < KD; ++c) cur[c] = th_src[static_cast<size_t>(c) * N + p];
-        const double lp_cur = log_prior(cur, KD, g);
-        const double lp_prop = log_prior(pr, KD, g);
-        const double beta = beta_vec ? beta_vec[p]
-                                     : (src.beta_dev ? src.beta_dev[step] : src.beta_host);
-        const double la = beta * (l_prop - l_cur) + (lp_prop - lp_cur);
-        const double u = u01_open(draw(seed, static_cast<uint32_t>(p), 0, step, kAcc, move).w0);
-        acc = (la >= 0.0) || (log(u) < la);
-        if (acc) {
-#pragma unroll
-            for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = pr[c];
-            l[p] = l_prop;
-        } else if (use_alt) {
-#pragma unroll
-            for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = cur[c];
-            l[p] = l_cur;
-        }
-        if (l_prop != l_prop) atomicOr(status, kStatusNaN);
-        if (ms.W_out) {
-            ms.W_out[p] = use_alt ? 1.0 / static_cast<double>(N)
-                                  : exp(ms.logw[p] - ms.state->M) / ms.state->S;
-        }
+        acc = rwmh_accept<KD>(p, N, [&](int c) { return pr[c]; }, l_prop, theta, l, beta_vec,
+                              src, step, seed, move, g, status, ms);
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
@@ -283,6 +232,7 @@ __global__ void k_prior(int N, uint64_t seed, GmmDev g, double* __restrict__ the
     X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(1, 8) X(2, 8) X(4, 8) X(8, 8)
 
 bool supported_kd(int k, int d, int prec) {
+    if (prec == SMC_PREC_BF16X3) return dd_supported(k, d);
     if (prec != SMC_PREC_FP32 && prec != SMC_PREC_FP64) return false;
 #define SMC_CASE(K, D) \
     if (k == K && d == D) return true;

@@ -60,6 +60,11 @@ struct Scratch {
     double* theta_tmp;         // [kd * cap]
     double* l_tmp;             // [cap]
     int64_t cap;
+    __bf16* mm_rows;           // MFMA path: data rows in the K layout [mm_rows_cap][64]
+    __bf16* mm_cols;           // MFMA path: particle-component columns [mm_n_cap * 8][64]
+    double* mm_prop;           // MFMA path: proposals [64][mm_n_cap]
+    double* mm_part;           // MFMA path: per-slice partial sums [16][mm_n_cap]
+    int64_t mm_rows_cap, mm_n_cap;
 };
 
 // How kernels obtain the step / iteration index and the inverse temperature:
@@ -112,6 +117,20 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
 hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,
                         hipStream_t s);
 bool supported_kd(int k, int d, int prec);
+
+// MFMA (split-BF16) form of the d-dimensional likelihood and move.
+int64_t dd_padded_rows(int64_t n);
+int dd_slices(int64_t n, int64_t N);
+bool dd_supported(int k, int d);
+hipError_t launch_dd_prep(const GmmDev& g, const float* y, int64_t n, __bf16* A, hipStream_t s);
+hipError_t launch_dd_loglik(const GmmDev& g, const __bf16* A, int64_t n, const double* theta,
+                            int64_t N, __bf16* B, double* part, int S, double* out, int* status,
+                            hipStream_t s);
+hipError_t launch_dd_rwmh(const GmmDev& g, const __bf16* A, int64_t n, double* theta, double* l,
+                          int64_t N, const double* beta_vec, StepSrc src, double sd,
+                          uint64_t seed, uint32_t move, unsigned long long* n_accept,
+                          __bf16* B, double* theta_prop, double* part, int S, int* status,
+                          MoveStep ms, hipStream_t s);
 
 // Reweight pass and its one-block finalisation. With t_dev set (fused step)
 // the finaliser also records t in the step state and advances the counter.

@@ -46,7 +46,7 @@ class SMCSampler:
             self.t = torch.ones(1, dtype=torch.int32, device="cuda")
             self.stats = torch.zeros(4, dtype=torch.float64, device="cuda")
             self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
-        ctx.reserve(self.N, model.kd)
+        ctx.reserve(self.N, model.kd, self.y.shape[0] if prec == "bf16x3" else 0)
         self.graph: Optional[Graph] = None
 
     def init(self):
@@ -116,6 +116,7 @@ class PTSampler:
             self.it = torch.zeros(1, dtype=torch.int32, device="cuda")
             self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
             self.n_swap = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ctx.reserve(self.M, model.kd, self.y.shape[0] if prec == "bf16x3" else 0)
         self.graph: Optional[Graph] = None
 
     def init(self):

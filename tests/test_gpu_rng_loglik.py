@@ -109,6 +109,36 @@ def test_loglik_ddim_parity(smc, ctx, k, prec, tol):
     _check_loglik(smc, ctx, g, y, th, prec, tol)
 
 
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
+@pytest.mark.parametrize("n,N", [(700, 130), (7, 5), (1000, 1)])
+def test_loglik_ddim_mfma_parity(smc, ctx, k, n, N):
+    """The split-BF16 MFMA form of the d = 8 likelihood is within the FP32 bound."""
+    announce(f"loglik mfma d=8 k={k} n={n} N={N}")
+    rng = np.random.default_rng(20 + k)
+    mu = 3.0 * rng.standard_normal((k, 8))
+    y = make_mixture_data(n, mu, 1.0, seed=k + n)
+    g = smc.Gmm.equal_weights(k, 8, 1.0)
+    th = np.hstack([theta_prior_draws(N - N // 2, k, 8, seed=k), theta_near_posterior(N // 2, mu, seed=k)])
+    _check_loglik(smc, ctx, g, y, th, "bf16x3", FP32_TOL)
+
+
+def test_loglik_ddim_mfma_headline_size_sampled(smc, ctx):
+    """d = 8, k = 8 at the full workload size (n = 65536, N = 16384), sampled particles."""
+    cfg = CONFIGS["gmm8d_k8_n65536_N16384"]
+    announce("loglik mfma headline size")
+    y = make_data(cfg)
+    mu = true_means_for(cfg)
+    N = cfg.N
+    th = np.hstack([theta_prior_draws(N // 2, 8, 8, seed=5), theta_near_posterior(N // 2, mu, seed=6)])
+    g = smc.Gmm.equal_weights(8, 8, cfg.sigma2)
+    got = smc.smc_loglik(ctx, g, torch.as_tensor(y).cuda(), torch.as_tensor(th).cuda(), "bf16x3")
+    got = got.cpu().numpy()
+    sample = np.unique(np.concatenate([np.arange(0, N, 1021), [N - 1, N // 2, N // 2 + 1]]))
+    ref = ogmm.loglik(th[:, sample], y, oracle_model(g), chunk_elems=1 << 24)
+    assert rel_err(got[sample], ref).max() <= FP32_TOL
+    assert np.all(np.isfinite(got))
+
+
 @pytest.mark.parametrize("slices", [1, 2, 5, 16])
 def test_loglik_slice_counts(smc, ctx, slices):
     """Every split of the data over waves gives the oracle's value."""

@@ -204,3 +204,33 @@ def test_exchange_matches_oracle(smc, ctx, M, parity, wrap):
     assert np.array_equal(lt.cpu().numpy(), l_ref)
     assert np.array_equal(tt.cpu().numpy(), th_ref)
     assert ns.item() == n_ref
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_rwmh_move_ddim_matches_oracle(smc, ctx, prec):
+    """d = 8, k = 4 move: MFMA form (and the FP64 VALU form) against the oracle."""
+    announce(f"rwmh d=8 {prec}")
+    rng = np.random.default_rng(3)
+    mu = 3.0 * rng.standard_normal((4, 8))
+    y = make_mixture_data(500, mu, 1.0, seed=7)
+    g = smc.Gmm.equal_weights(4, 8, 1.0)
+    om = oracle_model(g)
+    N = 600
+    th = np.hstack([theta_prior_draws(N // 2, 4, 8, seed=3), theta_near_posterior(N // 2, mu, seed=4)])
+    l = ogmm.loglik(th, y, om)
+    tt, lt = _cuda(th), _cuda(l)
+    acc = torch.zeros(1, dtype=torch.int64).cuda()
+    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, 0.8, 0.05, seed=21, step=4,
+                      move=1, prec=prec, n_accept=acc)
+    ctx.check()
+    th_ref, l_ref, a_ref = osmc.rwmh_move(th, l, y, om, 0.8, 0.05, 21, 4, 1)
+    got_th, got_l = tt.cpu().numpy(), lt.cpu().numpy()
+    a_got = np.any(got_th != th, axis=0)
+    flips = int(np.sum(a_got != a_ref))
+    assert flips <= (0 if prec == "fp64" else 2)
+    assert 0 < a_got.sum() < N
+    same = a_got == a_ref
+    assert acc.item() == int(a_got.sum())
+    assert np.max(np.abs(got_th[:, same] - th_ref[:, same])) <= 1e-12
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert rel_err(got_l[same], l_ref[same]).max() <= tol
