@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm1d_k4_n1000_N131072"
+OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384")
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
 # 3.93e13 non-packed FP32 VALU lane-operations per second. A transcendental
@@ -100,6 +101,30 @@ def cpu_baseline(cfg, y, betas, budget_s=12.0):
     }
 
 
+def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
+    """Population-MCMC iterations (one RW-MH move per chain, then exchanges),
+    one hipGraph replay per iteration."""
+    from workloads import pt_betas
+    betas = pt_betas(cfg.N, 4)
+    s = smc.PTSampler(ctx, g, y, betas, cfg.step_sd, cfg.run_seed, parity_mode=0, wrap=False,
+                      prec=prec)
+    s.init()
+    graph = s.capture()
+    for _ in range(warmup):
+        graph.launch()
+    s.stream.synchronize()
+    s.init()
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    s.stream.synchronize()
+    t1 = time.perf_counter()
+    ctx.check(s.stream)
+    r = s.results()
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, swaps=r["swaps"], accepted=r["accepted"])
+
+
 def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
                        ess_frac=cfg.ess_frac, prec=prec)
@@ -142,6 +167,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD, choices=(WORKLOAD,) + OTHER_WORKLOADS,
+                    help="the headline workload (default) or another measured configuration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,6 +182,8 @@ def main():
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
 
+    if args.workload != WORKLOAD:
+        return other_workload(args)
     cfg = CONFIGS[WORKLOAD]
     y = make_data(cfg)
     betas = beta_schedule(cfg.T, cfg.schedule)
@@ -215,6 +244,55 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def other_workload(args):
+    """Secondary measurements (same JSON shape, no CPU baseline)."""
+    import torch
+    import paper_0905_2441_amd as smc
+    from workloads import CONFIGS, beta_schedule, make_data
+
+    cfg = CONFIGS[args.workload]
+    y = make_data(cfg)
+    torch.cuda.set_device(0)
+    ctx = smc.Context(0)
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    evals = cfg.N * cfg.n * cfg.n_moves
+    out = {"metric": "particle×datum loglik evals/s; ms per SMC tempering step, FP32/batched vs FP64",
+           "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": cfg.name, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N}}
+    if cfg.sampler == "pt":
+        r = time_pt(smc, torch, ctx, cfg, g, y, "fp32", args.steps, args.warmup)
+        r64 = time_pt(smc, torch, ctx, cfg, g, y, "fp64", max(5, args.steps // 5), 2)
+        out.update(value=evals / (r["ms_per_step"] * 1e-3), ms_per_step=r["ms_per_step"],
+                   dtype="f32", fp64_ms_per_step=r64["ms_per_step"],
+                   fp32_over_fp64_speedup=r64["ms_per_step"] / r["ms_per_step"],
+                   swaps=r["swaps"], accepted=r["accepted"])
+        out["config"]["step"] = "one PT iteration: RW-MH per chain + exchanges (alternating parity)"
+    else:
+        betas = beta_schedule(cfg.T, cfg.schedule)
+        precs = list(cfg.precisions)
+        if cfg.d > 1 and "fp32" not in precs:
+            precs.append("fp32")
+        res = {}
+        for prec in precs:
+            steps = args.steps if prec != "fp64" else max(5, args.steps // 5)
+            res[prec] = time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, args.warmup)
+            log(f"[bench] {cfg.name} {prec}: {res[prec]['ms_per_step']:.4f} ms/step, "
+                f"move kernels {res[prec]['kernel_ms']:.4f} ms")
+        fast = precs[0]
+        out.update(value=evals / (res[fast]["ms_per_step"] * 1e-3),
+                   ms_per_step=res[fast]["ms_per_step"], dtype={"fp64": "f64", "fp32": "f32",
+                                                               "bf16x3": "bf16x3+f32"}[fast],
+                   per_precision={p: {"ms_per_step": r["ms_per_step"], "move_ms": r["kernel_ms"],
+                                      "move_evals_per_s": evals / (r["kernel_ms"] * 1e-3)}
+                                  for p, r in res.items()})
+        if "fp64" in res and fast != "fp64":
+            out["fp64_ms_per_step"] = res["fp64"]["ms_per_step"]
+            out["fast_over_fp64_speedup"] = res["fp64"]["ms_per_step"] / res[fast]["ms_per_step"]
     print(json.dumps(out), flush=True)
 
 
