@@ -31,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm1d_k4_n1000_N131072"
-OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384")
+OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384",
+                   "batched_256runs")
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
 # 3.93e13 non-packed FP32 VALU lane-operations per second. A transcendental
@@ -247,11 +248,58 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def time_batched(smc, torch, ctx, prec, steps, warmup, R=256):
+    """256 independent 1-D k = 4 runs (n log-uniform in [100, 1e5], N in
+    {1024, ..., 65536}) advanced by one graph-replayed batched step."""
+    from workloads import beta_schedule, make_mixture_data
+    from workloads.configs import BATCHED, batched_runs
+    runs = batched_runs(R)
+    datas = [make_mixture_data(r.n, r.true_means, BATCHED["sigma2"], r.data_seed) for r in runs]
+    g = smc.Gmm.equal_weights(4, 1, BATCHED["sigma2"])
+    betas = beta_schedule(BATCHED["T"], BATCHED["schedule"])
+    b = smc.BatchSampler(ctx, g, datas, [r.N for r in runs], [r.run_seed for r in runs], betas,
+                         BATCHED["step_sd"], BATCHED["n_moves"], ess_frac=BATCHED["ess_frac"],
+                         prec=prec)
+    b.init()
+    graph = b.capture()
+    for _ in range(warmup):
+        graph.launch()
+    b.stream.synchronize()
+    b.init()
+    b.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.launch()
+    b.stream.synchronize()
+    t1 = time.perf_counter()
+    ctx.check(b.stream)
+    evals = sum(r.N * r.n for r in runs) * BATCHED["n_moves"]
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, evals_per_step=evals, R=R,
+                N_total=sum(r.N for r in runs), n_total=sum(r.n for r in runs))
+
+
 def other_workload(args):
     """Secondary measurements (same JSON shape, no CPU baseline)."""
     import torch
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
+
+    if args.workload == "batched_256runs":
+        torch.cuda.set_device(0)
+        ctx = smc.Context(0)
+        r = time_batched(smc, torch, ctx, "fp32", args.steps, args.warmup)
+        r64 = time_batched(smc, torch, ctx, "fp64", max(2, args.steps // 5), 1)
+        out = {"metric": "particle×datum loglik evals/s; ms per SMC tempering step, FP32/batched vs FP64",
+               "value": r["evals_per_step"] / (r["ms_per_step"] * 1e-3), "unit": "evals/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "batched_256runs", "R": r["R"], "N_total": r["N_total"],
+                          "n_total": r["n_total"], "evals_per_step": r["evals_per_step"]},
+               "fp64_ms_per_step": r64["ms_per_step"],
+               "fp32_over_fp64_speedup": r64["ms_per_step"] / r["ms_per_step"]}
+        print(json.dumps(out), flush=True)
+        return
 
     cfg = CONFIGS[args.workload]
     y = make_data(cfg)

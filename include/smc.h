@@ -209,6 +209,40 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
                  smc_prec prec, unsigned long long* n_accept, unsigned int* n_swap,
                  void* stream);
 
+/* Many independent SMC runs advanced together (serving-style batch).
+ * Run r owns particles [p_off, p_off + N) of the concatenated state arrays (its
+ * theta block is [k*d][N] at theta + k*d*p_off) and observations
+ * [y_off, y_off + n) of the concatenated data; all runs share the model, the
+ * schedule beta[0..T] and the proposal sd, and each draws from its own Philox
+ * key `seed`, exactly as it would alone. */
+typedef struct {
+    int64_t p_off, y_off;
+    int32_t N, n;
+    uint64_t seed;
+} smc_run_desc;
+typedef struct smc_batch_s* smc_batch;
+
+/* [sync] Upload R run descriptors (host array) and size the batch scratch for
+ * runs of kd = k*d parameters; the work list (run, 64-particle tile) is ordered
+ * by decreasing n (longest first). d must be 1. */
+int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t kd,
+                     smc_batch* out);
+int smc_batch_destroy(smc_batch b);
+
+/* One tempering step of every run of the batch, graph-replayable like smc_step
+ * (t = *t_dev, advanced at the end):
+ *   one workgroup per run: reweight, log-sum-exp, ESS and the resampling
+ *   decision (ESS < ess_frac * N_r); one workgroup per resampling run:
+ *   systematic resampling and gather; then n_moves (>= 1) RW-MH moves as one
+ *   persistent launch over the work list (workgroups pull items from a device
+ *   counter). run_stats: device FP64 [R][4] = {log Z (accumulated), last ESS,
+ *   resample count, unused}. prec: FP32 or FP64. */
+int smc_step_batched(smc_ctx ctx, smc_batch b, const smc_gmm* model, const float* y,
+                     double* theta, double* loglik, double* logw, double* W, const double* beta,
+                     int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, double ess_frac,
+                     smc_prec prec, double* run_stats, unsigned long long* n_accept,
+                     void* stream);
+
 /* Graph helpers: capture `reps` calls of smc_step (or pt_iteration) enqueued by
  * the caller between smc_graph_begin and smc_graph_end on `stream` into one
  * executable hipGraph, then launch it. */

@@ -22,7 +22,8 @@ from .api import (  # noqa: F401
     smc_rng_words,
     smc_rwmh_move,
     smc_step,
+    smc_step_batched,
 )
-from .samplers import PTSampler, SMCSampler  # noqa: F401
+from .samplers import BatchSampler, PTSampler, SMCSampler  # noqa: F401
 
 load()

@@ -39,6 +39,11 @@ class SmcGmm(Structure):
                 ("prior_a", c_double), ("prior_b", c_double)]
 
 
+class SmcRunDesc(Structure):
+    _fields_ = [("p_off", c_int64), ("y_off", c_int64), ("N", c_int32), ("n", c_int32),
+                ("seed", c_uint64)]
+
+
 _P = c_void_p
 _GP = POINTER(SmcGmm)
 
@@ -64,6 +69,10 @@ SIGNATURES = {
                          c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
     "pt_iteration": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_double, c_uint64,
                              c_int32, c_int32, c_int, _P, _P, _P]),
+    "smc_batch_create": (c_int, [_P, POINTER(SmcRunDesc), c_int32, c_int32, POINTER(c_void_p)]),
+    "smc_batch_destroy": (c_int, [_P]),
+    "smc_step_batched": (c_int, [_P, _P, _GP, _P, _P, _P, _P, _P, _P, c_int32, _P, c_double,
+                                 c_int32, c_double, c_int, _P, _P, _P]),
     "smc_graph_begin": (c_int, [_P, _P]),
     "smc_graph_end": (c_int, [_P, _P, POINTER(c_void_p)]),
     "smc_graph_launch": (c_int, [_P, _P]),

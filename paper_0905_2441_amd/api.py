@@ -250,6 +250,43 @@ def smc_rng_normals(seed, count, per_index, step, purpose, move=0, out=None, str
     return out
 
 
+class Batch:
+    """An smc_batch: device descriptors and scratch of many independent runs."""
+
+    def __init__(self, ctx: Context, runs, kd: int):
+        arr = (L.SmcRunDesc * len(runs))()
+        for i, (p_off, y_off, N, n, seed) in enumerate(runs):
+            arr[i].p_off, arr[i].y_off, arr[i].N, arr[i].n, arr[i].seed = (
+                int(p_off), int(y_off), int(N), int(n), int(seed))
+        h = ctypes.c_void_p()
+        L.check(ctx._lib.smc_batch_create(ctx.handle, arr, len(runs), int(kd), ctypes.byref(h)))
+        self.ctx, self.handle, self.R = ctx, h, len(runs)
+
+    def close(self):
+        if self.handle.value:
+            self.ctx._lib.smc_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def smc_step_batched(ctx: Context, batch: Batch, model: Gmm, y, theta, loglik, logw, W, beta,
+                     t_dev, step_sd, n_moves, ess_frac, prec, run_stats, n_accept=None,
+                     stream=None):
+    L.check(ctx._lib.smc_step_batched(
+        ctx.handle, batch.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"),
+        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik"),
+        _ptr(logw, torch.float64, "logw"), _ptr(W, torch.float64, "W"),
+        _ptr(beta, torch.float64, "beta"), beta.numel() - 1, _ptr(t_dev, torch.int32, "t_dev", 1),
+        float(step_sd), int(n_moves), float(ess_frac), _prec(prec),
+        _ptr(run_stats, torch.float64, "run_stats", 4 * batch.R),
+        _opt(n_accept, torch.int64, "n_accept", 1), _stream(stream)))
+
+
 class Graph:
     """An executable hipGraph captured from calls enqueued on ``stream``."""
 

@@ -4,8 +4,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "wave.hpp"
@@ -628,6 +630,136 @@ int smc_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t st
     const hipError_t e = launch_rng_normals(seed, count, per_index, step, purpose, move, out,
                                             as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "rng launch");
+    return SMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched runs
+
+struct smc_batch_s {
+    int device = 0;
+    BatchDev dev{};
+    void* mem = nullptr;
+    int64_t n_total = 0, N_total = 0;
+    int kd = 0;
+};
+
+extern "C" {
+
+int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t kd,
+                     smc_batch* out) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!out || !runs) return fail(SMC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (R < 1) return fail(SMC_ERR_INVALID_ARG, "R must be >= 1");
+    if (kd < 1 || kd > SMC_KMAX) return fail(SMC_ERR_INVALID_ARG, "batched runs need d = 1, k <= 8");
+    int64_t N_total = 0, n_total = 0, n_items = 0;
+    for (int i = 0; i < R; ++i) {
+        const smc_run_desc& d = runs[i];
+        if (d.N < 1 || d.n < 1 || d.p_off < 0 || d.y_off < 0)
+            return fail(SMC_ERR_INVALID_ARG, "run needs N >= 1, n >= 1, offsets >= 0");
+        if (d.p_off + d.N > N_total) N_total = d.p_off + d.N;
+        if (d.y_off + d.n > n_total) n_total = d.y_off + d.n;
+        n_items += (d.N + 63) / 64;
+    }
+    if (N_total > INT32_MAX || n_items > INT32_MAX)
+        return fail(SMC_ERR_INVALID_ARG, "batch too large");
+    // work list: runs by decreasing data length (ties: larger N first), tiles in order
+    std::vector<int> order(R);
+    for (int i = 0; i < R; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (runs[a].n != runs[b].n) return runs[a].n > runs[b].n;
+        return runs[a].N > runs[b].N;
+    });
+    std::vector<BatchItem> items;
+    items.reserve(static_cast<size_t>(n_items));
+    for (int i : order)
+        for (int t = 0; t < (runs[i].N + 63) / 64; ++t) items.push_back(BatchItem{i, t});
+    std::vector<BatchRun> rd(R);
+    for (int i = 0; i < R; ++i)
+        rd[i] = BatchRun{runs[i].p_off, runs[i].y_off, runs[i].N, runs[i].n, runs[i].seed};
+    const size_t b_runs = align_up(sizeof(BatchRun) * R);
+    const size_t b_items = align_up(sizeof(BatchItem) * items.size());
+    const size_t b_work = align_up(sizeof(unsigned));
+    const size_t b_state = align_up(sizeof(StepState) * R);
+    const size_t b_cdf = align_up(sizeof(double) * N_total);
+    const size_t b_th = align_up(sizeof(double) * N_total * kd);
+    const size_t b_l = align_up(sizeof(double) * N_total);
+    const size_t total = b_runs + b_items + b_work + b_state + b_cdf + b_th + b_l;
+    void* p = nullptr;
+    if (hipMalloc(&p, total) != hipSuccess) return fail(SMC_ERR_NOMEM, "batch allocation failed");
+    smc_batch b = new (std::nothrow) smc_batch_s();
+    if (!b) {
+        (void)hipFree(p);
+        return fail(SMC_ERR_NOMEM, "host allocation failed");
+    }
+    char* c = static_cast<char*>(p);
+    b->device = ctx->device;
+    b->mem = p;
+    b->kd = kd;
+    b->N_total = N_total;
+    b->n_total = n_total;
+    BatchDev& d = b->dev;
+    d.R = R;
+    d.runs = reinterpret_cast<BatchRun*>(c);
+    d.items = reinterpret_cast<BatchItem*>(c + b_runs);
+    d.n_items = static_cast<int>(items.size());
+    d.work = reinterpret_cast<unsigned*>(c + b_runs + b_items);
+    d.state = reinterpret_cast<StepState*>(c + b_runs + b_items + b_work);
+    d.cdf = reinterpret_cast<double*>(c + b_runs + b_items + b_work + b_state);
+    d.theta_tmp = reinterpret_cast<double*>(c + b_runs + b_items + b_work + b_state + b_cdf);
+    d.l_tmp = reinterpret_cast<double*>(c + b_runs + b_items + b_work + b_state + b_cdf + b_th);
+    d.move_grid = batch_move_grid();
+    hipError_t e = hipMemset(p, 0, total);
+    if (e == hipSuccess) e = hipMemcpy(d.runs, rd.data(), sizeof(BatchRun) * R, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(d.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        delete b;
+        return hip_fail(e, "batch upload");
+    }
+    *out = b;
+    return SMC_OK;
+}
+
+int smc_batch_destroy(smc_batch b) {
+    if (!b) return SMC_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+    return SMC_OK;
+}
+
+int smc_step_batched(smc_ctx ctx, smc_batch b, const smc_gmm* model, const float* y,
+                     double* theta, double* loglik, double* logw, double* W, const double* beta,
+                     int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, double ess_frac,
+                     smc_prec prec, double* run_stats, unsigned long long* n_accept,
+                     void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!b) return fail(SMC_ERR_INVALID_ARG, "batch is NULL");
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if (g.d != 1 || g.k * g.d != b->kd)
+        return fail(SMC_ERR_INVALID_ARG, "model does not match the batch (d = 1, k*d = kd)");
+    if (prec != SMC_PREC_FP32 && prec != SMC_PREC_FP64)
+        return fail(SMC_ERR_UNSUPPORTED, "batched runs use FP32 or FP64");
+    if (!y || !theta || !loglik || !logw || !W || !beta || !t_dev || !run_stats)
+        return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (T < 1) return fail(SMC_ERR_INVALID_ARG, "T must be >= 1");
+    if (n_moves < 1) return fail(SMC_ERR_INVALID_ARG, "batched steps need n_moves >= 1");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
+    const hipError_t e = launch_batch_step(b->dev, g, y, theta, loglik, logw, W, beta, T, t_dev,
+                                           step_sd, n_moves, ess_frac, prec, run_stats, n_accept,
+                                           ctx->sc.status, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "batched step launch");
     return SMC_OK;
 }
 

@@ -16,6 +16,108 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
     return static_cast<double>(n) * g.cst + body;
 }
 
+// Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij} (FP32 arithmetic, FP64 result).
+template <int K, int D>
+__device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
+                                               const float (&nms)[K * D], float s,
+                                               const GmmDev& g) {
+    constexpr int U = 8;
+    double msum = 0.0;
+    float prod = 1.0f;
+    int expo = 0;
+    int j = j0;
+    auto datum = [&](const float* yj, float& m_out, float& e_out) {
+        float a[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if constexpr (D == 1) {
+                const float t = __builtin_fmaf(yj[0], s, nms[i]);
+                a[i] = __builtin_fmaf(-t, t, g.lw2[i]);
+            } else {
+                float q = 0.0f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const float t = __builtin_fmaf(yj[c], s, nms[i * D + c]);
+                    q = __builtin_fmaf(t, t, q);
+                }
+                a[i] = g.lw2[i] - q;
+            }
+        }
+        float m = a[0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) m = fmaxf(m, a[i]);
+        float e = __builtin_amdgcn_exp2f(a[0] - m);
+#pragma unroll
+        for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(a[i] - m);
+        m_out = m;
+        e_out = e;
+    };
+    for (; j + U <= j1; j += U) {
+        float mblk = 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float m, e;
+            datum(y + (size_t)(j + u) * D, m, e);
+            prod *= e;
+            mblk += m;
+        }
+        msum += static_cast<double>(mblk);
+        expo += __builtin_amdgcn_frexp_expf(prod);
+        prod = __builtin_amdgcn_frexp_mantf(prod);
+    }
+    for (; j < j1; ++j) {
+        float m, e;
+        datum(y + (size_t)j * D, m, e);
+        prod *= e;
+        msum += static_cast<double>(m);
+    }
+    return msum + static_cast<double>(expo) + log2(static_cast<double>(prod));
+}
+
+// Sum over data j in [j0, j1) of ln sum_i w_i exp(-||y_j - mu_i||^2 / (2 sigma2)), FP64.
+template <int K, int D>
+__device__ __forceinline__ double partial_fp64(const float* __restrict__ y, int j0, int j1,
+                                               const double (&mu)[K * D], const GmmDev& g) {
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const float* yj = y + (size_t)j * D;
+        double a[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            double q = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const double t = static_cast<double>(yj[c]) - mu[i * D + c];
+                q += t * t;
+            }
+            a[i] = g.lw[i] - q * g.inv2s2;
+        }
+        double m = a[0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) m = fmax(m, a[i]);
+        double e = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) e += exp(a[i] - m);
+        acc += m + log(e);
+    }
+    return acc;
+}
+
+// The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values).
+template <int K, int D, int PREC>
+__device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
+                                                const double (&pr)[K * D], const GmmDev& g) {
+    if constexpr (PREC == SMC_PREC_FP32) {
+        float nms[K * D];
+        const double s = static_cast<double>(g.s32);
+#pragma unroll
+        for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(s * pr[c]));
+        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g);
+    } else {
+        return partial_fp64<K, D>(y, j0, j1, pr, g);
+    }
+}
+
 // Metropolis-Hastings decision for particle p of a random-walk move and the
 // write-back: log alpha = beta (l' - l) + log p0(theta') - log p0(theta); accept
 // iff log alpha >= 0 or log u < log alpha, u from stream (p, 0, step, ACC, move).

@@ -106,6 +106,34 @@ struct WeightSrc {
     const StepState* state;
 };
 
+// Batched runs (one step for many independent SMC runs).
+struct BatchRun {
+    int64_t p_off, y_off;      // first particle / observation of the run
+    int N, n;
+    uint64_t seed;
+};
+struct BatchItem {
+    int run, tile;             // tile of 64 particles of run `run`
+};
+struct BatchDev {
+    int R;
+    BatchRun* runs;            // [R]
+    BatchItem* items;          // [n_items], longest data first
+    int n_items;
+    unsigned* work;            // work-queue counter, zero between launches
+    StepState* state;          // [R]
+    double* cdf;               // [N_total]
+    double* theta_tmp;         // [kd * N_total]
+    double* l_tmp;             // [N_total]
+    int move_grid;             // persistent grid size
+};
+int batch_move_grid();
+hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y, double* theta,
+                             double* l, double* logw, double* W, const double* beta, int T,
+                             int* t_dev, double sd, int n_moves, double ess_frac, int prec,
+                             double* stats, unsigned long long* n_acc, int* status,
+                             hipStream_t s);
+
 hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
                          int64_t N, int prec, double* out, int slices, int* status,
                          hipStream_t s);

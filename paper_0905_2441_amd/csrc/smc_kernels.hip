@@ -22,105 +22,10 @@
 // can be predicated on the device-side ESS test.
 #include "internal.hpp"
 #include "philox.hpp"
-#include "wave.hpp"
+#include "reduce.hpp"
 
 namespace smc {
 namespace {
-
-// ---------------------------------------------------------------- helpers
-
-struct Lse3 {
-    double m, s1, s2;          // sum exp(x - m), sum exp(2 (x - m))
-};
-
-__device__ __forceinline__ Lse3 lse3_empty() { return Lse3{-INFINITY, 0.0, 0.0}; }
-
-__device__ __forceinline__ Lse3 lse3_push(Lse3 a, double x) {
-    if (x == -INFINITY) return a;
-    if (x > a.m) {
-        const double r = (a.m == -INFINITY) ? 0.0 : exp(a.m - x);
-        return Lse3{x, a.s1 * r + 1.0, a.s2 * (r * r) + 1.0};
-    }
-    const double e = exp(x - a.m);
-    return Lse3{a.m, a.s1 + e, a.s2 + e * e};
-}
-
-__device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
-    if (b.m == -INFINITY) return a;
-    if (a.m == -INFINITY) return b;
-    if (a.m >= b.m) {
-        const double r = exp(b.m - a.m);
-        return Lse3{a.m, a.s1 + b.s1 * r, a.s2 + b.s2 * (r * r)};
-    }
-    const double r = exp(a.m - b.m);
-    return Lse3{b.m, b.s1 + a.s1 * r, b.s2 + a.s2 * (r * r)};
-}
-
-__device__ __forceinline__ Lse3 wave_lse3(Lse3 v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        Lse3 o{__shfl_xor(v.m, off, kWave), __shfl_xor(v.s1, off, kWave),
-               __shfl_xor(v.s2, off, kWave)};
-        v = (lane_id() & off) ? lse3_merge(o, v) : lse3_merge(v, o);
-    }
-    return v;
-}
-
-// Block (kRedBlock threads) reductions; the result is valid in thread 0.
-__device__ Lse3 block_lse3(Lse3 v) {
-    __shared__ double sm[kRedBlock / kWave], s1[kRedBlock / kWave], s2[kRedBlock / kWave];
-    v = wave_lse3(v);
-    if (lane_id() == 0) {
-        sm[wave_id()] = v.m;
-        s1[wave_id()] = v.s1;
-        s2[wave_id()] = v.s2;
-    }
-    __syncthreads();
-    Lse3 r = lse3_empty();
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kRedBlock / kWave; ++w) r = lse3_merge(r, Lse3{sm[w], s1[w], s2[w]});
-    __syncthreads();
-    return r;
-}
-
-__device__ double block_sum(double v) {
-    __shared__ double sh[kRedBlock / kWave];
-    v = wave_sum(v);
-    if (lane_id() == 0) sh[wave_id()] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kRedBlock / kWave; ++w) r += sh[w];
-    __syncthreads();
-    return r;
-}
-
-// Exclusive scan of one dd value per thread over the block (thread order);
-// also returns the block total in `total` (valid in every thread).
-__device__ dd block_dd_exclusive_scan(dd v, dd& total) {
-    __shared__ double wh[kRedBlock / kWave], wl[kRedBlock / kWave];
-    const int lane = lane_id();
-    dd inc = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const dd up{__shfl_up(inc.hi, o, kWave), __shfl_up(inc.lo, o, kWave)};
-        if (lane >= o) inc = dd_add(up, inc);
-    }
-    if (lane == kWave - 1) {
-        wh[wave_id()] = inc.hi;
-        wl[wave_id()] = inc.lo;
-    }
-    dd excl{__shfl_up(inc.hi, 1, kWave), __shfl_up(inc.lo, 1, kWave)};
-    if (lane == 0) excl = dd_zero();
-    __syncthreads();
-    dd off = dd_zero();
-    for (int w = 0; w < wave_id(); ++w) off = dd_add(off, dd{wh[w], wl[w]});
-    dd tot = dd_zero();
-    for (int w = 0; w < kRedBlock / kWave; ++w) tot = dd_add(tot, dd{wh[w], wl[w]});
-    total = tot;
-    __syncthreads();
-    return dd_add(off, excl);
-}
 
 // ---------------------------------------------------------------- reweight
 

@@ -7,6 +7,10 @@ resampling on the device, RW-MH moves at beta_t). The step reads t from a
 device counter, so a single captured hipGraph is replayed T times and the host
 never waits inside the run.
 
+BatchSampler: many independent tempered SMC runs (own data, size and seed each)
+advanced together by smc_step_batched: one graph replay per tempering step for
+the whole batch.
+
 PTSampler: population MCMC with tempered chains (Population-Based MCMC
 subsection): per iteration one RW-MH move per chain at its own beta, then
 exchange moves on one partition of adjacent pairs.
@@ -19,7 +23,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .api import (Context, Gmm, Graph, pt_iteration, smc_loglik, smc_prior_init, smc_step)
+from .api import (Batch, Context, Gmm, Graph, pt_iteration, smc_loglik, smc_prior_init,
+                  smc_step, smc_step_batched)
 
 
 def _dev(x, dtype):
@@ -159,3 +164,93 @@ class PTSampler:
         return dict(theta=self.theta.cpu().numpy(), l=self.loglik.cpu().numpy(),
                     accepted=int(self.n_accept.cpu().item()),
                     swaps=int(self.n_swap.cpu().item()), it=int(self.it.cpu().item()))
+
+
+class BatchSampler:
+    def __init__(self, ctx: Context, model: Gmm, datas, Ns, seeds, betas, step_sd: float,
+                 n_moves: int, ess_frac: float = 0.5, prec: str = "fp32",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if model.d != 1:
+            raise ValueError("batched runs are one-dimensional mixtures")
+        self.ctx, self.model = ctx, model
+        self.Ns = [int(x) for x in Ns]
+        self.ns = [int(np.asarray(y).size) for y in datas]
+        self.seeds = [int(x) for x in seeds]
+        self.R = len(self.Ns)
+        self.p_off = np.concatenate([[0], np.cumsum(self.Ns)[:-1]]).astype(np.int64)
+        self.y_off = np.concatenate([[0], np.cumsum(self.ns)[:-1]]).astype(np.int64)
+        self.N_total = int(sum(self.Ns))
+        self.step_sd, self.n_moves = float(step_sd), int(n_moves)
+        self.ess_frac, self.prec = float(ess_frac), prec
+        self.T = len(betas) - 1
+        self.stream = stream or torch.cuda.Stream()
+        kd = model.kd
+        with torch.cuda.stream(self.stream):
+            self.y = _dev(np.concatenate([np.asarray(y, dtype=np.float32).ravel() for y in datas]),
+                          torch.float32)
+            self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
+            self.theta = torch.empty(kd * self.N_total, dtype=torch.float64, device="cuda")
+            self.loglik = torch.empty(self.N_total, dtype=torch.float64, device="cuda")
+            self.logw = torch.zeros(self.N_total, dtype=torch.float64, device="cuda")
+            self.W = torch.empty(self.N_total, dtype=torch.float64, device="cuda")
+            self.t = torch.ones(1, dtype=torch.int32, device="cuda")
+            self.stats = torch.zeros(4 * self.R, dtype=torch.float64, device="cuda")
+            self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
+        self.batch = Batch(ctx, [(self.p_off[r], self.y_off[r], self.Ns[r], self.ns[r],
+                                  self.seeds[r]) for r in range(self.R)], kd)
+        ctx.reserve(max(self.Ns), kd)
+        self.graph: Optional[Graph] = None
+
+    def theta_of(self, r: int) -> torch.Tensor:
+        kd = self.model.kd
+        a = kd * int(self.p_off[r])
+        return self.theta[a:a + kd * self.Ns[r]].view(kd, self.Ns[r])
+
+    def _slice(self, t: torch.Tensor, r: int) -> torch.Tensor:
+        a = int(self.p_off[r])
+        return t[a:a + self.Ns[r]]
+
+    def init(self):
+        with torch.cuda.stream(self.stream):
+            for r in range(self.R):
+                smc_prior_init(self.ctx, self.model, self.Ns[r], self.seeds[r],
+                               out=self.theta_of(r), stream=self.stream)
+                a = int(self.y_off[r])
+                smc_loglik(self.ctx, self.model, self.y[a:a + self.ns[r]], self.theta_of(r),
+                           self.prec, out=self._slice(self.loglik, r), stream=self.stream)
+            self.logw.zero_()
+            self.t.fill_(1)
+            self.stats.zero_()
+            self.n_accept.zero_()
+
+    def enqueue_step(self):
+        smc_step_batched(self.ctx, self.batch, self.model, self.y, self.theta, self.loglik,
+                         self.logw, self.W, self.beta, self.t, self.step_sd, self.n_moves,
+                         self.ess_frac, self.prec, self.stats, self.n_accept, stream=self.stream)
+
+    def capture(self) -> Graph:
+        if self.graph is None:
+            g = Graph(self.ctx, self.stream)
+            with g:
+                self.enqueue_step()
+            self.graph = g
+        return self.graph
+
+    def run(self, graph: bool = True, steps: Optional[int] = None):
+        self.init()
+        for _ in range(self.T if steps is None else steps):
+            if graph:
+                self.capture().launch()
+            else:
+                self.enqueue_step()
+        self.stream.synchronize()
+        self.ctx.check(self.stream)
+        return self.results()
+
+    def results(self):
+        self.stream.synchronize()
+        st = self.stats.cpu().numpy().reshape(self.R, 4)
+        return dict(logZ=st[:, 0].copy(), ess=st[:, 1].copy(), resamples=st[:, 2].astype(int),
+                    accepted=int(self.n_accept.cpu().item()), t=int(self.t.cpu().item()),
+                    theta=[self.theta_of(r).cpu().numpy() for r in range(self.R)],
+                    l=[self._slice(self.loglik, r).cpu().numpy() for r in range(self.R)])

@@ -150,3 +150,54 @@ def test_pt_paper_mode_random_parity_wrap(smc, ctx):
     ref = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True)
     assert r["swaps"] == ref["swaps"]
     assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+
+
+def _batch_inputs():
+    rng = np.random.default_rng(44)
+    specs = [(1000, 700), (40, 63), (1, 5), (333, 256), (100, 1), (5000, 130)]
+    datas, Ns, seeds = [], [], []
+    for r, (n, N) in enumerate(specs):
+        mu = rng.uniform(-6, 9, size=4)
+        datas.append(make_mixture_data(n, mu, 0.55, seed=900 + r))
+        Ns.append(N)
+        seeds.append(5000 + r)
+    return datas, Ns, seeds
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_runs_match_oracle_fp64(smc, ctx, graph):
+    """Every run of a batch equals the oracle's sampler run alone with its own seed."""
+    announce(f"batched fp64 graph={graph}")
+    datas, Ns, seeds = _batch_inputs()
+    betas = beta_schedule(12, "quadratic")
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
+    b = smc.BatchSampler(ctx, g, datas, Ns, seeds, betas, 0.5, 1, ess_frac=0.5, prec="fp64")
+    r = b.run(graph=graph)
+    assert r["t"] == 13
+    acc_total = 0
+    for i in range(len(Ns)):
+        ref = osmc.smc_run(datas[i], om, betas, Ns[i], 0.5, 1, seeds[i], ess_frac=0.5)
+        assert r["resamples"][i] == int(np.sum(ref["trace"]["resampled"])), i
+        assert abs(r["logZ"][i] - ref["logZ"]) <= 1e-9 * max(1.0, abs(ref["logZ"])), i
+        assert np.max(np.abs(r["theta"][i] - ref["theta"])) <= 1e-9, i
+        assert rel_err(r["l"][i], ref["l"]).max() <= 1e-10, i
+        acc_total += int(np.sum(ref["trace"]["accepted"]))
+    assert r["accepted"] == acc_total
+
+
+def test_batched_fp32_two_moves_runs(smc, ctx):
+    announce("batched fp32 two moves")
+    datas, Ns, seeds = _batch_inputs()
+    betas = beta_schedule(8, "linear")
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    b = smc.BatchSampler(ctx, g, datas, Ns, seeds, betas, 0.5, 2, ess_frac=0.5, prec="fp32")
+    r1 = b.run(graph=True)
+    r2 = b.run(graph=True)
+    assert np.array_equal(r1["logZ"], r2["logZ"])
+    assert all(np.isfinite(r1["logZ"]))
+    om = oracle_model(g)
+    for i in range(len(Ns)):
+        ref = osmc.smc_run(datas[i], om, betas, Ns[i], 0.5, 2, seeds[i], ess_frac=0.5)
+        # same path unless an FP32 near-tie accept decision flipped
+        assert abs(r1["logZ"][i] - ref["logZ"]) <= max(1e-3, 0.5 * abs(ref["logZ"]) * 1e-2), i
