@@ -6,7 +6,9 @@ log-sum-exp normalisation, ESS, ESS-triggered systematic resampling, one
 RW-MH move whose proposal log-likelihood is the mixture likelihood over all
 observations) on the headline workload: 1-D k = 4 mixture, n = 1000
 observations, N = 131072 particles, 100 quadratic tempering steps. The step
-is captured once in a hipGraph and replayed; inputs are resident in HBM.
+is device-driven (step index, temperature and resampling decision live in
+device memory), so ten consecutive steps are captured in one hipGraph and
+replayed; inputs are resident in HBM.
 
 value = particle x datum log-likelihood evaluations per second over whole
 steps (FP32 path). The same run times the plain FP64 GPU form and reports the
@@ -41,6 +43,7 @@ OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 TRANS_SLOTS = 2.0
 HBM_PEAK_GBS = 8000.0
+STEPS_PER_GRAPH = 10    # tempering steps per hipGraph replay
 
 
 def ops_per_eval(k: int) -> float:
@@ -130,15 +133,12 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
                        ess_frac=cfg.ess_frac, prec=prec)
     s.init()
-    graph = s.capture()
-    for _ in range(warmup):
-        graph.launch()
-    s.stream.synchronize()
+    s.advance(warmup + STEPS_PER_GRAPH + 1, graph=True, steps_per_graph=STEPS_PER_GRAPH)
+    s.stream.synchronize()                 # graphs captured and warm
     s.init()                               # a fresh run from the prior for the timed steps
     s.stream.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        graph.launch()
+    s.advance(steps, graph=True, steps_per_graph=STEPS_PER_GRAPH)
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
@@ -238,7 +238,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N,
                    "T": cfg.T, "schedule": "(t/T)^2", "moves_per_step": cfg.n_moves,
-                   "ess_threshold": "N/2", "graph": "one hipGraph per step, replayed"},
+                   "ess_threshold": "N/2", "graph": f"{STEPS_PER_GRAPH} tempering steps per hipGraph replay"},
         "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
         "fp32_over_fp64_speedup": (r64["ms_per_step"] / r32["ms_per_step"]) if r64 else None,
         "fp64_move_kernel_ms": r64["kernel_ms"] if r64 else None,

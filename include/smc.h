@@ -184,19 +184,28 @@ int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, 
 
 /* One whole tempering step of the SMC sampler with every per-step value read on
  * the device, so the same enqueued work can be captured once in a hipGraph and
- * replayed T times:
+ * replayed (SMC Samplers subsection; resampling as in the Sequential Monte
+ * Carlo subsection):
  *   t = *t_dev clamped to 1..T; dbeta = beta[t] - beta[t-1];
- *   reweight (logw, W, *logZ, *ess) -> if *ess < ess_frac*N: systematic
- *   resampling with u from step t, gather into context scratch, logw = 0 ->
- *   n_moves RW-MH moves at beta[t] (move m uses stream move m) -> *t_dev = t+1.
- * beta: [T+1] device FP64 (beta[0..T]). theta/loglik/logw/W: [kd][N], [N], [N], [N] in/out.
- * stats: device FP64 [4] = {logZ (accumulated), last ESS, resample count,
- * unused}. n_accept: nullable device u64 counter. */
+ *   logw += dbeta * loglik_in; *logZ += lse(logw_new) - lse(logw_old);
+ *   ESS = 1 / sum W^2; if ESS < ess_frac * N: systematic resampling with the
+ *   offset of stream (0, 0, t, RESAMP, 0), logw = 0;
+ *   n_moves RW-MH moves at beta[t] (move m uses stream move m);
+ *   *t_dev = t + 1.
+ * The step reads the population (theta_in [k*d][N], loglik_in [N]) and writes
+ * the next one (theta_out, loglik_out): the ancestor search and gather are
+ * fused into the first move, so the two populations must not alias. Callers
+ * alternate two buffers between steps. logw [N] and W [N] are updated in place
+ * (W = the step's normalised weights, 1/N after resampling).
+ * beta: [T+1] device FP64. stats: device FP64 [4] = {logZ (accumulated), last
+ * ESS, resample count, unused}. n_accept: nullable device u64 counter.
+ * Kernels: reweight partials; combine + decision + CDF chunk scans (when
+ * resampling); the moves. */
 int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
-             double* theta, double* loglik, double* logw, double* W, const double* beta,
-             int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed,
-             double ess_frac, smc_prec prec, double* stats, unsigned long long* n_accept,
-             void* stream);
+             const double* theta_in, const double* loglik_in, double* theta_out,
+             double* loglik_out, double* logw, double* W, const double* beta, int32_t T,
+             int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed, double ess_frac,
+             smc_prec prec, double* stats, unsigned long long* n_accept, void* stream);
 
 /* One population-MCMC iteration with the iteration index read on the device
  * (graph-replayable): it = *it_dev; one RW-MH move per chain at its own

@@ -203,13 +203,17 @@ def pt_exchange(ctx: Context, theta, loglik, beta, parity, wrap, seed, iteration
                                  _opt(n_swap, torch.int32, "n_swap", 1), _stream(stream)))
 
 
-def smc_step(ctx: Context, model: Gmm, y, theta, loglik, logw, W, beta, t_dev, step_sd,
-             n_moves, seed, ess_frac, prec, stats, n_accept=None, stream=None):
+def smc_step(ctx: Context, model: Gmm, y, theta_in, loglik_in, theta_out, loglik_out, logw, W,
+             beta, t_dev, step_sd, n_moves, seed, ess_frac, prec, stats, n_accept=None,
+             stream=None):
     n = _data_shape(model, y)
-    N = _theta_shape(model, theta)
+    N = _theta_shape(model, theta_in)
     L.check(ctx._lib.smc_step(
         ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n, N,
-        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", N),
+        _ptr(theta_in, torch.float64, "theta_in", model.kd * N),
+        _ptr(loglik_in, torch.float64, "loglik_in", N),
+        _ptr(theta_out, torch.float64, "theta_out", model.kd * N),
+        _ptr(loglik_out, torch.float64, "loglik_out", N),
         _ptr(logw, torch.float64, "logw", N), _ptr(W, torch.float64, "W", N),
         _ptr(beta, torch.float64, "beta"), beta.numel() - 1, _ptr(t_dev, torch.int32, "t_dev", 1),
         float(step_sd), int(n_moves), int(seed), float(ess_frac), _prec(prec),

@@ -192,10 +192,11 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
                     ms.l_alt = l_tmp + rd.p_off;
                     ms.state = sr;
                     ms.W_out = W + rd.p_off;
-                    ms.logw = logw + rd.p_off;
+                    ms.logw = const_cast<double*>(logw) + rd.p_off;
                 }
-                acc = rwmh_accept<KD>(p, N, [&](int c) { return pr[c]; }, l_prop, th_run, l_run,
-                                      nullptr, src, step, rd.seed, move, g, status, ms);
+                const MoveSource srcs = move_source(ms, th_run, l_run);
+                acc = rwmh_accept<KD>(p, p, N, [&](int c) { return pr[c]; }, l_prop, srcs, th_run,
+                                      l_run, nullptr, src, step, rd.seed, move, g, status, ms);
             }
             const unsigned long long mask = __ballot(acc);
             if (lane == 0 && n_acc != nullptr && mask != 0ull)

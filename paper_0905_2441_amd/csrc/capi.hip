@@ -457,8 +457,9 @@ int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, 
 }
 
 int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
-             double* theta, double* loglik, double* logw, double* W, const double* beta,
-             int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed, double ess_frac,
+             const double* theta_in, const double* loglik_in, double* theta_out,
+             double* loglik_out, double* logw, double* W, const double* beta, int32_t T,
+             int32_t* t_dev, double step_sd, int32_t n_moves, uint64_t seed, double ess_frac,
              smc_prec prec, double* stats, unsigned long long* n_accept, void* stream) {
     int r = enter(ctx);
     if (r) return r;
@@ -466,8 +467,11 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     if ((r = check_model(model, &g))) return r;
     if ((r = check_prec(g, prec))) return r;
     if ((r = check_sizes(n, N))) return r;
-    if (!y || !theta || !loglik || !logw || !W || !beta || !t_dev || !stats)
+    if (!y || !theta_in || !loglik_in || !theta_out || !loglik_out || !logw || !W || !beta ||
+        !t_dev || !stats)
         return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (theta_in == theta_out || loglik_in == loglik_out)
+        return fail(SMC_ERR_INVALID_ARG, "the step reads one population and writes another");
     if (n_moves < 0) return fail(SMC_ERR_INVALID_ARG, "n_moves must be >= 0");
     if (T < 1) return fail(SMC_ERR_INVALID_ARG, "T must be >= 1");
     if (!(step_sd >= 0.0) || !isfinite(step_sd))
@@ -475,50 +479,66 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
     const hipStream_t s = as_stream(stream);
     const int kd = g.k * g.d;
+    const bool mfma = (prec == SMC_PREC_BF16X3);
     if ((r = ensure_scratch(ctx, N, kd, s))) return r;
-    // the reweight pass reads t from the caller's counter; its finaliser records t
-    // in the step state and advances the counter, and every later kernel of the
-    // step reads t from the state
+    if (mfma && (r = ensure_mm_scratch(ctx, n, N, s))) return r;
+    // the reweight pass reads t from the caller's counter; step_mid records t in
+    // the step state and advances the counter; later kernels read t from the state
     StepSrc src{};
     src.t_dev = t_dev;
     src.beta_dev = beta;
     src.t_max = T;
     StepSrc later = src;
     later.t_dev = &ctx->sc.state->t;
-    hipError_t e = launch_reweight(ctx->sc, logw, loglik, N, src, t_dev, stats, stats + 1,
-                                   ess_frac, stats + 2, s);
+    hipError_t e = launch_reweight_partial(ctx->sc, logw, loglik_in, N, src, s);
     if (e != hipSuccess) return hip_fail(e, "reweight launch");
-    WeightSrc ws{nullptr, logw, ctx->sc.state};
-    e = launch_resample(ctx->sc, ws, N, seed, later, nullptr, nullptr, 0.0, ctx->sc.state,
-                        nullptr, theta, ctx->sc.theta_tmp, kd, loglik, ctx->sc.l_tmp, logw, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "resample launch");
-    const int S = choose_slices(ctx, n, N);
-    const bool mfma = (prec == SMC_PREC_BF16X3);
-    if (mfma) {
-        if ((r = ensure_mm_scratch(ctx, n, N, s))) return r;
-        e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
-        if (e != hipSuccess) return hip_fail(e, "MFMA prep launch");
-    }
+    e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
     if (n_moves == 0) {
-        e = launch_copy_back(ctx->sc, theta, loglik, W, logw, N, kd, s);
-        if (e != hipSuccess) return hip_fail(e, "copy-back launch");
+        // adopt the resampled (or unchanged) population and publish W
+        e = launch_search_gather(ctx->sc, N, seed, later, ctx->sc.state, theta_in, theta_out, kd,
+                                 loglik_in, loglik_out, logw, 1, s);
+        if (e == hipSuccess) e = launch_publish_w(ctx->sc, W, logw, N, s);
+        if (e != hipSuccess) return hip_fail(e, "gather launch");
+        return SMC_OK;
     }
+    int chunk, nchunks;
+    cdf_layout(N, &chunk, &nchunks);
+    if (mfma) {
+        e = launch_search_gather(ctx->sc, N, seed, later, ctx->sc.state, theta_in,
+                                 ctx->sc.theta_tmp, kd, loglik_in, ctx->sc.l_tmp, logw, 0, s);
+        if (e == hipSuccess) e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
+        if (e != hipSuccess) return hip_fail(e, "gather launch");
+    }
+    const int S = choose_slices(ctx, n, N);
     for (int m = 0; m < n_moves; ++m) {
         MoveStep ms{};
         if (m == 0) {
-            ms.theta_alt = ctx->sc.theta_tmp;
-            ms.l_alt = ctx->sc.l_tmp;
+            ms.theta_src = theta_in;
+            ms.l_src = loglik_in;
             ms.state = ctx->sc.state;
             ms.W_out = W;
             ms.logw = logw;
+            if (mfma) {
+                ms.theta_alt = ctx->sc.theta_tmp;
+                ms.l_alt = ctx->sc.l_tmp;
+            } else {
+                ms.reset_logw = 1;
+                ms.cdf_hi = ctx->sc.cdf_hi;
+                ms.cdf_lo = ctx->sc.cdf_lo;
+                ms.chunk_tot = ctx->sc.dd_part;
+                ms.chunk = chunk;
+                ms.nchunks = nchunks;
+                ms.seed = seed;
+            }
         }
         if (mfma)
-            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, N, nullptr, later, step_sd,
-                               seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
+            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta_out, loglik_out, N, nullptr, later,
+                               step_sd, seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
                                ctx->sc.mm_prop, ctx->sc.mm_part, dd_slices(n, N), ctx->sc.status,
                                ms, s);
         else
-            e = launch_rwmh(g, y, n, theta, loglik, N, nullptr, later, step_sd, seed,
+            e = launch_rwmh(g, y, n, theta_out, loglik_out, N, nullptr, later, step_sd, seed,
                             static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status, ms, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }

@@ -129,8 +129,11 @@ k_dd_build(const double* __restrict__ theta, int N, int K, GmmDev g, double s2, 
     if (q >= N * K) return;
     const int p = q / K;
     const int i = q - p * K;
-    const bool use_alt = PROP && ms.state != nullptr && ms.state->resampled != 0;
-    const double* th = use_alt ? ms.theta_alt : theta;
+    const double* th = theta;
+    if constexpr (PROP) {
+        const bool rs = ms.state != nullptr && ms.state->resampled != 0;
+        th = (rs && ms.theta_alt) ? ms.theta_alt : (ms.theta_src ? ms.theta_src : theta);
+    }
     double mu[kDdDim];
 #pragma unroll
     for (int c = 0; c < kDdDim; ++c) mu[c] = th[static_cast<size_t>(i * kDdDim + c) * N + p];
@@ -308,9 +311,10 @@ k_dd_accept(const double* __restrict__ part, int S, int N, int n,
         double tot = part[p];
         for (int s = 1; s < S; ++s) tot += part[static_cast<size_t>(s) * N + p];
         const double l_prop = finish_loglik<SMC_PREC_FP32>(tot, n, g);
+        const MoveSource srcs = move_source(ms, theta, l);
         acc = rwmh_accept<KD>(
-            p, N, [&](int c) { return theta_prop[static_cast<size_t>(c) * N + p]; }, l_prop,
-            theta, l, beta_vec, src, step, seed, move, g, status, ms);
+            p, p, N, [&](int c) { return theta_prop[static_cast<size_t>(c) * N + p]; }, l_prop,
+            srcs, theta, l, beta_vec, src, step, seed, move, g, status, ms);
     }
     const unsigned long long mask = __ballot(acc);
     if (lane_id() == 0 && n_acc != nullptr && mask != 0ull)

@@ -118,24 +118,99 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
     }
 }
 
+// Source of a move's current state for the arrays (theta, l) it writes.
+struct MoveSource {
+    const double* th;
+    const double* l;
+    bool write_always;         // out of place: rejected particles are copied too
+};
+
+__device__ __forceinline__ MoveSource move_source(const MoveStep& ms, double* theta, double* l) {
+    const bool rs = (ms.state != nullptr) && (ms.state->resampled != 0);
+    if (rs && ms.theta_alt != nullptr) return MoveSource{ms.theta_alt, ms.l_alt, true};
+    const double* th = ms.theta_src ? ms.theta_src : theta;
+    const double* ll = ms.l_src ? ms.l_src : l;
+    return MoveSource{th, ll, th != theta};
+}
+
+// Ancestors of the 64 particles of this workgroup after systematic resampling
+// (cooperative: every thread of the block must call it). Wave 0 forms the chunk
+// offsets in LDS (exclusive double-double scan of the chunk totals), then each
+// of its lanes takes U = (i + u)/N for particle i and finds
+// idx = min{j : U < C_j} (or the first j with C_j = C_{N-1}), C_j = offset +
+// within-chunk prefix rounded once.
+__device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint32_t step, int pc,
+                                                int* anc, double* offh, double* offl) {
+    const int lane = lane_id();
+    if (wave_id() == 0) {
+        constexpr int per = kMaxChunks / kWave;
+        dd loc[per];
+        dd run = dd_zero();
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            loc[q] = run;
+            const int c = lane * per + q;
+            if (c < ms.nchunks) run = dd_add(run, dd{ms.chunk_tot[2 * c], ms.chunk_tot[2 * c + 1]});
+        }
+        dd inc = run;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const dd up{__shfl_up(inc.hi, o, kWave), __shfl_up(inc.lo, o, kWave)};
+            if (lane >= o) inc = dd_add(up, inc);
+        }
+        dd excl{__shfl_up(inc.hi, 1, kWave), __shfl_up(inc.lo, 1, kWave)};
+        if (lane == 0) excl = dd_zero();
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            const dd o = dd_add(excl, loc[q]);
+            offh[lane * per + q] = o.hi;
+            offl[lane * per + q] = o.lo;
+        }
+    }
+    __syncthreads();
+    if (wave_id() == 0) {
+        auto cdf = [&](int j) -> double {
+            const int b = j / ms.chunk;
+            return dd_add(dd{offh[b], offl[b]}, dd{ms.cdf_hi[j], ms.cdf_lo[j]}).hi;
+        };
+        const double u = u01_left_closed(draw(ms.seed, 0, 0, step, kResamp, 0).w0);
+        const double U = (static_cast<double>(pc) + u) / static_cast<double>(N);
+        const double clast = cdf(N - 1);
+        int lo = 0, hi = N - 1;
+        if (U < clast) {
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (U < cdf(mid)) hi = mid;
+                else lo = mid + 1;
+            }
+        } else {
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (cdf(mid) >= clast) hi = mid;
+                else lo = mid + 1;
+            }
+        }
+        anc[lane] = lo;
+    }
+    __syncthreads();
+}
+
 // Metropolis-Hastings decision for particle p of a random-walk move and the
 // write-back: log alpha = beta (l' - l) + log p0(theta') - log p0(theta); accept
 // iff log alpha >= 0 or log u < log alpha, u from stream (p, 0, step, ACC, move).
-// pr_at(c) returns coordinate c of the proposal. The prior terms are
-// accumulated coordinate by coordinate in index order, the current state is
-// re-read rather than held, and with the step duties of `ms` the current state
-// comes from the gathered population when the ESS test fired and the step's
-// normalised weight is published.
+// The current state is column a of (th_src, l_src) (a = p, or p's ancestor
+// after a fused resampling); pr_at(c) returns coordinate c of the proposal. The
+// prior terms are accumulated coordinate by coordinate in index order and the
+// current state is re-read rather than held. The step duties of `ms` publish
+// W and reset logw after resampling.
 template <int KD, class PropAt>
-__device__ __forceinline__ bool rwmh_accept(int p, int N, PropAt pr_at, double l_prop,
-                                            double* theta, double* l, const double* beta_vec,
-                                            const StepSrc& src, uint32_t step, uint64_t seed,
-                                            uint32_t move, const GmmDev& g, int* status,
-                                            const MoveStep& ms) {
-    const bool use_alt = (ms.state != nullptr) && (ms.state->resampled != 0);
-    const double* th_src = use_alt ? ms.theta_alt : theta;
-    const double* l_src = use_alt ? ms.l_alt : l;
-    const double l_cur = l_src[p];
+__device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, double l_prop,
+                                            const MoveSource& srcs, double* theta, double* l,
+                                            const double* beta_vec, const StepSrc& src,
+                                            uint32_t step, uint64_t seed, uint32_t move,
+                                            const GmmDev& g, int* status, const MoveStep& ms) {
+    const double* th_src = srcs.th;
+    const double l_cur = srcs.l[a];
     double lp_cur, lp_prop;
     if (g.prior == SMC_PRIOR_GAUSS) {
         const double den = 2.0 * g.pb * g.pb;
@@ -143,7 +218,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int N, PropAt pr_at, double l
         lp_prop = 0.0;
 #pragma unroll
         for (int c = 0; c < KD; ++c) {
-            const double zc = th_src[static_cast<size_t>(c) * N + p] - g.pa;
+            const double zc = th_src[static_cast<size_t>(c) * N + a] - g.pa;
             const double zp = pr_at(c) - g.pa;
             lp_cur += g.lp_const - (zc * zc) / den;
             lp_prop += g.lp_const - (zp * zp) / den;
@@ -152,7 +227,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int N, PropAt pr_at, double l
         bool in_cur = true, in_prop = true;
 #pragma unroll
         for (int c = 0; c < KD; ++c) {
-            const double xc = th_src[static_cast<size_t>(c) * N + p];
+            const double xc = th_src[static_cast<size_t>(c) * N + a];
             const double xp = pr_at(c);
             in_cur = in_cur && (xc >= g.pa) && (xc <= g.pb);
             in_prop = in_prop && (xp >= g.pa) && (xp <= g.pb);
@@ -170,17 +245,19 @@ __device__ __forceinline__ bool rwmh_accept(int p, int N, PropAt pr_at, double l
 #pragma unroll
         for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = pr_at(c);
         l[p] = l_prop;
-    } else if (use_alt) {
+    } else if (srcs.write_always) {
 #pragma unroll
         for (int c = 0; c < KD; ++c)
-            theta[static_cast<size_t>(c) * N + p] = th_src[static_cast<size_t>(c) * N + p];
+            theta[static_cast<size_t>(c) * N + p] = th_src[static_cast<size_t>(c) * N + a];
         l[p] = l_cur;
     }
     if (l_prop != l_prop) atomicOr(status, kStatusNaN);
+    const bool rs = (ms.state != nullptr) && (ms.state->resampled != 0);
     if (ms.W_out) {
-        ms.W_out[p] = use_alt ? 1.0 / static_cast<double>(N)
-                              : exp(ms.logw[p] - ms.state->M) / ms.state->S;
+        ms.W_out[p] = rs ? 1.0 / static_cast<double>(N)
+                         : exp(ms.logw[p] - ms.state->M) / ms.state->S;
     }
+    if (rs && ms.reset_logw) ms.logw[p] = 0.0;
     return acc;
 }
 

@@ -65,6 +65,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        uint32_t move, GmmDev g, unsigned long long* n_acc, int* status, MoveStep ms) {
     constexpr int KD = K * D;
     __shared__ double red[kMaxSlices][kWave];
+    __shared__ int anc[kWave];
+    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
@@ -73,15 +75,17 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
     const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
     const uint32_t step = static_cast<uint32_t>(step_index(src));
-    const bool use_alt = (ms.state != nullptr) && (ms.state->resampled != 0);
-    const double* th_src = use_alt ? ms.theta_alt : theta;
+    const bool fused = (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
+    if (fused) fused_ancestors(ms, N, step, pc, anc, offh, offl);
+    const MoveSource srcs = move_source(ms, theta, l);
+    const int a = fused ? anc[lane] : pc;
 
     double pr[KD];
     {
         double z[KD];
         normals<KD>(seed, static_cast<uint32_t>(pc), step, kProp, move, z);
 #pragma unroll
-        for (int c = 0; c < KD; ++c) pr[c] = th_src[static_cast<size_t>(c) * N + pc] + sd * z[c];
+        for (int c = 0; c < KD; ++c) pr[c] = srcs.th[static_cast<size_t>(c) * N + a] + sd * z[c];
     }
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
     __syncthreads();
@@ -92,8 +96,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         double tot = red[0][lane];
         for (int s = 1; s < S; ++s) tot += red[s][lane];
         const double l_prop = finish_loglik<PREC>(tot, n, g);
-        acc = rwmh_accept<KD>(p, N, [&](int c) { return pr[c]; }, l_prop, theta, l, beta_vec,
-                              src, step, seed, move, g, status, ms);
+        acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
+                              beta_vec, src, step, seed, move, g, status, ms);
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)

@@ -87,15 +87,33 @@ __device__ __forceinline__ int step_index(const StepSrc& src) {
     return t;
 }
 
-// Extra duties of the first RW-MH move of a fused tempering step: start from
-// the resampled population when the ESS test fired, and publish the
-// normalised weights of the step (1/N after resampling).
+// Where a random-walk move reads each particle's current state and the extra
+// duties of the first move of a fused tempering step.
+//   * The move writes the arrays it is given (theta, l). Its current state is
+//     read from theta_src/l_src (default: the written arrays, i.e. in place).
+//   * When the step's ESS test fired (state->resampled):
+//       - with theta_alt set, the current state is the population gathered by a
+//         separate search-and-gather pass;
+//       - with cdf_hi set, the move finds each particle's ancestor itself
+//         (systematic offsets, binary search of the correctly rounded CDF kept
+//         as within-chunk prefixes plus chunk totals) and reads the ancestor
+//         from theta_src/l_src, which must then differ from the written arrays.
+//   * W_out: publish the step's normalised weights (1/N after resampling);
+//     reset_logw: set logw to 0 after resampling.
 struct MoveStep {
-    const double* theta_alt;   // gathered population (scratch)
+    const double* theta_src;
+    const double* l_src;
+    const double* theta_alt;
     const double* l_alt;
     const StepState* state;    // nullable: no step duties
-    double* W_out;             // nullable
-    const double* logw;        // log-weights after the reweight
+    double* W_out;
+    double* logw;
+    int reset_logw;
+    const double* cdf_hi;
+    const double* cdf_lo;
+    const double* chunk_tot;   // [2 * nchunks] (hi, lo)
+    int chunk, nchunks;
+    uint64_t seed;
 };
 
 // How the CDF kernels obtain the normalised weights: read W, or form
@@ -180,8 +198,19 @@ hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t s
 hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
                            int32_t kd, int parity_mode, int parity_host, int wrap,
                            uint64_t seed, StepSrc src, unsigned* n_swap, hipStream_t s);
-hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, double* W,
-                            const double* logw, int64_t N, int kd, hipStream_t s);
+// Fused tempering step pieces: reweight partials -> step_mid (combine, decide,
+// CDF chunks) -> moves (ancestor search fused into the first move).
+hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
+                           double* stats, double ess_frac, const double* logw, hipStream_t s);
+void cdf_layout(int64_t N, int* chunk, int* nchunks);
+hipError_t launch_search_gather(const Scratch& sc, int64_t N, uint64_t seed, StepSrc src,
+                                const StepState* pred_state, const double* theta_in,
+                                double* theta_out, int32_t kd, const double* l_in, double* l_out,
+                                double* logw, int copy_when_skipped, hipStream_t s);
+hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, int64_t N,
+                            hipStream_t s);
+hipError_t launch_reweight_partial(const Scratch& sc, double* logw, const double* l, int64_t N,
+                                   StepSrc src, hipStream_t s);
 hipError_t launch_counter_inc(int* counter, hipStream_t s);
 hipError_t launch_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
                             uint32_t purpose, uint32_t move, uint32_t* out, hipStream_t s);

@@ -34,31 +34,35 @@ __device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
     return Lse3{b.m, b.s1 + a.s1 * r, b.s2 + a.s2 * (r * r)};
 }
 
-__device__ __forceinline__ Lse3 wave_lse3(Lse3 v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        Lse3 o{__shfl_xor(v.m, off, kWave), __shfl_xor(v.s1, off, kWave),
-               __shfl_xor(v.s2, off, kWave)};
-        v = (lane_id() & off) ? lse3_merge(o, v) : lse3_merge(v, o);
-    }
-    return v;
-}
-
-// Block (kRedBlock threads) reductions; the result is valid in thread 0.
+// Block (kRedBlock threads) log-sum-exp; the result is valid in thread 0.
+// The block maximum is formed first, then every thread rescales its sums to it
+// with one exp and the rescaled sums are added in fixed order: one exp per
+// thread instead of one per butterfly stage.
 __device__ __forceinline__ Lse3 block_lse3(Lse3 v) {
     __shared__ double sm[kRedBlock / kWave], s1[kRedBlock / kWave], s2[kRedBlock / kWave];
-    v = wave_lse3(v);
+    const double mw = wave_max(v.m);
+    if (lane_id() == 0) sm[wave_id()] = mw;
+    __syncthreads();
+    double M = sm[0];
+#pragma unroll
+    for (int w = 1; w < kRedBlock / kWave; ++w) M = fmax(M, sm[w]);
+    const double r = (v.m == -INFINITY) ? 0.0 : exp(v.m - M);
+    const double a = wave_sum(v.s1 * r);
+    const double b = wave_sum(v.s2 * (r * r));
     if (lane_id() == 0) {
-        sm[wave_id()] = v.m;
-        s1[wave_id()] = v.s1;
-        s2[wave_id()] = v.s2;
+        s1[wave_id()] = a;
+        s2[wave_id()] = b;
     }
     __syncthreads();
-    Lse3 r = lse3_empty();
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kRedBlock / kWave; ++w) r = lse3_merge(r, Lse3{sm[w], s1[w], s2[w]});
+    Lse3 out{M, 0.0, 0.0};
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kRedBlock / kWave; ++w) {
+            out.s1 += s1[w];
+            out.s2 += s2[w];
+        }
+    }
     __syncthreads();
-    return r;
+    return out;
 }
 
 __device__ __forceinline__ double block_sum(double v) {

@@ -131,12 +131,12 @@ __device__ __forceinline__ double weight_at(const WeightSrc& w, int j) {
     return exp(w.logw[j] - w.state->M) / w.state->S;
 }
 
-// Phase 1: within-chunk inclusive prefixes (double-double) and chunk totals.
+// Within-chunk inclusive prefixes (double-double) of chunk b and its total.
 // Chunk b covers [b*chunk, min(N, (b+1)*chunk)), processed kScanChunk at a time.
-__global__ void __launch_bounds__(kRedBlock)
-k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
-    if (!should_fire(pred)) return;
-    const int begin = blockIdx.x * chunk;
+template <class WeightAt>
+__device__ __forceinline__ void scan_chunk(int b, int N, int chunk, const Scratch& sc,
+                                           WeightAt weight) {
+    const int begin = b * chunk;
     const int end = min(N, begin + chunk);
     dd carry = dd_zero();
     for (int piece = begin; piece < end; piece += kScanChunk) {
@@ -145,7 +145,7 @@ k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
         dd run = dd_zero();
 #pragma unroll
         for (int e = 0; e < kScanPerThread; ++e) {
-            if (base + e < end) run = dd_add(run, weight_at(w, base + e));
+            if (base + e < end) run = dd_add(run, weight(base + e));
             pre[e] = run;
         }
         dd total;
@@ -162,9 +162,73 @@ k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
         carry = dd_add(carry, total);
     }
     if (threadIdx.x == 0) {
-        sc.dd_part[2 * blockIdx.x] = carry.hi;
-        sc.dd_part[2 * blockIdx.x + 1] = carry.lo;
+        sc.dd_part[2 * b] = carry.hi;
+        sc.dd_part[2 * b + 1] = carry.lo;
     }
+}
+
+// Phase 1 of standalone resampling: the chunk scans.
+__global__ void __launch_bounds__(kRedBlock)
+k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
+    if (!should_fire(pred)) return;
+    scan_chunk(blockIdx.x, N, chunk, sc, [&](int j) { return weight_at(w, j); });
+}
+
+// Middle of a fused tempering step: every workgroup combines the reweight
+// partials in block order (so all reach the same M, S1, S2 and decision);
+// workgroup 0 publishes the step state, the statistics and the next step index;
+// when the ESS test fires, workgroup b scans CDF chunk b of the weights
+// exp(logw - M) / S1.
+__global__ void __launch_bounds__(kRedBlock)
+k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
+           double* stats, double ess_frac, const double* __restrict__ logw) {
+    __shared__ double sh_M, sh_S;
+    __shared__ int sh_fire;
+    Lse3 o = lse3_empty(), nw = lse3_empty();
+    for (int b = threadIdx.x; b < parts; b += blockDim.x) {
+        const RwPartial q = sc.rw_part[b];
+        o = lse3_merge(o, Lse3{q.mo, q.so, 0.0});
+        nw = lse3_merge(nw, Lse3{q.mn, q.s1, q.s2});
+    }
+    o = block_lse3(o);
+    nw = block_lse3(nw);
+    if (threadIdx.x == 0) {
+        const double e = (nw.s1 * nw.s1) / nw.s2;
+        const int fire = (ess_frac > 0.0) && (e < ess_frac * static_cast<double>(N));
+        sh_M = nw.m;
+        sh_S = nw.s1;
+        sh_fire = fire;
+        if (blockIdx.x == 0) {
+            StepState* st = sc.state;
+            const int t = step_index(src);
+            st->M = nw.m;
+            st->S = nw.s1;
+            st->S2 = nw.s2;
+            st->lse_old = (o.m == -INFINITY) ? -INFINITY : o.m + log(o.s1);
+            st->lse_new = (nw.m == -INFINITY) ? -INFINITY : nw.m + log(nw.s1);
+            st->ess = e;
+            st->resampled = fire;
+            st->t = t;
+            if (nw.m == -INFINITY || !(e == e)) atomicOr(sc.status, kStatusAllZeroWeight);
+            stats[0] += st->lse_new - st->lse_old;
+            stats[1] = e;
+            if (fire) stats[2] += 1.0;
+            *t_advance = t + 1;
+        }
+    }
+    __syncthreads();
+    if (!sh_fire) return;
+    const double M = sh_M, S = sh_S;
+    scan_chunk(blockIdx.x, N, chunk, sc, [&](int j) { return exp(logw[j] - M) / S; });
+}
+
+// Publish the normalised weights of a step that made no move.
+__global__ void __launch_bounds__(kRedBlock)
+k_publish_w(double* __restrict__ W, const double* __restrict__ logw, int N, Scratch sc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const StepState* st = sc.state;
+    W[i] = st->resampled ? 1.0 / static_cast<double>(N) : exp(logw[i] - st->M) / st->S;
 }
 
 // Phase 2: chunk offsets (exclusive scan of the chunk totals, once per block in
@@ -284,24 +348,6 @@ k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __r
     }
 }
 
-// A step whose moves were all skipped: adopt the resampled population and
-// publish the step's weights.
-__global__ void __launch_bounds__(kRedBlock)
-k_copy_back(double* __restrict__ theta, double* __restrict__ l, double* __restrict__ W,
-            const double* __restrict__ logw, int N, int kd, Scratch sc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const StepState* st = sc.state;
-    if (st->resampled) {
-        for (int c = 0; c < kd; ++c)
-            theta[static_cast<size_t>(c) * N + i] = sc.theta_tmp[static_cast<size_t>(c) * N + i];
-        l[i] = sc.l_tmp[i];
-        W[i] = 1.0 / static_cast<double>(N);
-    } else {
-        W[i] = exp(logw[i] - st->M) / st->S;
-    }
-}
-
 __global__ void k_counter_inc(int* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c += 1;
 }
@@ -360,6 +406,13 @@ hipError_t launch_reweight(const Scratch& sc, double* logw, const double* l, int
     return hipGetLastError();
 }
 
+hipError_t launch_reweight_partial(const Scratch& sc, double* logw, const double* l, int64_t N,
+                                   StepSrc src, hipStream_t s) {
+    hipLaunchKernelGGL(k_reweight_partial, dim3(red_grid(N)), dim3(kRedBlock), 0, s, logw, l,
+                       static_cast<int>(N), src, sc);
+    return hipGetLastError();
+}
+
 hipError_t launch_weights(const Scratch& sc, const double* logw, int64_t N, double* W,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_weights, dim3(red_grid(N)), dim3(kRedBlock), 0, s, logw,
@@ -408,11 +461,40 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_copy_back(const Scratch& sc, double* theta, double* l, double* W,
-                            const double* logw, int64_t N, int kd, hipStream_t s) {
+hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
+                           double* stats, double ess_frac, const double* logw, hipStream_t s) {
+    const int parts = red_grid(N);
+    const int chunk = cdf_chunk(N);
+    const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_step_mid, dim3(nchunks), dim3(kRedBlock), 0, s, parts, static_cast<int>(N),
+                       chunk, src, t_advance, sc, stats, ess_frac, logw);
+    return hipGetLastError();
+}
+
+void cdf_layout(int64_t N, int* chunk, int* nchunks) {
+    *chunk = cdf_chunk(N);
+    *nchunks = static_cast<int>((N + *chunk - 1) / *chunk);
+}
+
+hipError_t launch_search_gather(const Scratch& sc, int64_t N, uint64_t seed, StepSrc src,
+                                const StepState* pred_state, const double* theta_in,
+                                double* theta_out, int32_t kd, const double* l_in, double* l_out,
+                                double* logw, int copy_when_skipped, hipStream_t s) {
+    ResamplePred pred{nullptr, 0.0, pred_state};
+    int chunk, nchunks;
+    cdf_layout(N, &chunk, &nchunks);
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
-    hipLaunchKernelGGL(k_copy_back, dim3(g), dim3(kRedBlock), 0, s, theta, l, W, logw,
-                       static_cast<int>(N), kd, sc);
+    hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N), chunk,
+                       nchunks, sc, pred, seed, src, static_cast<const double*>(nullptr),
+                       static_cast<int32_t*>(nullptr), theta_in, theta_out, kd, l_in, l_out, logw,
+                       copy_when_skipped);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, int64_t N,
+                            hipStream_t s) {
+    const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
+    hipLaunchKernelGGL(k_publish_w, dim3(g), dim3(kRedBlock), 0, s, W, logw, static_cast<int>(N), sc);
     return hipGetLastError();
 }
 

@@ -35,42 +35,4 @@ __device__ __forceinline__ dd wave_sum(dd v) {
     return v;
 }
 
-// Running log-sum-exp state: the set {x} is represented by (m, s) with
-// sum exp(x) = s * exp(m). Combining is associative up to rounding.
-struct LseAcc {
-    double m, s;
-};
-
-__device__ __forceinline__ LseAcc lse_empty() { return LseAcc{-INFINITY, 0.0}; }
-
-__device__ __forceinline__ LseAcc lse_push(LseAcc a, double x) {
-    if (x == -INFINITY) return a;
-    if (x > a.m) {
-        const double s = (a.m == -INFINITY) ? 0.0 : a.s * exp(a.m - x);
-        return LseAcc{x, s + 1.0};
-    }
-    return LseAcc{a.m, a.s + exp(x - a.m)};
-}
-
-__device__ __forceinline__ LseAcc lse_merge(LseAcc a, LseAcc b) {
-    if (b.m == -INFINITY) return a;
-    if (a.m == -INFINITY) return b;
-    if (a.m >= b.m) return LseAcc{a.m, a.s + b.s * exp(b.m - a.m)};
-    return LseAcc{b.m, b.s + a.s * exp(a.m - b.m)};
-}
-
-__device__ __forceinline__ LseAcc wave_lse(LseAcc v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        LseAcc o{__shfl_xor(v.m, off, kWave), __shfl_xor(v.s, off, kWave)};
-        // combine in lane order so that lanes agree bit for bit
-        v = (lane_id() & off) ? lse_merge(o, v) : lse_merge(v, o);
-    }
-    return v;
-}
-
-__device__ __forceinline__ double lse_value(LseAcc a) {
-    return (a.m == -INFINITY) ? -INFINITY : a.m + log(a.s);
-}
-
 }  // namespace smc

@@ -4,8 +4,9 @@ call per tempering step or PT iteration. All arithmetic runs in libsmcgpu.
 SMCSampler: tempered SMC sampler (SMC Samplers and SMC Sampler subsections):
 prior draws, then for t = 1..T one smc_step (reweight, ESS test and systematic
 resampling on the device, RW-MH moves at beta_t). The step reads t from a
-device counter, so a single captured hipGraph is replayed T times and the host
-never waits inside the run.
+device counter and moves the population between two buffers, so two captured
+hipGraphs (one per direction) are replayed alternately and the host never
+waits inside the run.
 
 BatchSampler: many independent tempered SMC runs (own data, size and seed each)
 advanced together by smc_step_batched: one graph replay per tempering step for
@@ -44,53 +45,89 @@ class SMCSampler:
             self.y = _dev(y, torch.float32)
             self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
             kd = model.kd
-            self.theta = torch.empty((kd, self.N), dtype=torch.float64, device="cuda")
-            self.loglik = torch.empty(self.N, dtype=torch.float64, device="cuda")
+            self.thetas = [torch.empty((kd, self.N), dtype=torch.float64, device="cuda")
+                           for _ in range(2)]
+            self.logliks = [torch.empty(self.N, dtype=torch.float64, device="cuda")
+                            for _ in range(2)]
             self.logw = torch.zeros(self.N, dtype=torch.float64, device="cuda")
             self.W = torch.full((self.N,), 1.0 / self.N, dtype=torch.float64, device="cuda")
             self.t = torch.ones(1, dtype=torch.int32, device="cuda")
             self.stats = torch.zeros(4, dtype=torch.float64, device="cuda")
             self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
         ctx.reserve(self.N, model.kd, self.y.shape[0] if prec == "bf16x3" else 0)
-        self.graph: Optional[Graph] = None
+        self.cur = 0                       # buffer holding the current population
+        self.graphs: dict = {}             # (start buffer, steps) -> Graph
+
+    @property
+    def theta(self) -> torch.Tensor:
+        return self.thetas[self.cur]
+
+    @property
+    def loglik(self) -> torch.Tensor:
+        return self.logliks[self.cur]
 
     def init(self):
         """theta_0 from the prior, l(theta_0), logw = 0, t = 1, statistics cleared."""
+        self.cur = 0
         with torch.cuda.stream(self.stream):
-            smc_prior_init(self.ctx, self.model, self.N, self.seed, out=self.theta,
+            smc_prior_init(self.ctx, self.model, self.N, self.seed, out=self.thetas[0],
                            stream=self.stream)
-            smc_loglik(self.ctx, self.model, self.y, self.theta, self.prec, out=self.loglik,
-                       stream=self.stream)
+            smc_loglik(self.ctx, self.model, self.y, self.thetas[0], self.prec,
+                       out=self.logliks[0], stream=self.stream)
             self.logw.zero_()
             self.W.fill_(1.0 / self.N)
             self.t.fill_(1)
             self.stats.zero_()
             self.n_accept.zero_()
 
-    def enqueue_step(self):
-        smc_step(self.ctx, self.model, self.y, self.theta, self.loglik, self.logw, self.W,
-                 self.beta, self.t, self.step_sd, self.n_moves, self.seed, self.ess_frac,
-                 self.prec, self.stats, self.n_accept, stream=self.stream)
+    def enqueue_step(self, src: int):
+        dst = 1 - src
+        smc_step(self.ctx, self.model, self.y, self.thetas[src], self.logliks[src],
+                 self.thetas[dst], self.logliks[dst], self.logw, self.W, self.beta, self.t,
+                 self.step_sd, self.n_moves, self.seed, self.ess_frac, self.prec, self.stats,
+                 self.n_accept, stream=self.stream)
 
-    def capture(self) -> Graph:
-        """Capture one tempering step into a hipGraph (replayable for every t)."""
-        if self.graph is None:
+    def capture(self, src: Optional[int] = None, steps: int = 1) -> Graph:
+        """The hipGraph of `steps` consecutive tempering steps starting from buffer
+        `src` (replayable for every t: t, beta_t and the resampling decision live
+        on the device). An even number of steps ends on the buffer it started from."""
+        src = self.cur if src is None else src
+        key = (src, int(steps))
+        if key not in self.graphs:
             g = Graph(self.ctx, self.stream)
             with g:
-                self.enqueue_step()
-            self.graph = g
-        return self.graph
+                b = src
+                for _ in range(int(steps)):
+                    self.enqueue_step(b)
+                    b = 1 - b
+            self.graphs[key] = g
+        return self.graphs[key]
 
-    def step(self, graph: bool = True):
+    def step(self, graph: bool = True, steps: int = 1):
+        """Advance `steps` tempering steps (one graph replay when graph=True)."""
         if graph:
-            self.capture().launch()
+            self.capture(self.cur, steps).launch()
         else:
-            self.enqueue_step()
+            for _ in range(int(steps)):
+                self.enqueue_step(self.cur)
+                self.cur = 1 - self.cur
+            return
+        self.cur = self.cur ^ (int(steps) & 1)
 
-    def run(self, graph: bool = True, steps: Optional[int] = None):
+    def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 10):
+        """Advance `steps` steps with graphs of `steps_per_graph` steps (plus single steps)."""
+        if not graph:
+            self.step(False, steps)
+            return
+        u = max(1, int(steps_per_graph))
+        for _ in range(steps // u):
+            self.step(True, u)
+        for _ in range(steps % u):
+            self.step(True, 1)
+
+    def run(self, graph: bool = True, steps: Optional[int] = None, steps_per_graph: int = 1):
         self.init()
-        for _ in range(self.T if steps is None else steps):
-            self.step(graph)
+        self.advance(self.T if steps is None else steps, graph, steps_per_graph)
         self.stream.synchronize()
         self.ctx.check(self.stream)
         return self.results()

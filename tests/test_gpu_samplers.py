@@ -62,6 +62,29 @@ def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph):
     assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
     assert rel_err(r["l"], ref["l"]).max() <= 1e-10
     assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+    assert np.max(np.abs(r["W"] - ref["W"])) <= 1e-14
+    assert np.max(np.abs(r["logw"] - ref["logw"])) <= 1e-9
+
+
+@pytest.mark.parametrize("n_moves,ess_frac", [(0, 0.5), (3, 0.5), (1, 0.0), (2, 1.0)])
+def test_smc_step_variants_match_oracle(smc, ctx, small, n_moves, ess_frac):
+    """No moves (pure reweight/resample), several moves per step, no resampling
+    (annealed importance sampling), and resampling at every step."""
+    cfg, y, betas = small
+    announce(f"smc variants moves={n_moves} ess_frac={ess_frac}")
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2)
+    N = 300
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2)
+    s = smc.SMCSampler(ctx, g, y, N, betas[:13], cfg.step_sd, n_moves, 77, ess_frac=ess_frac,
+                       prec="fp64")
+    r = s.run(graph=True)
+    ref = osmc.smc_run(y, om, betas[:13], N, cfg.step_sd, n_moves, 77, ess_frac=ess_frac,
+                       resample=ess_frac > 0.0)
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"]))
+    assert abs(r["logZ"] - ref["logZ"]) <= 1e-9 * max(1.0, abs(ref["logZ"]))
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert np.max(np.abs(r["W"] - ref["W"])) <= 1e-14
 
 
 def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
@@ -71,6 +94,10 @@ def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
     b = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True)
     assert a["logZ"] == b["logZ"]
     assert np.array_equal(a["theta"], b["theta"])
+    for spg in (2, 7, 10):              # several steps captured in one graph
+        c = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True, steps_per_graph=spg)
+        assert c["logZ"] == a["logZ"] and np.array_equal(c["theta"], a["theta"])
+        assert np.array_equal(c["W"], a["W"]) and c["t"] == cfg.T + 1
     # repeated replays of the same sampler give the same answer again
     s = _sampler(smc, ctx, cfg, y, betas, "fp32")
     c = s.run(graph=True)
