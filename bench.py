@@ -107,26 +107,37 @@ def cpu_baseline(cfg, y, betas, budget_s=12.0):
 
 def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
     """Population-MCMC iterations (one RW-MH move per chain, then exchanges),
-    one hipGraph replay per iteration."""
+    ten iterations per hipGraph replay."""
     from workloads import pt_betas
     betas = pt_betas(cfg.N, 4)
     s = smc.PTSampler(ctx, g, y, betas, cfg.step_sd, cfg.run_seed, parity_mode=0, wrap=False,
                       prec=prec)
     s.init()
-    graph = s.capture()
-    for _ in range(warmup):
-        graph.launch()
-    s.stream.synchronize()
+    s.advance(warmup + STEPS_PER_GRAPH + 1, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+    s.stream.synchronize()                 # graphs captured and warm
     s.init()
     s.stream.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        graph.launch()
+    s.advance(steps, graph=True, iters_per_graph=STEPS_PER_GRAPH)
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
     r = s.results()
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, swaps=r["swaps"], accepted=r["accepted"])
+
+
+def tune(ctx, cfg, precs, no_tune):
+    """Pick the launch shape (data slices per 64-particle tile) of each precision
+    with the package's autotuner (timed moves of this exact shape) and install
+    it in the context's launch table; {prec: {"slices", "ms_per_move"}}."""
+    if no_tune:
+        return {p: {"slices": "built-in"} for p in precs}
+    from paper_0905_2441_amd import autotune
+    rules = autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, cfg.N, p) for p in precs], reps=10,
+                                exact=True, log=log)
+    ctx.set_launch_table(rules)
+    return {r["prec"]: {"slices": r["slices"], "ms_per_move": r["ms"][str(r["slices"])]}
+            for r in rules}
 
 
 def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
@@ -168,6 +179,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the built-in launch shape instead of autotuning it first")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (HBM counter calibration)")
     ap.add_argument("--workload", default=WORKLOAD, choices=(WORKLOAD,) + OTHER_WORKLOADS,
                     help="the headline workload (default) or another measured configuration")
     args = ap.parse_args()
@@ -183,6 +198,8 @@ def main():
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
 
+    if args.copy_calibration:
+        return copy_calibration()
     if args.workload != WORKLOAD:
         return other_workload(args)
     cfg = CONFIGS[WORKLOAD]
@@ -193,6 +210,7 @@ def main():
     g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
                               prior_b=cfg.prior_b)
     evals_per_step = cfg.N * cfg.n * cfg.n_moves
+    launch = tune(ctx, cfg, ["fp32"] + ([] if args.no_fp64 else ["fp64"]), args.no_tune)
 
     log(f"[bench] {WORKLOAD}: fp32 {args.steps} steps after {args.warmup} warm-up")
     r32 = time_precision(smc, torch, ctx, cfg, g, y, betas, "fp32", args.steps, args.warmup)
@@ -238,7 +256,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N,
                    "T": cfg.T, "schedule": "(t/T)^2", "moves_per_step": cfg.n_moves,
-                   "ess_threshold": "N/2", "graph": f"{STEPS_PER_GRAPH} tempering steps per hipGraph replay"},
+                   "ess_threshold": "N/2", "graph": f"{STEPS_PER_GRAPH} tempering steps per hipGraph replay",
+                   "launch": launch},
         "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
         "fp32_over_fp64_speedup": (r64["ms_per_step"] / r32["ms_per_step"]) if r64 else None,
         "fp64_move_kernel_ms": r64["kernel_ms"] if r64 else None,
@@ -278,6 +297,19 @@ def time_batched(smc, torch, ctx, prec, steps, warmup, R=256):
                 N_total=sum(r.N for r in runs), n_total=sum(r.n for r in runs))
 
 
+def copy_calibration(nbytes=1 << 28, reps=4):
+    """A plain device-to-device copy of `nbytes` (read nbytes, write nbytes), the
+    reference for scaling the HBM byte counters of a profiled run."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def other_workload(args):
     """Secondary measurements (same JSON shape, no CPU baseline)."""
     import torch
@@ -313,6 +345,7 @@ def other_workload(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
            "config": {"workload": cfg.name, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N}}
     if cfg.sampler == "pt":
+        out["config"]["launch"] = tune(ctx, cfg, ["fp32", "fp64"], args.no_tune)
         r = time_pt(smc, torch, ctx, cfg, g, y, "fp32", args.steps, args.warmup)
         r64 = time_pt(smc, torch, ctx, cfg, g, y, "fp64", max(5, args.steps // 5), 2)
         out.update(value=evals / (r["ms_per_step"] * 1e-3), ms_per_step=r["ms_per_step"],
@@ -326,6 +359,7 @@ def other_workload(args):
         if cfg.d > 1 and "fp32" not in precs:
             precs.append("fp32")
         res = {}
+        out["config"]["launch"] = tune(ctx, cfg, precs, args.no_tune)
         for prec in precs:
             steps = args.steps if prec != "fp64" else max(5, args.steps // 5)
             res[prec] = time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, args.warmup)

@@ -104,10 +104,33 @@ int smc_check(smc_ctx ctx, void* stream);
 
 const char* smc_last_error(void);
 
-/* Override the number of data slices (waves per workgroup that split the
- * observations of the same 64 particles) used by the likelihood kernels;
- * 0 restores the built-in choice. Range 0..16. */
+/* Override the number of data slices (contiguous ranges of the observations
+ * whose partial sums for the same 64 particles are formed by separate waves)
+ * used by the likelihood kernels; 0 restores the built-in choice. Range 0..128.
+ * Up to 16 slices run as the waves of one workgroup; a move with more slices
+ * and N <= 32768 spreads them over up to 8 workgroups per 64 particles and
+ * completes in a second, per-particle kernel. Other kernels use min(slices, 16).
+ * Results depend on the slicing only through the order of FP64 additions. */
 int smc_set_slices(smc_ctx ctx, int32_t slices);
+
+/* One entry of a context's launch table (the output of the autotuner in the
+ * Python package): calls whose model, precision and sizes fall in the rule's
+ * ranges use `slices` data slices per 64-particle tile (same meaning and range
+ * as smc_set_slices; the MFMA form uses min(slices, 16)). k, d = 0 and
+ * prec = -1 match anything; ranges are inclusive. */
+typedef struct {
+    int32_t k, d, prec;
+    int32_t slices;
+    int64_t n_lo, n_hi;
+    int64_t N_lo, N_hi;
+} smc_launch_rule;
+
+/* Replace the context's launch table with a copy of `rules[0..count-1]`
+ * (count = 0 clears it). The first matching rule wins; an explicit
+ * smc_set_slices override takes precedence over the table, and calls that
+ * match no rule use the built-in choice. Invalid rules (slices outside 1..128,
+ * empty ranges) reject the whole table and leave the old one in place. */
+int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t count);
 
 /* Per-particle log-likelihood (Mixture Modelling section):
  *   loglik[p] = sum_j log sum_i w_i N_d(y_j; mu_{p,i}, sigma2 I).
@@ -211,7 +234,9 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
  * (graph-replayable): it = *it_dev; one RW-MH move per chain at its own
  * beta[i] with step = it; exchanges on partition parity (it & 1 when
  * parity_mode = 0; a Philox bit from stream (0, 0, it, PARITY, 0) when 1), with
- * the wrap pair if `wrap`; then *it_dev = it + 1. */
+ * the wrap pair if `wrap`; then *it_dev = it + 1. The move records `it` in the
+ * context's step state and the exchange kernel advances *it_dev from there, so
+ * the iteration is the move kernel(s) plus one exchange kernel. */
 int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
                  double* theta, double* loglik, const double* beta, int32_t* it_dev,
                  double step_sd, uint64_t seed, int32_t parity_mode, int32_t wrap,

@@ -44,6 +44,11 @@ class SmcRunDesc(Structure):
                 ("seed", c_uint64)]
 
 
+class SmcLaunchRule(Structure):
+    _fields_ = [("k", c_int32), ("d", c_int32), ("prec", c_int32), ("slices", c_int32),
+                ("n_lo", c_int64), ("n_hi", c_int64), ("N_lo", c_int64), ("N_hi", c_int64)]
+
+
 _P = c_void_p
 _GP = POINTER(SmcGmm)
 
@@ -55,6 +60,7 @@ SIGNATURES = {
     "smc_check": (c_int, [_P, _P]),
     "smc_last_error": (c_char_p, []),
     "smc_set_slices": (c_int, [_P, c_int32]),
+    "smc_set_launch_table": (c_int, [_P, POINTER(SmcLaunchRule), c_int32]),
     "smc_loglik": (c_int, [_P, _GP, _P, c_int64, _P, c_int64, c_int, _P, _P]),
     "smc_prior_init": (c_int, [_P, _GP, c_int64, c_uint64, _P, _P]),
     "smc_rwmh_move": (c_int, [_P, _GP, _P, c_int64, _P, _P, c_int64, _P, c_double, c_double,
@@ -99,7 +105,7 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_0905_2441_amd.build` "
+            f"{LIB_PATH} is missing: build it with `python paper_0905_2441_amd/build.py` "
             "(there is no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():

@@ -113,6 +113,17 @@ class Context:
     def set_slices(self, slices: int) -> None:
         L.check(self._lib.smc_set_slices(self.handle, int(slices)))
 
+    def set_launch_table(self, rules: Sequence[dict]) -> None:
+        """Install launch rules (dicts with k, d, prec, slices, n_lo, n_hi, N_lo,
+        N_hi; prec is a name of PREC or "any"); an empty list clears the table."""
+        arr = (L.SmcLaunchRule * max(1, len(rules)))()
+        for i, r in enumerate(rules):
+            prec = r.get("prec", "any")
+            arr[i] = L.SmcLaunchRule(int(r.get("k", 0)), int(r.get("d", 0)),
+                                     -1 if prec == "any" else PREC[prec], int(r["slices"]),
+                                     int(r["n_lo"]), int(r["n_hi"]), int(r["N_lo"]), int(r["N_hi"]))
+        L.check(self._lib.smc_set_launch_table(self.handle, arr, len(rules)))
+
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
             self._lib.smc_destroy(self.handle)

@@ -1,6 +1,7 @@
 """Build libsmcgpu.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-Usage: python -m paper_0905_2441_amd.build  [--verbose]
+Usage: python paper_0905_2441_amd/build.py [--verbose]   (by path: importing the
+package loads the library, which may be missing or stale before a build)
 """
 
 from __future__ import annotations

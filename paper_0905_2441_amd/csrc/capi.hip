@@ -17,6 +17,7 @@ using namespace smc;
 struct smc_ctx_s {
     int device = 0;
     int slices_override = 0;
+    std::vector<smc_launch_rule> table;
     Scratch sc{};
     void* fixed = nullptr;       // partials, chunk totals, status, state
     void* grow = nullptr;        // cdf, dd partials, l_tmp, theta_tmp
@@ -116,20 +117,52 @@ int check_sizes(int64_t n, int64_t N) {
     return SMC_OK;
 }
 
-// Data slices per 64-particle workgroup: enough waves to fill 256 CUs several
-// times over, at least 32 observations per slice, and a grid within 2^32 threads.
-int choose_slices(const smc_ctx_s* ctx, int64_t n, int64_t N) {
-    const int64_t tiles = (N + kWave - 1) / kWave;
-    int64_t S = ctx->slices_override;
-    if (S <= 0) {
-        S = (8192 + tiles - 1) / tiles;
-        if (S > kMaxSlices) S = kMaxSlices;
-        while (S > 1 && n / S < 32) --S;
+// Slices per tile from the launch table (0 when no rule matches).
+int64_t table_slices(const smc_ctx_s* ctx, const GmmDev& g, int prec, int64_t n, int64_t N) {
+    for (const smc_launch_rule& r : ctx->table) {
+        if ((r.k == 0 || r.k == g.k) && (r.d == 0 || r.d == g.d) &&
+            (r.prec < 0 || r.prec == prec) && n >= r.n_lo && n <= r.n_hi && N >= r.N_lo &&
+            N <= r.N_hi)
+            return r.slices;
     }
-    if (S > n) S = n;
-    if (S < 1) S = 1;
-    while (S > 1 && tiles * kWave * S >= (int64_t{1} << 32)) --S;
-    return static_cast<int>(S);
+    return 0;
+}
+
+// Data slices per 64-particle tile: the explicit override, else the launch
+// table, else the built-in choice: enough waves to fill 256 CUs several times
+// over (about 8192), at least 32 observations per slice, and a grid within 2^32
+// threads. More than kMaxSlices slices (small N, long data) are spread over up
+// to kMaxGroups workgroups per tile so that every CU receives work; only moves
+// with N <= kSplitCap do that, everything else stays within one workgroup.
+Split choose_split(const smc_ctx_s* ctx, const GmmDev& g, int prec, int64_t n, int64_t N,
+                   bool allow_groups) {
+    const int64_t tiles = (N + kWave - 1) / kWave;
+    int64_t T = ctx->slices_override;
+    if (T <= 0) T = table_slices(ctx, g, prec, n, N);
+    if (T <= 0) {
+        T = (8192 + tiles - 1) / tiles;
+        if (T > kMaxSlices * kMaxGroups) T = kMaxSlices * kMaxGroups;
+        while (T > 1 && n / T < 32) --T;
+    }
+    if (T > n) T = n;
+    if (T < 1) T = 1;
+    if (!allow_groups || N > kSplitCap) T = T < kMaxSlices ? T : kMaxSlices;
+    const int64_t G = (T + kMaxSlices - 1) / kMaxSlices;
+    int64_t S = (T + G - 1) / G;
+    while (S > 1 && tiles * kWave * S * G >= (int64_t{1} << 32)) --S;
+    return Split{static_cast<int>(S), static_cast<int>(G)};
+}
+
+int choose_slices(const smc_ctx_s* ctx, const GmmDev& g, int prec, int64_t n, int64_t N) {
+    return choose_split(ctx, g, prec, n, N, false).slices;
+}
+
+// Slices of the MFMA form: the override or table entry clamped to its limits,
+// else its own built-in choice.
+int choose_dd_slices(const smc_ctx_s* ctx, const GmmDev& g, int64_t n, int64_t N) {
+    int64_t T = ctx->slices_override;
+    if (T <= 0) T = table_slices(ctx, g, SMC_PREC_BF16X3, n, N);
+    return T > 0 ? dd_clamp_slices(n, T) : dd_slices(n, N);
 }
 
 int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
@@ -238,7 +271,9 @@ int smc_create(smc_ctx* out, int device) {
     const size_t b_dd = align_up(sizeof(double) * 2 * kMaxChunks);
     const size_t b_st = align_up(sizeof(int));
     const size_t b_state = align_up(sizeof(StepState));
-    const size_t total = b_part + b_sq + b_dd + b_st + b_state;
+    const size_t b_mv = align_up(sizeof(double) * kMaxGroups * kSplitCap);
+    const size_t b_anc = align_up(sizeof(int) * kSplitCap);
+    const size_t total = b_part + b_sq + b_dd + b_st + b_state + b_mv + b_anc;
     void* p = nullptr;
     if (hipMalloc(&p, total) != hipSuccess) {
         delete ctx;
@@ -256,6 +291,8 @@ int smc_create(smc_ctx* out, int device) {
     ctx->sc.dd_part = reinterpret_cast<double*>(c + b_part + b_sq);
     ctx->sc.status = reinterpret_cast<int*>(c + b_part + b_sq + b_dd);
     ctx->sc.state = reinterpret_cast<StepState*>(c + b_part + b_sq + b_dd + b_st);
+    ctx->sc.mv_part = reinterpret_cast<double*>(c + b_part + b_sq + b_dd + b_st + b_state);
+    ctx->sc.mv_anc = reinterpret_cast<int*>(c + b_part + b_sq + b_dd + b_st + b_state + b_mv);
     *out = ctx;
     return SMC_OK;
 }
@@ -303,8 +340,23 @@ int smc_check(smc_ctx ctx, void* stream) {
 
 int smc_set_slices(smc_ctx ctx, int32_t slices) {
     if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
-    if (slices < 0 || slices > kMaxSlices) return fail(SMC_ERR_INVALID_ARG, "slices in 0..16");
+    if (slices < 0 || slices > kMaxSlices * kMaxGroups)
+        return fail(SMC_ERR_INVALID_ARG, "slices in 0..128");
     ctx->slices_override = slices;
+    return SMC_OK;
+}
+
+int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t count) {
+    if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
+    if (count < 0 || (count > 0 && !rules)) return fail(SMC_ERR_INVALID_ARG, "bad rule array");
+    for (int32_t i = 0; i < count; ++i) {
+        const smc_launch_rule& r = rules[i];
+        if (r.slices < 1 || r.slices > kMaxSlices * kMaxGroups)
+            return fail(SMC_ERR_INVALID_ARG, "rule slices in 1..128");
+        if (r.n_lo > r.n_hi || r.N_lo > r.N_hi || r.k < 0 || r.d < 0 || r.prec < -1)
+            return fail(SMC_ERR_INVALID_ARG, "rule ranges are empty or fields negative");
+    }
+    ctx->table.assign(rules, rules + count);
     return SMC_OK;
 }
 
@@ -323,12 +375,12 @@ int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
         hipError_t e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
         if (e == hipSuccess)
             e = launch_dd_loglik(g, ctx->sc.mm_rows, n, theta, N, ctx->sc.mm_cols, ctx->sc.mm_part,
-                                 dd_slices(n, N), loglik, ctx->sc.status, s);
+                                 choose_dd_slices(ctx, g, n, N), loglik, ctx->sc.status, s);
         if (e != hipSuccess) return hip_fail(e, "MFMA loglik launch");
         return SMC_OK;
     }
     const hipError_t e = launch_loglik(g, y, n, theta, N, prec, loglik,
-                                       choose_slices(ctx, n, N), ctx->sc.status, s);
+                                       choose_slices(ctx, g, prec, n, N), ctx->sc.status, s);
     if (e != hipSuccess) return hip_fail(e, "loglik launch");
     return SMC_OK;
 }
@@ -372,14 +424,14 @@ int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
             e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, N, beta_vec,
                                host_src(static_cast<int>(step), beta, 0.0), step_sd, seed, move,
                                n_accept, ctx->sc.mm_cols, ctx->sc.mm_prop, ctx->sc.mm_part,
-                               dd_slices(n, N), ctx->sc.status, MoveStep{}, s);
+                               choose_dd_slices(ctx, g, n, N), ctx->sc.status, MoveStep{}, s);
         if (e != hipSuccess) return hip_fail(e, "MFMA rwmh launch");
         return SMC_OK;
     }
     const hipError_t e = launch_rwmh(g, y, n, theta, loglik, N, beta_vec,
                                      host_src(static_cast<int>(step), beta, 0.0), step_sd, seed,
-                                     move, prec, n_accept, choose_slices(ctx, n, N),
-                                     ctx->sc.status, MoveStep{}, as_stream(stream));
+                                     move, prec, n_accept, choose_split(ctx, g, prec, n, N, true),
+                                     ctx->sc, MoveStep{}, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     return SMC_OK;
 }
@@ -450,8 +502,8 @@ int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, 
     if (parity != 0 && parity != 1) return fail(SMC_ERR_INVALID_ARG, "parity is 0 or 1");
     if (iter > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "iter must fit in 32 bits");
     const hipError_t e = launch_exchange(theta, loglik, beta, M, kd, 2, parity, wrap ? 1 : 0,
-                                         seed, host_src(static_cast<int>(iter), 0, 0), n_swap,
-                                         as_stream(stream));
+                                         seed, host_src(static_cast<int>(iter), 0, 0), nullptr,
+                                         n_swap, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "exchange launch");
     return SMC_OK;
 }
@@ -510,7 +562,7 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
         if (e == hipSuccess) e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
         if (e != hipSuccess) return hip_fail(e, "gather launch");
     }
-    const int S = choose_slices(ctx, n, N);
+    const Split sp = choose_split(ctx, g, prec, n, N, true);
     for (int m = 0; m < n_moves; ++m) {
         MoveStep ms{};
         if (m == 0) {
@@ -535,11 +587,11 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
         if (mfma)
             e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta_out, loglik_out, N, nullptr, later,
                                step_sd, seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
-                               ctx->sc.mm_prop, ctx->sc.mm_part, dd_slices(n, N), ctx->sc.status,
-                               ms, s);
+                               ctx->sc.mm_prop, ctx->sc.mm_part, choose_dd_slices(ctx, g, n, N),
+                               ctx->sc.status, ms, s);
         else
             e = launch_rwmh(g, y, n, theta_out, loglik_out, N, nullptr, later, step_sd, seed,
-                            static_cast<uint32_t>(m), prec, n_accept, S, ctx->sc.status, ms, s);
+                            static_cast<uint32_t>(m), prec, n_accept, sp, ctx->sc, ms, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }
     return SMC_OK;
@@ -561,8 +613,14 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
     if (!(step_sd >= 0.0) || !isfinite(step_sd))
         return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
     const hipStream_t s = as_stream(stream);
+    // the move reads the iteration from the caller's counter and records it in
+    // the step state; the exchange reads that record and advances the counter
     StepSrc src{};
     src.t_dev = it_dev;
+    StepSrc later{};
+    later.t_dev = &ctx->sc.state->t;
+    MoveStep ms{};
+    ms.t_out = &ctx->sc.state->t;
     hipError_t e;
     if (prec == SMC_PREC_BF16X3) {
         if ((r = ensure_mm_scratch(ctx, n, M, s))) return r;
@@ -570,17 +628,15 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
         if (e == hipSuccess)
             e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, M, beta, src, step_sd, seed, 0,
                                n_accept, ctx->sc.mm_cols, ctx->sc.mm_prop, ctx->sc.mm_part,
-                               dd_slices(n, M), ctx->sc.status, MoveStep{}, s);
+                               choose_dd_slices(ctx, g, n, M), ctx->sc.status, ms, s);
     } else {
         e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec, n_accept,
-                        choose_slices(ctx, n, M), ctx->sc.status, MoveStep{}, s);
+                        choose_split(ctx, g, prec, n, M, true), ctx->sc, ms, s);
     }
     if (e != hipSuccess) return hip_fail(e, "rwmh launch");
-    e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed, src,
-                        n_swap, s);
+    e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed,
+                        later, it_dev, n_swap, s);
     if (e != hipSuccess) return hip_fail(e, "exchange launch");
-    e = launch_counter_inc(it_dev, s);
-    if (e != hipSuccess) return hip_fail(e, "counter launch");
     return SMC_OK;
 }
 

@@ -306,6 +306,8 @@ k_dd_accept(const double* __restrict__ part, int S, int N, int n,
     constexpr int KD = K * kDdDim;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t step = static_cast<uint32_t>(step_index(src));
+    if (ms.t_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+        *ms.t_out = static_cast<int>(step);
     bool acc = false;
     if (p < N) {
         double tot = part[p];
@@ -327,14 +329,17 @@ double s2_of(const GmmDev& g) { return g.inv2s2 * kLog2e; }
 
 int64_t dd_padded_rows(int64_t n) { return ((n + kTileRows - 1) / kTileRows) * kTileRows; }
 
-int dd_slices(int64_t n, int64_t N) {
-    const int64_t groups = (N + 63) / 64;
-    int64_t S = (2048 + groups - 1) / groups;
-    if (S > 16) S = 16;
+int dd_clamp_slices(int64_t n, int64_t S) {
     const int64_t tiles = dd_padded_rows(n) / kTileRows;
+    if (S > 16) S = 16;
     if (S > tiles) S = tiles;
     if (S < 1) S = 1;
     return static_cast<int>(S);
+}
+
+int dd_slices(int64_t n, int64_t N) {
+    const int64_t groups = (N + 63) / 64;
+    return dd_clamp_slices(n, (2048 + groups - 1) / groups);
 }
 
 bool dd_supported(int k, int d) { return d == kDdDim && (k == 1 || k == 2 || k == 4 || k == 8); }

@@ -143,12 +143,11 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
                                                 int* anc, double* offh, double* offl) {
     const int lane = lane_id();
     if (wave_id() == 0) {
+        // two passes over the lane's chunk totals (sum, then running offsets)
+        // keep the register footprint of this prologue small
         constexpr int per = kMaxChunks / kWave;
-        dd loc[per];
         dd run = dd_zero();
-#pragma unroll
         for (int q = 0; q < per; ++q) {
-            loc[q] = run;
             const int c = lane * per + q;
             if (c < ms.nchunks) run = dd_add(run, dd{ms.chunk_tot[2 * c], ms.chunk_tot[2 * c + 1]});
         }
@@ -160,11 +159,11 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
         }
         dd excl{__shfl_up(inc.hi, 1, kWave), __shfl_up(inc.lo, 1, kWave)};
         if (lane == 0) excl = dd_zero();
-#pragma unroll
         for (int q = 0; q < per; ++q) {
-            const dd o = dd_add(excl, loc[q]);
-            offh[lane * per + q] = o.hi;
-            offl[lane * per + q] = o.lo;
+            const int c = lane * per + q;
+            offh[c] = excl.hi;
+            offl[c] = excl.lo;
+            if (c < ms.nchunks) excl = dd_add(excl, dd{ms.chunk_tot[2 * c], ms.chunk_tot[2 * c + 1]});
         }
     }
     __syncthreads();

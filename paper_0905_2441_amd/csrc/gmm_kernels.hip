@@ -62,7 +62,8 @@ template <int K, int D, int PREC>
 __global__ void __launch_bounds__(1024)
 k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        const double* __restrict__ beta_vec, StepSrc src, double sd, uint64_t seed,
-       uint32_t move, GmmDev g, unsigned long long* n_acc, int* status, MoveStep ms) {
+       uint32_t move, GmmDev g, unsigned long long* n_acc, int* status, MoveStep ms, int G,
+       double* __restrict__ part, int* __restrict__ anc_out) {
     constexpr int KD = K * D;
     __shared__ double red[kMaxSlices][kWave];
     __shared__ int anc[kWave];
@@ -70,11 +71,17 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
-    const int p = blockIdx.x * kWave + lane;
+    const int tile = static_cast<int>(blockIdx.x) / G;
+    const int grp = static_cast<int>(blockIdx.x) - tile * G;
+    const int p = tile * kWave + lane;
     const int pc = p < N ? p : N - 1;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    const int64_t nsl = static_cast<int64_t>(S) * G;
+    const int sl = grp * S + w;
+    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / nsl));
+    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / nsl));
     const uint32_t step = static_cast<uint32_t>(step_index(src));
+    if (ms.t_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+        *ms.t_out = static_cast<int>(step);
     const bool fused = (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
     if (fused) fused_ancestors(ms, N, step, pc, anc, offh, offl);
     const MoveSource srcs = move_source(ms, theta, l);
@@ -91,6 +98,16 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     __syncthreads();
     if (w != 0) return;
 
+    if (G > 1) {
+        // this group's share; k_rwmh_accept adds the groups and decides
+        if (p < N) {
+            double tot = red[0][lane];
+            for (int s = 1; s < S; ++s) tot += red[s][lane];
+            part[static_cast<size_t>(grp) * N + p] = tot;
+            if (grp == 0 && fused) anc_out[p] = a;
+        }
+        return;
+    }
     bool acc = false;
     if (p < N) {
         double tot = red[0][lane];
@@ -101,6 +118,41 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
+        atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
+}
+
+// Second half of a move whose tile data were split over G workgroups: one
+// thread per particle adds the G partial sums in group order, re-forms the same
+// proposal (same counter, same arithmetic) and takes the MH decision.
+template <int KD, int PREC>
+__global__ void __launch_bounds__(256)
+k_rwmh_accept(int n, double* theta, double* l, int N, const double* __restrict__ beta_vec,
+              StepSrc src, double sd, uint64_t seed, uint32_t move, GmmDev g,
+              unsigned long long* n_acc, int* status, MoveStep ms, int G,
+              const double* __restrict__ part, const int* __restrict__ anc_in) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t step = static_cast<uint32_t>(step_index(src));
+    bool acc = false;
+    if (p < N) {
+        const bool fused =
+            (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
+        const MoveSource srcs = move_source(ms, theta, l);
+        const int a = fused ? anc_in[p] : p;
+        double pr[KD];
+        {
+            double z[KD];
+            normals<KD>(seed, static_cast<uint32_t>(p), step, kProp, move, z);
+#pragma unroll
+            for (int c = 0; c < KD; ++c) pr[c] = srcs.th[static_cast<size_t>(c) * N + a] + sd * z[c];
+        }
+        double tot = part[p];
+        for (int q = 1; q < G; ++q) tot += part[static_cast<size_t>(q) * N + p];
+        const double l_prop = finish_loglik<PREC>(tot, n, g);
+        acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
+                              beta_vec, src, step, seed, move, g, status, ms);
+    }
+    const unsigned long long mask = __ballot(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0 && n_acc != nullptr && mask != 0ull)
         atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
 }
 
@@ -168,24 +220,37 @@ hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const doubl
 hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
                        int64_t N, const double* beta_vec, StepSrc src, double sd,
                        uint64_t seed, uint32_t move, int prec,
-                       unsigned long long* n_accept, int slices, int* status, MoveStep ms,
+                       unsigned long long* n_accept, Split sp, const Scratch& sc, MoveStep ms,
                        hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
-    const dim3 block(static_cast<unsigned>(kWave * slices));
+    const int G = sp.groups;
+    if (G < 1 || G > kMaxGroups || sp.slices < 1 || sp.slices > kMaxSlices ||
+        (G > 1 && N > kSplitCap))
+        return hipErrorInvalidValue;
+    const int64_t tiles = (N + kWave - 1) / kWave;
+    const dim3 grid(static_cast<unsigned>(tiles * G));
+    const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+    const dim3 agrid(static_cast<unsigned>((N + 255) / 256));
+    const int n32 = static_cast<int>(n), N32 = static_cast<int>(N);
+#define SMC_MOVE(K, D, P)                                                                     \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_rwmh<K, D, P>), grid, block, 0, s, y, n32, theta, l, N32,       \
+                           beta_vec, src, sd, seed, move, g, n_accept, sc.status, ms, G,      \
+                           sc.mv_part, sc.mv_anc);                                            \
+        if (G > 1)                                                                            \
+            hipLaunchKernelGGL((k_rwmh_accept<K * D, P>), agrid, dim3(256), 0, s, n32, theta, \
+                               l, N32, beta_vec, src, sd, seed, move, g, n_accept, sc.status, \
+                               ms, G, static_cast<const double*>(sc.mv_part),                 \
+                               static_cast<const int*>(sc.mv_anc));                           \
+    } while (0)
 #define SMC_CASE(K, D)                                                                        \
     if (g.k == K && g.d == D) {                                                               \
-        if (prec == SMC_PREC_FP32)                                                            \
-            hipLaunchKernelGGL((k_rwmh<K, D, SMC_PREC_FP32>), grid, block, 0, s, y,           \
-                               static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,  \
-                               src, sd, seed, move, g, n_accept, status, ms);                 \
-        else                                                                                  \
-            hipLaunchKernelGGL((k_rwmh<K, D, SMC_PREC_FP64>), grid, block, 0, s, y,           \
-                               static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,  \
-                               src, sd, seed, move, g, n_accept, status, ms);                 \
+        if (prec == SMC_PREC_FP32) SMC_MOVE(K, D, SMC_PREC_FP32);                             \
+        else SMC_MOVE(K, D, SMC_PREC_FP64);                                                   \
         return hipGetLastError();                                                             \
     }
     SMC_KD_CASES(SMC_CASE)
 #undef SMC_CASE
+#undef SMC_MOVE
     return hipErrorInvalidValue;
 }
 

@@ -8,6 +8,8 @@
 namespace smc {
 
 constexpr int kMaxSlices = 16;          // waves per workgroup in the likelihood kernels
+constexpr int kMaxGroups = 8;           // workgroups sharing one 64-particle tile's data
+constexpr int kSplitCap = 32768;        // largest N whose move may use several groups
 constexpr int kRedBlock = 256;          // threads per block in the weight/resample kernels
 constexpr int kMaxRedBlocks = 1024;     // grid cap of the grid-stride weight kernels
 constexpr int kScanPerThread = 8;       // W elements per thread in the CDF scan
@@ -65,6 +67,8 @@ struct Scratch {
     double* mm_prop;           // MFMA path: proposals [64][mm_n_cap]
     double* mm_part;           // MFMA path: per-slice partial sums [16][mm_n_cap]
     int64_t mm_rows_cap, mm_n_cap;
+    double* mv_part;           // split move: partial sums [kMaxGroups][kSplitCap]
+    int* mv_anc;               // split move: ancestors of the fused resampling [kSplitCap]
 };
 
 // How kernels obtain the step / iteration index and the inverse temperature:
@@ -114,6 +118,16 @@ struct MoveStep {
     const double* chunk_tot;   // [2 * nchunks] (hi, lo)
     int chunk, nchunks;
     uint64_t seed;
+    int* t_out;                // nullable: the move records its step index here
+};
+
+// Launch shape of a VALU move for one 64-particle tile: `groups` workgroups of
+// `slices` waves split the observations into groups * slices contiguous slices.
+// With groups > 1 each workgroup writes its partial sums to scratch and a
+// per-particle kernel completes the move.
+struct Split {
+    int slices;
+    int groups;
 };
 
 // How the CDF kernels obtain the normalised weights: read W, or form
@@ -158,7 +172,7 @@ hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const doubl
 hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
                        int64_t N, const double* beta_vec, StepSrc src, double sd,
                        uint64_t seed, uint32_t move, int prec,
-                       unsigned long long* n_accept, int slices, int* status, MoveStep ms,
+                       unsigned long long* n_accept, Split sp, const Scratch& sc, MoveStep ms,
                        hipStream_t s);
 hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,
                         hipStream_t s);
@@ -167,6 +181,7 @@ bool supported_kd(int k, int d, int prec);
 // MFMA (split-BF16) form of the d-dimensional likelihood and move.
 int64_t dd_padded_rows(int64_t n);
 int dd_slices(int64_t n, int64_t N);
+int dd_clamp_slices(int64_t n, int64_t S);   // to 1..min(16, 16-row data tiles)
 bool dd_supported(int k, int d);
 hipError_t launch_dd_prep(const GmmDev& g, const float* y, int64_t n, __bf16* A, hipStream_t s);
 hipError_t launch_dd_loglik(const GmmDev& g, const __bf16* A, int64_t n, const double* theta,
@@ -197,7 +212,8 @@ hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t s
                            int copy_when_skipped, hipStream_t s);
 hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
                            int32_t kd, int parity_mode, int parity_host, int wrap,
-                           uint64_t seed, StepSrc src, unsigned* n_swap, hipStream_t s);
+                           uint64_t seed, StepSrc src, int* t_advance, unsigned* n_swap,
+                           hipStream_t s);
 // Fused tempering step pieces: reweight partials -> step_mid (combine, decide,
 // CDF chunks) -> moves (ancestor search fused into the first move).
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
@@ -211,7 +227,6 @@ hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, in
                             hipStream_t s);
 hipError_t launch_reweight_partial(const Scratch& sc, double* logw, const double* l, int64_t N,
                                    StepSrc src, hipStream_t s);
-hipError_t launch_counter_inc(int* counter, hipStream_t s);
 hipError_t launch_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
                             uint32_t purpose, uint32_t move, uint32_t* out, hipStream_t s);
 hipError_t launch_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t step,

@@ -314,8 +314,12 @@ k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, ui
 __global__ void __launch_bounds__(kRedBlock)
 k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __restrict__ beta,
            int M, int kd, int parity_mode, int parity_host, int wrap, uint64_t seed,
-           StepSrc src, unsigned* n_swap) {
+           StepSrc src, int* t_advance, unsigned* n_swap) {
     const uint32_t it = static_cast<uint32_t>(step_index(src));
+    // the iteration index is read from a snapshot, so the caller's counter can
+    // be advanced here without racing the other blocks' reads
+    if (t_advance != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+        *t_advance = static_cast<int>(it) + 1;
     int parity;
     if (parity_mode == 0) parity = static_cast<int>(it & 1u);
     else if (parity_mode == 1) parity = static_cast<int>(draw(seed, 0, 0, it, kParity, 0).w0 >> 31);
@@ -346,10 +350,6 @@ k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __r
         }
         if (n_swap) atomicAdd(n_swap, 1u);
     }
-}
-
-__global__ void k_counter_inc(int* c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c += 1;
 }
 
 __global__ void k_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
@@ -452,12 +452,13 @@ hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t s
 
 hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t M,
                            int32_t kd, int parity_mode, int parity_host, int wrap,
-                           uint64_t seed, StepSrc src, unsigned* n_swap, hipStream_t s) {
+                           uint64_t seed, StepSrc src, int* t_advance, unsigned* n_swap,
+                           hipStream_t s) {
     const int64_t pairs = M / 2 + 1;
     const int g = static_cast<int>((pairs + kRedBlock - 1) / kRedBlock);
     hipLaunchKernelGGL(k_exchange, dim3(g), dim3(kRedBlock), 0, s, theta, l, beta,
                        static_cast<int>(M), kd, parity_mode, parity_host, wrap, seed, src,
-                       n_swap);
+                       t_advance, n_swap);
     return hipGetLastError();
 }
 
@@ -495,11 +496,6 @@ hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, in
                             hipStream_t s) {
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
     hipLaunchKernelGGL(k_publish_w, dim3(g), dim3(kRedBlock), 0, s, W, logw, static_cast<int>(N), sc);
-    return hipGetLastError();
-}
-
-hipError_t launch_counter_inc(int* counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_counter_inc, dim3(1), dim3(64), 0, s, counter);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ exchange moves on one partition of adjacent pairs.
 
 from __future__ import annotations
 
-from typing import Optional
+from typing import Dict, Optional
 
 import numpy as np
 import torch
@@ -159,7 +159,7 @@ class PTSampler:
             self.n_accept = torch.zeros(1, dtype=torch.int64, device="cuda")
             self.n_swap = torch.zeros(1, dtype=torch.int32, device="cuda")
         ctx.reserve(self.M, model.kd, self.y.shape[0] if prec == "bf16x3" else 0)
-        self.graph: Optional[Graph] = None
+        self.graphs: Dict[int, Graph] = {}
 
     def init(self):
         with torch.cuda.stream(self.stream):
@@ -177,21 +177,31 @@ class PTSampler:
                      self.n_accept, self.n_swap, stream=self.stream)
 
     def capture(self, iterations: int = 1) -> Graph:
-        if self.graph is None:
+        """A graph of `iterations` consecutive iterations (the iteration index
+        lives on the device, so one graph serves every position in the run)."""
+        g = self.graphs.get(iterations)
+        if g is None:
             g = Graph(self.ctx, self.stream)
             with g:
                 for _ in range(iterations):
                     self.enqueue_iteration()
-            self.graph = g
-        return self.graph
+            self.graphs[iterations] = g
+        return g
 
-    def run(self, iterations: int, graph: bool = True):
-        self.init()
-        for _ in range(iterations):
+    def advance(self, iterations: int, graph: bool = True, iters_per_graph: int = 1):
+        done = 0
+        while done < iterations:
+            c = min(int(iters_per_graph), iterations - done)
             if graph:
-                self.capture().launch()
+                self.capture(c).launch()
             else:
-                self.enqueue_iteration()
+                for _ in range(c):
+                    self.enqueue_iteration()
+            done += c
+
+    def run(self, iterations: int, graph: bool = True, iters_per_graph: int = 1):
+        self.init()
+        self.advance(iterations, graph, iters_per_graph)
         self.stream.synchronize()
         self.ctx.check(self.stream)
         return self.results()

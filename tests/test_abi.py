@@ -28,7 +28,7 @@ def test_header_declares_the_hot_path_calls():
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
-        pytest.fail("libsmcgpu.so is not built (run python -m paper_0905_2441_amd.build)")
+        pytest.fail("libsmcgpu.so is not built (run python paper_0905_2441_amd/build.py)")
     lib = ctypes.CDLL(LIB)
     for name in declared_functions():
         assert hasattr(lib, name), name

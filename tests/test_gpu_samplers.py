@@ -66,6 +66,25 @@ def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph):
     assert np.max(np.abs(r["logw"] - ref["logw"])) <= 1e-9
 
 
+def test_smc_split_tiles_match_oracle(smc, ctx, small, small_oracle):
+    """The small run with each tile's data spread over 3 workgroups per move
+    (42 slices of 2-3 observations); the fused ancestor search then runs in every
+    workgroup and the decision kernel reads group 0's ancestors."""
+    cfg, y, betas = small
+    announce("smc small fp64 split tiles")
+    ctx.set_slices(40)
+    try:
+        r = _sampler(smc, ctx, cfg, y, betas, "fp64").run(graph=True)
+    finally:
+        ctx.set_slices(0)
+    ref = small_oracle
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"]))
+    assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+    assert np.max(np.abs(r["W"] - ref["W"])) <= 1e-14
+
+
 @pytest.mark.parametrize("n_moves,ess_frac", [(0, 0.5), (3, 0.5), (1, 0.0), (2, 1.0)])
 def test_smc_step_variants_match_oracle(smc, ctx, small, n_moves, ess_frac):
     """No moves (pure reweight/resample), several moves per step, no resampling
@@ -146,16 +165,23 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     print(f"fp32 flipped decisions: {flips} of {decisions}")
 
 
-def test_pt_matches_oracle(smc, ctx):
-    announce("pt small fp64")
+@pytest.mark.parametrize("slices,iters_per_graph", [(0, 1), (24, 7)])
+def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph):
+    """slices = 24 spreads each tile over 2 workgroups; 7 iterations per graph
+    leave a ragged last graph (25 = 3 * 7 + 4)."""
+    announce(f"pt small fp64 slices={slices} iters_per_graph={iters_per_graph}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     y = make_mixture_data(300, mu, 0.55, seed=3)
     M, iters = 128, 25
     betas = pt_betas(M, 4)
     g = smc.Gmm.equal_weights(4, 1, 0.55)
     om = oracle_model(g)
-    s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=103, parity_mode=0, wrap=False, prec="fp64")
-    r = s.run(iters, graph=True)
+    ctx.set_slices(slices)
+    try:
+        s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=103, parity_mode=0, wrap=False, prec="fp64")
+        r = s.run(iters, graph=True, iters_per_graph=iters_per_graph)
+    finally:
+        ctx.set_slices(0)
     ref = osmc.pt_run(y, om, betas, iters, 0.5, 103, parity_mode="alternate", wrap=False)
     assert r["it"] == iters
     assert r["swaps"] == ref["swaps"]

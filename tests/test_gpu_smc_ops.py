@@ -136,9 +136,12 @@ def test_resample_gather_and_predicate(smc, ctx):
 
 # ------------------------------------------------------------------ RW-MH move
 
+@pytest.mark.parametrize("slices", [0, 40, 128])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_rwmh_move_matches_oracle(smc, ctx, prec):
-    announce(f"rwmh {prec}")
+def test_rwmh_move_matches_oracle(smc, ctx, prec, slices):
+    """slices 40 and 128 spread each 64-particle tile over 3 and 8 workgroups
+    (partials in scratch, decision in a second kernel)."""
+    announce(f"rwmh {prec} slices={slices}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     y = make_mixture_data(200, mu, 0.55, seed=2)
     g = smc.Gmm.equal_weights(4, 1, 0.55)
@@ -149,9 +152,13 @@ def test_rwmh_move_matches_oracle(smc, ctx, prec):
     tt, lt = _cuda(th), _cuda(l)
     acc = torch.zeros(1, dtype=torch.int64).cuda()
     beta = 0.37
-    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, beta, 0.5, seed=11, step=6,
-                      move=2, prec=prec, n_accept=acc)
-    ctx.check()
+    ctx.set_slices(slices)
+    try:
+        smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, beta, 0.5, seed=11, step=6,
+                          move=2, prec=prec, n_accept=acc)
+        ctx.check()
+    finally:
+        ctx.set_slices(0)
     th_ref, l_ref, a_ref = osmc.rwmh_move(th, l, y, om, beta, 0.5, 11, 6, 2)
     got_th, got_l = tt.cpu().numpy(), lt.cpu().numpy()
     a_got = np.any(got_th != th, axis=0)
@@ -185,6 +192,89 @@ def test_rwmh_per_chain_beta_and_box_prior(smc, ctx):
     assert np.max(np.abs(tt.cpu().numpy() - th_ref)) <= 1e-12
     assert rel_err(lt.cpu().numpy(), l_ref).max() <= 1e-12
     assert np.all(tt.cpu().numpy() <= 10.0) and np.all(tt.cpu().numpy() >= -10.0)
+
+
+def test_launch_table_selects_slices(smc, ctx):
+    """A matching launch rule gives the same bits as the same explicit slice
+    count; a non-matching rule leaves the built-in choice; bad rules raise."""
+    announce("launch table")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = _cuda(make_mixture_data(200, mu, 0.55, seed=2), torch.float32)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    th0 = _cuda(theta_prior_draws(4000, 4, 1, seed=3))
+    l0 = torch.zeros(4000, dtype=torch.float64, device="cuda")
+
+    def run():
+        th, l = th0.clone(), l0.clone()
+        smc.smc_loglik(ctx, g, y, th, "fp32", out=l)
+        smc.smc_rwmh_move(ctx, g, y, th, l, 0.5, 0.5, seed=3, step=2, prec="fp32")
+        torch.cuda.synchronize()
+        return th.cpu().numpy(), l.cpu().numpy()
+
+    base = run()
+    ctx.set_slices(40)
+    try:
+        forced = run()
+    finally:
+        ctx.set_slices(0)
+    rule = dict(k=4, d=1, prec="fp32", slices=40, n_lo=100, n_hi=300, N_lo=1, N_hi=5000)
+    try:
+        ctx.set_launch_table([rule])
+        tabled = run()
+        ctx.set_launch_table([dict(rule, n_lo=201)])
+        missed = run()
+        with pytest.raises(smc.SmcError):
+            ctx.set_launch_table([dict(rule, slices=129)])
+        with pytest.raises(smc.SmcError):
+            ctx.set_launch_table([dict(rule, N_lo=6000)])
+    finally:
+        ctx.set_launch_table([])
+    assert all(np.array_equal(a, b) for a, b in zip(tabled, forced))
+    assert all(np.array_equal(a, b) for a, b in zip(missed, base))
+    assert not np.array_equal(forced[1], base[1])          # the slicing changed the sums
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rwmh_move_pt_size_sampled(smc, ctx, prec):
+    """One move of 8192 chains at their own temperatures over n = 10000 data (the
+    population-MCMC workload, automatic launch shape: 4 workgroups per tile),
+    checked against the oracle's move on 256 sampled chains. Each chain's move
+    depends only on its own state and counter, so the sample is exact."""
+    announce(f"rwmh pt-size sampled {prec}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    n, M, kd = 10000, 8192, 4
+    y = make_mixture_data(n, mu, 0.55, seed=21)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
+    betas = pt_betas(M, 4)
+    th = np.hstack([theta_prior_draws(M // 2, 4, 1, seed=22), theta_near_posterior(M // 2, mu, seed=23)])
+    rng = np.random.default_rng(24)
+    idx = np.unique(np.concatenate([np.arange(64), rng.choice(M, 128, replace=False),
+                                    np.arange(M - 64, M)]))
+    l = np.full(M, -1.0e4)
+    l[idx] = ogmm.loglik(th[:, idx], y, om)
+    tt, lt = _cuda(th), _cuda(l)
+    sd, seed, step, move = 0.05, 31, 9, 0
+    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, 0.0, sd, seed=seed, step=step,
+                      move=move, prec=prec, beta_vec=_cuda(betas))
+    ctx.check()
+    uidx = idx.astype(np.uint64)
+    prop = th[:, idx] + sd * opx.normals(seed, uidx, step, opx.PROP, move, kd)
+    l_prop = ogmm.loglik(prop, y, om)
+    la = osmc.rwmh_log_alpha(betas[idx], l[idx], l_prop, ogmm.log_prior(th[:, idx], om),
+                             ogmm.log_prior(prop, om))
+    acc_ref = (la >= 0.0) | (np.log(opx.uniforms_open(seed, uidx, step, opx.ACC, move)) < la)
+    got_th, got_l = tt.cpu().numpy()[:, idx], lt.cpu().numpy()[idx]
+    acc_got = np.any(got_th != th[:, idx], axis=0)
+    flips = int(np.sum(acc_got != acc_ref))
+    assert flips == 0 if prec == "fp64" else flips <= 2
+    assert 10 < int(acc_ref.sum()) < idx.size - 10          # both outcomes occur
+    same = acc_got == acc_ref
+    want_th = np.where(acc_ref, prop, th[:, idx])
+    want_l = np.where(acc_ref, l_prop, l[idx])
+    assert np.max(np.abs(got_th[:, same] - want_th[:, same])) <= 1e-12
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert rel_err(got_l[same], want_l[same]).max() <= tol
 
 
 # ------------------------------------------------------------------ exchange
