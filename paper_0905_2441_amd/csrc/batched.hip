@@ -141,6 +141,7 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
          GmmDev g, unsigned long long* n_acc, int* status) {
     constexpr int KD = K;
     __shared__ double red[kBatchWaves][kWave];
+    __shared__ double prs[KD][kWave];
     __shared__ int item_sh;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
@@ -166,12 +167,8 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
         int S = n / 32;
         S = S < 1 ? 1 : (S > kBatchWaves ? kBatchWaves : S);
         double pr[KD];
-        {
-            double z[KD];
-            normals<KD>(rd.seed, static_cast<uint32_t>(pc), step, kProp, move, z);
-#pragma unroll
-            for (int c = 0; c < KD; ++c) pr[c] = th_src[static_cast<size_t>(c) * N + pc] + sd * z[c];
-        }
+        block_proposals<KD>(rd.seed, static_cast<uint32_t>(pc), step, move, th_src, N, pc, sd, w,
+                            kBatchWaves, prs, pr);
         double part = 0.0;
         if (w < S) {
             const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));

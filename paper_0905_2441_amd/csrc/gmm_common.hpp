@@ -118,6 +118,32 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
     }
 }
 
+// Random-walk proposals th_src[:, a] + sd * z for the 64 particles of a
+// workgroup. The ceil(KD/2) Box-Muller pairs of each particle are shared out
+// over the block's nw waves (pair q: Philox block q/2, words 0-1 for even q and
+// 2-3 for odd q, normals 2q and 2q+1) and exchanged through LDS, so no wave
+// repeats another's draws. Cooperative: every thread of the block calls it (it
+// contains one barrier); prs holds KD rows of 64 doubles.
+template <int KD>
+__device__ __forceinline__ void block_proposals(uint64_t seed, uint32_t index, uint32_t step,
+                                                uint32_t move, const double* th_src, int N,
+                                                int a, double sd, int w, int nw,
+                                                double (*prs)[kWave], double (&pr)[KD]) {
+    const int lane = lane_id();
+    for (int q = w; q < (KD + 1) / 2; q += nw) {
+        const Words4 wd = draw(seed, index, static_cast<uint32_t>(q / 2), step, kProp, move);
+        double z0, z1;
+        if (q & 1) box_muller(wd.w2, wd.w3, z0, z1);
+        else box_muller(wd.w0, wd.w1, z0, z1);
+        const int c = 2 * q;
+        prs[c][lane] = th_src[static_cast<size_t>(c) * N + a] + sd * z0;
+        if (c + 1 < KD) prs[c + 1][lane] = th_src[static_cast<size_t>(c + 1) * N + a] + sd * z1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < KD; ++c) pr[c] = prs[c][lane];
+}
+
 // Source of a move's current state for the arrays (theta, l) it writes.
 struct MoveSource {
     const double* th;

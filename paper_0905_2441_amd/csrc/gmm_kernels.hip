@@ -68,6 +68,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     __shared__ double red[kMaxSlices][kWave];
     __shared__ int anc[kWave];
     __shared__ double offh[kMaxChunks], offl[kMaxChunks];
+    __shared__ double prs[KD][kWave];
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
@@ -88,12 +89,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int a = fused ? anc[lane] : pc;
 
     double pr[KD];
-    {
-        double z[KD];
-        normals<KD>(seed, static_cast<uint32_t>(pc), step, kProp, move, z);
-#pragma unroll
-        for (int c = 0; c < KD; ++c) pr[c] = srcs.th[static_cast<size_t>(c) * N + a] + sd * z[c];
-    }
+    block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
+                        pr);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
     __syncthreads();
     if (w != 0) return;
