@@ -43,6 +43,41 @@ OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 TRANS_SLOTS = 2.0
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of the dominant kernel (the FP32 move at the headline shape, the
+# standalone launches timed below) from two rocprofv3 --pmc runs of this same
+# command: FETCH_SIZE and WRITE_SIZE in KiB per dispatch, averaged over those
+# launches, each scaled by what the counter reads for a plain 256 MiB device
+# copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them). The
+# figures belong to the kernel sources whose SHA-256 is recorded; after any
+# change to them the traffic is reported as null until it is measured again.
+MOVE_COUNTERS = {
+    "sources_sha256": None,
+    "fetch_kib": None, "fetch_scale": 2.0,
+    "write_kib": None, "write_scale": 1.0,
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0905_2441_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "paper_0905_2441_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def move_traffic():
+    """HBM bytes per launch of the dominant kernel, or None if the counters were
+    taken on other kernel sources."""
+    c = MOVE_COUNTERS
+    if c["fetch_kib"] is None or c["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 STEPS_PER_GRAPH = 10    # tempering steps per hipGraph replay
 
 
@@ -228,7 +263,8 @@ def main():
         "peak": PEAK_LANE_OPS / 1e12,
         "unit": "Tlane-op/s",
         "frac": achieved / PEAK_LANE_OPS,
-        "traffic": None,
+        "traffic": move_traffic(),
+        "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
         "kernel_ms": r32["kernel_ms"],

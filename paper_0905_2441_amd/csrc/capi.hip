@@ -629,14 +629,16 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
             e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta, loglik, M, beta, src, step_sd, seed, 0,
                                n_accept, ctx->sc.mm_cols, ctx->sc.mm_prop, ctx->sc.mm_part,
                                choose_dd_slices(ctx, g, n, M), ctx->sc.status, ms, s);
-    } else {
-        e = launch_rwmh(g, y, n, theta, loglik, M, beta, src, step_sd, seed, 0, prec, n_accept,
-                        choose_split(ctx, g, prec, n, M, true), ctx->sc, ms, s);
+        if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+        e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0,
+                            seed, later, it_dev, n_swap, s);
+        if (e != hipSuccess) return hip_fail(e, "exchange launch");
+        return SMC_OK;
     }
-    if (e != hipSuccess) return hip_fail(e, "rwmh launch");
-    e = launch_exchange(theta, loglik, beta, M, g.k * g.d, parity_mode, 0, wrap ? 1 : 0, seed,
-                        later, it_dev, n_swap, s);
-    if (e != hipSuccess) return hip_fail(e, "exchange launch");
+    e = launch_pt_iteration(g, y, n, theta, loglik, M, beta, src, later, step_sd, seed, prec,
+                            n_accept, choose_split(ctx, g, prec, n, M, true), ctx->sc, ms,
+                            parity_mode, wrap ? 1 : 0, it_dev, n_swap, s);
+    if (e != hipSuccess) return hip_fail(e, "population MCMC launch");
     return SMC_OK;
 }
 

@@ -1,0 +1,73 @@
+// Exchange moves of population MCMC (Population-based MCMC subsection):
+// adjacent chains (a, b) of the current partition swap states with
+// probability min(1, exp((beta_a - beta_b) (l_b - l_a))); the prior cancels.
+#pragma once
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace smc {
+
+// Partition parity of iteration `it`: it & 1 (alternating), one Philox bit of
+// stream (0, 0, it, PARITY, 0) (random), or a host value.
+__device__ __forceinline__ int pt_parity(int parity_mode, int parity_host, uint64_t seed,
+                                         uint32_t it) {
+    if (parity_mode == 0) return static_cast<int>(it & 1u);
+    if (parity_mode == 1) return static_cast<int>(draw(seed, 0, 0, it, kParity, 0).w0 >> 31);
+    return parity_host & 1;
+}
+
+// Slot q of the partition: the pairs (parity + 2q, parity + 2q + 1), then the
+// wrap pair (M-1, 0) when `wrap`, parity is 1 and M is even, else the chains
+// left without a partner (0 when parity is 1, M-1 when M - parity is odd) as
+// singles (b = -1). Returns false past the last slot.
+__device__ __forceinline__ bool pt_slot(int M, int parity, int wrap, int q, int& a, int& b) {
+    const int regular = (M - parity) / 2;
+    if (q < regular) {
+        a = parity + 2 * q;
+        b = a + 1;
+        return true;
+    }
+    q -= regular;
+    const bool lead = parity == 1;
+    const bool tail = ((M - parity) & 1) == 1;
+    if (wrap && lead && tail) {
+        a = M - 1;
+        b = 0;
+        return q == 0;
+    }
+    b = -1;
+    if (lead) {
+        if (q == 0) {
+            a = 0;
+            return true;
+        }
+        --q;
+    }
+    if (tail && q == 0) {
+        a = M - 1;
+        return true;
+    }
+    return false;
+}
+
+// The exchange decision of pair (a, b) with the uniform of stream
+// (a, 0, it, EXCH, 0); on acceptance the two columns of theta [kd][M] and the
+// two log-likelihoods are swapped in place. Returns whether they were.
+__device__ __forceinline__ bool pt_swap(double* theta, double* l, const double* beta, int M,
+                                        int kd, int a, int b, uint64_t seed, uint32_t it) {
+    const double la = (beta[a] - beta[b]) * (l[b] - l[a]);
+    const double u = u01_open(draw(seed, static_cast<uint32_t>(a), 0, it, kExch, 0).w0);
+    if (!(la >= 0.0 || log(u) < la)) return false;
+    const double t = l[a];
+    l[a] = l[b];
+    l[b] = t;
+    for (int c = 0; c < kd; ++c) {
+        double* r = theta + static_cast<size_t>(c) * M;
+        const double x = r[a];
+        r[a] = r[b];
+        r[b] = x;
+    }
+    return true;
+}
+
+}  // namespace smc

@@ -26,6 +26,7 @@
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.
+#include "exchange.hpp"
 #include "gmm_common.hpp"
 
 namespace smc {
@@ -118,9 +119,40 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
 }
 
-// Second half of a move whose tile data were split over G workgroups: one
-// thread per particle adds the G partial sums in group order, re-forms the same
-// proposal (same counter, same arithmetic) and takes the MH decision.
+// Second half of a move whose tile data were split over G workgroups, for
+// particle p: add the G partial sums in group order, re-form the same proposal
+// (same counter, same arithmetic) and take the MH decision.
+template <int KD, int PREC>
+__device__ __forceinline__ bool complete_split_move(int p, int n, double* theta, double* l, int N,
+                                                    const double* beta_vec, const StepSrc& src,
+                                                    uint32_t step, double sd, uint64_t seed,
+                                                    uint32_t move, const GmmDev& g, int* status,
+                                                    const MoveStep& ms, int G,
+                                                    const double* part, const int* anc_in) {
+    const bool fused = (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
+    const MoveSource srcs = move_source(ms, theta, l);
+    const int a = fused ? anc_in[p] : p;
+    double pr[KD];
+    {
+        double z[KD];
+        normals<KD>(seed, static_cast<uint32_t>(p), step, kProp, move, z);
+#pragma unroll
+        for (int c = 0; c < KD; ++c) pr[c] = srcs.th[static_cast<size_t>(c) * N + a] + sd * z[c];
+    }
+    double tot = part[p];
+    for (int q = 1; q < G; ++q) tot += part[static_cast<size_t>(q) * N + p];
+    const double l_prop = finish_loglik<PREC>(tot, n, g);
+    return rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
+                           beta_vec, src, step, seed, move, g, status, ms);
+}
+
+__device__ __forceinline__ void count_accepts(bool acc, unsigned long long* n_acc) {
+    const unsigned long long mask = __ballot(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0 && n_acc != nullptr && mask != 0ull)
+        atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
+}
+
+// One thread per particle completes a split move.
 template <int KD, int PREC>
 __global__ void __launch_bounds__(256)
 k_rwmh_accept(int n, double* theta, double* l, int N, const double* __restrict__ beta_vec,
@@ -130,27 +162,42 @@ k_rwmh_accept(int n, double* theta, double* l, int N, const double* __restrict__
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     bool acc = false;
-    if (p < N) {
-        const bool fused =
-            (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
-        const MoveSource srcs = move_source(ms, theta, l);
-        const int a = fused ? anc_in[p] : p;
-        double pr[KD];
-        {
-            double z[KD];
-            normals<KD>(seed, static_cast<uint32_t>(p), step, kProp, move, z);
-#pragma unroll
-            for (int c = 0; c < KD; ++c) pr[c] = srcs.th[static_cast<size_t>(c) * N + a] + sd * z[c];
+    if (p < N)
+        acc = complete_split_move<KD, PREC>(p, n, theta, l, N, beta_vec, src, step, sd, seed, move,
+                                            g, status, ms, G, part, anc_in);
+    count_accepts(acc, n_acc);
+}
+
+// Population-MCMC iteration after a split move: one thread per slot of the
+// iteration's partition completes the moves of its chain or pair of chains
+// and then, for a pair, takes the exchange decision on the moved states (the
+// same result as all moves followed by all exchanges: the moves are
+// independent per chain and the pairs are disjoint). The iteration index comes
+// from the step state recorded by the move; the caller's counter is advanced.
+template <int KD, int PREC>
+__global__ void __launch_bounds__(256)
+k_pt_accept_exchange(int n, double* theta, double* l, int M, const double* __restrict__ beta,
+                     StepSrc src, double sd, uint64_t seed, GmmDev g, int G,
+                     const double* __restrict__ part, int parity_mode, int wrap, int* t_advance,
+                     unsigned long long* n_acc, unsigned* n_swap, int* status) {
+    const uint32_t it = static_cast<uint32_t>(step_index(src));
+    if (t_advance != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+        *t_advance = static_cast<int>(it) + 1;
+    const int parity = pt_parity(parity_mode, 0, seed, it);
+    const MoveStep ms{};
+    int a, b;
+    bool acc_a = false, acc_b = false;
+    if (pt_slot(M, parity, wrap, blockIdx.x * blockDim.x + threadIdx.x, a, b)) {
+        acc_a = complete_split_move<KD, PREC>(a, n, theta, l, M, beta, src, it, sd, seed, 0, g,
+                                              status, ms, G, part, nullptr);
+        if (b >= 0) {
+            acc_b = complete_split_move<KD, PREC>(b, n, theta, l, M, beta, src, it, sd, seed, 0, g,
+                                                  status, ms, G, part, nullptr);
+            if (pt_swap(theta, l, beta, M, KD, a, b, seed, it) && n_swap) atomicAdd(n_swap, 1u);
         }
-        double tot = part[p];
-        for (int q = 1; q < G; ++q) tot += part[static_cast<size_t>(q) * N + p];
-        const double l_prop = finish_loglik<PREC>(tot, n, g);
-        acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
-                              beta_vec, src, step, seed, move, g, status, ms);
     }
-    const unsigned long long mask = __ballot(acc);
-    if ((threadIdx.x & (kWave - 1)) == 0 && n_acc != nullptr && mask != 0ull)
-        atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
+    count_accepts(acc_a, n_acc);
+    count_accepts(acc_b, n_acc);
 }
 
 template <int KD>
@@ -214,40 +261,92 @@ hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const doubl
     return hipErrorInvalidValue;
 }
 
+namespace {
+
+bool valid_split(const Split& sp, int64_t N) {
+    return sp.groups >= 1 && sp.groups <= kMaxGroups && sp.slices >= 1 &&
+           sp.slices <= kMaxSlices && (sp.groups == 1 || N <= kSplitCap);
+}
+
+// The likelihood half of a move (with the decision when groups == 1).
+template <int K, int D, int P>
+void launch_move_partials(const float* y, int64_t n, double* theta, double* l, int64_t N,
+                          const double* beta_vec, const StepSrc& src, double sd, uint64_t seed,
+                          uint32_t move, const GmmDev& g, unsigned long long* n_accept,
+                          const Split& sp, const Scratch& sc, const MoveStep& ms, hipStream_t s) {
+    const int64_t tiles = (N + kWave - 1) / kWave;
+    hipLaunchKernelGGL((k_rwmh<K, D, P>), dim3(static_cast<unsigned>(tiles * sp.groups)),
+                       dim3(static_cast<unsigned>(kWave * sp.slices)), 0, s, y,
+                       static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec, src, sd, seed,
+                       move, g, n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
+}
+
+}  // namespace
+
 hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
                        int64_t N, const double* beta_vec, StepSrc src, double sd,
                        uint64_t seed, uint32_t move, int prec,
                        unsigned long long* n_accept, Split sp, const Scratch& sc, MoveStep ms,
                        hipStream_t s) {
-    const int G = sp.groups;
-    if (G < 1 || G > kMaxGroups || sp.slices < 1 || sp.slices > kMaxSlices ||
-        (G > 1 && N > kSplitCap))
-        return hipErrorInvalidValue;
-    const int64_t tiles = (N + kWave - 1) / kWave;
-    const dim3 grid(static_cast<unsigned>(tiles * G));
-    const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+    if (!valid_split(sp, N)) return hipErrorInvalidValue;
     const dim3 agrid(static_cast<unsigned>((N + 255) / 256));
-    const int n32 = static_cast<int>(n), N32 = static_cast<int>(N);
-#define SMC_MOVE(K, D, P)                                                                     \
-    do {                                                                                      \
-        hipLaunchKernelGGL((k_rwmh<K, D, P>), grid, block, 0, s, y, n32, theta, l, N32,       \
-                           beta_vec, src, sd, seed, move, g, n_accept, sc.status, ms, G,      \
-                           sc.mv_part, sc.mv_anc);                                            \
-        if (G > 1)                                                                            \
-            hipLaunchKernelGGL((k_rwmh_accept<K * D, P>), agrid, dim3(256), 0, s, n32, theta, \
-                               l, N32, beta_vec, src, sd, seed, move, g, n_accept, sc.status, \
-                               ms, G, static_cast<const double*>(sc.mv_part),                 \
-                               static_cast<const int*>(sc.mv_anc));                           \
+#define SMC_MOVE(K, D, P)                                                                      \
+    do {                                                                                       \
+        launch_move_partials<K, D, P>(y, n, theta, l, N, beta_vec, src, sd, seed, move, g,     \
+                                      n_accept, sp, sc, ms, s);                                \
+        if (sp.groups > 1)                                                                     \
+            hipLaunchKernelGGL((k_rwmh_accept<K * D, P>), agrid, dim3(256), 0, s,              \
+                               static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,   \
+                               src, sd, seed, move, g, n_accept, sc.status, ms, sp.groups,     \
+                               static_cast<const double*>(sc.mv_part),                         \
+                               static_cast<const int*>(sc.mv_anc));                            \
     } while (0)
-#define SMC_CASE(K, D)                                                                        \
-    if (g.k == K && g.d == D) {                                                               \
-        if (prec == SMC_PREC_FP32) SMC_MOVE(K, D, SMC_PREC_FP32);                             \
-        else SMC_MOVE(K, D, SMC_PREC_FP64);                                                   \
-        return hipGetLastError();                                                             \
+#define SMC_CASE(K, D)                                                                         \
+    if (g.k == K && g.d == D) {                                                                \
+        if (prec == SMC_PREC_FP32) SMC_MOVE(K, D, SMC_PREC_FP32);                              \
+        else SMC_MOVE(K, D, SMC_PREC_FP64);                                                    \
+        return hipGetLastError();                                                              \
     }
     SMC_KD_CASES(SMC_CASE)
 #undef SMC_CASE
 #undef SMC_MOVE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pt_iteration(const GmmDev& g, const float* y, int64_t n, double* theta,
+                               double* l, int64_t M, const double* beta, StepSrc src,
+                               StepSrc later, double sd, uint64_t seed, int prec,
+                               unsigned long long* n_accept, Split sp, const Scratch& sc,
+                               MoveStep ms, int parity_mode, int wrap, int* t_advance,
+                               unsigned* n_swap, hipStream_t s) {
+    if (!valid_split(sp, M)) return hipErrorInvalidValue;
+    if (sp.groups == 1) {
+        hipError_t e = launch_rwmh(g, y, n, theta, l, M, beta, src, sd, seed, 0, prec, n_accept,
+                                   sp, sc, ms, s);
+        if (e != hipSuccess) return e;
+        return launch_exchange(theta, l, beta, M, g.k * g.d, parity_mode, 0, wrap, seed, later,
+                               t_advance, n_swap, s);
+    }
+    // slots: at most M/2 pairs plus two singles
+    const dim3 xgrid(static_cast<unsigned>((M / 2 + 2 + 255) / 256));
+#define SMC_PT(K, D, P)                                                                        \
+    do {                                                                                       \
+        launch_move_partials<K, D, P>(y, n, theta, l, M, beta, src, sd, seed, 0, g, n_accept,  \
+                                      sp, sc, ms, s);                                          \
+        hipLaunchKernelGGL((k_pt_accept_exchange<K * D, P>), xgrid, dim3(256), 0, s,           \
+                           static_cast<int>(n), theta, l, static_cast<int>(M), beta, later,    \
+                           sd, seed, g, sp.groups, static_cast<const double*>(sc.mv_part),     \
+                           parity_mode, wrap, t_advance, n_accept, n_swap, sc.status);         \
+    } while (0)
+#define SMC_CASE(K, D)                                                                         \
+    if (g.k == K && g.d == D) {                                                                \
+        if (prec == SMC_PREC_FP32) SMC_PT(K, D, SMC_PREC_FP32);                                \
+        else SMC_PT(K, D, SMC_PREC_FP64);                                                      \
+        return hipGetLastError();                                                              \
+    }
+    SMC_KD_CASES(SMC_CASE)
+#undef SMC_CASE
+#undef SMC_PT
     return hipErrorInvalidValue;
 }
 

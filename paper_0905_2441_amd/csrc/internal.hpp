@@ -174,6 +174,15 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
                        uint64_t seed, uint32_t move, int prec,
                        unsigned long long* n_accept, Split sp, const Scratch& sc, MoveStep ms,
                        hipStream_t s);
+// One population-MCMC iteration: the move (reading the iteration from src and
+// recording it through ms.t_out), then the exchanges (reading it from later and
+// advancing *t_advance); with groups > 1 the decisions of both run in one kernel.
+hipError_t launch_pt_iteration(const GmmDev& g, const float* y, int64_t n, double* theta,
+                               double* l, int64_t M, const double* beta, StepSrc src,
+                               StepSrc later, double sd, uint64_t seed, int prec,
+                               unsigned long long* n_accept, Split sp, const Scratch& sc,
+                               MoveStep ms, int parity_mode, int wrap, int* t_advance,
+                               unsigned* n_swap, hipStream_t s);
 hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,
                         hipStream_t s);
 bool supported_kd(int k, int d, int prec);

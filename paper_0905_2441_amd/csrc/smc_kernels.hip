@@ -22,6 +22,7 @@
 // can be predicated on the device-side ESS test.
 #include "internal.hpp"
 #include "philox.hpp"
+#include "exchange.hpp"
 #include "reduce.hpp"
 
 namespace smc {
@@ -320,36 +321,10 @@ k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __r
     // be advanced here without racing the other blocks' reads
     if (t_advance != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
         *t_advance = static_cast<int>(it) + 1;
-    int parity;
-    if (parity_mode == 0) parity = static_cast<int>(it & 1u);
-    else if (parity_mode == 1) parity = static_cast<int>(draw(seed, 0, 0, it, kParity, 0).w0 >> 31);
-    else parity = parity_host & 1;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int regular = (M - parity) / 2;        // pairs (parity + 2q, parity + 2q + 1)
+    const int parity = pt_parity(parity_mode, parity_host, seed, it);
     int a, b;
-    if (q < regular) {
-        a = parity + 2 * q;
-        b = a + 1;
-    } else if (q == regular && wrap && parity == 1 && M >= 2 && (M % 2) == 0) {
-        a = M - 1;
-        b = 0;
-    } else {
-        return;
-    }
-    const double la = (beta[a] - beta[b]) * (l[b] - l[a]);
-    const double u = u01_open(draw(seed, static_cast<uint32_t>(a), 0, it, kExch, 0).w0);
-    if (la >= 0.0 || log(u) < la) {
-        const double t = l[a];
-        l[a] = l[b];
-        l[b] = t;
-        for (int c = 0; c < kd; ++c) {
-            double* r = theta + static_cast<size_t>(c) * M;
-            const double x = r[a];
-            r[a] = r[b];
-            r[b] = x;
-        }
-        if (n_swap) atomicAdd(n_swap, 1u);
-    }
+    if (!pt_slot(M, parity, wrap, blockIdx.x * blockDim.x + threadIdx.x, a, b) || b < 0) return;
+    if (pt_swap(theta, l, beta, M, kd, a, b, seed, it) && n_swap) atomicAdd(n_swap, 1u);
 }
 
 __global__ void k_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,

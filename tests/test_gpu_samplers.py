@@ -190,18 +190,27 @@ def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph):
     assert rel_err(r["l"], ref["l"]).max() <= 1e-10
 
 
-def test_pt_paper_mode_random_parity_wrap(smc, ctx):
-    announce("pt paper mode")
+@pytest.mark.parametrize("M,slices", [(32, 0), (32, 40), (33, 24)])
+def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices):
+    """Random parity with the wrap pair; slices > 16 run the moves' decisions and
+    the exchanges in one kernel (pairs, the wrap pair, and for odd M the
+    unpaired chain 0)."""
+    announce(f"pt paper mode M={M} slices={slices}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     y = make_mixture_data(100, mu, 0.3025, seed=1)
-    M, iters = 32, 15
+    iters = 15
     betas = pt_betas(M, 2)
     g = smc.Gmm.equal_weights(4, 1, 0.3025, prior="box", prior_a=-10.0, prior_b=10.0)
     om = oracle_model(g)
-    s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64")
-    r = s.run(iters, graph=False)
+    ctx.set_slices(slices)
+    try:
+        s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64")
+        r = s.run(iters, graph=False)
+    finally:
+        ctx.set_slices(0)
     ref = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True)
     assert r["swaps"] == ref["swaps"]
+    assert r["accepted"] == ref["accepted"]
     assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
 
 
