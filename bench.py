@@ -34,14 +34,17 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm1d_k4_n1000_N131072"
 OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384",
-                   "batched_256runs")
+                   "batched_256runs", "probes")
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
-# 3.93e13 non-packed FP32 VALU lane-operations per second. A transcendental
-# (v_exp_f32) issues at half that rate on CDNA4, i.e. it occupies TRANS_SLOTS = 2
-# slots (an issue-rate probe measured 1.5-1.8 slot equivalents when mixed with FMAs).
+# 3.93e13 non-packed FP32 VALU lane-operations per second (one wave64 VALU
+# instruction per SIMD every 4 cycles). Every instruction of the algorithm,
+# the hardware exp2 included, is counted as one slot: the batched workload's
+# long-data moves sustain 0.89 of this peak with one exp per six instructions,
+# so an exp costs no more than a slot in this mix (a model charging it two
+# slots would put that kernel above 100%).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-TRANS_SLOTS = 2.0
+TRANS_SLOTS = 1.0
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of the dominant kernel (the FP32 move at the headline shape, the
@@ -58,14 +61,18 @@ MOVE_COUNTERS = {
 }
 
 
+# the files the move kernel is compiled from (with the build flags in build.py)
+MOVE_SOURCES = ("gmm_kernels.hip", "gmm_common.hpp", "exchange.hpp", "internal.hpp",
+                "philox.hpp", "wave.hpp", "dd.hpp", "../../include/smc.h")
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0905_2441_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in MOVE_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     with open(os.path.join(ROOT, "paper_0905_2441_amd", "build.py"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()
@@ -85,7 +92,7 @@ def ops_per_eval(k: int) -> float:
     """Algorithmic VALU work of one particle x datum evaluation in the FP32 form:
     per component a distance FMA, a square-and-weight FMA, a shift subtract and
     one exp2; per datum k-1 max, k-1 adds, the product update and the max
-    accumulation."""
+    accumulation: 5k VALU + k transcendental (24 slots for k = 4)."""
     return 5.0 * k + TRANS_SLOTS * k
 
 
@@ -191,18 +198,19 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     res = s.results()
     ms_step = (t1 - t0) * 1e3 / steps
     # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept),
-    # timed with HIP events recorded on the stream it runs on
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # each launch bracketed by its own pair of HIP events recorded on the stream
+    # it runs on, so the average excludes the gaps between launches
     reps = max(10, steps)
-    e0.record(s.stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
     for i in range(reps):
+        ev[i][0].record(s.stream)
         smc.smc_rwmh_move(ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed,
                           cfg.T + 1 + i, 0, prec, stream=s.stream)
-    e1.record(s.stream)
-    e1.synchronize()
+        ev[i][1].record(s.stream)
+    ev[-1][1].synchronize()
     ctx.check(s.stream)
-    kern_ms = e0.elapsed_time(e1) / reps
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / reps
     return dict(ms_per_step=ms_step, kernel_ms=kern_ms, resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"])
 
@@ -346,11 +354,89 @@ def copy_calibration(nbytes=1 << 28, reps=4):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def time_launches(torch, stream, fn, reps):
+    """Average device time (ms) of fn() over `reps` calls, each bracketed by its
+    own HIP events on `stream` (gaps between calls excluded)."""
+    fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    ev[-1][1].synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
+
+
+def probes(smc, torch, ctx, reps):
+    """Roofline probes away from launch latency: the FP32 likelihood at
+    N = 2^20, n = 4096 (issue-slot bound), and the reweight (+ W) and the
+    systematic resampling with gather at N = 2^17, 2^20, 2^24 with log-normal
+    weights (sigma = 3) (HBM bound, algorithmic bytes 40 and 100 per particle
+    at k*d = 4)."""
+    import numpy as np
+    from workloads import lognormal_logw, make_mixture_data, theta_prior_draws
+    s = torch.cuda.Stream()
+    out = {}
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    N, n = 1 << 20, 4096
+    with torch.cuda.stream(s):
+        y = torch.as_tensor(make_mixture_data(n, np.array([-3.0, 0.0, 3.0, 6.0]), 0.55, 7)).cuda()
+        th = torch.as_tensor(theta_prior_draws(N, 4, 1, seed=8)).cuda()
+        l = torch.empty(N, dtype=torch.float64, device="cuda")
+    ms = time_launches(torch, s, lambda: smc.smc_loglik(ctx, g, y, th, "fp32", out=l, stream=s),
+                       reps)
+    evals = N * n / (ms * 1e-3)
+    out["loglik_fp32_N1048576_n4096"] = {
+        "us": ms * 1e3, "evals_per_s": evals,
+        "frac_issue_slots": evals * ops_per_eval(4) / PEAK_LANE_OPS}
+    del th, l
+    for logN in (17, 20, 24):
+        N = 1 << logN
+        with torch.cuda.stream(s):
+            logw0 = torch.as_tensor(lognormal_logw(N, seed=logN)).cuda()
+            logw = logw0.clone()
+            l = torch.as_tensor(lognormal_logw(N, seed=logN + 100)).cuda()
+            W = torch.empty_like(logw)
+            lz = torch.zeros(1, dtype=torch.float64, device="cuda")
+            ess = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.reserve(N, 4)
+        rw = time_launches(torch, s, lambda: smc.smc_reweight(ctx, logw, l, 1e-3, W=W, logZ=lz,
+                                                              ess=ess, stream=s), reps)
+        with torch.cuda.stream(s):
+            th_in = torch.randn((4, N), dtype=torch.float64, device="cuda")
+            th_out = torch.empty_like(th_in)
+            l_out = torch.empty_like(l)
+            idx = torch.empty(N, dtype=torch.int32, device="cuda")
+            lw2 = torch.empty_like(logw)
+            smc.smc_reweight(ctx, logw0.clone(), torch.zeros_like(l), 0.0, W=W, stream=s)
+        rs = time_launches(torch, s, lambda: smc.smc_resample_systematic(
+            ctx, W, 11, 3, idx=idx, theta_in=th_in, theta_out=th_out, l_in=l, l_out=l_out,
+            logw=lw2, stream=s), reps)
+        ctx.check(s)
+        out[f"reweight_N{N}"] = {"us": rw * 1e3, "GBps": 40.0 * N / (rw * 1e-3) / 1e9,
+                                 "frac_hbm": 40.0 * N / (rw * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[f"resample_gather_N{N}"] = {"us": rs * 1e3, "GBps": 100.0 * N / (rs * 1e-3) / 1e9,
+                                        "frac_hbm": 100.0 * N / (rs * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del th_in, th_out, l_out, idx, lw2, logw, logw0, l, W
+    return out
+
+
 def other_workload(args):
     """Secondary measurements (same JSON shape, no CPU baseline)."""
     import torch
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
+
+    if args.workload == "probes":
+        torch.cuda.set_device(0)
+        ctx = smc.Context(0)
+        r = probes(smc, torch, ctx, max(10, args.steps))
+        out = {"metric": "roofline probes (kernel time per call; algorithmic evals or bytes)",
+               "n_gpus": 1, "steps": max(10, args.steps), "warmup": 1, "data": "synthetic",
+               "config": {"workload": "probes"}, "probes": r}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload == "batched_256runs":
         torch.cuda.set_device(0)

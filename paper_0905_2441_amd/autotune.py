@@ -61,7 +61,8 @@ def tune_shape(ctx: Context, k: int, d: int, n: int, N: int, prec: str = "fp32",
     stream = torch.cuda.Stream()
     gen = torch.Generator(device="cuda").manual_seed(seed)
     with torch.cuda.stream(stream):
-        y = torch.randn(n * d, generator=gen, device="cuda", dtype=torch.float32)
+        y = torch.randn((n, d) if d > 1 else (n,), generator=gen, device="cuda",
+                        dtype=torch.float32)
         theta = torch.randn((k * d, N), generator=gen, device="cuda", dtype=torch.float64)
         loglik = torch.full((N,), -1.0e6, device="cuda", dtype=torch.float64)
     ctx.reserve(N, k * d, n if prec == "bf16x3" else 0)

@@ -21,7 +21,7 @@ template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const float (&nms)[K * D], float s,
                                                const GmmDev& g) {
-    constexpr int U = 8;
+    constexpr int U = 16;
     double msum = 0.0;
     float prod = 1.0f;
     int expo = 0;

@@ -19,8 +19,8 @@
 //   m = max_i a_i;  e = sum_i 2^(a_i - m)   (hardware v_exp_f32)
 // and log2 of the datum's mixture density (up to the constant) is m + log2 e.
 // Instead of one log per datum, the e's are multiplied into a running FP32
-// product whose exponent is extracted exactly every 8 data (frexp), and the
-// m's are summed in blocks of 8 in FP32 and promoted into an FP64
+// product whose exponent is extracted exactly every 16 data (frexp), and the
+// m's are summed in blocks of 16 in FP32 and promoted into an FP64
 // accumulator. Both are compensated schemes: the relative error of the
 // particle's log-likelihood stays below 1e-6 for n up to 10^5.
 //

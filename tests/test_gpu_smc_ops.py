@@ -234,6 +234,23 @@ def test_launch_table_selects_slices(smc, ctx):
     assert not np.array_equal(forced[1], base[1])          # the slicing changed the sums
 
 
+def test_autotune_shapes(smc, ctx):
+    """The tuner times every candidate of a 1-D and a d-dim shape and its rules
+    install in the launch table."""
+    announce("autotune")
+    from paper_0905_2441_amd import autotune
+    shapes = [(4, 1, 300, 2000, "fp32"), (8, 8, 256, 512, "bf16x3"), (2, 8, 200, 300, "fp64")]
+    try:
+        rules = autotune.make_rules(ctx, shapes, reps=2)
+        ctx.set_launch_table(rules)
+    finally:
+        ctx.set_launch_table([])
+    for (k, d, n, N, prec), r in zip(shapes, rules):
+        assert r["slices"] in autotune.candidates(n, N, prec)
+        assert set(r["ms"]) == {str(t) for t in autotune.candidates(n, N, prec)}
+        assert r["n_lo"] <= n <= r["n_hi"] and r["N_lo"] <= N <= r["N_hi"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rwmh_move_pt_size_sampled(smc, ctx, prec):
     """One move of 8192 chains at their own temperatures over n = 10000 data (the
