@@ -13,14 +13,17 @@ struct Lse3 {
 
 __device__ __forceinline__ Lse3 lse3_empty() { return Lse3{-INFINITY, 0.0, 0.0}; }
 
+// Add x to a running (m, s1, s2). One exp whichever of x and m is larger:
+// e = exp(-|x - m|) rescales the old sums when x is the new maximum and is the
+// new term otherwise (selects instead of branches, so divergent lanes do not
+// issue both exps). Bitwise the same as branching on x > m.
 __device__ __forceinline__ Lse3 lse3_push(Lse3 a, double x) {
     if (x == -INFINITY) return a;
-    if (x > a.m) {
-        const double r = (a.m == -INFINITY) ? 0.0 : exp(a.m - x);
-        return Lse3{x, a.s1 * r + 1.0, a.s2 * (r * r) + 1.0};
-    }
-    const double e = exp(x - a.m);
-    return Lse3{a.m, a.s1 + e, a.s2 + e * e};
+    const double d = x - a.m;                   // +inf while the sums are empty
+    const double e = exp(-fabs(d));
+    const bool up = d > 0.0;
+    return Lse3{up ? x : a.m, up ? a.s1 * e + 1.0 : a.s1 + e,
+                up ? a.s2 * (e * e) + 1.0 : a.s2 + e * e};
 }
 
 __device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
