@@ -197,20 +197,14 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     ctx.check(s.stream)
     res = s.results()
     ms_step = (t1 - t0) * 1e3 / steps
-    # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept),
-    # each launch bracketed by its own pair of HIP events recorded on the stream
-    # it runs on, so the average excludes the gaps between launches
+    # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept)
+    # launched back to back, timed with HIP events recorded on the stream it
+    # runs on (an event pair around every launch would add its own overhead)
     reps = max(10, steps)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for i in range(reps):
-        ev[i][0].record(s.stream)
-        smc.smc_rwmh_move(ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed,
-                          cfg.T + 1 + i, 0, prec, stream=s.stream)
-        ev[i][1].record(s.stream)
-    ev[-1][1].synchronize()
+    kern_ms = time_launches(torch, s.stream, lambda i: smc.smc_rwmh_move(
+        ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed, cfg.T + 1 + i, 0, prec,
+        stream=s.stream), reps)
     ctx.check(s.stream)
-    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / reps
     return dict(ms_per_step=ms_step, kernel_ms=kern_ms, resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"])
 
@@ -355,17 +349,18 @@ def copy_calibration(nbytes=1 << 28, reps=4):
 
 
 def time_launches(torch, stream, fn, reps):
-    """Average device time (ms) of fn() over `reps` calls, each bracketed by its
-    own HIP events on `stream` (gaps between calls excluded)."""
-    fn()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for a, b in ev:
-        a.record(stream)
-        fn()
-        b.record(stream)
-    ev[-1][1].synchronize()
-    return sum(a.elapsed_time(b) for a, b in ev) / reps
+    """Average device time (ms) of fn(i), i = 0..reps-1, enqueued back to back
+    on `stream` between two HIP events recorded on that stream (after one
+    untimed call)."""
+    fn(0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(reps):
+        fn(i)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def probes(smc, torch, ctx, reps):
@@ -384,7 +379,7 @@ def probes(smc, torch, ctx, reps):
         y = torch.as_tensor(make_mixture_data(n, np.array([-3.0, 0.0, 3.0, 6.0]), 0.55, 7)).cuda()
         th = torch.as_tensor(theta_prior_draws(N, 4, 1, seed=8)).cuda()
         l = torch.empty(N, dtype=torch.float64, device="cuda")
-    ms = time_launches(torch, s, lambda: smc.smc_loglik(ctx, g, y, th, "fp32", out=l, stream=s),
+    ms = time_launches(torch, s, lambda i: smc.smc_loglik(ctx, g, y, th, "fp32", out=l, stream=s),
                        reps)
     evals = N * n / (ms * 1e-3)
     out["loglik_fp32_N1048576_n4096"] = {
@@ -401,7 +396,7 @@ def probes(smc, torch, ctx, reps):
             lz = torch.zeros(1, dtype=torch.float64, device="cuda")
             ess = torch.zeros(1, dtype=torch.float64, device="cuda")
         ctx.reserve(N, 4)
-        rw = time_launches(torch, s, lambda: smc.smc_reweight(ctx, logw, l, 1e-3, W=W, logZ=lz,
+        rw = time_launches(torch, s, lambda i: smc.smc_reweight(ctx, logw, l, 1e-3, W=W, logZ=lz,
                                                               ess=ess, stream=s), reps)
         with torch.cuda.stream(s):
             th_in = torch.randn((4, N), dtype=torch.float64, device="cuda")
@@ -410,7 +405,7 @@ def probes(smc, torch, ctx, reps):
             idx = torch.empty(N, dtype=torch.int32, device="cuda")
             lw2 = torch.empty_like(logw)
             smc.smc_reweight(ctx, logw0.clone(), torch.zeros_like(l), 0.0, W=W, stream=s)
-        rs = time_launches(torch, s, lambda: smc.smc_resample_systematic(
+        rs = time_launches(torch, s, lambda i: smc.smc_resample_systematic(
             ctx, W, 11, 3, idx=idx, theta_in=th_in, theta_out=th_out, l_in=l, l_out=l_out,
             logw=lw2, stream=s), reps)
         ctx.check(s)
