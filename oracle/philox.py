@@ -95,6 +95,14 @@ def u01_left_closed(w) -> np.ndarray:
     return np.asarray(w, dtype=np.float64) * TWO_POW_M32
 
 
+def u01_53(wa, wb) -> np.ndarray:
+    """A 53-bit uniform in [0, 1) from two words: (wa * 2^21 + (wb >> 11)) * 2^-53,
+    exact in FP64 (per-particle offsets of stratified and multinomial resampling)."""
+    hi = np.asarray(wa, dtype=np.uint64) << np.uint64(21)
+    lo = np.asarray(wb, dtype=np.uint64) >> np.uint64(11)
+    return (hi | lo).astype(np.float64) * 2.0 ** -53
+
+
 def box_muller(wa, wb):
     """Two standard normals from two words (Box & Muller, 1958), FP64."""
     u0 = u01_open(wa)

@@ -138,6 +138,70 @@ def systematic_resample(W, u) -> np.ndarray:
     return idx.astype(np.int32)
 
 
+# Resampling schemes (Sequential Monte Carlo subsection: the new population is
+# drawn from the empirical CDF of the weights). All three take
+# idx_i = min{j : U_i < C_j} on the same correctly rounded CDF, with the same
+# clamp, and differ only in the points U_i:
+#   systematic   U_i = (i + u) / N, one u per step;
+#   stratified   U_i = (i + u_i) / N, one u_i per stratum i;
+#   multinomial  U_i = u_i, N independent uniforms ("sampling N times").
+SCHEMES = ("systematic", "stratified", "multinomial")
+
+
+def per_index_uniforms(seed, step, N, scheme):
+    """u_i in [0, 1) for stratified (scheme code 1) or multinomial (code 2)
+    resampling: 53-bit uniforms from words 0, 1 of stream (i, 0, step, RESAMP, code)."""
+    code = SCHEMES.index(scheme)
+    w0, w1, _, _ = px.words(seed, np.arange(N, dtype=np.uint64), 0, step, px.RESAMP, code)
+    return px.u01_53(w0, w1)
+
+
+def resample_points(N, scheme, seed, step):
+    """The points U_i of a scheme in FP64 (each a single rounding of its formula)."""
+    if scheme == "systematic":
+        return systematic_offsets(N, resample_offset(seed, step))
+    u = per_index_uniforms(seed, step, N, scheme)
+    if scheme == "stratified":
+        return (np.arange(N, dtype=np.float64) + u) / float(N)
+    if scheme == "multinomial":
+        return u
+    raise ValueError(f"unknown resampling scheme {scheme!r}")
+
+
+def search_cdf(W, U) -> np.ndarray:
+    """idx_i = min{j : U_i < C_j} on the correctly rounded CDF of W; U_i >= C_{N-1}
+    (possible only through rounding) maps to the first j with C_j = C_{N-1}."""
+    W = np.asarray(W, dtype=np.float64)
+    C = prefix_sums_correctly_rounded(W)
+    idx = np.searchsorted(C, U, side="right")
+    last = int(np.searchsorted(C, C[-1], side="left"))
+    return np.where(idx >= W.size, last, idx).astype(np.int32)
+
+
+def resample_indices(W, scheme, seed, step) -> np.ndarray:
+    """Ancestor indices of one resampling under `scheme`."""
+    W = np.asarray(W, dtype=np.float64)
+    return search_cdf(W, resample_points(W.size, scheme, seed, step))
+
+
+def search_bruteforce(W, U):
+    """Exact-rational search for tiny N: C_j and the given U_i as fractions,
+    linear scan, the same clamp."""
+    Wf = [Fraction(float(w)) for w in W]
+    C, acc = [], Fraction(0)
+    for w in Wf:
+        acc += w
+        C.append(acc)
+    out = []
+    for Ui in U:
+        Uf = Fraction(float(Ui))
+        j = next((j for j in range(len(W)) if Uf < C[j]), None)
+        if j is None:
+            j = next(j for j in range(len(W)) if C[j] == C[-1])
+        out.append(j)
+    return np.asarray(out, dtype=np.int32)
+
+
 def systematic_resample_bruteforce(W, u):
     """Exact-rational version for tiny N: the same definition with U_i, C_j as
     exact fractions and a linear scan."""
@@ -216,19 +280,19 @@ def rwmh_move(theta, l, y, model: Model, beta, step_sd, seed, step, move):
 # SMC sampler
 
 def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
-             ess_frac=0.5, resample=True):
+             ess_frac=0.5, resample=True, scheme="systematic"):
     """Tempering step t >= 1: reweight by L^(beta_t - beta_{t-1}); if
-    ESS < ess_frac * N resample systematically (offset from stream (seed, t)) and
-    reset the log-weights; then n_moves RW-MH moves at beta_t (move m uses
-    stream move m). Returns (theta, l, logw, W, logZ_increment, info)."""
+    ESS < ess_frac * N resample (systematic by default; points from the streams
+    of step t) and reset the log-weights; then n_moves RW-MH moves at beta_t
+    (move m uses stream move m). Returns (theta, l, logw, W, logZ_increment, info)."""
     N = l.size
     dbeta = betas[t] - betas[t - 1]
     logw, W, inc, e = reweight(logw, l, dbeta)
     did = bool(resample and e < ess_frac * N)
     u = None
     if did:
-        u = resample_offset(seed, t)
-        idx = systematic_resample(W, u)
+        u = resample_offset(seed, t) if scheme == "systematic" else None
+        idx = resample_indices(W, scheme, seed, t)
         theta = theta[:, idx]
         l = l[idx]
         logw = np.zeros(N)
@@ -242,7 +306,7 @@ def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
 
 
 def smc_run(y, model: Model, betas, N, step_sd, n_moves, seed, ess_frac=0.5,
-            resample=True):
+            resample=True, scheme="systematic"):
     """Tempered SMC sampler from beta_0 = 0 to beta_T = 1.
 
     Returns a dict with theta, l, logw, W, logZ and per-step traces (ESS,
@@ -257,7 +321,7 @@ def smc_run(y, model: Model, betas, N, step_sd, n_moves, seed, ess_frac=0.5,
     tr = dict(ess=[], resampled=[], accepted=[], logZ_inc=[], u=[])
     for t in range(1, T + 1):
         theta, l, logw, W, inc, info = smc_step(theta, l, logw, y, model, betas, t, step_sd,
-                                                n_moves, seed, ess_frac, resample)
+                                                n_moves, seed, ess_frac, resample, scheme)
         logZ += inc
         tr["ess"].append(info["ess"])
         tr["resampled"].append(info["resampled"])
