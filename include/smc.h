@@ -69,6 +69,18 @@ typedef enum {
 
 typedef enum { SMC_PRIOR_GAUSS = 0, SMC_PRIOR_BOX = 1 } smc_prior_kind;
 
+/* Resampling schemes (Sequential Monte Carlo subsection: the new population is
+ * drawn from the empirical CDF of the weights). All use idx_i = min{j : U_i < C_j}
+ * on the correctly rounded CDF; they differ in the points U_i:
+ *   SYSTEMATIC   (i + u)/N, one u = w0 2^-32 per step from stream (0, 0, step, RESAMP, 0);
+ *   STRATIFIED   (i + u_i)/N, MULTINOMIAL  u_i (N independent draws),
+ *   with u_i = (w0 2^21 + (w1 >> 11)) 2^-53 from stream (i, 0, step, RESAMP, scheme). */
+typedef enum {
+    SMC_RESAMPLE_SYSTEMATIC = 0,
+    SMC_RESAMPLE_STRATIFIED = 1,
+    SMC_RESAMPLE_MULTINOMIAL = 2
+} smc_resampling;
+
 /* The mixture model: k components in d dimensions with known covariance
  * sigma2 * I and known natural-log weights log_w[0..k-1] (summing to one in
  * probability); the unknowns are the k means. Prior on every coordinate of
@@ -195,6 +207,19 @@ int smc_resample_systematic(smc_ctx ctx, const double* W, int64_t N, uint64_t se
                             double* theta_out, int32_t kd, const double* l_in,
                             double* l_out, double* logw, void* stream);
 
+/* Resampling under any scheme of smc_resampling, with the same arguments and
+ * behaviour as smc_resample_systematic (no offset override). Multinomial
+ * indices are in draw order (not sorted). Bit-exact for N <= 2^20. */
+int smc_resample(smc_ctx ctx, smc_resampling scheme, const double* W, int64_t N, uint64_t seed,
+                 uint64_t step, const double* ess, double ess_threshold, int32_t* idx,
+                 const double* theta_in, double* theta_out, int32_t kd, const double* l_in,
+                 double* l_out, double* logw, void* stream);
+
+/* The scheme used by later smc_step and smc_step_batched calls on this
+ * context (default SYSTEMATIC); a captured graph keeps the scheme it was
+ * captured with. */
+int smc_set_resampling(smc_ctx ctx, smc_resampling scheme);
+
 /* Exchange moves between adjacent chains (Population-Based MCMC subsection).
  * Pairs (a, a+1) with a = parity, parity+2, ... < M-1; with `wrap` and
  * parity 1 (M even) also (M-1, 0). log alpha = (beta[a] - beta[b]) (l_b - l_a);
@@ -211,8 +236,9 @@ int pt_exchange(smc_ctx ctx, double* theta, double* loglik, const double* beta, 
  * Carlo subsection):
  *   t = *t_dev clamped to 1..T; dbeta = beta[t] - beta[t-1];
  *   logw += dbeta * loglik_in; *logZ += lse(logw_new) - lse(logw_old);
- *   ESS = 1 / sum W^2; if ESS < ess_frac * N: systematic resampling with the
- *   offset of stream (0, 0, t, RESAMP, 0), logw = 0;
+ *   ESS = 1 / sum W^2; if ESS < ess_frac * N: resampling under the context's
+ *   scheme (smc_set_resampling; systematic by default) with the points of
+ *   step t, logw = 0;
  *   n_moves RW-MH moves at beta[t] (move m uses stream move m);
  *   *t_dev = t + 1.
  * The step reads the population (theta_in [k*d][N], loglik_in [N]) and writes

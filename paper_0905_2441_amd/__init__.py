@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     smc_ess,
     smc_loglik,
     smc_prior_init,
+    smc_resample,
     smc_resample_systematic,
     smc_reweight,
     smc_rng_normals,

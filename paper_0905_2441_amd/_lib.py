@@ -29,6 +29,10 @@ SMC_PREC_FP64 = 0
 SMC_PREC_FP32 = 1
 SMC_PREC_BF16X3 = 2
 
+SMC_RESAMPLE_SYSTEMATIC = 0
+SMC_RESAMPLE_STRATIFIED = 1
+SMC_RESAMPLE_MULTINOMIAL = 2
+
 SMC_PRIOR_GAUSS = 0
 SMC_PRIOR_BOX = 1
 
@@ -69,6 +73,9 @@ SIGNATURES = {
     "smc_ess": (c_int, [_P, _P, c_int64, _P, _P]),
     "smc_resample_systematic": (c_int, [_P, _P, c_int64, c_uint64, c_uint64, _P, _P, c_double,
                                         _P, _P, _P, c_int32, _P, _P, _P, _P]),
+    "smc_resample": (c_int, [_P, c_int, _P, c_int64, c_uint64, c_uint64, _P, c_double, _P, _P,
+                             _P, c_int32, _P, _P, _P, _P]),
+    "smc_set_resampling": (c_int, [_P, c_int]),
     "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
                             c_uint64, _P, _P]),
     "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,

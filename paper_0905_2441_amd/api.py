@@ -19,6 +19,8 @@ from . import _lib as L
 
 PREC = {"fp64": L.SMC_PREC_FP64, "fp32": L.SMC_PREC_FP32, "bf16x3": L.SMC_PREC_BF16X3}
 PURPOSE = {"prior": 1, "prop": 2, "acc": 3, "resamp": 4, "exch": 5, "parity": 6}
+SCHEME = {"systematic": L.SMC_RESAMPLE_SYSTEMATIC, "stratified": L.SMC_RESAMPLE_STRATIFIED,
+          "multinomial": L.SMC_RESAMPLE_MULTINOMIAL}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -113,6 +115,10 @@ class Context:
     def set_slices(self, slices: int) -> None:
         L.check(self._lib.smc_set_slices(self.handle, int(slices)))
 
+    def set_resampling(self, scheme: str) -> None:
+        """Resampling scheme of later smc_step / smc_step_batched calls."""
+        L.check(self._lib.smc_set_resampling(self.handle, SCHEME[scheme]))
+
     def set_launch_table(self, rules: Sequence[dict]) -> None:
         """Install launch rules (dicts with k, d, prec, slices, n_lo, n_hi, N_lo,
         N_hi; prec is a name of PREC or "any"); an empty list clears the table."""
@@ -197,6 +203,23 @@ def smc_resample_systematic(ctx: Context, W, seed, step, u_override=None, ess=No
         _opt(u_override, torch.float64, "u_override", 1), _opt(ess, torch.float64, "ess", 1),
         float(ess_threshold), _opt(idx, torch.int32, "idx", N),
         _opt(theta_in, torch.float64, "theta_in", kd * N),
+        _opt(theta_out, torch.float64, "theta_out", kd * N), kd,
+        _opt(l_in, torch.float64, "l_in", N), _opt(l_out, torch.float64, "l_out", N),
+        _opt(logw, torch.float64, "logw", N), _stream(stream)))
+
+
+def smc_resample(ctx: Context, W, scheme, seed, step, ess=None, ess_threshold=0.0, idx=None,
+                 theta_in=None, theta_out=None, l_in=None, l_out=None, logw=None, stream=None):
+    N = W.numel()
+    kd = 0
+    if theta_in is not None:
+        if theta_in.dim() != 2 or theta_in.shape[1] != N:
+            raise ValueError("theta_in must be [kd, N]")
+        kd = theta_in.shape[0]
+    L.check(ctx._lib.smc_resample(
+        ctx.handle, SCHEME[scheme], _ptr(W, torch.float64, "W"), N, int(seed), int(step),
+        _opt(ess, torch.float64, "ess", 1), float(ess_threshold),
+        _opt(idx, torch.int32, "idx", N), _opt(theta_in, torch.float64, "theta_in", kd * N),
         _opt(theta_out, torch.float64, "theta_out", kd * N), kd,
         _opt(l_in, torch.float64, "l_in", N), _opt(l_out, torch.float64, "l_out", N),
         _opt(logw, torch.float64, "logw", N), _stream(stream)))

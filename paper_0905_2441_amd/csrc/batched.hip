@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(kRedBlock)
 k_b_resample(const BatchRun* __restrict__ runs, const StepState* __restrict__ st,
              double* __restrict__ logw, const double* __restrict__ theta,
              const double* __restrict__ l, double* __restrict__ cdf,
-             double* __restrict__ theta_tmp, double* __restrict__ l_tmp, int kd, StepSrc src) {
+             double* __restrict__ theta_tmp, double* __restrict__ l_tmp, int kd, StepSrc src,
+             int scheme) {
     const BatchRun rd = runs[blockIdx.x];
     const StepState s = st[blockIdx.x];
     if (!s.resampled) return;
@@ -103,12 +104,12 @@ k_b_resample(const BatchRun* __restrict__ runs, const StepState* __restrict__ st
     __threadfence_block();
     __syncthreads();
     const uint32_t step = static_cast<uint32_t>(s.t);
-    const double u = u01_left_closed(draw(rd.seed, 0, 0, step, kResamp, 0).w0);
+    const double u = scheme == 0 ? u01_left_closed(draw(rd.seed, 0, 0, step, kResamp, 0).w0) : 0.0;
     const double clast = C[N - 1];
     const double* th = theta + static_cast<size_t>(kd) * rd.p_off;
     double* tt = theta_tmp + static_cast<size_t>(kd) * rd.p_off;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const double U = (static_cast<double>(i) + u) / static_cast<double>(N);
+        const double U = resample_point(scheme, rd.seed, step, i, N, u);
         int lo = 0, hi = N - 1;
         if (U < clast) {
             while (lo < hi) {
@@ -231,7 +232,7 @@ int batch_move_grid() {
 hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y, double* theta,
                              double* l, double* logw, double* W, const double* beta, int T,
                              int* t_dev, double sd, int n_moves, double ess_frac, int prec,
-                             double* stats, unsigned long long* n_acc, int* status,
+                             double* stats, unsigned long long* n_acc, int* status, int scheme,
                              hipStream_t s) {
     StepSrc src{};
     src.t_dev = t_dev;
@@ -242,7 +243,7 @@ hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_b_resample, dim3(b.R), dim3(kRedBlock), 0, s, b.runs, b.state, logw,
-                       theta, l, b.cdf, b.theta_tmp, b.l_tmp, g.k * g.d, src);
+                       theta, l, b.cdf, b.theta_tmp, b.l_tmp, g.k * g.d, src, scheme);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int grid = b.n_items < b.move_grid ? b.n_items : b.move_grid;

@@ -17,6 +17,7 @@ using namespace smc;
 struct smc_ctx_s {
     int device = 0;
     int slices_override = 0;
+    int scheme = SMC_RESAMPLE_SYSTEMATIC;
     std::vector<smc_launch_rule> table;
     Scratch sc{};
     void* fixed = nullptr;       // partials, chunk totals, status, state
@@ -483,11 +484,51 @@ int smc_resample_systematic(smc_ctx ctx, const double* W, int64_t N, uint64_t se
     if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
     if ((r = ensure_scratch(ctx, N, 1, as_stream(stream)))) return r;
     WeightSrc ws{W, nullptr, nullptr};
-    const hipError_t e = launch_resample(ctx->sc, ws, N, seed, host_src(static_cast<int>(step), 0, 0),
-                                         u_override, ess, ess_threshold, nullptr, idx, theta_in,
-                                         theta_out, theta_in ? kd : 0, l_in, l_out, logw, 1,
+    const hipError_t e = launch_resample(ctx->sc, ws, N, SMC_RESAMPLE_SYSTEMATIC, seed,
+                                         host_src(static_cast<int>(step), 0, 0), u_override, ess,
+                                         ess_threshold, nullptr, idx, theta_in, theta_out,
+                                         theta_in ? kd : 0, l_in, l_out, logw, 1,
                                          as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "resample launch");
+    return SMC_OK;
+}
+
+int smc_resample(smc_ctx ctx, smc_resampling scheme, const double* W, int64_t N, uint64_t seed,
+                 uint64_t step, const double* ess, double ess_threshold, int32_t* idx,
+                 const double* theta_in, double* theta_out, int32_t kd, const double* l_in,
+                 double* l_out, double* logw, void* stream) {
+    if (scheme != SMC_RESAMPLE_SYSTEMATIC && scheme != SMC_RESAMPLE_STRATIFIED &&
+        scheme != SMC_RESAMPLE_MULTINOMIAL)
+        return fail(SMC_ERR_INVALID_ARG, "unknown resampling scheme");
+    int r = enter(ctx);
+    if (r) return r;
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!W) return fail(SMC_ERR_INVALID_ARG, "W is NULL");
+    if ((theta_in == nullptr) != (theta_out == nullptr))
+        return fail(SMC_ERR_INVALID_ARG, "theta_in and theta_out go together");
+    if (theta_in && (kd < 1 || kd > SMC_KDMAX)) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
+    if (theta_in && theta_in == theta_out) return fail(SMC_ERR_INVALID_ARG, "theta_out aliases theta_in");
+    if ((l_in == nullptr) != (l_out == nullptr))
+        return fail(SMC_ERR_INVALID_ARG, "l_in and l_out go together");
+    if (l_in && l_in == l_out) return fail(SMC_ERR_INVALID_ARG, "l_out aliases l_in");
+    if (step > 0xFFFFFFFFull) return fail(SMC_ERR_INVALID_ARG, "step must fit in 32 bits");
+    if ((r = ensure_scratch(ctx, N, 1, as_stream(stream)))) return r;
+    WeightSrc ws{W, nullptr, nullptr};
+    const hipError_t e = launch_resample(ctx->sc, ws, N, scheme, seed,
+                                         host_src(static_cast<int>(step), 0, 0), nullptr, ess,
+                                         ess_threshold, nullptr, idx, theta_in, theta_out,
+                                         theta_in ? kd : 0, l_in, l_out, logw, 1,
+                                         as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "resample launch");
+    return SMC_OK;
+}
+
+int smc_set_resampling(smc_ctx ctx, smc_resampling scheme) {
+    if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
+    if (scheme != SMC_RESAMPLE_SYSTEMATIC && scheme != SMC_RESAMPLE_STRATIFIED &&
+        scheme != SMC_RESAMPLE_MULTINOMIAL)
+        return fail(SMC_ERR_INVALID_ARG, "unknown resampling scheme");
+    ctx->scheme = scheme;
     return SMC_OK;
 }
 
@@ -548,8 +589,8 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if (n_moves == 0) {
         // adopt the resampled (or unchanged) population and publish W
-        e = launch_search_gather(ctx->sc, N, seed, later, ctx->sc.state, theta_in, theta_out, kd,
-                                 loglik_in, loglik_out, logw, 1, s);
+        e = launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, theta_in,
+                                 theta_out, kd, loglik_in, loglik_out, logw, 1, s);
         if (e == hipSuccess) e = launch_publish_w(ctx->sc, W, logw, N, s);
         if (e != hipSuccess) return hip_fail(e, "gather launch");
         return SMC_OK;
@@ -557,7 +598,7 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     int chunk, nchunks;
     cdf_layout(N, &chunk, &nchunks);
     if (mfma) {
-        e = launch_search_gather(ctx->sc, N, seed, later, ctx->sc.state, theta_in,
+        e = launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, theta_in,
                                  ctx->sc.theta_tmp, kd, loglik_in, ctx->sc.l_tmp, logw, 0, s);
         if (e == hipSuccess) e = launch_dd_prep(g, y, n, ctx->sc.mm_rows, s);
         if (e != hipSuccess) return hip_fail(e, "gather launch");
@@ -582,6 +623,7 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
                 ms.chunk = chunk;
                 ms.nchunks = nchunks;
                 ms.seed = seed;
+                ms.scheme = ctx->scheme;
             }
         }
         if (mfma)
@@ -836,7 +878,7 @@ int smc_step_batched(smc_ctx ctx, smc_batch b, const smc_gmm* model, const float
     if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
     const hipError_t e = launch_batch_step(b->dev, g, y, theta, loglik, logw, W, beta, T, t_dev,
                                            step_sd, n_moves, ess_frac, prec, run_stats, n_accept,
-                                           ctx->sc.status, as_stream(stream));
+                                           ctx->sc.status, ctx->scheme, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
     return SMC_OK;
 }

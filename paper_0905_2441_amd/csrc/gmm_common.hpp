@@ -162,7 +162,7 @@ __device__ __forceinline__ MoveSource move_source(const MoveStep& ms, double* th
 // Ancestors of the 64 particles of this workgroup after systematic resampling
 // (cooperative: every thread of the block must call it). Wave 0 forms the chunk
 // offsets in LDS (exclusive double-double scan of the chunk totals), then each
-// of its lanes takes U = (i + u)/N for particle i and finds
+// of its lanes takes the scheme's point U_i for particle i and finds
 // idx = min{j : U < C_j} (or the first j with C_j = C_{N-1}), C_j = offset +
 // within-chunk prefix rounded once.
 __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint32_t step, int pc,
@@ -198,8 +198,9 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
             const int b = j / ms.chunk;
             return dd_add(dd{offh[b], offl[b]}, dd{ms.cdf_hi[j], ms.cdf_lo[j]}).hi;
         };
-        const double u = u01_left_closed(draw(ms.seed, 0, 0, step, kResamp, 0).w0);
-        const double U = (static_cast<double>(pc) + u) / static_cast<double>(N);
+        const double u = ms.scheme == 0 ? u01_left_closed(draw(ms.seed, 0, 0, step, kResamp, 0).w0)
+                                        : 0.0;
+        const double U = resample_point(ms.scheme, ms.seed, step, pc, N, u);
         const double clast = cdf(N - 1);
         int lo = 0, hi = N - 1;
         if (U < clast) {

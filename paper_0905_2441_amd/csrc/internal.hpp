@@ -118,6 +118,7 @@ struct MoveStep {
     const double* chunk_tot;   // [2 * nchunks] (hi, lo)
     int chunk, nchunks;
     uint64_t seed;
+    int scheme;                // resampling points (smc_resampling)
     int* t_out;                // nullable: the move records its step index here
 };
 
@@ -163,7 +164,7 @@ int batch_move_grid();
 hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y, double* theta,
                              double* l, double* logw, double* W, const double* beta, int T,
                              int* t_dev, double sd, int n_moves, double ess_frac, int prec,
-                             double* stats, unsigned long long* n_acc, int* status,
+                             double* stats, unsigned long long* n_acc, int* status, int scheme,
                              hipStream_t s);
 
 hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
@@ -211,9 +212,9 @@ hipError_t launch_weights(const Scratch& sc, const double* logw, int64_t N, doub
                           hipStream_t s);
 hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess,
                       hipStream_t s);
-// Systematic resampling: CDF of the weights, then search and gather. pred_ess /
-// pred_state make both kernels no-ops unless the ESS test fired.
-hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t seed,
+// Resampling (scheme: smc_resampling): CDF of the weights, then search and
+// gather. pred_ess / pred_state make both kernels no-ops unless the ESS test fired.
+hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, int scheme, uint64_t seed,
                            StepSrc src, const double* u_override, const double* pred_ess,
                            double ess_threshold, const StepState* pred_state,
                            int32_t* idx, const double* theta_in, double* theta_out,
@@ -228,8 +229,8 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
                            double* stats, double ess_frac, const double* logw, hipStream_t s);
 void cdf_layout(int64_t N, int* chunk, int* nchunks);
-hipError_t launch_search_gather(const Scratch& sc, int64_t N, uint64_t seed, StepSrc src,
-                                const StepState* pred_state, const double* theta_in,
+hipError_t launch_search_gather(const Scratch& sc, int64_t N, int scheme, uint64_t seed,
+                                StepSrc src, const StepState* pred_state, const double* theta_in,
                                 double* theta_out, int32_t kd, const double* l_in, double* l_out,
                                 double* logw, int copy_when_skipped, hipStream_t s);
 hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, int64_t N,

@@ -70,6 +70,25 @@ __device__ __forceinline__ double u01_left_closed(uint32_t w) {
     return static_cast<double>(w) * 0x1p-32;
 }
 
+// (wa 2^21 + (wb >> 11)) 2^-53: a 53-bit uniform in [0, 1), exact in FP64.
+__device__ __forceinline__ double u01_53(uint32_t wa, uint32_t wb) {
+    const uint64_t v = (static_cast<uint64_t>(wa) << 21) | static_cast<uint64_t>(wb >> 11);
+    return static_cast<double>(v) * 0x1p-53;
+}
+
+// Point U_i of a resampling scheme (codes as the C ABI's smc_resampling):
+// 0 systematic (i + u)/N with the step's single offset u_sys, 1 stratified
+// (i + u_i)/N, 2 multinomial u_i, where u_i is the 53-bit uniform of stream
+// (i, 0, step, RESAMP, scheme). Each point is one rounding of its formula.
+__device__ __forceinline__ double resample_point(int scheme, uint64_t seed, uint32_t step, int i,
+                                                 int N, double u_sys) {
+    if (scheme == 0) return (static_cast<double>(i) + u_sys) / static_cast<double>(N);
+    const Words4 w = draw(seed, static_cast<uint32_t>(i), 0, step, kResamp,
+                          static_cast<uint32_t>(scheme));
+    const double u = u01_53(w.w0, w.w1);
+    return scheme == 1 ? (static_cast<double>(i) + u) / static_cast<double>(N) : u;
+}
+
 // sin and cos of an angle a in [0, 2 pi]. Reduction to x = a - k pi/2 with k
 // the nearest integer to a * 2/pi and pi/2 split in two doubles P1 + P2: for
 // k >= 1, a >= pi/4 and k*P1 are both multiples of 2^-53, so a - k*P1 (one FMA)

@@ -233,11 +233,11 @@ k_publish_w(double* __restrict__ W, const double* __restrict__ logw, int N, Scra
 }
 
 // Phase 2: chunk offsets (exclusive scan of the chunk totals, once per block in
-// LDS), then U_i = (i + u)/N, idx_i = min{j : U_i < C_j} (or the first j with
+// LDS), then the scheme's point U_i, idx_i = min{j : U_i < C_j} (or the first j with
 // C_j = C_{N-1} when U_i >= C_{N-1}), then gather.
 __global__ void __launch_bounds__(kRedBlock)
-k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, uint64_t seed,
-                StepSrc src, const double* u_override, int32_t* idx_out,
+k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, int scheme,
+                uint64_t seed, StepSrc src, const double* u_override, int32_t* idx_out,
                 const double* __restrict__ theta_in, double* __restrict__ theta_out, int kd,
                 const double* __restrict__ l_in, double* __restrict__ l_out, double* logw,
                 int copy_when_skipped) {
@@ -278,14 +278,11 @@ k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, ui
         const int b = j / chunk;
         return dd_add(dd{offh[b], offl[b]}, dd{sc.cdf_hi[j], sc.cdf_lo[j]}).hi;
     };
-    double u;
-    if (u_override) {
-        u = *u_override;
-    } else {
-        const uint32_t step = static_cast<uint32_t>(step_index(src));
-        u = u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
-    }
-    const double U = (static_cast<double>(i) + u) / static_cast<double>(N);
+    const uint32_t step = static_cast<uint32_t>(step_index(src));
+    double u = 0.0;
+    if (scheme == 0)
+        u = u_override ? *u_override : u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
+    const double U = resample_point(scheme, seed, step, i, N, u);
     const double clast = cdf(N - 1);
     int lo = 0, hi = N - 1;
     if (U < clast) {
@@ -405,7 +402,7 @@ hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t seed,
+hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, int scheme, uint64_t seed,
                            StepSrc src, const double* u_override, const double* pred_ess,
                            double ess_threshold, const StepState* pred_state,
                            int32_t* idx, const double* theta_in, double* theta_out,
@@ -420,7 +417,7 @@ hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, uint64_t s
     if (e != hipSuccess) return e;
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
     hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N),
-                       chunk, nchunks, sc, pred, seed, src, u_override, idx, theta_in,
+                       chunk, nchunks, sc, pred, scheme, seed, src, u_override, idx, theta_in,
                        theta_out, kd, l_in, l_out, logw, copy_when_skipped);
     return hipGetLastError();
 }
@@ -452,8 +449,8 @@ void cdf_layout(int64_t N, int* chunk, int* nchunks) {
     *nchunks = static_cast<int>((N + *chunk - 1) / *chunk);
 }
 
-hipError_t launch_search_gather(const Scratch& sc, int64_t N, uint64_t seed, StepSrc src,
-                                const StepState* pred_state, const double* theta_in,
+hipError_t launch_search_gather(const Scratch& sc, int64_t N, int scheme, uint64_t seed,
+                                StepSrc src, const StepState* pred_state, const double* theta_in,
                                 double* theta_out, int32_t kd, const double* l_in, double* l_out,
                                 double* logw, int copy_when_skipped, hipStream_t s) {
     ResamplePred pred{nullptr, 0.0, pred_state};
@@ -461,7 +458,7 @@ hipError_t launch_search_gather(const Scratch& sc, int64_t N, uint64_t seed, Ste
     cdf_layout(N, &chunk, &nchunks);
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
     hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N), chunk,
-                       nchunks, sc, pred, seed, src, static_cast<const double*>(nullptr),
+                       nchunks, sc, pred, scheme, seed, src, static_cast<const double*>(nullptr),
                        static_cast<int32_t*>(nullptr), theta_in, theta_out, kd, l_in, l_out, logw,
                        copy_when_skipped);
     return hipGetLastError();

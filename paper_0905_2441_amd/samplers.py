@@ -35,10 +35,10 @@ def _dev(x, dtype):
 class SMCSampler:
     def __init__(self, ctx: Context, model: Gmm, y, N: int, betas, step_sd: float,
                  n_moves: int, seed: int, ess_frac: float = 0.5, prec: str = "fp32",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, scheme: str = "systematic"):
         self.ctx, self.model, self.N = ctx, model, int(N)
         self.step_sd, self.n_moves, self.seed = float(step_sd), int(n_moves), int(seed)
-        self.ess_frac, self.prec = float(ess_frac), prec
+        self.ess_frac, self.prec, self.scheme = float(ess_frac), prec, scheme
         self.T = len(betas) - 1
         self.stream = stream or torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
@@ -82,6 +82,7 @@ class SMCSampler:
 
     def enqueue_step(self, src: int):
         dst = 1 - src
+        self.ctx.set_resampling(self.scheme)
         smc_step(self.ctx, self.model, self.y, self.thetas[src], self.logliks[src],
                  self.thetas[dst], self.logliks[dst], self.logw, self.W, self.beta, self.t,
                  self.step_sd, self.n_moves, self.seed, self.ess_frac, self.prec, self.stats,
@@ -216,10 +217,10 @@ class PTSampler:
 class BatchSampler:
     def __init__(self, ctx: Context, model: Gmm, datas, Ns, seeds, betas, step_sd: float,
                  n_moves: int, ess_frac: float = 0.5, prec: str = "fp32",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, scheme: str = "systematic"):
         if model.d != 1:
             raise ValueError("batched runs are one-dimensional mixtures")
-        self.ctx, self.model = ctx, model
+        self.ctx, self.model, self.scheme = ctx, model, scheme
         self.Ns = [int(x) for x in Ns]
         self.ns = [int(np.asarray(y).size) for y in datas]
         self.seeds = [int(x) for x in seeds]
@@ -271,6 +272,7 @@ class BatchSampler:
             self.n_accept.zero_()
 
     def enqueue_step(self):
+        self.ctx.set_resampling(self.scheme)
         smc_step_batched(self.ctx, self.batch, self.model, self.y, self.theta, self.loglik,
                          self.logw, self.W, self.beta, self.t, self.step_sd, self.n_moves,
                          self.ess_frac, self.prec, self.stats, self.n_accept, stream=self.stream)

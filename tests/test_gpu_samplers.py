@@ -66,6 +66,32 @@ def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph):
     assert np.max(np.abs(r["logw"] - ref["logw"])) <= 1e-9
 
 
+@pytest.mark.parametrize("scheme", ["stratified", "multinomial"])
+def test_smc_other_schemes_match_oracle(smc, ctx, small, scheme):
+    """The small FP64 run with stratified or multinomial resampling (chosen by
+    the context setting, searched inside the first move) equals the oracle's."""
+    cfg, y, betas = small
+    announce(f"smc small fp64 {scheme}")
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                             prior_b=cfg.prior_b)
+    ref = osmc.smc_run(y, om, betas, cfg.N, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac, scheme=scheme)
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac, prec="fp64", scheme=scheme)
+    try:
+        r = s.run(graph=True)
+    finally:
+        ctx.set_resampling("systematic")
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"])) > 0
+    assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+    assert abs(r["logZ"] - ref["logZ"]) <= 1e-3
+
+
 def test_smc_split_tiles_match_oracle(smc, ctx, small, small_oracle):
     """The small run with each tile's data spread over 3 workgroups per move
     (42 slices of 2-3 observations); the fused ancestor search then runs in every
@@ -226,20 +252,26 @@ def _batch_inputs():
     return datas, Ns, seeds
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batched_runs_match_oracle_fp64(smc, ctx, graph):
+@pytest.mark.parametrize("graph,scheme", [(False, "systematic"), (True, "systematic"),
+                                          (True, "multinomial")])
+def test_batched_runs_match_oracle_fp64(smc, ctx, graph, scheme):
     """Every run of a batch equals the oracle's sampler run alone with its own seed."""
-    announce(f"batched fp64 graph={graph}")
+    announce(f"batched fp64 graph={graph} {scheme}")
     datas, Ns, seeds = _batch_inputs()
     betas = beta_schedule(12, "quadratic")
     g = smc.Gmm.equal_weights(4, 1, 0.55)
     om = oracle_model(g)
-    b = smc.BatchSampler(ctx, g, datas, Ns, seeds, betas, 0.5, 1, ess_frac=0.5, prec="fp64")
-    r = b.run(graph=graph)
+    b = smc.BatchSampler(ctx, g, datas, Ns, seeds, betas, 0.5, 1, ess_frac=0.5, prec="fp64",
+                         scheme=scheme)
+    try:
+        r = b.run(graph=graph)
+    finally:
+        ctx.set_resampling("systematic")
     assert r["t"] == 13
     acc_total = 0
     for i in range(len(Ns)):
-        ref = osmc.smc_run(datas[i], om, betas, Ns[i], 0.5, 1, seeds[i], ess_frac=0.5)
+        ref = osmc.smc_run(datas[i], om, betas, Ns[i], 0.5, 1, seeds[i], ess_frac=0.5,
+                           scheme=scheme)
         assert r["resamples"][i] == int(np.sum(ref["trace"]["resampled"])), i
         assert abs(r["logZ"][i] - ref["logZ"]) <= 1e-9 * max(1.0, abs(ref["logZ"])), i
         assert np.max(np.abs(r["theta"][i] - ref["theta"])) <= 1e-9, i

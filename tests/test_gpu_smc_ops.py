@@ -134,6 +134,48 @@ def test_resample_gather_and_predicate(smc, ctx):
     assert np.array_equal(idx2.cpu().numpy(), osmc.systematic_resample(W, osmc.resample_offset(3, 4)))
 
 
+@pytest.mark.parametrize("N", [1, 7, 1000, 2049, 131072, 1 << 20])
+@pytest.mark.parametrize("scheme", ["stratified", "multinomial", "systematic"])
+def test_resample_schemes_bit_exact(smc, ctx, scheme, N):
+    """Every scheme's indices equal the oracle's bit for bit when the GPU is fed
+    the oracle's weights; the points come from each side's own Philox."""
+    announce(f"resample {scheme} N={N}")
+    W = osmc.normalise(lognormal_logw(N, seed=N % 97))
+    idx = torch.empty(N, dtype=torch.int32).cuda()
+    for step in (1, 5):
+        smc.smc_resample(ctx, _cuda(W), scheme, 21, step, idx=idx)
+        assert np.array_equal(idx.cpu().numpy(), osmc.resample_indices(W, scheme, 21, step))
+
+
+@pytest.mark.parametrize("scheme", ["stratified", "multinomial"])
+def test_resample_schemes_degenerate_and_gather(smc, ctx, scheme):
+    announce(f"resample {scheme} degenerate + gather")
+    N, kd = 5000, 4
+    for W in (np.full(N, 1.0 / N), np.eye(1, N, 4321).ravel(),
+              np.where(np.arange(N) % 3 == 0, 1.0, 0.0) / (N // 3 + 1)):
+        W = W / W.sum()
+        idx = torch.empty(N, dtype=torch.int32).cuda()
+        smc.smc_resample(ctx, _cuda(W), scheme, 4, 9, idx=idx)
+        assert np.array_equal(idx.cpu().numpy(), osmc.resample_indices(W, scheme, 4, 9))
+    W = osmc.normalise(lognormal_logw(N, seed=3))
+    theta = np.random.default_rng(0).normal(size=(kd, N))
+    l = np.random.default_rng(1).normal(size=N)
+    th_out = torch.empty((kd, N), dtype=torch.float64).cuda()
+    l_out = torch.empty(N, dtype=torch.float64).cuda()
+    logw = _cuda(np.ones(N))
+    smc.smc_resample(ctx, _cuda(W), scheme, 8, 2, theta_in=_cuda(theta), theta_out=th_out,
+                     l_in=_cuda(l), l_out=l_out, logw=logw)
+    ref = osmc.resample_indices(W, scheme, 8, 2)
+    assert np.array_equal(th_out.cpu().numpy(), theta[:, ref])
+    assert np.array_equal(l_out.cpu().numpy(), l[ref])
+    assert np.all(logw.cpu().numpy() == 0.0)
+    th = _cuda(theta)
+    with pytest.raises(smc.SmcError):                       # aliasing is refused
+        smc.smc_resample(ctx, _cuda(W), "systematic", 8, 2, theta_in=th, theta_out=th)
+    with pytest.raises(KeyError):
+        smc.smc_resample(ctx, _cuda(W), "residual", 8, 2)
+
+
 # ------------------------------------------------------------------ RW-MH move
 
 @pytest.mark.parametrize("slices", [0, 40, 128])
