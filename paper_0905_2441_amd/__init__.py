@@ -25,6 +25,6 @@ from .api import (  # noqa: F401
     smc_step,
     smc_step_batched,
 )
-from .samplers import BatchSampler, PTSampler, SMCSampler  # noqa: F401
+from .samplers import BatchSampler, PTSampler, SMCSampler, mode_census  # noqa: F401
 
 load()

@@ -303,3 +303,29 @@ class BatchSampler:
                     accepted=int(self.n_accept.cpu().item()), t=int(self.t.cpu().item()),
                     theta=[self.theta_of(r).cpu().numpy() for r in range(self.R)],
                     l=[self._slice(self.loglik, r).cpu().numpy() for r in range(self.R)])
+
+
+def mode_census(theta, W=None):
+    """Weight of each of the k! symmetric posterior modes (Mixture Modelling:
+    with exchangeable priors the posterior of the k means is invariant to
+    relabelling). A 1-D particle belongs to the mode given by the ranks of its k
+    means. theta: [k][N] (tensor or array); W: normalised weights (None: equal).
+    Returns {rank tuple: weight share}, the shares summing to one. Host-side
+    analysis of a finished run; nothing here is on the sampling path."""
+    th = theta.detach().cpu().numpy() if isinstance(theta, torch.Tensor) else np.asarray(theta)
+    k, N = th.shape
+    w = (np.full(N, 1.0 / N) if W is None else
+         (W.detach().cpu().numpy() if isinstance(W, torch.Tensor) else np.asarray(W, float)))
+    ranks = np.argsort(np.argsort(th, axis=0, kind="stable"), axis=0, kind="stable")
+    code = np.zeros(N, dtype=np.int64)
+    for c in range(k):
+        code = code * k + ranks[c]
+    shares = np.bincount(code, weights=w, minlength=k ** k)
+    out = {}
+    for v in np.nonzero(shares)[0]:
+        digits, x = [], int(v)
+        for _ in range(k):
+            digits.append(x % k)
+            x //= k
+        out[tuple(reversed(digits))] = float(shares[v])
+    return out
