@@ -34,7 +34,17 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm1d_k4_n1000_N131072"
 OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384",
-                   "batched_256runs", "probes")
+                   "batched_256runs", "probes", "paper_tables")
+
+# The paper's running times on its GTX 280 in seconds (tables of running times
+# in the SMC Sampler and Population-Based MCMC subsections): context for the
+# paper-mode runs, not a target.
+PAPER_GTX280_S = {
+    "smc": {8192: 0.597, 16384: 1.114, 32768: 2.114, 65536: 4.270, 131072: 8.075,
+            262144: 16.219},
+    "pt": {8: 1.083, 32: 1.098, 128: 1.100, 512: 1.235, 2048: 1.427, 8192: 2.323,
+           32768: 7.729, 131072: 28.349},
+}
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
 # 3.93e13 non-packed FP32 VALU lane-operations per second (one wave64 VALU
@@ -417,11 +427,88 @@ def probes(smc, torch, ctx, reps):
     return out
 
 
+def paper_tables(smc, torch, ctx):
+    """The paper's own SMC-sampler and population-MCMC runs, whole runs timed
+    end to end (prior draws, initial likelihoods, every step; FP32 likelihood):
+    uniform prior on [-10, 10]^4, sigma = 0.55 as a scale, m = 100 observations,
+    N(0, I) random walk. SMC: 200 steps of (t/200)^2, 10 moves per step, ESS < N/2
+    resampling. Population MCMC: beta_i = (i/M)^2, random parity with the wrap
+    pair, 8192 iterations. Each shape's launch is autotuned first (untimed)."""
+    import numpy as np
+    from paper_0905_2441_amd import autotune
+    from workloads import beta_schedule, make_data, pt_betas
+    from workloads.configs import paper_mode
+    out = {"smc": {}, "pt": {}}
+    for N in sorted(PAPER_GTX280_S["smc"]):
+        cfg = paper_mode(N)
+        y = make_data(cfg)
+        betas = beta_schedule(cfg.T, cfg.schedule)
+        g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                                  prior_b=cfg.prior_b)
+        ctx.set_launch_table(autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, N, "fp32")], reps=10,
+                                                 exact=True))
+        s = smc.SMCSampler(ctx, g, y, N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                           ess_frac=cfg.ess_frac, prec="fp32")
+        s.run(graph=True, steps_per_graph=STEPS_PER_GRAPH)          # capture and warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.init()
+        s.advance(cfg.T, graph=True, steps_per_graph=STEPS_PER_GRAPH)
+        s.stream.synchronize()
+        dt = time.perf_counter() - t0
+        r = s.results()
+        census = smc.mode_census(r["theta"], r["W"])
+        shares = np.array(list(census.values()))
+        out["smc"][N] = {"s": dt, "gtx280_s": PAPER_GTX280_S["smc"][N],
+                         "speedup_vs_gtx280": PAPER_GTX280_S["smc"][N] / dt,
+                         "evals_per_s": cfg.T * cfg.n_moves * N * cfg.n / dt,
+                         "resamples": r["resamples"], "log_Z": r["logZ"],
+                         "modes_with_1pct": int(np.sum(shares >= 0.01)),
+                         "largest_mode_share": float(shares.max())}
+        log(f"[bench] paper SMC N={N}: {dt * 1e3:.1f} ms "
+            f"({PAPER_GTX280_S['smc'][N] / dt:.0f}x the GTX 280)")
+    cfg = paper_mode(8192)
+    y = make_data(cfg)
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    iters = 8192
+    for M in sorted(PAPER_GTX280_S["pt"]):
+        ctx.set_launch_table(autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, M, "fp32")], reps=10,
+                                                 exact=True))
+        s = smc.PTSampler(ctx, g, y, pt_betas(M, 2), cfg.step_sd, 301, parity_mode=1, wrap=True,
+                          prec="fp32")
+        s.run(2 * STEPS_PER_GRAPH, graph=True, iters_per_graph=STEPS_PER_GRAPH)  # capture, warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.init()
+        s.advance(iters, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+        s.stream.synchronize()
+        dt = time.perf_counter() - t0
+        r = s.results()
+        out["pt"][M] = {"s": dt, "gtx280_s": PAPER_GTX280_S["pt"][M],
+                        "speedup_vs_gtx280": PAPER_GTX280_S["pt"][M] / dt,
+                        "evals_per_s": iters * M * cfg.n / dt, "swaps": r["swaps"]}
+        log(f"[bench] paper PT M={M}: {dt * 1e3:.1f} ms "
+            f"({PAPER_GTX280_S['pt'][M] / dt:.0f}x the GTX 280)")
+    ctx.set_launch_table([])
+    return out
+
+
 def other_workload(args):
     """Secondary measurements (same JSON shape, no CPU baseline)."""
     import torch
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
+
+    if args.workload == "paper_tables":
+        torch.cuda.set_device(0)
+        ctx = smc.Context(0)
+        r = paper_tables(smc, torch, ctx)
+        out = {"metric": "whole-run seconds of the paper's SMC-sampler and population-MCMC runs",
+               "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+               "config": {"workload": "paper_tables"}, "paper_tables": r}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload == "probes":
         torch.cuda.set_device(0)
