@@ -604,36 +604,36 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
         if (e != hipSuccess) return hip_fail(e, "gather launch");
     }
     const Split sp = choose_split(ctx, g, prec, n, N, true);
+    MoveStep first{};
+    first.theta_src = theta_in;
+    first.l_src = loglik_in;
+    first.state = ctx->sc.state;
+    first.W_out = W;
+    first.logw = logw;
+    if (mfma) {
+        first.theta_alt = ctx->sc.theta_tmp;
+        first.l_alt = ctx->sc.l_tmp;
+    } else {
+        first.reset_logw = 1;
+        first.cdf_hi = ctx->sc.cdf_hi;
+        first.cdf_lo = ctx->sc.cdf_lo;
+        first.chunk_tot = ctx->sc.dd_part;
+        first.chunk = chunk;
+        first.nchunks = nchunks;
+        first.seed = seed;
+        first.scheme = ctx->scheme;
+    }
+    if (!mfma) {
+        e = launch_rwmh_moves(g, y, n, theta_out, loglik_out, N, later, step_sd, seed, n_moves,
+                              prec, n_accept, sp, ctx->sc, first, s);
+        if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+        return SMC_OK;
+    }
     for (int m = 0; m < n_moves; ++m) {
-        MoveStep ms{};
-        if (m == 0) {
-            ms.theta_src = theta_in;
-            ms.l_src = loglik_in;
-            ms.state = ctx->sc.state;
-            ms.W_out = W;
-            ms.logw = logw;
-            if (mfma) {
-                ms.theta_alt = ctx->sc.theta_tmp;
-                ms.l_alt = ctx->sc.l_tmp;
-            } else {
-                ms.reset_logw = 1;
-                ms.cdf_hi = ctx->sc.cdf_hi;
-                ms.cdf_lo = ctx->sc.cdf_lo;
-                ms.chunk_tot = ctx->sc.dd_part;
-                ms.chunk = chunk;
-                ms.nchunks = nchunks;
-                ms.seed = seed;
-                ms.scheme = ctx->scheme;
-            }
-        }
-        if (mfma)
-            e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta_out, loglik_out, N, nullptr, later,
-                               step_sd, seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
-                               ctx->sc.mm_prop, ctx->sc.mm_part, choose_dd_slices(ctx, g, n, N),
-                               ctx->sc.status, ms, s);
-        else
-            e = launch_rwmh(g, y, n, theta_out, loglik_out, N, nullptr, later, step_sd, seed,
-                            static_cast<uint32_t>(m), prec, n_accept, sp, ctx->sc, ms, s);
+        e = launch_dd_rwmh(g, ctx->sc.mm_rows, n, theta_out, loglik_out, N, nullptr, later, step_sd,
+                           seed, static_cast<uint32_t>(m), n_accept, ctx->sc.mm_cols,
+                           ctx->sc.mm_prop, ctx->sc.mm_part, choose_dd_slices(ctx, g, n, N),
+                           ctx->sc.status, m == 0 ? first : MoveStep{}, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }
     return SMC_OK;

@@ -221,22 +221,16 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
     __syncthreads();
 }
 
-// Metropolis-Hastings decision for particle p of a random-walk move and the
-// write-back: log alpha = beta (l' - l) + log p0(theta') - log p0(theta); accept
-// iff log alpha >= 0 or log u < log alpha, u from stream (p, 0, step, ACC, move).
-// The current state is column a of (th_src, l_src) (a = p, or p's ancestor
-// after a fused resampling); pr_at(c) returns coordinate c of the proposal. The
-// prior terms are accumulated coordinate by coordinate in index order and the
-// current state is re-read rather than held. The step duties of `ms` publish
-// W and reset logw after resampling.
-template <int KD, class PropAt>
-__device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, double l_prop,
-                                            const MoveSource& srcs, double* theta, double* l,
-                                            const double* beta_vec, const StepSrc& src,
-                                            uint32_t step, uint64_t seed, uint32_t move,
-                                            const GmmDev& g, int* status, const MoveStep& ms) {
-    const double* th_src = srcs.th;
-    const double l_cur = srcs.l[a];
+// Metropolis-Hastings decision for particle p of a random-walk move:
+// log alpha = beta (l' - l) + log p0(theta') - log p0(theta); accept iff
+// log alpha >= 0 or log u < log alpha, u from stream (p, 0, step, ACC, move).
+// cur_at(c) / pr_at(c) return coordinate c of the current state / proposal;
+// the prior terms are accumulated coordinate by coordinate in index order.
+template <int KD, class PropAt, class CurAt>
+__device__ __forceinline__ bool rwmh_decide(int p, PropAt pr_at, CurAt cur_at, double l_cur,
+                                            double l_prop, const double* beta_vec,
+                                            const StepSrc& src, uint32_t step, uint64_t seed,
+                                            uint32_t move, const GmmDev& g) {
     double lp_cur, lp_prop;
     if (g.prior == SMC_PRIOR_GAUSS) {
         const double den = 2.0 * g.pb * g.pb;
@@ -244,7 +238,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
         lp_prop = 0.0;
 #pragma unroll
         for (int c = 0; c < KD; ++c) {
-            const double zc = th_src[static_cast<size_t>(c) * N + a] - g.pa;
+            const double zc = cur_at(c) - g.pa;
             const double zp = pr_at(c) - g.pa;
             lp_cur += g.lp_const - (zc * zc) / den;
             lp_prop += g.lp_const - (zp * zp) / den;
@@ -253,7 +247,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
         bool in_cur = true, in_prop = true;
 #pragma unroll
         for (int c = 0; c < KD; ++c) {
-            const double xc = th_src[static_cast<size_t>(c) * N + a];
+            const double xc = cur_at(c);
             const double xp = pr_at(c);
             in_cur = in_cur && (xc >= g.pa) && (xc <= g.pb);
             in_prop = in_prop && (xp >= g.pa) && (xp <= g.pb);
@@ -266,7 +260,35 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
                                  : (src.beta_dev ? src.beta_dev[step] : src.beta_host);
     const double la = beta * (l_prop - l_cur) + (lp_prop - lp_cur);
     const double u = u01_open(draw(seed, static_cast<uint32_t>(p), 0, step, kAcc, move).w0);
-    const bool acc = (la >= 0.0) || (log(u) < la);
+    return (la >= 0.0) || (log(u) < la);
+}
+
+// The step duties of a move's first launch: publish W (1/N after resampling)
+// and reset logw after resampling.
+__device__ __forceinline__ void move_duties(int p, int N, const MoveStep& ms) {
+    const bool rs = (ms.state != nullptr) && (ms.state->resampled != 0);
+    if (ms.W_out) {
+        ms.W_out[p] = rs ? 1.0 / static_cast<double>(N)
+                         : exp(ms.logw[p] - ms.state->M) / ms.state->S;
+    }
+    if (rs && ms.reset_logw) ms.logw[p] = 0.0;
+}
+
+// Decision and write-back of particle p of a random-walk move. The current
+// state is column a of (th_src, l_src) (a = p, or p's ancestor after a fused
+// resampling) and is re-read rather than held; pr_at(c) returns coordinate c of
+// the proposal. Rejected particles are copied when the move is out of place.
+template <int KD, class PropAt>
+__device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, double l_prop,
+                                            const MoveSource& srcs, double* theta, double* l,
+                                            const double* beta_vec, const StepSrc& src,
+                                            uint32_t step, uint64_t seed, uint32_t move,
+                                            const GmmDev& g, int* status, const MoveStep& ms) {
+    const double* th_src = srcs.th;
+    const double l_cur = srcs.l[a];
+    const bool acc = rwmh_decide<KD>(
+        p, pr_at, [&](int c) { return th_src[static_cast<size_t>(c) * N + a]; }, l_cur, l_prop,
+        beta_vec, src, step, seed, move, g);
     if (acc) {
 #pragma unroll
         for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = pr_at(c);
@@ -278,12 +300,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
         l[p] = l_cur;
     }
     if (l_prop != l_prop) atomicOr(status, kStatusNaN);
-    const bool rs = (ms.state != nullptr) && (ms.state->resampled != 0);
-    if (ms.W_out) {
-        ms.W_out[p] = rs ? 1.0 / static_cast<double>(N)
-                         : exp(ms.logw[p] - ms.state->M) / ms.state->S;
-    }
-    if (rs && ms.reset_logw) ms.logw[p] = 0.0;
+    move_duties(p, N, ms);
     return acc;
 }
 

@@ -119,6 +119,76 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
 }
 
+// Several consecutive moves of one tempering step in one launch (one
+// workgroup per 64-particle tile): the tile's state lives in LDS between moves,
+// wave 0 decides each move and updates it, and the output population, W and
+// logw are written once at the end. The moves of a particle use only its own
+// state, so this equals n_moves separate launches bit for bit.
+template <int K, int D, int PREC>
+__global__ void __launch_bounds__(1024)
+k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N, StepSrc src,
+             double sd, uint64_t seed, uint32_t move0, int n_moves, GmmDev g,
+             unsigned long long* n_acc, int* status, MoveStep ms) {
+    constexpr int KD = K * D;
+    __shared__ double red[kMaxSlices][kWave];
+    __shared__ int anc[kWave];
+    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
+    __shared__ double prs[KD][kWave];
+    __shared__ double cur[KD][kWave];
+    __shared__ double lcur[kWave];
+    const int S = wave_uniform(blockDim.x / kWave);
+    const int lane = lane_id();
+    const int w = wave_uniform(threadIdx.x / kWave);
+    const int p = static_cast<int>(blockIdx.x) * kWave + lane;
+    const int pc = p < N ? p : N - 1;
+    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
+    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    const uint32_t step = static_cast<uint32_t>(step_index(src));
+    const bool fused = (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
+    if (fused) fused_ancestors(ms, N, step, pc, anc, offh, offl);
+    const MoveSource srcs = move_source(ms, theta, l);
+    if (w == 0) {
+        const int a = fused ? anc[lane] : pc;
+#pragma unroll
+        for (int c = 0; c < KD; ++c) cur[c][lane] = srcs.th[static_cast<size_t>(c) * N + a];
+        lcur[lane] = srcs.l[a];
+    }
+    __syncthreads();
+    unsigned long long accepted = 0;
+    for (int m = 0; m < n_moves; ++m) {
+        const uint32_t mv = move0 + static_cast<uint32_t>(m);
+        double pr[KD];
+        block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, mv, &cur[0][0], kWave, lane, sd,
+                            w, S, prs, pr);
+        red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
+        __syncthreads();
+        if (w == 0) {
+            double tot = red[0][lane];
+            for (int q = 1; q < S; ++q) tot += red[q][lane];
+            const double l_prop = finish_loglik<PREC>(tot, n, g);
+            const bool acc = rwmh_decide<KD>(
+                pc, [&](int c) { return pr[c]; }, [&](int c) { return cur[c][lane]; }, lcur[lane],
+                l_prop, nullptr, src, step, seed, mv, g);
+            if (acc) {
+#pragma unroll
+                for (int c = 0; c < KD; ++c) cur[c][lane] = pr[c];
+                lcur[lane] = l_prop;
+            }
+            if (p < N && l_prop != l_prop) atomicOr(status, kStatusNaN);
+            accepted += static_cast<unsigned long long>(__popcll(__ballot(acc && p < N)));
+        }
+        __syncthreads();
+    }
+    if (w != 0) return;
+    if (p < N) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = cur[c][lane];
+        l[p] = lcur[lane];
+        move_duties(p, N, ms);
+    }
+    if (lane == 0 && n_acc != nullptr && accepted != 0ull) atomicAdd(n_acc, accepted);
+}
+
 // Second half of a move whose tile data were split over G workgroups, for
 // particle p: add the G partial sums in group order, re-form the same proposal
 // (same counter, same arithmetic) and take the MH decision.
@@ -310,6 +380,47 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
     SMC_KD_CASES(SMC_CASE)
 #undef SMC_CASE
 #undef SMC_MOVE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double* theta,
+                             double* l, int64_t N, StepSrc src, double sd, uint64_t seed,
+                             int n_moves, int prec, unsigned long long* n_accept, Split sp,
+                             const Scratch& sc, MoveStep ms, hipStream_t s) {
+    if (!valid_split(sp, N) || n_moves < 1) return hipErrorInvalidValue;
+    bool one_launch = false;
+    if (n_moves > 1 && sp.groups == 1) {
+#define SMC_CASE(K, D)                                                                         \
+        if (g.k == K && g.d == D && K * D <= 16) one_launch = true;
+        SMC_KD_CASES(SMC_CASE)
+#undef SMC_CASE
+    }
+    if (!one_launch) {
+        for (int m = 0; m < n_moves; ++m) {
+            const hipError_t e = launch_rwmh(g, y, n, theta, l, N, nullptr, src, sd, seed,
+                                             static_cast<uint32_t>(m), prec, n_accept, sp, sc,
+                                             m == 0 ? ms : MoveStep{}, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
+    const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+#define SMC_MULTI(K, D, P)                                                                     \
+    hipLaunchKernelGGL((k_rwmh_multi<K, D, P>), grid, block, 0, s, y, static_cast<int>(n),     \
+                       theta, l, static_cast<int>(N), src, sd, seed, 0u, n_moves, g, n_accept, \
+                       sc.status, ms)
+#define SMC_CASE(K, D)                                                                         \
+    if constexpr (K * D <= 16) {                                                               \
+        if (g.k == K && g.d == D) {                                                            \
+            if (prec == SMC_PREC_FP32) SMC_MULTI(K, D, SMC_PREC_FP32);                         \
+            else SMC_MULTI(K, D, SMC_PREC_FP64);                                               \
+            return hipGetLastError();                                                          \
+        }                                                                                      \
+    }
+    SMC_KD_CASES(SMC_CASE)
+#undef SMC_CASE
+#undef SMC_MULTI
     return hipErrorInvalidValue;
 }
 

@@ -175,6 +175,13 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
                        uint64_t seed, uint32_t move, int prec,
                        unsigned long long* n_accept, Split sp, const Scratch& sc, MoveStep ms,
                        hipStream_t s);
+// The n_moves moves of one tempering step (move numbers 0..n_moves-1; ms holds
+// the first move's duties): one launch with the tiles' states in LDS when a
+// tile fits one workgroup and k*d <= 16, else one launch per move.
+hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double* theta,
+                             double* l, int64_t N, StepSrc src, double sd, uint64_t seed,
+                             int n_moves, int prec, unsigned long long* n_accept, Split sp,
+                             const Scratch& sc, MoveStep ms, hipStream_t s);
 // One population-MCMC iteration: the move (reading the iteration from src and
 // recording it through ms.t_out), then the exchanges (reading it from later and
 // advancing *t_advance); with groups > 1 the decisions of both run in one kernel.

@@ -92,6 +92,38 @@ def test_smc_other_schemes_match_oracle(smc, ctx, small, scheme):
     assert abs(r["logZ"] - ref["logZ"]) <= 1e-3
 
 
+@pytest.mark.parametrize("slices", [0, 40])
+def test_smc_paper_mode_ten_moves_match_oracle(smc, ctx, slices):
+    """The paper's sampler settings (box prior, sigma = 0.55 as a scale, ten
+    N(0, I) moves per step) over 30 steps, FP64: with one workgroup per tile the
+    ten moves run in one launch (states in LDS); slices = 40 spreads each tile
+    over three workgroups and launches the moves one by one. Both equal the
+    oracle."""
+    from workloads.configs import paper_mode
+    announce(f"smc paper mode ten moves slices={slices}")
+    cfg = paper_mode(512)
+    y = make_data(cfg)
+    betas = beta_schedule(30, "quadratic")
+    g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
+                              prior_b=cfg.prior_b)
+    om = oracle_model(g)
+    ref = osmc.smc_run(y, om, betas, cfg.N, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac)
+    ctx.set_slices(slices)
+    try:
+        s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                           ess_frac=cfg.ess_frac, prec="fp64")
+        r = s.run(graph=True, steps_per_graph=10)
+    finally:
+        ctx.set_slices(0)
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"])) > 0
+    assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+    assert np.max(np.abs(r["W"] - ref["W"])) <= 1e-14
+    assert abs(r["logZ"] - ref["logZ"]) <= 1e-3
+
+
 def test_smc_split_tiles_match_oracle(smc, ctx, small, small_oracle):
     """The small run with each tile's data spread over 3 workgroups per move
     (42 slices of 2-3 observations); the fused ancestor search then runs in every
