@@ -488,6 +488,13 @@ def paper_tables(smc, torch, ctx):
         out["pt"][M] = {"s": dt, "gtx280_s": PAPER_GTX280_S["pt"][M],
                         "speedup_vs_gtx280": PAPER_GTX280_S["pt"][M] / dt,
                         "evals_per_s": iters * M * cfg.n / dt, "swaps": r["swaps"]}
+        if M <= 8192:
+            # untimed: the same run recording the beta = 1 chain after every
+            # iteration, for the iterations it takes to visit all 24 modes
+            s = smc.PTSampler(ctx, g, y, pt_betas(M, 2), cfg.step_sd, 301, parity_mode=1,
+                              wrap=True, prec="fp32", record_chain=M - 1, record_iters=iters)
+            rr = s.run(iters, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+            out["pt"][M]["traversal_iters"] = smc.traversal_time(rr["chain"])
         log(f"[bench] paper PT M={M}: {dt * 1e3:.1f} ms "
             f"({PAPER_GTX280_S['pt'][M] / dt:.0f}x the GTX 280)")
     ctx.set_launch_table([])

@@ -269,6 +269,15 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
                  smc_prec prec, unsigned long long* n_accept, unsigned int* n_swap,
                  void* stream);
 
+/* Record one chain's state after an iteration (graph-replayable; enqueue it
+ * after pt_iteration): with it = *it_dev (the number of finished iterations),
+ * out[(it - 1) * kd + c] = theta[c * M + chain] for c < kd, when
+ * 1 <= it <= max_iters (otherwise nothing is written). out: device FP64
+ * [max_iters][kd]. Used for the mode-traversal time of the beta = 1 chain
+ * (Population-Based MCMC subsection). */
+int pt_record(smc_ctx ctx, const double* theta, int64_t M, int32_t kd, int64_t chain,
+              const int32_t* it_dev, double* out, int64_t max_iters, void* stream);
+
 /* Many independent SMC runs advanced together (serving-style batch).
  * Run r owns particles [p_off, p_off + N) of the concatenated state arrays (its
  * theta block is [k*d][N] at theta + k*d*p_off) and observations

@@ -13,6 +13,7 @@ from .api import (  # noqa: F401
     PREC,
     pt_exchange,
     pt_iteration,
+    pt_record,
     smc_ess,
     smc_loglik,
     smc_prior_init,
@@ -25,6 +26,6 @@ from .api import (  # noqa: F401
     smc_step,
     smc_step_batched,
 )
-from .samplers import BatchSampler, PTSampler, SMCSampler, mode_census  # noqa: F401
+from .samplers import BatchSampler, PTSampler, SMCSampler, mode_census, traversal_time  # noqa: F401
 
 load()

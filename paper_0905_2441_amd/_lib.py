@@ -78,6 +78,7 @@ SIGNATURES = {
     "smc_set_resampling": (c_int, [_P, c_int]),
     "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
                             c_uint64, _P, _P]),
+    "pt_record": (c_int, [_P, _P, c_int64, c_int32, c_int64, _P, _P, c_int64, _P]),
     "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,
                          c_double, c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
     "pt_iteration": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_double, c_uint64,

@@ -269,6 +269,16 @@ def pt_iteration(ctx: Context, model: Gmm, y, theta, loglik, beta, it_dev, step_
         _stream(stream)))
 
 
+def pt_record(ctx: Context, theta, chain, it_dev, out, stream=None):
+    """out[it - 1] = theta[:, chain] after iteration it (out: [max_iters, kd] FP64)."""
+    kd, M = theta.shape
+    if out.dim() != 2 or out.shape[1] != kd:
+        raise ValueError("out must be [max_iters, kd]")
+    L.check(ctx._lib.pt_record(ctx.handle, _ptr(theta, torch.float64, "theta"), M, kd, int(chain),
+                               _ptr(it_dev, torch.int32, "it_dev", 1),
+                               _ptr(out, torch.float64, "out"), out.shape[0], _stream(stream)))
+
+
 def smc_rng_words(seed, count, block, step, purpose, move=0, out=None, stream=None):
     if out is None:
         out = torch.empty((count, 4), dtype=torch.int32, device="cuda")

@@ -684,6 +684,21 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
     return SMC_OK;
 }
 
+int pt_record(smc_ctx ctx, const double* theta, int64_t M, int32_t kd, int64_t chain,
+              const int32_t* it_dev, double* out, int64_t max_iters, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!theta || !it_dev || !out) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (M < 1 || M > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "M must be in 1..2^31-1");
+    if (kd < 1 || kd > SMC_KDMAX) return fail(SMC_ERR_INVALID_ARG, "kd in 1..64");
+    if (chain < 0 || chain >= M) return fail(SMC_ERR_INVALID_ARG, "chain must be in 0..M-1");
+    if (max_iters < 1) return fail(SMC_ERR_INVALID_ARG, "max_iters must be >= 1");
+    const hipError_t e = launch_pt_record(theta, M, kd, chain, it_dev, out, max_iters,
+                                          as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "record launch");
+    return SMC_OK;
+}
+
 int smc_graph_begin(smc_ctx ctx, void* stream) {
     int r = enter(ctx);
     if (r) return r;

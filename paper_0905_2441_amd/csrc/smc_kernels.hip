@@ -324,6 +324,14 @@ k_exchange(double* __restrict__ theta, double* __restrict__ l, const double* __r
     if (pt_swap(theta, l, beta, M, kd, a, b, seed, it) && n_swap) atomicAdd(n_swap, 1u);
 }
 
+__global__ void k_pt_record(const double* __restrict__ theta, int M, int kd, int chain,
+                            const int32_t* it_dev, double* __restrict__ out, int64_t max_iters) {
+    const int64_t it = *it_dev;
+    const int c = threadIdx.x;
+    if (it < 1 || it > max_iters || c >= kd) return;
+    out[(it - 1) * kd + c] = theta[static_cast<size_t>(c) * M + chain];
+}
+
 __global__ void k_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
                             uint32_t purpose, uint32_t move, uint32_t* out) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -468,6 +476,13 @@ hipError_t launch_publish_w(const Scratch& sc, double* W, const double* logw, in
                             hipStream_t s) {
     const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
     hipLaunchKernelGGL(k_publish_w, dim3(g), dim3(kRedBlock), 0, s, W, logw, static_cast<int>(N), sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pt_record(const double* theta, int64_t M, int32_t kd, int64_t chain,
+                            const int32_t* it_dev, double* out, int64_t max_iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_pt_record, dim3(1), dim3(64), 0, s, theta, static_cast<int>(M), kd,
+                       static_cast<int>(chain), it_dev, out, max_iters);
     return hipGetLastError();
 }
 

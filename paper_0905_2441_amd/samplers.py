@@ -19,13 +19,14 @@ exchange moves on one partition of adjacent pairs.
 
 from __future__ import annotations
 
+import math
 from typing import Dict, Optional
 
 import numpy as np
 import torch
 
-from .api import (Batch, Context, Gmm, Graph, pt_iteration, smc_loglik, smc_prior_init,
-                  smc_step, smc_step_batched)
+from .api import (Batch, Context, Gmm, Graph, pt_iteration, pt_record, smc_loglik,
+                  smc_prior_init, smc_step, smc_step_batched)
 
 
 def _dev(x, dtype):
@@ -145,7 +146,8 @@ class SMCSampler:
 class PTSampler:
     def __init__(self, ctx: Context, model: Gmm, y, betas, step_sd: float, seed: int,
                  parity_mode: int = 0, wrap: bool = False, prec: str = "fp32",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, record_chain: Optional[int] = None,
+                 record_iters: int = 0):
         self.ctx, self.model = ctx, model
         self.M = len(betas)
         self.step_sd, self.seed = float(step_sd), int(seed)
@@ -161,6 +163,9 @@ class PTSampler:
             self.n_swap = torch.zeros(1, dtype=torch.int32, device="cuda")
         ctx.reserve(self.M, model.kd, self.y.shape[0] if prec == "bf16x3" else 0)
         self.graphs: Dict[int, Graph] = {}
+        self.record_chain = record_chain
+        self.record = (torch.zeros((int(record_iters), model.kd), dtype=torch.float64,
+                                   device="cuda") if record_chain is not None else None)
 
     def init(self):
         with torch.cuda.stream(self.stream):
@@ -176,6 +181,9 @@ class PTSampler:
         pt_iteration(self.ctx, self.model, self.y, self.theta, self.loglik, self.beta, self.it,
                      self.step_sd, self.seed, self.parity_mode, self.wrap, self.prec,
                      self.n_accept, self.n_swap, stream=self.stream)
+        if self.record is not None:
+            pt_record(self.ctx, self.theta, self.record_chain, self.it, self.record,
+                      stream=self.stream)
 
     def capture(self, iterations: int = 1) -> Graph:
         """A graph of `iterations` consecutive iterations (the iteration index
@@ -211,7 +219,8 @@ class PTSampler:
         self.stream.synchronize()
         return dict(theta=self.theta.cpu().numpy(), l=self.loglik.cpu().numpy(),
                     accepted=int(self.n_accept.cpu().item()),
-                    swaps=int(self.n_swap.cpu().item()), it=int(self.it.cpu().item()))
+                    swaps=int(self.n_swap.cpu().item()), it=int(self.it.cpu().item()),
+                    chain=None if self.record is None else self.record.cpu().numpy())
 
 
 class BatchSampler:
@@ -329,3 +338,22 @@ def mode_census(theta, W=None):
             x //= k
         out[tuple(reversed(digits))] = float(shares[v])
     return out
+
+
+def traversal_time(chain) -> Optional[int]:
+    """Iterations until a recorded chain has visited all k! symmetric modes
+    (Population-Based MCMC subsection); chain: [iterations, k] of 1-D means.
+    None if some mode was never visited."""
+    ch = np.asarray(chain)
+    k = ch.shape[1]
+    ranks = np.argsort(np.argsort(ch, axis=1, kind="stable"), axis=1, kind="stable")
+    code = np.zeros(ch.shape[0], dtype=np.int64)
+    for c in range(k):
+        code = code * k + ranks[:, c]
+    seen = set()
+    need = math.factorial(k)
+    for t, v in enumerate(code):
+        seen.add(int(v))
+        if len(seen) == need:
+            return t + 1
+    return None

@@ -269,6 +269,14 @@ def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices):
     ref = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True)
     assert r["swaps"] == ref["swaps"]
     assert r["accepted"] == ref["accepted"]
+    if slices == 0:
+        # the beta = 1 chain recorded after every iteration, as the oracle records it
+        s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64",
+                          record_chain=M - 1, record_iters=iters)
+        rr = s.run(iters, graph=True, iters_per_graph=4)
+        ref2 = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True,
+                           record_chain=M - 1)
+        assert np.max(np.abs(rr["chain"] - ref2["chain"])) <= 1e-9
     assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
 
 
