@@ -65,9 +65,10 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": None,
-    "fetch_kib": None, "fetch_scale": 2.0,
-    "write_kib": None, "write_scale": 1.0,
+    "sources_sha256": "8c948fe4e7ce8312f1e436a35d887adce69c00b18c252de9a879b8370e5f575a",
+    "fetch_kib": 2716.0, "fetch_scale": 2.0,
+    "write_kib": 32.18, "write_scale": 1.0,
+    "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
 }
 
 
@@ -488,13 +489,15 @@ def paper_tables(smc, torch, ctx):
         out["pt"][M] = {"s": dt, "gtx280_s": PAPER_GTX280_S["pt"][M],
                         "speedup_vs_gtx280": PAPER_GTX280_S["pt"][M] / dt,
                         "evals_per_s": iters * M * cfg.n / dt, "swaps": r["swaps"]}
-        if M <= 8192:
-            # untimed: the same run recording the beta = 1 chain after every
+        if M <= 2048:
+            # untimed: a longer run recording the beta = 1 chain after every
             # iteration, for the iterations it takes to visit all 24 modes
+            long = 8 * iters
             s = smc.PTSampler(ctx, g, y, pt_betas(M, 2), cfg.step_sd, 301, parity_mode=1,
-                              wrap=True, prec="fp32", record_chain=M - 1, record_iters=iters)
-            rr = s.run(iters, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+                              wrap=True, prec="fp32", record_chain=M - 1, record_iters=long)
+            rr = s.run(long, graph=True, iters_per_graph=STEPS_PER_GRAPH)
             out["pt"][M]["traversal_iters"] = smc.traversal_time(rr["chain"])
+            out["pt"][M]["traversal_run"] = long
         log(f"[bench] paper PT M={M}: {dt * 1e3:.1f} ms "
             f"({PAPER_GTX280_S['pt'][M] / dt:.0f}x the GTX 280)")
     ctx.set_launch_table([])
