@@ -59,8 +59,8 @@ def propagate(model, x, seed, t):
 
 def particle_filter(y, model, N, seed, ess_frac=0.5):
     """Run the filter over y [T][M]. Returns dict(loglik, loglik_inc [T], mean [T][K],
-    sd [T][K], ess [T], resampled [T], x, logw) with x, logw the final population
-    before its resampling (the GPU adopts a resampling at the start of the next step)."""
+    sd [T][K], ess [T], resampled [T], x, logw, x_end, logw_end): x, logw are the
+    final population before its resampling, x_end, logw_end after it."""
     y = np.asarray(y, dtype=np.float64)
     T = y.shape[0]
     K = model.k
@@ -85,6 +85,7 @@ def particle_filter(y, model, N, seed, ess_frac=0.5):
             idx = systematic_resample(W, resample_offset(seed, t))
             x = x[:, idx]
             logw = np.zeros(N)
+    out["x_end"], out["logw_end"] = x, logw             # after the last step's resampling
     out["loglik"] = float(np.sum(out["loglik_inc"]))
     for key in ("loglik_inc", "ess"):
         out[key] = np.asarray(out[key])

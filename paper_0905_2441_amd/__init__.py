@@ -10,6 +10,8 @@ from ._lib import SmcError, load  # noqa: F401
 from .api import (  # noqa: F401
     Context,
     Gmm,
+    fsv_init,
+    fsv_step,
     PREC,
     pt_exchange,
     pt_iteration,
@@ -26,6 +28,7 @@ from .api import (  # noqa: F401
     smc_step,
     smc_step_batched,
 )
-from .samplers import BatchSampler, PTSampler, SMCSampler, mode_census, traversal_time  # noqa: F401
+from .samplers import (BatchSampler, FSVFilter, PTSampler, SMCSampler,  # noqa: F401
+                       mode_census, traversal_time)
 
 load()

@@ -48,6 +48,16 @@ class SmcRunDesc(Structure):
                 ("seed", c_uint64)]
 
 
+SMC_FSV_MMAX = 8
+SMC_FSV_KMAX = 4
+
+
+class SmcFsv(Structure):
+    _fields_ = [("m", c_int32), ("k", c_int32), ("B", c_double * (SMC_FSV_MMAX * SMC_FSV_KMAX)),
+                ("psi", c_double * SMC_FSV_MMAX), ("phi", c_double * SMC_FSV_KMAX),
+                ("U", c_double * (SMC_FSV_KMAX * SMC_FSV_KMAX))]
+
+
 class SmcLaunchRule(Structure):
     _fields_ = [("k", c_int32), ("d", c_int32), ("prec", c_int32), ("slices", c_int32),
                 ("n_lo", c_int64), ("n_hi", c_int64), ("N_lo", c_int64), ("N_hi", c_int64)]
@@ -56,7 +66,8 @@ class SmcLaunchRule(Structure):
 _P = c_void_p
 _GP = POINTER(SmcGmm)
 
-# name -> (restype, argtypes); every function declared in include/smc.h.
+# name -> (restype, argtypes); every function declared in include/smc.h and
+# include/smc_fsv.h.
 SIGNATURES = {
     "smc_create": (c_int, [POINTER(c_void_p), c_int]),
     "smc_destroy": (c_int, [_P]),
@@ -79,6 +90,9 @@ SIGNATURES = {
     "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
                             c_uint64, _P, _P]),
     "pt_record": (c_int, [_P, _P, c_int64, c_int32, c_int64, _P, _P, c_int64, _P]),
+    "fsv_init": (c_int, [_P, c_int32, c_int64, _P, _P, _P]),
+    "fsv_step": (c_int, [_P, POINTER(SmcFsv), _P, c_int32, c_int64, _P, _P, _P, _P, c_uint64,
+                         c_double, _P, _P, _P]),
     "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,
                          c_double, c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
     "pt_iteration": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_double, c_uint64,

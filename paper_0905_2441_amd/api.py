@@ -279,6 +279,42 @@ def pt_record(ctx: Context, theta, chain, it_dev, out, stream=None):
                                _ptr(out, torch.float64, "out"), out.shape[0], _stream(stream)))
 
 
+def _fsv_struct(model) -> "L.SmcFsv":
+    """smc_fsv from any object with B (m x k), psi (m), phi (k), U (k x k)."""
+    st = L.SmcFsv()
+    m, k = len(model.psi), len(model.phi)
+    st.m, st.k = m, k
+    for i in range(m):
+        st.psi[i] = float(model.psi[i])
+        for c in range(k):
+            st.B[i * L.SMC_FSV_KMAX + c] = float(model.B[i][c])
+    for c in range(k):
+        st.phi[c] = float(model.phi[c])
+        for j in range(k):
+            st.U[c * L.SMC_FSV_KMAX + j] = float(model.U[c][j])
+    return st
+
+
+def fsv_init(ctx: Context, x, logw, stream=None):
+    k, N = x.shape
+    L.check(ctx._lib.fsv_init(ctx.handle, k, N, _ptr(x, torch.float64, "x"),
+                              _ptr(logw, torch.float64, "logw", N), _stream(stream)))
+
+
+def fsv_step(ctx: Context, model, y, x, x_tmp, logw, t_dev, seed, ess_frac, stats, moments,
+             stream=None):
+    """One particle-filter step of the factor stochastic-volatility model
+    (C ABI fsv_step); y: [T, m] FP64 device tensor."""
+    T = y.shape[0]
+    k, N = x.shape
+    L.check(ctx._lib.fsv_step(
+        ctx.handle, ctypes.byref(_fsv_struct(model)), _ptr(y, torch.float64, "y"), T, N,
+        _ptr(x, torch.float64, "x"), _ptr(x_tmp, torch.float64, "x_tmp", k * N),
+        _ptr(logw, torch.float64, "logw", N), _ptr(t_dev, torch.int32, "t_dev", 1), int(seed),
+        float(ess_frac), _ptr(stats, torch.float64, "stats", 4),
+        _ptr(moments, torch.float64, "moments", T * 2 * k), _stream(stream)))
+
+
 def smc_rng_words(seed, count, block, step, purpose, move=0, out=None, stream=None):
     if out is None:
         out = torch.empty((count, 4), dtype=torch.int32, device="cuda")

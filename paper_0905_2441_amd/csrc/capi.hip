@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "fsv.hpp"
 #include "internal.hpp"
 #include "wave.hpp"
 
@@ -24,6 +25,7 @@ struct smc_ctx_s {
     void* grow = nullptr;        // cdf, dd partials, l_tmp, theta_tmp
     int64_t grow_kd = 0;
     void* mm = nullptr;          // MFMA form: data rows, columns, proposals, partials
+    double* fsv_mom = nullptr;   // particle filter: per-block moment sums (in `fixed`)
 };
 
 struct smc_graph_s {
@@ -274,7 +276,8 @@ int smc_create(smc_ctx* out, int device) {
     const size_t b_state = align_up(sizeof(StepState));
     const size_t b_mv = align_up(sizeof(double) * kMaxGroups * kSplitCap);
     const size_t b_anc = align_up(sizeof(int) * kSplitCap);
-    const size_t total = b_part + b_sq + b_dd + b_st + b_state + b_mv + b_anc;
+    const size_t b_fsv = align_up(sizeof(double) * kMaxRedBlocks * 2 * SMC_FSV_KMAX);
+    const size_t total = b_part + b_sq + b_dd + b_st + b_state + b_mv + b_anc + b_fsv;
     void* p = nullptr;
     if (hipMalloc(&p, total) != hipSuccess) {
         delete ctx;
@@ -294,6 +297,8 @@ int smc_create(smc_ctx* out, int device) {
     ctx->sc.state = reinterpret_cast<StepState*>(c + b_part + b_sq + b_dd + b_st);
     ctx->sc.mv_part = reinterpret_cast<double*>(c + b_part + b_sq + b_dd + b_st + b_state);
     ctx->sc.mv_anc = reinterpret_cast<int*>(c + b_part + b_sq + b_dd + b_st + b_state + b_mv);
+    ctx->fsv_mom =
+        reinterpret_cast<double*>(c + b_part + b_sq + b_dd + b_st + b_state + b_mv + b_anc);
     *out = ctx;
     return SMC_OK;
 }
@@ -696,6 +701,93 @@ int pt_record(smc_ctx ctx, const double* theta, int64_t M, int32_t kd, int64_t c
     const hipError_t e = launch_pt_record(theta, M, kd, chain, it_dev, out, max_iters,
                                           as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "record launch");
+    return SMC_OK;
+}
+
+int fsv_init(smc_ctx ctx, int32_t k, int64_t N, double* x, double* logw, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (k < 1 || k > SMC_FSV_KMAX) return fail(SMC_ERR_INVALID_ARG, "k in 1..4");
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!x || !logw) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    const hipError_t e = launch_fsv_init(k, N, x, logw, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    return SMC_OK;
+}
+
+namespace {
+
+// Lower Cholesky factor of the k x k matrix U (row-major); false if U is not
+// positive definite.
+bool host_cholesky(const double* U, int k, double* L) {
+    for (int i = 0; i < SMC_FSV_KMAX * SMC_FSV_KMAX; ++i) L[i] = 0.0;
+    for (int i = 0; i < k; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = U[i * SMC_FSV_KMAX + j];
+            for (int q = 0; q < j; ++q) s -= L[i * SMC_FSV_KMAX + q] * L[j * SMC_FSV_KMAX + q];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * SMC_FSV_KMAX + i] = sqrt(s);
+            } else {
+                L[i * SMC_FSV_KMAX + j] = s / L[j * SMC_FSV_KMAX + j];
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int64_t N,
+             double* x, double* x_tmp, double* logw, int32_t* t_dev, uint64_t seed,
+             double ess_frac, double* stats, double* moments, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!model) return fail(SMC_ERR_INVALID_ARG, "model is NULL");
+    if (!fsv_supported(model->m, model->k))
+        return fail(SMC_ERR_UNSUPPORTED, "(m, k) of the factor model is not compiled");
+    if (T < 1) return fail(SMC_ERR_INVALID_ARG, "T must be >= 1");
+    if (N < 1 || N > INT32_MAX) return fail(SMC_ERR_INVALID_ARG, "N must be in 1..2^31-1");
+    if (!y || !x || !x_tmp || !logw || !t_dev || !stats || !moments)
+        return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (x == x_tmp) return fail(SMC_ERR_INVALID_ARG, "x_tmp must not alias x");
+    if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
+    FsvDev f{};
+    f.m = model->m;
+    f.k = model->k;
+    for (int i = 0; i < f.m; ++i) {
+        if (!(model->psi[i] > 0.0) || !isfinite(model->psi[i]))
+            return fail(SMC_ERR_INVALID_ARG, "psi must be finite and > 0");
+        f.psi[i] = model->psi[i];
+        for (int c = 0; c < f.k; ++c) {
+            if (!isfinite(model->B[i * SMC_FSV_KMAX + c]))
+                return fail(SMC_ERR_INVALID_ARG, "B must be finite");
+            f.B[i * SMC_FSV_KMAX + c] = model->B[i * SMC_FSV_KMAX + c];
+        }
+    }
+    for (int c = 0; c < f.k; ++c) {
+        if (!isfinite(model->phi[c])) return fail(SMC_ERR_INVALID_ARG, "phi must be finite");
+        f.phi[c] = model->phi[c];
+    }
+    if (!host_cholesky(model->U, f.k, f.L))
+        return fail(SMC_ERR_INVALID_ARG, "U is not symmetric positive definite");
+    f.cst = -0.5 * f.m * log(2.0 * M_PI);
+    const hipStream_t s = as_stream(stream);
+    if ((r = ensure_scratch(ctx, N, f.k, s))) return r;
+    StepSrc src{};
+    src.t_dev = t_dev;
+    src.t_max = T;
+    StepSrc later{};
+    later.t_dev = &ctx->sc.state->t;
+    hipError_t e = launch_fsv_weight(f, y, T, x, x_tmp, logw, N, src, seed, ctx->sc,
+                                     ctx->fsv_mom, s);
+    if (e == hipSuccess) e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s);
+    if (e == hipSuccess)
+        e = launch_fsv_moments(f.k, fsv_parts(N), ctx->sc, ctx->fsv_mom, moments, s);
+    if (e == hipSuccess)
+        e = launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, x_tmp, x,
+                                 f.k, nullptr, nullptr, logw, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "particle filter launch");
     return SMC_OK;
 }
 

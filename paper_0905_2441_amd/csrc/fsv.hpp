@@ -1,0 +1,30 @@
+// Factor stochastic-volatility particle filter: device model and launchers.
+#pragma once
+#include "../../include/smc_fsv.h"
+#include "internal.hpp"
+
+namespace smc {
+
+// Model constants as the kernels consume them (built on the host per call).
+struct FsvDev {
+    int m, k;
+    double B[SMC_FSV_MMAX * SMC_FSV_KMAX];
+    double psi[SMC_FSV_MMAX];
+    double phi[SMC_FSV_KMAX];
+    double L[SMC_FSV_KMAX * SMC_FSV_KMAX];      // lower Cholesky factor of U, row-major
+    double cst;                                 // -(m/2) ln(2 pi)
+};
+
+bool fsv_supported(int m, int k);
+// Number of per-block partials the weight pass writes (as the step's combine expects).
+int fsv_parts(int64_t N);
+hipError_t launch_fsv_init(int k, int64_t N, double* x, double* logw, hipStream_t s);
+// Propagate + weight + reweight partials (sc.rw_part) + moment partials (mom).
+hipError_t launch_fsv_weight(const FsvDev& f, const double* y, int T, const double* x,
+                             double* x_out, double* logw, int64_t N, StepSrc src, uint64_t seed,
+                             const Scratch& sc, double* mom, hipStream_t s);
+// Weighted moments of step state->t from the partials into moments[t-1].
+hipError_t launch_fsv_moments(int k, int parts, const Scratch& sc, const double* mom,
+                              double* moments, hipStream_t s);
+
+}  // namespace smc

@@ -25,8 +25,8 @@ from typing import Dict, Optional
 import numpy as np
 import torch
 
-from .api import (Batch, Context, Gmm, Graph, pt_iteration, pt_record, smc_loglik,
-                  smc_prior_init, smc_step, smc_step_batched)
+from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, pt_iteration, pt_record,
+                  smc_loglik, smc_prior_init, smc_step, smc_step_batched)
 
 
 def _dev(x, dtype):
@@ -357,3 +357,74 @@ def traversal_time(chain) -> Optional[int]:
         if len(seen) == need:
             return t + 1
     return None
+
+
+class FSVFilter:
+    """Bootstrap particle filter of the factor stochastic-volatility model over
+    observations y [T, m]; the step index lives on the device, so a graph of
+    several steps replays anywhere in the run."""
+
+    def __init__(self, ctx: Context, model, y, N: int, seed: int, ess_frac: float = 0.5,
+                 stream: Optional[torch.cuda.Stream] = None, scheme: str = "systematic"):
+        self.ctx, self.model, self.N, self.seed = ctx, model, int(N), int(seed)
+        self.ess_frac, self.scheme = float(ess_frac), scheme
+        self.k = len(model.phi)
+        self.stream = stream or torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.y = _dev(np.asarray(y, dtype=np.float64), torch.float64)
+            self.T = int(self.y.shape[0])
+            self.x = torch.zeros((self.k, self.N), dtype=torch.float64, device="cuda")
+            self.x_tmp = torch.empty_like(self.x)
+            self.logw = torch.zeros(self.N, dtype=torch.float64, device="cuda")
+            self.t = torch.ones(1, dtype=torch.int32, device="cuda")
+            self.stats = torch.zeros(4, dtype=torch.float64, device="cuda")
+            self.moments = torch.zeros((self.T, 2 * self.k), dtype=torch.float64, device="cuda")
+        ctx.reserve(self.N, self.k)
+        self.graphs: Dict[int, Graph] = {}
+
+    def init(self):
+        with torch.cuda.stream(self.stream):
+            fsv_init(self.ctx, self.x, self.logw, stream=self.stream)
+            self.t.fill_(1)
+            self.stats.zero_()
+
+    def enqueue_step(self):
+        self.ctx.set_resampling(self.scheme)
+        fsv_step(self.ctx, self.model, self.y, self.x, self.x_tmp, self.logw, self.t, self.seed,
+                 self.ess_frac, self.stats, self.moments, stream=self.stream)
+
+    def capture(self, steps: int = 1) -> Graph:
+        g = self.graphs.get(steps)
+        if g is None:
+            g = Graph(self.ctx, self.stream)
+            with g:
+                for _ in range(steps):
+                    self.enqueue_step()
+            self.graphs[steps] = g
+        return g
+
+    def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 1):
+        done = 0
+        while done < steps:
+            c = min(int(steps_per_graph), steps - done)
+            if graph:
+                self.capture(c).launch()
+            else:
+                for _ in range(c):
+                    self.enqueue_step()
+            done += c
+
+    def run(self, graph: bool = True, steps_per_graph: int = 1):
+        self.init()
+        self.advance(self.T, graph, steps_per_graph)
+        self.stream.synchronize()
+        self.ctx.check(self.stream)
+        return self.results()
+
+    def results(self):
+        self.stream.synchronize()
+        st = self.stats.cpu().numpy()
+        mom = self.moments.cpu().numpy()
+        return dict(loglik=float(st[0]), ess=float(st[1]), resamples=int(st[2]),
+                    mean=mom[:, :self.k], sd=mom[:, self.k:], x=self.x.cpu().numpy(),
+                    logw=self.logw.cpu().numpy(), t=int(self.t.cpu().item()))

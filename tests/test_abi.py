@@ -1,5 +1,5 @@
-"""The C-ABI library loads and exports every function include/smc.h declares
-(no compute call: runs without a GPU)."""
+"""The C-ABI library loads and exports every function the headers in include/
+declare (no compute call: runs without a GPU)."""
 
 import ctypes
 import os
@@ -8,12 +8,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "smc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("smc.h", "smc_fsv.h")]
 LIB = os.path.join(ROOT, "paper_0905_2441_amd", "libsmcgpu.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?(?:int|char\s*\*|void)\s*\**\s*(\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))

@@ -1,0 +1,75 @@
+"""GPU parity of the factor stochastic-volatility particle filter against the
+FP64 oracle on the same seeded observations and Philox streams."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce
+from oracle import fsv as ofsv
+from workloads.fsv import PAPER_FSV, FsvModel, simulate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import paper_0905_2441_amd as smc
+    return smc
+
+
+@pytest.fixture(scope="module")
+def ctx(smc):
+    return smc.Context(0)
+
+
+def _compare(r, ref, N):
+    assert r["resamples"] == int(ref["resampled"].sum())
+    assert abs(r["loglik"] - ref["loglik"]) <= 1e-9 * max(1.0, abs(ref["loglik"]))
+    assert np.max(np.abs(r["mean"] - ref["mean"])) <= 1e-9
+    assert np.max(np.abs(r["sd"] - ref["sd"])) <= 1e-8
+    assert np.max(np.abs(r["x"] - ref["x_end"])) <= 1e-11
+    assert np.max(np.abs(r["logw"] - ref["logw_end"])) <= 1e-9 * max(1.0, np.abs(ref["logw_end"]).max())
+
+
+@pytest.mark.parametrize("N,graph", [(1000, False), (1000, True), (1, False), (4097, True)])
+def test_fsv_paper_model_matches_oracle(smc, ctx, N, graph):
+    announce(f"fsv paper model N={N} graph={graph}")
+    _, y = simulate(PAPER_FSV, 40, 11)
+    f = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=5)
+    r = f.run(graph=graph, steps_per_graph=7)
+    assert r["t"] == 41
+    ref = ofsv.particle_filter(y, PAPER_FSV, N, 5)
+    _compare(r, ref, N)
+
+
+@pytest.mark.parametrize("model", [FsvModel(B=((1.1,),), psi=(0.5,), phi=(0.9,), U=((0.5,),)),
+                                   FsvModel(B=((1.0, 0.0), (0.4, 0.8)), psi=(0.3, 0.6),
+                                            phi=(0.95, 0.8), U=((0.4, 0.1), (0.1, 0.3)))])
+def test_fsv_small_models_match_oracle(smc, ctx, model):
+    announce(f"fsv m={model.m} k={model.k}")
+    _, y = simulate(model, 30, 3)
+    r = smc.FSVFilter(ctx, model, y, 2000, seed=8).run(graph=True, steps_per_graph=10)
+    _compare(r, ofsv.particle_filter(y, model, 2000, 8), 2000)
+
+
+def test_fsv_paper_length_run(smc, ctx):
+    """T = 200 observations, N = 16384 particles, as in the paper's runs."""
+    announce("fsv T=200 N=16384")
+    x_true, y = simulate(PAPER_FSV, 200, 7)
+    r = smc.FSVFilter(ctx, PAPER_FSV, y, 16384, seed=3).run(graph=True, steps_per_graph=10)
+    ref = ofsv.particle_filter(y, PAPER_FSV, 16384, 3)
+    _compare(r, ref, 16384)
+    assert np.corrcoef(r["mean"][:, 0], x_true[1:, 0])[0, 1] > 0.5
+
+
+def test_fsv_rejects_bad_models(smc, ctx):
+    _, y = simulate(PAPER_FSV, 5, 1)
+    import dataclasses
+    bad_u = dataclasses.replace(PAPER_FSV, U=((1.0, 2.0, 0.0), (2.0, 1.0, 0.0), (0.0, 0.0, 1.0)))
+    with pytest.raises(smc.SmcError):
+        smc.FSVFilter(ctx, bad_u, y, 64, seed=1).run(graph=False)
+    unsupported = FsvModel(B=((1.0, 0.0, 0.0),) * 4, psi=(0.5,) * 4, phi=(0.9,) * 3,
+                           U=PAPER_FSV.U)
+    with pytest.raises(smc.SmcError):
+        smc.FSVFilter(ctx, unsupported, y[:, :4], 64, seed=1).run(graph=False)
