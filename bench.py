@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm1d_k4_n1000_N131072"
 OTHER_WORKLOADS = ("gmm1d_k4_n100_N1024", "pt_k4_n10000_M8192", "gmm8d_k8_n65536_N16384",
-                   "batched_256runs", "probes", "paper_tables")
+                   "batched_256runs", "probes", "paper_tables", "fsv_pf")
 
 # The paper's running times on its GTX 280 in seconds (tables of running times
 # in the SMC Sampler and Population-Based MCMC subsections): context for the
@@ -44,6 +44,8 @@ PAPER_GTX280_S = {
             262144: 16.219},
     "pt": {8: 1.083, 32: 1.098, 128: 1.100, 512: 1.235, 2048: 1.427, 8192: 2.323,
            32768: 7.729, 131072: 28.349},
+    # factor stochastic-volatility particle filter, T = 200 (Factor Stochastic Volatility)
+    "fsv": {8192: 0.082, 16384: 0.144, 32768: 0.249, 65536: 0.465, 131072: 0.929},
 }
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
@@ -504,11 +506,46 @@ def paper_tables(smc, torch, ctx):
     return out
 
 
+def fsv_runs(smc, torch, ctx):
+    """The paper's particle filter for the factor stochastic-volatility model:
+    m = 5, k = 3, T = 200 simulated observations, FP64, whole runs timed end to end
+    at the paper's N and at 2^20 (ten filter steps per graph)."""
+    from workloads.fsv import PAPER_FSV, simulate
+    _, y = simulate(PAPER_FSV, 200, 7)
+    out = {}
+    for N in sorted(PAPER_GTX280_S["fsv"]) + [1 << 20]:
+        f = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=3)
+        f.run(graph=True, steps_per_graph=STEPS_PER_GRAPH)             # capture and warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.init()
+        f.advance(f.T, graph=True, steps_per_graph=STEPS_PER_GRAPH)
+        f.stream.synchronize()
+        dt = time.perf_counter() - t0
+        r = f.results()
+        ref = PAPER_GTX280_S["fsv"].get(N)
+        out[N] = {"s": dt, "us_per_step": dt / f.T * 1e6, "particle_steps_per_s": N * f.T / dt,
+                  "loglik": r["loglik"], "resamples": r["resamples"],
+                  "gtx280_s": ref, "speedup_vs_gtx280": (ref / dt) if ref else None}
+        log(f"[bench] fsv N={N}: {dt * 1e3:.2f} ms" + (f" ({ref / dt:.0f}x the GTX 280)" if ref else ""))
+    return out
+
+
 def other_workload(args):
     """Secondary measurements (same JSON shape, no CPU baseline)."""
     import torch
     import paper_0905_2441_amd as smc
     from workloads import CONFIGS, beta_schedule, make_data
+
+    if args.workload == "fsv_pf":
+        torch.cuda.set_device(0)
+        ctx = smc.Context(0)
+        r = fsv_runs(smc, torch, ctx)
+        out = {"metric": "whole-run seconds of the factor stochastic-volatility particle filter",
+               "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+               "config": {"workload": "fsv_pf", "m": 5, "k": 3, "T": 200}, "fsv": r}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload == "paper_tables":
         torch.cuda.set_device(0)
