@@ -50,11 +50,12 @@ PAPER_GTX280_S = {
 
 # Issue-slot model of gfx950: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz =
 # 3.93e13 non-packed FP32 VALU lane-operations per second (one wave64 VALU
-# instruction per SIMD every 4 cycles). Every instruction of the algorithm,
-# the hardware exp2 included, is counted as one slot: the batched workload's
-# long-data moves sustain 0.89 of this peak with one exp per six instructions,
-# so an exp costs no more than a slot in this mix (a model charging it two
-# slots would put that kernel above 100%).
+# instruction per SIMD every 4 cycles). `frac` counts every instruction of the
+# algorithm, the hardware exp2 included, as one slot (a lower bound on the
+# pipeline's occupancy); the counters show v_exp_f32 holding the VALU for two
+# issue cycles, so the roofline also reports the fraction with exp charged
+# two slots and the counter-measured VALU-busy share. (The part clocks at
+# about 2.47 GHz under this load, so the two-slot fraction can pass 1.)
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 TRANS_SLOTS = 1.0
 HBM_PEAK_GBS = 8000.0
@@ -67,14 +68,18 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "8c948fe4e7ce8312f1e436a35d887adce69c00b18c252de9a879b8370e5f575a",
+    "sources_sha256": "75753bded19240e8e192a487a25e08ec3fb988bf05e4fc6f7de2912ba7d37497",
     "fetch_kib": 2716.0, "fetch_scale": 2.0,
     "write_kib": 32.18, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
+    # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
+    # same launches: the share of SIMD cycles the VALU pipeline was issuing
+    # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
+    "valu_busy": 0.972,
 }
 
 
-# the files the move kernel is compiled from (with the build flags in build.py)
+# the files the move kernel is compiled from (with the compiler flags of build.py)
 MOVE_SOURCES = ("gmm_kernels.hip", "gmm_common.hpp", "exchange.hpp", "internal.hpp",
                 "philox.hpp", "wave.hpp", "dd.hpp", "../../include/smc.h")
 
@@ -86,9 +91,19 @@ def kernel_sources_sha256() -> str:
     for name in MOVE_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
-    with open(os.path.join(ROOT, "paper_0905_2441_amd", "build.py"), "rb") as f:
-        h.update(f.read())
+    # and the compiler flags (the CXXFLAGS assignment of the build script)
+    import re
+    with open(os.path.join(ROOT, "paper_0905_2441_amd", "build.py")) as f:
+        flags = re.search(r"^CXXFLAGS = \[.*?\]", f.read(), flags=re.S | re.M)
+    h.update(flags.group(0).encode() if flags else b"?")
     return h.hexdigest()
+
+
+def move_valu_busy():
+    """Counter-measured VALU-busy share of the dominant kernel, or None if the
+    counters were taken on other kernel sources."""
+    c = MOVE_COUNTERS
+    return c["valu_busy"] if c["sources_sha256"] == kernel_sources_sha256() else None
 
 
 def move_traffic():
@@ -282,6 +297,11 @@ def main():
         "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
+        # the hardware issues v_exp_f32 over two VALU cycles (SQ_ACTIVE_INST_VALU -
+        # SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32); charged so, an evaluation is
+        # 28 slots and the same kernel time is this fraction of the peak
+        "frac_exp_two_slots": kern_evals * (ops_per_eval(cfg.k) + cfg.k) / PEAK_LANE_OPS,
+        "valu_busy_measured": move_valu_busy(),
         "kernel_ms": r32["kernel_ms"],
         "kernel_evals_per_s": kern_evals,
     }
