@@ -114,6 +114,7 @@ def move_traffic():
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 STEPS_PER_GRAPH = 10    # tempering steps per hipGraph replay
+PT_ITERS_PER_GRAPH = 64  # population-MCMC iterations per replay in the paper's runs
 
 
 def ops_per_eval(k: int) -> float:
@@ -456,7 +457,9 @@ def paper_tables(smc, torch, ctx):
     uniform prior on [-10, 10]^4, sigma = 0.55 as a scale, m = 100 observations,
     N(0, I) random walk. SMC: 200 steps of (t/200)^2, 10 moves per step, ESS < N/2
     resampling. Population MCMC: beta_i = (i/M)^2, random parity with the wrap
-    pair, 8192 iterations. Each shape's launch is autotuned first (untimed)."""
+    pair, 8192 iterations, 64 per graph replay (small populations run a
+    replay's iterations in one single-workgroup launch). Each shape's launch is
+    autotuned first (untimed)."""
     import numpy as np
     from paper_0905_2441_amd import autotune
     from workloads import beta_schedule, make_data, pt_betas
@@ -500,11 +503,11 @@ def paper_tables(smc, torch, ctx):
                                                  exact=True))
         s = smc.PTSampler(ctx, g, y, pt_betas(M, 2), cfg.step_sd, 301, parity_mode=1, wrap=True,
                           prec="fp32")
-        s.run(2 * STEPS_PER_GRAPH, graph=True, iters_per_graph=STEPS_PER_GRAPH)  # capture, warm
+        s.run(2 * PT_ITERS_PER_GRAPH, graph=True, iters_per_graph=PT_ITERS_PER_GRAPH)  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.init()
-        s.advance(iters, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+        s.advance(iters, graph=True, iters_per_graph=PT_ITERS_PER_GRAPH)
         s.stream.synchronize()
         dt = time.perf_counter() - t0
         r = s.results()

@@ -269,6 +269,27 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
                  smc_prec prec, unsigned long long* n_accept, unsigned int* n_swap,
                  void* stream);
 
+/* n_iters consecutive pt_iteration calls: the same arguments, the same random
+ * streams and the same results (bit for bit, for the same data slicing).
+ * Small populations run all n_iters iterations in one launch of a single
+ * workgroup that keeps the chains' states in LDS and takes each iteration's
+ * exchanges there; this needs FP32 or FP64, M at most 1024 chains at
+ * k*d <= 4 (576 at 7, 512 at 8, 256 at 16) and, by default, a small iteration
+ * (64-chain tiles x n x k*d <= 2^17; see pt_set_single_workgroup). Otherwise
+ * n_iters iterations are enqueued. The single launch takes smc_set_slices'
+ * value (at most 16 waves in all) or its own choice. *it_dev advances by
+ * n_iters; n_iters < 1 is an argument error. */
+int pt_iterations(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
+                  double* theta, double* loglik, const double* beta, int32_t* it_dev,
+                  int32_t n_iters, double step_sd, uint64_t seed, int32_t parity_mode,
+                  int32_t wrap, smc_prec prec, unsigned long long* n_accept,
+                  unsigned int* n_swap, void* stream);
+
+/* When pt_iterations uses its single-workgroup form: mode 0 (default) when
+ * the population fits and the iteration is small, 1 whenever the population
+ * fits, -1 never. */
+int pt_set_single_workgroup(smc_ctx ctx, int32_t mode);
+
 /* Record one chain's state after an iteration (graph-replayable; enqueue it
  * after pt_iteration): with it = *it_dev (the number of finished iterations),
  * out[(it - 1) * kd + c] = theta[c * M + chain] for c < kd, when

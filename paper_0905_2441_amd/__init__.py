@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     PREC,
     pt_exchange,
     pt_iteration,
+    pt_iterations,
     pt_record,
     smc_ess,
     smc_loglik,

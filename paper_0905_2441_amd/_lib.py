@@ -75,6 +75,7 @@ SIGNATURES = {
     "smc_check": (c_int, [_P, _P]),
     "smc_last_error": (c_char_p, []),
     "smc_set_slices": (c_int, [_P, c_int32]),
+    "pt_set_single_workgroup": (c_int, [_P, c_int32]),
     "smc_set_launch_table": (c_int, [_P, POINTER(SmcLaunchRule), c_int32]),
     "smc_loglik": (c_int, [_P, _GP, _P, c_int64, _P, c_int64, c_int, _P, _P]),
     "smc_prior_init": (c_int, [_P, _GP, c_int64, c_uint64, _P, _P]),
@@ -89,6 +90,8 @@ SIGNATURES = {
     "smc_set_resampling": (c_int, [_P, c_int]),
     "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
                             c_uint64, _P, _P]),
+    "pt_iterations": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_int32, c_double,
+                              c_uint64, c_int32, c_int32, c_int, _P, _P, _P]),
     "pt_record": (c_int, [_P, _P, c_int64, c_int32, c_int64, _P, _P, c_int64, _P]),
     "fsv_init": (c_int, [_P, c_int32, c_int64, _P, _P, _P]),
     "fsv_step": (c_int, [_P, POINTER(SmcFsv), _P, c_int32, c_int64, _P, _P, _P, _P, c_uint64,

@@ -115,6 +115,11 @@ class Context:
     def set_slices(self, slices: int) -> None:
         L.check(self._lib.smc_set_slices(self.handle, int(slices)))
 
+    def set_pt_single_workgroup(self, mode: int) -> None:
+        """pt_iterations' single-workgroup form: 0 automatic, 1 whenever the
+        population fits, -1 never."""
+        L.check(self._lib.pt_set_single_workgroup(self.handle, int(mode)))
+
     def set_resampling(self, scheme: str) -> None:
         """Resampling scheme of later smc_step / smc_step_batched calls."""
         L.check(self._lib.smc_set_resampling(self.handle, SCHEME[scheme]))
@@ -265,6 +270,20 @@ def pt_iteration(ctx: Context, model: Gmm, y, theta, loglik, beta, it_dev, step_
         _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", M),
         _ptr(beta, torch.float64, "beta", M), _ptr(it_dev, torch.int32, "it_dev", 1),
         float(step_sd), int(seed), int(parity_mode), int(bool(wrap)), _prec(prec),
+        _opt(n_accept, torch.int64, "n_accept", 1), _opt(n_swap, torch.int32, "n_swap", 1),
+        _stream(stream)))
+
+
+def pt_iterations(ctx: Context, model: Gmm, y, theta, loglik, beta, it_dev, n_iters, step_sd,
+                  seed, parity_mode=0, wrap=False, prec="fp32", n_accept=None, n_swap=None,
+                  stream=None):
+    n = _data_shape(model, y)
+    M = _theta_shape(model, theta)
+    L.check(ctx._lib.pt_iterations(
+        ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n, M,
+        _ptr(theta, torch.float64, "theta"), _ptr(loglik, torch.float64, "loglik", M),
+        _ptr(beta, torch.float64, "beta", M), _ptr(it_dev, torch.int32, "it_dev", 1),
+        int(n_iters), float(step_sd), int(seed), int(parity_mode), int(bool(wrap)), _prec(prec),
         _opt(n_accept, torch.int64, "n_accept", 1), _opt(n_swap, torch.int32, "n_swap", 1),
         _stream(stream)))
 

@@ -18,6 +18,7 @@ using namespace smc;
 struct smc_ctx_s {
     int device = 0;
     int slices_override = 0;
+    int pt_single = 0;                        // pt_set_single_workgroup mode
     int scheme = SMC_RESAMPLE_SYSTEMATIC;
     std::vector<smc_launch_rule> table;
     Scratch sc{};
@@ -349,6 +350,13 @@ int smc_set_slices(smc_ctx ctx, int32_t slices) {
     if (slices < 0 || slices > kMaxSlices * kMaxGroups)
         return fail(SMC_ERR_INVALID_ARG, "slices in 0..128");
     ctx->slices_override = slices;
+    return SMC_OK;
+}
+
+int pt_set_single_workgroup(smc_ctx ctx, int32_t mode) {
+    if (!ctx) return fail(SMC_ERR_INVALID_ARG, "context is NULL");
+    if (mode < -1 || mode > 1) return fail(SMC_ERR_INVALID_ARG, "mode in -1..1");
+    ctx->pt_single = mode;
     return SMC_OK;
 }
 
@@ -685,6 +693,43 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
     e = launch_pt_iteration(g, y, n, theta, loglik, M, beta, src, later, step_sd, seed, prec,
                             n_accept, choose_split(ctx, g, prec, n, M, true), ctx->sc, ms,
                             parity_mode, wrap ? 1 : 0, it_dev, n_swap, s);
+    if (e != hipSuccess) return hip_fail(e, "population MCMC launch");
+    return SMC_OK;
+}
+
+int pt_iterations(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
+                  double* theta, double* loglik, const double* beta, int32_t* it_dev,
+                  int32_t n_iters, double step_sd, uint64_t seed, int32_t parity_mode,
+                  int32_t wrap, smc_prec prec, unsigned long long* n_accept,
+                  unsigned int* n_swap, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (n_iters < 1) return fail(SMC_ERR_INVALID_ARG, "n_iters must be >= 1");
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, M))) return r;
+    const int kd = g.k * g.d;
+    const bool local = prec != SMC_PREC_BF16X3 && M >= 2 && M <= pt_local_chains(kd) &&
+                       (ctx->pt_single > 0 || (ctx->pt_single == 0 && pt_local_pays(kd, n, M)));
+    if (!local) {
+        for (int32_t i = 0; i < n_iters; ++i) {
+            r = pt_iteration(ctx, model, y, n, M, theta, loglik, beta, it_dev, step_sd, seed,
+                             parity_mode, wrap, prec, n_accept, n_swap, stream);
+            if (r) return r;
+        }
+        return SMC_OK;
+    }
+    if (!y || !theta || !loglik || !beta || !it_dev) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (parity_mode != 0 && parity_mode != 1) return fail(SMC_ERR_INVALID_ARG, "parity_mode 0 or 1");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    const hipError_t e = launch_pt_local(g, y, n, theta, loglik, M, beta, it_dev, n_iters,
+                                         step_sd, seed, prec, parity_mode, wrap ? 1 : 0,
+                                         ctx->slices_override > 0 ? ctx->slices_override
+                                                                  : pt_local_slices(n, M),
+                                         n_accept, n_swap,
+                                         ctx->sc.status, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "population MCMC launch");
     return SMC_OK;
 }

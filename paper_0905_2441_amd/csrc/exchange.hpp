@@ -50,14 +50,14 @@ __device__ __forceinline__ bool pt_slot(int M, int parity, int wrap, int q, int&
     return false;
 }
 
-// The exchange decision of pair (a, b) with the uniform of stream
-// (a, 0, it, EXCH, 0); on acceptance the two columns of theta [kd][M] and the
-// two log-likelihoods are swapped in place. Returns whether they were.
-__device__ __forceinline__ bool pt_swap(double* theta, double* l, const double* beta, int M,
-                                        int kd, int a, int b, uint64_t seed, uint32_t it) {
-    const double la = (beta[a] - beta[b]) * (l[b] - l[a]);
-    const double u = u01_open(draw(seed, static_cast<uint32_t>(a), 0, it, kExch, 0).w0);
-    if (!(la >= 0.0 || log(u) < la)) return false;
+// log u of the exchange test of the pair led by chain a: stream (a, 0, it, EXCH, 0).
+__device__ __forceinline__ double pt_log_u(int a, uint64_t seed, uint32_t it) {
+    return log(u01_open(draw(seed, static_cast<uint32_t>(a), 0, it, kExch, 0).w0));
+}
+
+// Swap columns a and b of theta [kd][M] (row stride M) and of l.
+__device__ __forceinline__ void pt_swap_columns(double* theta, double* l, int M, int kd, int a,
+                                                int b) {
     const double t = l[a];
     l[a] = l[b];
     l[b] = t;
@@ -67,7 +67,22 @@ __device__ __forceinline__ bool pt_swap(double* theta, double* l, const double* 
         r[a] = r[b];
         r[b] = x;
     }
+}
+
+// The exchange decision of pair (a, b) given log u; on acceptance the two
+// states are swapped in place. Returns whether they were.
+__device__ __forceinline__ bool pt_swap_given(double* theta, double* l, const double* beta, int M,
+                                              int kd, int a, int b, double log_u) {
+    const double la = (beta[a] - beta[b]) * (l[b] - l[a]);
+    if (!(la >= 0.0 || log_u < la)) return false;
+    pt_swap_columns(theta, l, M, kd, a, b);
     return true;
+}
+
+// The exchange decision of pair (a, b) with the uniform of its own stream.
+__device__ __forceinline__ bool pt_swap(double* theta, double* l, const double* beta, int M,
+                                        int kd, int a, int b, uint64_t seed, uint32_t it) {
+    return pt_swap_given(theta, l, beta, M, kd, a, b, pt_log_u(a, seed, it));
 }
 
 }  // namespace smc

@@ -65,6 +65,7 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         expo += __builtin_amdgcn_frexp_expf(prod);
         prod = __builtin_amdgcn_frexp_mantf(prod);
     }
+#pragma unroll 4
     for (; j < j1; ++j) {
         float m, e;
         datum(y + (size_t)j * D, m, e);
@@ -221,16 +222,15 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
     __syncthreads();
 }
 
-// Metropolis-Hastings decision for particle p of a random-walk move:
-// log alpha = beta (l' - l) + log p0(theta') - log p0(theta); accept iff
-// log alpha >= 0 or log u < log alpha, u from stream (p, 0, step, ACC, move).
+// Metropolis-Hastings log acceptance ratio for particle p of a random-walk
+// move: log alpha = beta (l' - l) + log p0(theta') - log p0(theta).
 // cur_at(c) / pr_at(c) return coordinate c of the current state / proposal;
 // the prior terms are accumulated coordinate by coordinate in index order.
 template <int KD, class PropAt, class CurAt>
-__device__ __forceinline__ bool rwmh_decide(int p, PropAt pr_at, CurAt cur_at, double l_cur,
-                                            double l_prop, const double* beta_vec,
-                                            const StepSrc& src, uint32_t step, uint64_t seed,
-                                            uint32_t move, const GmmDev& g) {
+__device__ __forceinline__ double rwmh_log_alpha(int p, PropAt pr_at, CurAt cur_at, double l_cur,
+                                                 double l_prop, const double* beta_vec,
+                                                 const StepSrc& src, uint32_t step,
+                                                 const GmmDev& g) {
     double lp_cur, lp_prop;
     if (g.prior == SMC_PRIOR_GAUSS) {
         const double den = 2.0 * g.pb * g.pb;
@@ -258,9 +258,22 @@ __device__ __forceinline__ bool rwmh_decide(int p, PropAt pr_at, CurAt cur_at, d
     }
     const double beta = beta_vec ? beta_vec[p]
                                  : (src.beta_dev ? src.beta_dev[step] : src.beta_host);
-    const double la = beta * (l_prop - l_cur) + (lp_prop - lp_cur);
-    const double u = u01_open(draw(seed, static_cast<uint32_t>(p), 0, step, kAcc, move).w0);
-    return (la >= 0.0) || (log(u) < la);
+    return beta * (l_prop - l_cur) + (lp_prop - lp_cur);
+}
+
+// log u of the acceptance test of particle p, u from stream (p, 0, step, ACC, move).
+__device__ __forceinline__ double rwmh_log_u(int p, uint32_t step, uint64_t seed, uint32_t move) {
+    return log(u01_open(draw(seed, static_cast<uint32_t>(p), 0, step, kAcc, move).w0));
+}
+
+// Metropolis-Hastings decision: accept iff log alpha >= 0 or log u < log alpha.
+template <int KD, class PropAt, class CurAt>
+__device__ __forceinline__ bool rwmh_decide(int p, PropAt pr_at, CurAt cur_at, double l_cur,
+                                            double l_prop, const double* beta_vec,
+                                            const StepSrc& src, uint32_t step, uint64_t seed,
+                                            uint32_t move, const GmmDev& g) {
+    const double la = rwmh_log_alpha<KD>(p, pr_at, cur_at, l_cur, l_prop, beta_vec, src, step, g);
+    return (la >= 0.0) || (rwmh_log_u(p, step, seed, move) < la);
 }
 
 // The step duties of a move's first launch: publish W (1/N after resampling)

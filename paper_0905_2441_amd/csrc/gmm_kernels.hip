@@ -189,6 +189,135 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
     if (lane == 0 && n_acc != nullptr && accepted != 0ull) atomicAdd(n_acc, accepted);
 }
 
+// Data (floats) the one-launch population-MCMC kernel stages in LDS.
+constexpr int kPtLocalData = 2048;
+
+// Several population-MCMC iterations in one launch of one workgroup, for
+// populations small enough that every chain's state fits in LDS. The
+// workgroup's waves are `tiles` 64-chain tiles x S data slices. An iteration
+// has three phases separated by barriers:
+//   1. every wave forms its tile's proposals (state + sd * the normals held in
+//      LDS) and sums its data slice;
+//   2. the first wave of each tile adds the slices and decides each chain's
+//      move at its own beta, while the tile's other waves draw the next
+//      iteration's random numbers (normals, log u of the acceptance and
+//      exchange tests, the partition parity) into LDS;
+//   3. the workgroup takes the iteration's exchanges on the LDS states.
+// The chains' states, their betas and (when n d <= kPtLocalData) the data
+// stay in LDS for the whole launch.
+// The random numbers are drawn from the same streams and with the same
+// arithmetic as in separate iterations, so the results (bit for bit, for the
+// same slicing) equal those of n_iters pt_iteration calls. The iteration
+// index is read once from the caller's counter, which ends advanced by n_iters.
+template <int K, int D, int PREC, int MAXC>
+__global__ void __launch_bounds__(1024)
+k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
+           const double* __restrict__ beta, int* it_dev, int n_iters, double sd, uint64_t seed,
+           int parity_mode, int wrap, int S, GmmDev g, unsigned long long* n_acc,
+           unsigned* n_swap, int* status) {
+    constexpr int KD = K * D;
+    constexpr int NP = (KD + 1) / 2;            // Box-Muller pairs per chain
+    constexpr int NITEM = NP + 2;               // + the acceptance and exchange uniforms
+    __shared__ double red[kMaxSlices][kWave];
+    __shared__ double cur[KD][MAXC];
+    __shared__ double zs[KD][MAXC];             // the coming iteration's normals
+    __shared__ double lcur[MAXC];
+    __shared__ double lua[2][MAXC];             // log u of the acceptance tests
+    __shared__ double lux[2][MAXC];             // log u of the exchange led by each chain
+    __shared__ double lbeta[MAXC];
+    __shared__ float ys[kPtLocalData];          // the data, when they fit
+    __shared__ int par[2];
+    const int lane = lane_id();
+    const int w = wave_uniform(threadIdx.x / kWave);
+    const int tile = w / S;
+    const int sl = w - tile * S;
+    const int col = tile * kWave + lane;          // chain held by this lane
+    const int cc = col < M ? col : M - 1;
+    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / S));
+    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / S));
+    // random items of chain col for iteration it, items first, first + stride, ...
+    auto draw_items = [&](uint32_t it, int buf, int first, int stride) {
+        for (int i = first; i < NITEM; i += stride) {
+            if (i < NP) {
+                const Words4 wd = draw(seed, static_cast<uint32_t>(cc), static_cast<uint32_t>(i / 2),
+                                       it, kProp, 0);
+                double z0, z1;
+                if (i & 1) box_muller(wd.w2, wd.w3, z0, z1);
+                else box_muller(wd.w0, wd.w1, z0, z1);
+                zs[2 * i][col] = z0;
+                if (2 * i + 1 < KD) zs[2 * i + 1][col] = z1;
+            } else if (i == NP) {
+                lua[buf][col] = rwmh_log_u(cc, it, seed, 0);
+            } else {
+                lux[buf][col] = pt_log_u(cc, seed, it);
+                if (col == 0) par[buf] = pt_parity(parity_mode, 0, seed, it);
+            }
+        }
+    };
+    const int it0 = *it_dev;
+    if (sl == 0) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) cur[c][col] = theta[static_cast<size_t>(c) * M + cc];
+        lcur[col] = l[cc];
+        lbeta[col] = beta[cc];
+    }
+    const bool stage = static_cast<int64_t>(n) * D <= kPtLocalData;
+    if (stage)
+        for (int i = threadIdx.x; i < n * D; i += blockDim.x) ys[i] = y[i];
+    const float* yl = stage ? ys : y;
+    draw_items(static_cast<uint32_t>(it0), 0, sl, S);
+    __syncthreads();
+    unsigned long long accepted = 0;
+    unsigned swaps = 0;
+    for (int m = 0; m < n_iters; ++m) {
+        const uint32_t it = static_cast<uint32_t>(it0 + m);
+        const int buf = m & 1;
+        double pr[KD];
+#pragma unroll
+        for (int c = 0; c < KD; ++c) pr[c] = cur[c][col] + sd * zs[c][col];
+        red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g);
+        __syncthreads();
+        if (sl == 0) {
+            double tot = red[w][lane];
+            for (int q = 1; q < S; ++q) tot += red[w + q][lane];
+            const double l_prop = finish_loglik<PREC>(tot, n, g);
+            const double la = rwmh_log_alpha<KD>(
+                col, [&](int c) { return pr[c]; }, [&](int c) { return cur[c][col]; }, lcur[col],
+                l_prop, lbeta, StepSrc{}, it, g);
+            const bool acc = (la >= 0.0) || (lua[buf][col] < la);
+            if (acc) {
+#pragma unroll
+                for (int c = 0; c < KD; ++c) cur[c][col] = pr[c];
+                lcur[col] = l_prop;
+            }
+            if (col < M && l_prop != l_prop) atomicOr(status, kStatusNaN);
+            accepted += static_cast<unsigned long long>(__popcll(__ballot(acc && col < M)));
+        }
+        if (m + 1 < n_iters) {
+            if (S == 1) draw_items(it + 1u, buf ^ 1, 0, 1);
+            else if (sl > 0) draw_items(it + 1u, buf ^ 1, sl - 1, S - 1);
+        }
+        __syncthreads();
+        const int parity = par[buf];
+        for (int q = threadIdx.x;; q += blockDim.x) {
+            int a, b;
+            if (!pt_slot(M, parity, wrap, q, a, b)) break;
+            if (b < 0) continue;
+            if (pt_swap_given(&cur[0][0], lcur, lbeta, MAXC, KD, a, b, lux[buf][a])) ++swaps;
+        }
+        __syncthreads();
+    }
+    if (sl == 0 && col < M) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * M + col] = cur[c][col];
+        l[col] = lcur[col];
+    }
+    if (sl == 0 && lane == 0 && n_acc != nullptr && accepted != 0ull) atomicAdd(n_acc, accepted);
+    if (n_swap != nullptr && swaps != 0u) atomicAdd(n_swap, swaps);
+    __syncthreads();
+    if (threadIdx.x == 0) *it_dev = it0 + n_iters;
+}
+
 // Second half of a move whose tile data were split over G workgroups, for
 // particle p: add the G partial sums in group order, re-form the same proposal
 // (same counter, same arithmetic) and take the MH decision.
@@ -421,6 +550,68 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
     SMC_KD_CASES(SMC_CASE)
 #undef SMC_CASE
 #undef SMC_MULTI
+    return hipErrorInvalidValue;
+}
+
+// Chains per workgroup of the one-launch form: at most 4096 state doubles
+// (two 32 KB arrays in LDS at k*d = 4), in whole 64-chain tiles, at most 16 tiles.
+constexpr int kPtLocalCap = 4096;
+
+constexpr int pt_local_cap(int kd) {
+    return kd > 16 ? 0 : ((kPtLocalCap / kd) / kWave * kWave < 1024 ? (kPtLocalCap / kd) / kWave * kWave : 1024);
+}
+
+int pt_local_chains(int kd) { return kd < 1 ? 0 : pt_local_cap(kd); }
+
+// One workgroup runs on one compute unit, so the single-launch form pays off
+// only while an iteration's likelihood work (64-lane tiles x n data x k*d) is
+// small enough that the launches it saves cost more than the parallelism it
+// gives up: measured on the paper's population-MCMC runs (n = 100, k = 4), up
+// to 256 chains at n = 100 and about 32 at n = 1000.
+constexpr int64_t kPtLocalWork = int64_t{1} << 17;
+
+bool pt_local_pays(int kd, int64_t n, int64_t M) {
+    const int64_t tiles = (M + kWave - 1) / kWave;
+    return tiles * kWave * n * kd <= kPtLocalWork;
+}
+
+int pt_local_slices(int64_t n, int64_t M) {
+    const int tiles = static_cast<int>((M + kWave - 1) / kWave);
+    int S = 8 / tiles;                       // about eight waves in all
+    const int64_t by_data = n / 12;          // at least a dozen data per slice
+    if (by_data < S) S = static_cast<int>(by_data);
+    return S < 1 ? 1 : S;
+}
+
+hipError_t launch_pt_local(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
+                           int64_t M, const double* beta, int* it_dev, int n_iters, double sd,
+                           uint64_t seed, int prec, int parity_mode, int wrap, int slices,
+                           unsigned long long* n_accept, unsigned* n_swap, int* status,
+                           hipStream_t s) {
+    const int kd = g.k * g.d;
+    const int tiles = static_cast<int>((M + kWave - 1) / kWave);
+    if (M < 2 || M > pt_local_chains(kd) || tiles > kMaxSlices) return hipErrorInvalidValue;
+    int S = slices < 1 ? 1 : slices;
+    if (S * tiles > kMaxSlices) S = kMaxSlices / tiles;
+    if (S > n) S = static_cast<int>(n);
+    if (S < 1) S = 1;
+    const dim3 block(static_cast<unsigned>(kWave * tiles * S));
+#define SMC_LOCAL(K, D, P, C)                                                                  \
+    hipLaunchKernelGGL((k_pt_local<K, D, P, C>), dim3(1), block, 0, s, y, static_cast<int>(n), \
+                       theta, l, static_cast<int>(M), beta, it_dev, n_iters, sd, seed,         \
+                       parity_mode, wrap, S, g, n_accept, n_swap, status)
+#define SMC_CASE(K, D)                                                                         \
+    if constexpr (K * D <= 16) {                                                               \
+        if (g.k == K && g.d == D) {                                                            \
+            constexpr int C = pt_local_cap(K * D);                                              \
+            if (prec == SMC_PREC_FP32) SMC_LOCAL(K, D, SMC_PREC_FP32, C);                      \
+            else SMC_LOCAL(K, D, SMC_PREC_FP64, C);                                            \
+            return hipGetLastError();                                                          \
+        }                                                                                      \
+    }
+    SMC_KD_CASES(SMC_CASE)
+#undef SMC_CASE
+#undef SMC_LOCAL
     return hipErrorInvalidValue;
 }
 

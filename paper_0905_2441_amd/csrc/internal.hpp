@@ -182,6 +182,17 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
                              double* l, int64_t N, StepSrc src, double sd, uint64_t seed,
                              int n_moves, int prec, unsigned long long* n_accept, Split sp,
                              const Scratch& sc, MoveStep ms, hipStream_t s);
+// Largest population the one-workgroup population-MCMC form holds (0: none).
+int pt_local_chains(int kd);
+bool pt_local_pays(int kd, int64_t n, int64_t M);
+int pt_local_slices(int64_t n, int64_t M);
+// n_iters population-MCMC iterations in one single-workgroup launch (chains in
+// LDS; M <= pt_local_chains(k*d)); `slices` data slices per 64-chain tile.
+hipError_t launch_pt_local(const GmmDev& g, const float* y, int64_t n, double* theta, double* l,
+                           int64_t M, const double* beta, int* it_dev, int n_iters, double sd,
+                           uint64_t seed, int prec, int parity_mode, int wrap, int slices,
+                           unsigned long long* n_accept, unsigned* n_swap, int* status,
+                           hipStream_t s);
 // One population-MCMC iteration: the move (reading the iteration from src and
 // recording it through ms.t_out), then the exchanges (reading it from later and
 // advancing *t_advance); with groups > 1 the decisions of both run in one kernel.

@@ -25,8 +25,8 @@ from typing import Dict, Optional
 import numpy as np
 import torch
 
-from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, pt_iteration, pt_record,
-                  smc_loglik, smc_prior_init, smc_step, smc_step_batched)
+from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, pt_iteration, pt_iterations,
+                  pt_record, smc_loglik, smc_prior_init, smc_step, smc_step_batched)
 
 
 def _dev(x, dtype):
@@ -147,9 +147,10 @@ class PTSampler:
     def __init__(self, ctx: Context, model: Gmm, y, betas, step_sd: float, seed: int,
                  parity_mode: int = 0, wrap: bool = False, prec: str = "fp32",
                  stream: Optional[torch.cuda.Stream] = None, record_chain: Optional[int] = None,
-                 record_iters: int = 0):
+                 record_iters: int = 0, fused_iterations: bool = True):
         self.ctx, self.model = ctx, model
         self.M = len(betas)
+        self.fused = bool(fused_iterations)
         self.step_sd, self.seed = float(step_sd), int(seed)
         self.parity_mode, self.wrap, self.prec = int(parity_mode), bool(wrap), prec
         self.stream = stream or torch.cuda.Stream()
@@ -185,6 +186,18 @@ class PTSampler:
             pt_record(self.ctx, self.theta, self.record_chain, self.it, self.record,
                       stream=self.stream)
 
+    def enqueue_iterations(self, count: int):
+        """`count` iterations: one pt_iterations call (a single launch for small
+        populations) unless the target chain is recorded after every iteration
+        or the sampler was made with fused_iterations=False."""
+        if self.record is not None or not self.fused:
+            for _ in range(count):
+                self.enqueue_iteration()
+            return
+        pt_iterations(self.ctx, self.model, self.y, self.theta, self.loglik, self.beta, self.it,
+                      count, self.step_sd, self.seed, self.parity_mode, self.wrap, self.prec,
+                      self.n_accept, self.n_swap, stream=self.stream)
+
     def capture(self, iterations: int = 1) -> Graph:
         """A graph of `iterations` consecutive iterations (the iteration index
         lives on the device, so one graph serves every position in the run)."""
@@ -192,8 +205,7 @@ class PTSampler:
         if g is None:
             g = Graph(self.ctx, self.stream)
             with g:
-                for _ in range(iterations):
-                    self.enqueue_iteration()
+                self.enqueue_iterations(iterations)
             self.graphs[iterations] = g
         return g
 
@@ -204,8 +216,7 @@ class PTSampler:
             if graph:
                 self.capture(c).launch()
             else:
-                for _ in range(c):
-                    self.enqueue_iteration()
+                self.enqueue_iterations(c)
             done += c
 
     def run(self, iterations: int, graph: bool = True, iters_per_graph: int = 1):

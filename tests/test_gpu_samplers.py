@@ -223,11 +223,13 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     print(f"fp32 flipped decisions: {flips} of {decisions}")
 
 
-@pytest.mark.parametrize("slices,iters_per_graph", [(0, 1), (24, 7)])
-def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph):
+@pytest.mark.parametrize("slices,iters_per_graph,fused", [(0, 1, False), (24, 7, False),
+                                                          (0, 7, True), (3, 25, True)])
+def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph, fused):
     """slices = 24 spreads each tile over 2 workgroups; 7 iterations per graph
-    leave a ragged last graph (25 = 3 * 7 + 4)."""
-    announce(f"pt small fp64 slices={slices} iters_per_graph={iters_per_graph}")
+    leave a ragged last graph (25 = 3 * 7 + 4); fused runs each graph's
+    iterations in one single-workgroup launch."""
+    announce(f"pt small fp64 slices={slices} iters_per_graph={iters_per_graph} fused={fused}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     y = make_mixture_data(300, mu, 0.55, seed=3)
     M, iters = 128, 25
@@ -235,11 +237,14 @@ def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph):
     g = smc.Gmm.equal_weights(4, 1, 0.55)
     om = oracle_model(g)
     ctx.set_slices(slices)
+    ctx.set_pt_single_workgroup(1 if fused else 0)
     try:
-        s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=103, parity_mode=0, wrap=False, prec="fp64")
+        s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=103, parity_mode=0, wrap=False, prec="fp64",
+                          fused_iterations=fused)
         r = s.run(iters, graph=True, iters_per_graph=iters_per_graph)
     finally:
         ctx.set_slices(0)
+        ctx.set_pt_single_workgroup(0)
     ref = osmc.pt_run(y, om, betas, iters, 0.5, 103, parity_mode="alternate", wrap=False)
     assert r["it"] == iters
     assert r["swaps"] == ref["swaps"]
@@ -248,12 +253,13 @@ def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph):
     assert rel_err(r["l"], ref["l"]).max() <= 1e-10
 
 
-@pytest.mark.parametrize("M,slices", [(32, 0), (32, 40), (33, 24)])
-def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices):
+@pytest.mark.parametrize("M,slices,fused", [(32, 0, False), (32, 40, False), (33, 24, False),
+                                            (32, 0, True), (33, 5, True)])
+def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices, fused):
     """Random parity with the wrap pair; slices > 16 run the moves' decisions and
     the exchanges in one kernel (pairs, the wrap pair, and for odd M the
     unpaired chain 0)."""
-    announce(f"pt paper mode M={M} slices={slices}")
+    announce(f"pt paper mode M={M} slices={slices} fused={fused}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     y = make_mixture_data(100, mu, 0.3025, seed=1)
     iters = 15
@@ -262,14 +268,15 @@ def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices):
     om = oracle_model(g)
     ctx.set_slices(slices)
     try:
-        s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64")
+        s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64",
+                          fused_iterations=fused)
         r = s.run(iters, graph=False)
     finally:
         ctx.set_slices(0)
     ref = osmc.pt_run(y, om, betas, iters, 1.0, 7, parity_mode="random", wrap=True)
     assert r["swaps"] == ref["swaps"]
     assert r["accepted"] == ref["accepted"]
-    if slices == 0:
+    if slices == 0 and not fused:
         # the beta = 1 chain recorded after every iteration, as the oracle records it
         s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=7, parity_mode=1, wrap=True, prec="fp64",
                           record_chain=M - 1, record_iters=iters)

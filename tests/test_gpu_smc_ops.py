@@ -355,6 +355,98 @@ def test_exchange_matches_oracle(smc, ctx, M, parity, wrap):
     assert ns.item() == n_ref
 
 
+# ------------------------------------------------------------------ several PT iterations
+
+@pytest.mark.parametrize("k,d,prec,M,slices,parity,wrap,iters", [
+    (4, 1, "fp32", 1024, 1, 0, False, 6),      # 16 tiles: the largest population at k*d = 4
+    (4, 1, "fp64", 100, 8, 1, True, 9),        # ragged tile, random parity with the wrap pair
+    (7, 1, "fp64", 576, 1, 1, True, 5),        # k*d = 7: 576 chains in LDS
+    (2, 8, "fp32", 256, 4, 0, False, 4),       # k*d = 16: 256 chains
+    (1, 1, "fp32", 2, 16, 1, False, 11),       # two chains, 16 slices of one tile
+    (4, 1, "fp32", 1025, 0, 0, False, 3),      # past the single-workgroup form: per iteration
+])
+def test_pt_iterations_equal_single_iterations(smc, ctx, k, d, prec, M, slices, parity, wrap,
+                                               iters):
+    """pt_iterations(n) leaves exactly the state, counter and tallies of n
+    pt_iteration calls with the same launch shape (both sum a tile's slices in
+    the same order, so even FP32 agrees bit for bit)."""
+    announce(f"pt_iterations k={k} d={d} {prec} M={M} slices={slices} parity={parity}")
+    rng = np.random.default_rng(M + 7 * k)
+    mu = rng.uniform(-4.0, 6.0, size=(k, d)) if d > 1 else np.linspace(-3.0, 6.0, k)
+    y = make_mixture_data(700, mu, 0.55, seed=M)
+    g = smc.Gmm.equal_weights(k, d, 0.55)
+    om = oracle_model(g)
+    betas = pt_betas(M, 4)
+    th = theta_prior_draws(M, k, d, seed=M + 1)
+    l = ogmm.loglik(th, y, om)
+    yd = _cuda(y, torch.float32)
+    bd = _cuda(betas)
+    outs = []
+    ctx.set_slices(slices)
+    ctx.set_pt_single_workgroup(1)
+    try:
+        for fused in (True, False):
+            tt, lt = _cuda(th), _cuda(l)
+            it = torch.full((1,), 5, dtype=torch.int32).cuda()
+            na = torch.zeros(1, dtype=torch.int64).cuda()
+            ns = torch.zeros(1, dtype=torch.int32).cuda()
+            if fused:
+                smc.pt_iterations(ctx, g, yd, tt, lt, bd, it, iters, 0.3, 41, parity, wrap, prec,
+                                  na, ns)
+            else:
+                for _ in range(iters):
+                    smc.pt_iteration(ctx, g, yd, tt, lt, bd, it, 0.3, 41, parity, wrap, prec,
+                                     na, ns)
+            ctx.check()
+            outs.append((tt.cpu().numpy(), lt.cpu().numpy(), it.item(), na.item(), ns.item()))
+    finally:
+        ctx.set_slices(0)
+        ctx.set_pt_single_workgroup(0)
+    (t1, l1, i1, a1, s1), (t2, l2, i2, a2, s2) = outs
+    assert i1 == i2 == 5 + iters
+    assert np.array_equal(t1, t2) and np.array_equal(l1, l2)
+    assert (a1, s1) == (a2, s2)
+    assert 0 < a1 < M * iters          # moves both accepted and rejected
+    if M > 2:
+        assert s1 > 0
+
+
+def test_pt_iterations_matches_oracle_and_rejects_bad_count(smc, ctx):
+    """Twenty iterations of 300 chains against the oracle's population MCMC
+    run (FP64, alternating parity) in each of pt_iterations' forms (one
+    single-workgroup launch; automatic; per iteration), and n_iters < 1 or an
+    unknown mode refused."""
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(250, mu, 0.55, seed=12)
+    M, iters = 300, 20
+    betas = pt_betas(M, 4)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
+    ref = osmc.pt_run(y, om, betas, iters, 0.5, 88, parity_mode="alternate", wrap=False)
+    try:
+        for mode in (1, 0, -1):
+            announce(f"pt_iterations oracle M=300 mode={mode}")
+            ctx.set_pt_single_workgroup(mode)
+            s = smc.PTSampler(ctx, g, y, betas, 0.5, seed=88, parity_mode=0, wrap=False,
+                              prec="fp64")
+            s.init()
+            smc.pt_iterations(ctx, g, s.y, s.theta, s.loglik, s.beta, s.it, iters, 0.5, 88, 0,
+                              False, "fp64", s.n_accept, s.n_swap, stream=s.stream)
+            s.stream.synchronize()
+            ctx.check()
+            assert s.it.item() == iters
+            assert s.n_swap.item() == ref["swaps"]
+            assert s.n_accept.item() == ref["accepted"]
+            assert np.max(np.abs(s.theta.cpu().numpy() - ref["theta"])) <= 1e-9
+            assert rel_err(s.loglik.cpu().numpy(), ref["l"]).max() <= 1e-10
+    finally:
+        ctx.set_pt_single_workgroup(0)
+    with pytest.raises(smc.SmcError):
+        smc.pt_iterations(ctx, g, s.y, s.theta, s.loglik, s.beta, s.it, 0, 0.5, 88)
+    with pytest.raises(smc.SmcError):
+        ctx.set_pt_single_workgroup(2)
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
 def test_rwmh_move_ddim_matches_oracle(smc, ctx, prec):
     """d = 8, k = 4 move: MFMA form (and the FP64 VALU form) against the oracle."""
