@@ -117,12 +117,17 @@ STEPS_PER_GRAPH = 10    # tempering steps per hipGraph replay
 PT_ITERS_PER_GRAPH = 64  # population-MCMC iterations per replay in the paper's runs
 
 
-def ops_per_eval(k: int) -> float:
-    """Algorithmic VALU work of one particle x datum evaluation in the FP32 form:
-    per component a distance FMA, a square-and-weight FMA, a shift subtract and
-    one exp2; per datum k-1 max, k-1 adds, the product update and the max
-    accumulation: 5k VALU + k transcendental (24 slots for k = 4)."""
-    return 5.0 * k + TRANS_SLOTS * k
+def ops_per_eval(k: int, form: str = "direct") -> float:
+    """Algorithmic VALU issue slots of one particle x datum evaluation in the
+    FP32 form (exp2 counted as TRANS_SLOTS slots).
+    direct (waves whose particles sit near the data, as in a population that
+    has reached the posterior): per component a distance FMA, a
+    square-and-weight FMA and one exp2; per datum k-1 adds and the product
+    update: 3k VALU + k transcendental (16 slots for k = 4).
+    shifted (waves holding a particle far from the data): per component also a
+    shift subtract; per datum k-1 max and the max accumulation: 5k VALU + k
+    transcendental (24 slots for k = 4)."""
+    return (3.0 if form == "direct" else 5.0) * k + TRANS_SLOTS * k
 
 
 def log(msg):
@@ -296,11 +301,11 @@ def main():
         "frac": achieved / PEAK_LANE_OPS,
         "traffic": move_traffic(),
         "traffic_unit": "bytes per launch",
-        "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
+        "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept; direct form)",
         "ops_per_eval": ops_per_eval(cfg.k),
         # the hardware issues v_exp_f32 over two VALU cycles (SQ_ACTIVE_INST_VALU -
-        # SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32); charged so, an evaluation is
-        # 28 slots and the same kernel time is this fraction of the peak
+        # SQ_INSTS_VALU = SQ_INSTS_VALU_TRANS_F32); charged so, a direct-form
+        # evaluation is 20 slots and the same kernel time is this fraction of the peak
         "frac_exp_two_slots": kern_evals * (ops_per_eval(cfg.k) + cfg.k) / PEAK_LANE_OPS,
         "valu_busy_measured": move_valu_busy(),
         "kernel_ms": r32["kernel_ms"],
@@ -418,7 +423,8 @@ def probes(smc, torch, ctx, reps):
     evals = N * n / (ms * 1e-3)
     out["loglik_fp32_N1048576_n4096"] = {
         "us": ms * 1e3, "evals_per_s": evals,
-        "frac_issue_slots": evals * ops_per_eval(4) / PEAK_LANE_OPS}
+        "form": "shifted (prior draws, far from the data)",
+        "frac_issue_slots": evals * ops_per_eval(4, "shifted") / PEAK_LANE_OPS}
     del th, l
     for logN in (17, 20, 24):
         N = 1 << logN

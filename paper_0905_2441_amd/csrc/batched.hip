@@ -164,6 +164,7 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
         double* th_run = theta + static_cast<size_t>(KD) * rd.p_off;
         double* l_run = l + rd.p_off;
         const double* th_src = use_alt ? theta_tmp + static_cast<size_t>(KD) * rd.p_off : th_run;
+        const double l_src = use_alt ? l_tmp[rd.p_off + pc] : l_run[pc];
         // active slices: at least 32 observations each
         int S = n / 32;
         S = S < 1 ? 1 : (S > kBatchWaves ? kBatchWaves : S);
@@ -174,7 +175,7 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
         if (w < S) {
             const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
             const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
-            part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g);
+            part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g));
         }
         red[w][lane] = part;
         __syncthreads();

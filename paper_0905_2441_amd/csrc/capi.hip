@@ -91,11 +91,14 @@ int check_model(const smc_gmm* m, GmmDev* out) {
     g.d = m->d;
     const double log2e = 1.4426950408889634;
     g.s32 = static_cast<float>(sqrt(log2e / (2.0 * m->sigma2)));
+    double mass = 0.0;
     for (int i = 0; i < SMC_KMAX; ++i) {
         const double lw = (i < m->k) ? m->log_w[i] : -INFINITY;
         g.lw[i] = lw;
         g.lw2[i] = static_cast<float>(lw * log2e);
+        mass += exp(lw);
     }
+    g.unit_mass = mass <= 1.0 + 1e-6 ? 1 : 0;
     g.inv2s2 = 1.0 / (2.0 * m->sigma2);
     g.cst = -0.5 * static_cast<double>(m->d) * log(2.0 * M_PI * m->sigma2);
     g.prior = m->prior;

@@ -16,18 +16,36 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
     return static_cast<double>(n) * g.cst + body;
 }
 
-// Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij} (FP32 arithmetic, FP64 result).
+// Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij}, a_ij = log2 w_i - s^2 ||y_j - mu_i||^2
+// (FP32 arithmetic, FP64 result). The per-datum sums are multiplied into a
+// running product that is renormalised (frexp) after each block of data, its
+// exponents summed as integers. Two forms:
+//  - direct (weights of total mass <= 1): e_j = sum_i 2^{a_ij}. Every factor
+//    is then <= 1, so the partial products only fall, and a block of 8 whose
+//    product ends at or above 2^-100 had no factor or partial product in the
+//    FP32 subnormal range: it is as accurate as the shifted form;
+//  - shifted: each datum's sum is taken relative to its largest term
+//    m_j = max_i a_ij (blocks of 16), and the m_j are added apart.
+// A wave starts in the direct form when every lane's `near` hint holds (the
+// caller's guess that the particle sits near the data, from its current
+// log-likelihood) and, at the first block where any of its lanes ends below
+// 2^-100 (a particle far from these data, or a NaN), drops that block and
+// runs the rest of its slice in the shifted form; otherwise it runs the
+// shifted form throughout. Both forms are within the FP32 error bound; which
+// one a particle's data went through depends on the wave it shares (fixed for
+// a given launch shape and population).
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const float (&nms)[K * D], float s,
-                                               const GmmDev& g) {
-    constexpr int U = 16;
+                                               const GmmDev& g, bool near) {
+    constexpr int UF = 8;            // direct-form block
+    constexpr int US = 16;           // shifted-form block
+    constexpr float kFloor = 0x1p-100f;
     double msum = 0.0;
     float prod = 1.0f;
     int expo = 0;
     int j = j0;
-    auto datum = [&](const float* yj, float& m_out, float& e_out) {
-        float a[K];
+    auto exponents = [&](const float* yj, float (&a)[K]) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             if constexpr (D == 1) {
@@ -43,6 +61,10 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
                 a[i] = g.lw2[i] - q;
             }
         }
+    };
+    auto shifted = [&](const float* yj, float& m_out, float& e_out) {
+        float a[K];
+        exponents(yj, a);
         float m = a[0];
 #pragma unroll
         for (int i = 1; i < K; ++i) m = fmaxf(m, a[i]);
@@ -52,12 +74,31 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         m_out = m;
         e_out = e;
     };
-    for (; j + U <= j1; j += U) {
+    auto direct = [&](const float* yj) {
+        float a[K];
+        exponents(yj, a);
+        float e = __builtin_amdgcn_exp2f(a[0]);
+#pragma unroll
+        for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(a[i]);
+        return e;
+    };
+    if (g.unit_mass != 0 && __all(near)) {
+        for (; j + UF <= j1; j += UF) {
+            const float* yb = y + (size_t)wave_uniform(j) * D;    // wave-uniform: scalar loads
+            float p = prod;
+#pragma unroll
+            for (int u = 0; u < UF; ++u) p *= direct(yb + u * D);
+            if (!__all(p >= kFloor)) break;
+            expo += __builtin_amdgcn_frexp_expf(p);
+            prod = __builtin_amdgcn_frexp_mantf(p);
+        }
+    }
+    for (; j + US <= j1; j += US) {
         float mblk = 0.0f;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < US; ++u) {
             float m, e;
-            datum(y + (size_t)(j + u) * D, m, e);
+            shifted(y + (size_t)(j + u) * D, m, e);
             prod *= e;
             mblk += m;
         }
@@ -68,7 +109,7 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
 #pragma unroll 4
     for (; j < j1; ++j) {
         float m, e;
-        datum(y + (size_t)j * D, m, e);
+        shifted(y + (size_t)j * D, m, e);
         prod *= e;
         msum += static_cast<double>(m);
     }
@@ -104,16 +145,25 @@ __device__ __forceinline__ double partial_fp64(const float* __restrict__ y, int 
     return acc;
 }
 
-// The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values).
+// Whether a particle with log-likelihood l over n data sits near the data in
+// the sense the FP32 direct form needs: its per-datum mixture sums average at
+// least 2^-6 (blocks of 8 then stay far above 2^-100). False for NaN and -inf.
+__device__ __forceinline__ bool near_data(double l, int n, const GmmDev& g) {
+    return l >= static_cast<double>(n) * (g.cst - 6.0 * kLn2);
+}
+
+// The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values);
+// `near` is the hint of partial_fp32 (unused in FP64).
 template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
-                                                const double (&pr)[K * D], const GmmDev& g) {
+                                                const double (&pr)[K * D], const GmmDev& g,
+                                                bool near = true) {
     if constexpr (PREC == SMC_PREC_FP32) {
         float nms[K * D];
         const double s = static_cast<double>(g.s32);
 #pragma unroll
         for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(s * pr[c]));
-        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g);
+        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g, near);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
     }

@@ -92,7 +92,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g));
     __syncthreads();
     if (w != 0) return;
 
@@ -160,7 +160,7 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         double pr[KD];
         block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, mv, &cur[0][0], kWave, lane, sd,
                             w, S, prs, pr);
-        red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
+        red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g));
         __syncthreads();
         if (w == 0) {
             double tot = red[0][lane];
@@ -275,7 +275,7 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
         double pr[KD];
 #pragma unroll
         for (int c = 0; c < KD; ++c) pr[c] = cur[c][col] + sd * zs[c][col];
-        red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g);
+        red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g, near_data(lcur[col], n, g));
         __syncthreads();
         if (sl == 0) {
             double tot = red[w][lane];

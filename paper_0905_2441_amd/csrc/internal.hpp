@@ -29,6 +29,7 @@ struct GmmDev {
     int prior;                 // SMC_PRIOR_GAUSS or SMC_PRIOR_BOX
     double pa, pb;
     double lp_const;           // Gaussian prior: -(1/2) ln(2 pi pb^2) per coordinate
+    int unit_mass;             // sum_i w_i <= 1 (+1e-6): the FP32 form may skip the max shift
 };
 
 // Per-step values one kernel computes and later kernels of the same step read.

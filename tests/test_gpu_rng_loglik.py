@@ -184,12 +184,57 @@ def test_loglik_long_data_fp32(smc, ctx):
     _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
 
 
-def test_loglik_nan_raises_status(smc, ctx):
-    announce("loglik NaN status")
+@pytest.mark.parametrize("case", ["unnormalised_weights", "interleaved", "outlier_block",
+                                  "far_tile", "d8_outlier_block"])
+def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
+    """The FP32 likelihood takes a direct form (no per-datum max shift) for
+    waves near the data and the shifted form otherwise, switching mid-slice
+    at a block of data far from every component; every mix agrees with the
+    oracle: weights of total mass 4 (shifted only), near and far particles
+    interleaved lane by lane, near particles whose data hold a block of
+    outliers at +40, one far tile among near ones, and the same outliers in
+    d = 8."""
+    announce(f"loglik fp32 forms {case}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    n, N = 1000, 640
+    y = make_mixture_data(n, mu, 0.55, seed=31)
+    near = theta_near_posterior(N, mu, seed=32)
+    far = theta_prior_draws(N, 4, 1, seed=33)
     g = smc.Gmm.equal_weights(4, 1, 0.55)
-    y = torch.tensor([0.0, float("nan"), 1.0], dtype=torch.float32).cuda()
+    th = near
+    if case == "unnormalised_weights":
+        g = smc.Gmm(k=4, d=1, sigma2=0.55, log_w=(0.0, 0.0, 0.0, 0.0))
+        th = np.hstack([near[:, : N // 2], far[:, N // 2:]])
+    elif case == "interleaved":
+        th = np.where(np.arange(N) % 7 == 3, far, near)
+    elif case == "outlier_block":
+        y = y.copy()
+        y[480:520] = 40.0 + np.arange(40, dtype=np.float32) * 0.01
+    elif case == "far_tile":
+        th = near.copy()
+        th[:, 128:192] = far[:, 128:192]
+    elif case == "d8_outlier_block":
+        rng = np.random.default_rng(34)
+        mu8 = 3.0 * rng.standard_normal((4, 8))
+        y = make_mixture_data(600, mu8, 1.0, seed=35)
+        y[300:340] += 40.0
+        g = smc.Gmm.equal_weights(4, 8, 1.0)
+        th = theta_near_posterior(200, mu8, seed=36)
+    for slices in (0, 3):
+        ctx.set_slices(slices)
+        try:
+            _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
+        finally:
+            ctx.set_slices(0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_loglik_nan_raises_status(smc, ctx, prec):
+    announce(f"loglik NaN status {prec}")
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    y = torch.tensor([0.0, float("nan"), 1.0] + [0.5] * 30, dtype=torch.float32).cuda()
     th = torch.zeros((4, 64), dtype=torch.float64).cuda()
-    smc.smc_loglik(ctx, g, y, th, "fp64")
+    smc.smc_loglik(ctx, g, y, th, prec)
     with pytest.raises(smc.SmcError):
         ctx.check()
     ctx.check()  # cleared
