@@ -31,8 +31,9 @@
 // (l mod 16) of B for K elements 8*(l/16)..+7, so every lane handles exactly one
 // slot per MFMA, and the output lane holds four data rows 4*(l/16)..+3 of its
 // column. One MFMA pair per mixture component puts all k component values of a
-// (datum, particle) pair in the same lane: the log-sum-exp epilogue (max,
-// hardware exp2, sum, product accumulation) needs no cross-lane traffic.
+// (datum, particle) pair in the same lane: the epilogue (hardware exp2, sum,
+// product accumulation; with the per-datum max shift only for waves holding a
+// particle far from the data) needs no cross-lane traffic.
 //
 // Workgroup = 4 waves x 16 particles; the data rows of a slice are staged in LDS
 // (16 KB stages, double-buffered, 16-byte slots XOR-swizzled by row to spread
@@ -186,7 +187,7 @@ k_dd_build(const double* __restrict__ theta, int N, int K, GmmDev g, double s2, 
 template <int K>
 __global__ void __launch_bounds__(kDdBlock)
 k_dd_partial(const __bf16* __restrict__ A, int n, int n_pad, const __bf16* __restrict__ B, int N,
-             int S, double* __restrict__ part) {
+             int S, int unit_mass, double* __restrict__ part) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[2][kStageBytes];
     const int lane = lane_id();
     const int w = wave_id();
@@ -211,6 +212,11 @@ k_dd_partial(const __bf16* __restrict__ A, int n, int n_pad, const __bf16* __res
     double msum = 0.0;
     float prod = 1.0f;
     int expo = 0;
+    // direct form (no per-datum max shift) while every lane's tile product
+    // stays >= 2^-100; the wave keeps the shifted form from the first tile
+    // where one does not (the same rule as the VALU form's partial_fp32)
+    bool direct = unit_mass != 0;
+    constexpr float kFloor = 0x1p-100f;
     const int nst = (t1 - t0 + kStageTiles - 1) / kStageTiles;
     uint4 regs[4];
     auto load_stage = [&](int st) {
@@ -258,21 +264,42 @@ k_dd_partial(const __bf16* __restrict__ A, int n, int n_pad, const __bf16* __res
                 acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2[i], acc[i], 0, 0, 0);
             }
             const int grow = (tile0 + tt) * kTileRows + grp * 4;
-            float mblk = 0.0f;
+            bool done = false;
+            if (direct) {
+                float pd = prod;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (grow + r < n) {
-                    float m = acc[0][r];
+                for (int r = 0; r < 4; ++r) {
+                    if (grow + r < n) {
+                        float e = __builtin_amdgcn_exp2f(acc[0][r]);
 #pragma unroll
-                    for (int i = 1; i < K; ++i) m = fmaxf(m, acc[i][r]);
-                    float e = __builtin_amdgcn_exp2f(acc[0][r] - m);
-#pragma unroll
-                    for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(acc[i][r] - m);
-                    prod *= e;
-                    mblk += m;
+                        for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(acc[i][r]);
+                        pd *= e;
+                    }
+                }
+                if (__all(pd >= kFloor)) {
+                    prod = pd;
+                    done = true;
+                } else {
+                    direct = false;
                 }
             }
-            msum += static_cast<double>(mblk);
+            if (!done) {
+                float mblk = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (grow + r < n) {
+                        float m = acc[0][r];
+#pragma unroll
+                        for (int i = 1; i < K; ++i) m = fmaxf(m, acc[i][r]);
+                        float e = __builtin_amdgcn_exp2f(acc[0][r] - m);
+#pragma unroll
+                        for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(acc[i][r] - m);
+                        prod *= e;
+                        mblk += m;
+                    }
+                }
+                msum += static_cast<double>(mblk);
+            }
             expo += __builtin_amdgcn_frexp_expf(prod);
             prod = __builtin_amdgcn_frexp_mantf(prod);
         }
@@ -365,7 +392,7 @@ hipError_t launch_dd_loglik(const GmmDev& g, const __bf16* A, int64_t n, const d
 #define SMC_DD(KK)                                                                              \
     if (g.k == KK)                                                                              \
         hipLaunchKernelGGL((k_dd_partial<KK>), grid, dim3(kDdBlock), 0, s, A, static_cast<int>(n), \
-                           static_cast<int>(np), B, static_cast<int>(N), S, part);
+                           static_cast<int>(np), B, static_cast<int>(N), S, g.unit_mass, part);
     SMC_DD(1) SMC_DD(2) SMC_DD(4) SMC_DD(8)
 #undef SMC_DD
     e = hipGetLastError();
@@ -391,7 +418,7 @@ hipError_t launch_dd_rwmh(const GmmDev& g, const __bf16* A, int64_t n, double* t
 #define SMC_DD(KK)                                                                              \
     if (g.k == KK) {                                                                            \
         hipLaunchKernelGGL((k_dd_partial<KK>), grid, dim3(kDdBlock), 0, s, A, static_cast<int>(n), \
-                           static_cast<int>(np), B, static_cast<int>(N), S, part);              \
+                           static_cast<int>(np), B, static_cast<int>(N), S, g.unit_mass, part);              \
         e = hipGetLastError();                                                                  \
         if (e != hipSuccess) return e;                                                          \
         hipLaunchKernelGGL((k_dd_accept<KK>), g1, dim3(256), 0, s, part, S, static_cast<int>(N), \

@@ -193,7 +193,7 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
     oracle: weights of total mass 4 (shifted only), near and far particles
     interleaved lane by lane, near particles whose data hold a block of
     outliers at +40, one far tile among near ones, and the same outliers in
-    d = 8."""
+    d = 8 (VALU and MFMA forms)."""
     announce(f"loglik fp32 forms {case}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     n, N = 1000, 640
@@ -220,10 +220,12 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
         y[300:340] += 40.0
         g = smc.Gmm.equal_weights(4, 8, 1.0)
         th = theta_near_posterior(200, mu8, seed=36)
+    precs = ("fp32", "bf16x3") if case.startswith("d8") else ("fp32",)
     for slices in (0, 3):
         ctx.set_slices(slices)
         try:
-            _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
+            for prec in precs:
+                _check_loglik(smc, ctx, g, y, th, prec, FP32_TOL)
         finally:
             ctx.set_slices(0)
 
