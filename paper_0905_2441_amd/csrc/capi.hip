@@ -829,9 +829,9 @@ int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int6
     later.t_dev = &ctx->sc.state->t;
     hipError_t e = launch_fsv_weight(f, y, T, x, x_tmp, logw, N, src, seed, ctx->sc,
                                      ctx->fsv_mom, s);
-    if (e == hipSuccess) e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s);
     if (e == hipSuccess)
-        e = launch_fsv_moments(f.k, fsv_parts(N), ctx->sc, ctx->fsv_mom, moments, s);
+        e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s, ctx->fsv_mom, f.k,
+                            2 * SMC_FSV_KMAX, moments);
     if (e == hipSuccess)
         e = launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, x_tmp, x,
                                  f.k, nullptr, nullptr, logw, 1, s);

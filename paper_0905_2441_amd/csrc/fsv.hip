@@ -133,34 +133,6 @@ k_fsv_weight(FsvDev f, const double* __restrict__ y, int T, const double* __rest
     }
 }
 
-// One workgroup: the weighted mean and standard deviation of x_t from the
-// per-workgroup sums (rescaled to the global maximum M of the step state).
-__global__ void __launch_bounds__(kRedBlock)
-k_fsv_moments(int k, int parts, Scratch sc, const double* __restrict__ mom,
-              double* __restrict__ moments) {
-    const StepState* st = sc.state;
-    const double M = st->M, S = st->S;
-    const int t = st->t;
-    double* out = moments + static_cast<size_t>(t - 1) * 2 * k;
-    for (int c = 0; c < k; ++c) {
-        double a = 0.0, b = 0.0;
-        for (int q = threadIdx.x; q < parts; q += blockDim.x) {
-            const double mb = sc.rw_part[q].mn;
-            const double r = (mb == -INFINITY) ? 0.0 : exp(mb - M);
-            a += mom[static_cast<size_t>(q) * 2 * SMC_FSV_KMAX + c] * r;
-            b += mom[static_cast<size_t>(q) * 2 * SMC_FSV_KMAX + k + c] * r;
-        }
-        a = block_sum(a);
-        b = block_sum(b);
-        if (threadIdx.x == 0) {
-            const double mean = a / S;
-            const double var = b / S - mean * mean;
-            out[c] = mean;
-            out[k + c] = sqrt(var > 0.0 ? var : 0.0);
-        }
-    }
-}
-
 __global__ void k_fsv_init(int k, int N, double* __restrict__ x, double* __restrict__ logw) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -205,12 +177,6 @@ hipError_t launch_fsv_weight(const FsvDev& f, const double* y, int T, const doub
     SMC_FSV_CASES(SMC_CASE)
 #undef SMC_CASE
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_fsv_moments(int k, int parts, const Scratch& sc, const double* mom,
-                              double* moments, hipStream_t s) {
-    hipLaunchKernelGGL(k_fsv_moments, dim3(1), dim3(kRedBlock), 0, s, k, parts, sc, mom, moments);
-    return hipGetLastError();
 }
 
 }  // namespace smc

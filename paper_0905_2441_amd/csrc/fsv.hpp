@@ -23,8 +23,5 @@ hipError_t launch_fsv_init(int k, int64_t N, double* x, double* logw, hipStream_
 hipError_t launch_fsv_weight(const FsvDev& f, const double* y, int T, const double* x,
                              double* x_out, double* logw, int64_t N, StepSrc src, uint64_t seed,
                              const Scratch& sc, double* mom, hipStream_t s);
-// Weighted moments of step state->t from the partials into moments[t-1].
-hipError_t launch_fsv_moments(int k, int parts, const Scratch& sc, const double* mom,
-                              double* moments, hipStream_t s);
 
 }  // namespace smc

@@ -245,8 +245,12 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
                            hipStream_t s);
 // Fused tempering step pieces: reweight partials -> step_mid (combine, decide,
 // CDF chunks) -> moves (ancestor search fused into the first move).
+// With `mom` (a particle filter's moment partials), also the step's weighted
+// moments into moments[(t-1) * 2 mom_k ...] (means, then standard deviations).
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
-                           double* stats, double ess_frac, const double* logw, hipStream_t s);
+                           double* stats, double ess_frac, const double* logw, hipStream_t s,
+                           const double* mom = nullptr, int mom_k = 0, int mom_stride = 0,
+                           double* moments = nullptr);
 void cdf_layout(int64_t N, int* chunk, int* nchunks);
 hipError_t launch_search_gather(const Scratch& sc, int64_t N, int scheme, uint64_t seed,
                                 StepSrc src, const StepState* pred_state, const double* theta_in,

@@ -179,12 +179,17 @@ k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
 // partials in block order (so all reach the same M, S1, S2 and decision);
 // workgroup 0 publishes the step state, the statistics and the next step index;
 // when the ESS test fires, workgroup b scans CDF chunk b of the weights
-// exp(logw - M) / S1.
+// exp(logw - M) / S1. With `mom` (a particle filter's per-workgroup sums of
+// w x and w x^2 over k state components, w = exp(logw - block max), stride
+// mom_stride per workgroup), workgroup 0 also writes the step's weighted means
+// and standard deviations to moments[(t-1) * 2k ...].
 __global__ void __launch_bounds__(kRedBlock)
 k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
-           double* stats, double ess_frac, const double* __restrict__ logw) {
+           double* stats, double ess_frac, const double* __restrict__ logw,
+           const double* __restrict__ mom, int mom_k, int mom_stride,
+           double* __restrict__ moments) {
     __shared__ double sh_M, sh_S;
-    __shared__ int sh_fire;
+    __shared__ int sh_fire, sh_t;
     Lse3 o = lse3_empty(), nw = lse3_empty();
     for (int b = threadIdx.x; b < parts; b += blockDim.x) {
         const RwPartial q = sc.rw_part[b];
@@ -202,6 +207,7 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
         if (blockIdx.x == 0) {
             StepState* st = sc.state;
             const int t = step_index(src);
+            sh_t = t;
             st->M = nw.m;
             st->S = nw.s1;
             st->S2 = nw.s2;
@@ -218,8 +224,29 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
         }
     }
     __syncthreads();
-    if (!sh_fire) return;
     const double M = sh_M, S = sh_S;
+    if (mom != nullptr && blockIdx.x == 0) {
+        // each workgroup's sums rescaled from its own maximum to M, added in order
+        double* out = moments + static_cast<size_t>(sh_t - 1) * 2 * mom_k;
+        for (int c = 0; c < mom_k; ++c) {
+            double a = 0.0, b = 0.0;
+            for (int q = threadIdx.x; q < parts; q += blockDim.x) {
+                const double mb = sc.rw_part[q].mn;
+                const double r = (mb == -INFINITY) ? 0.0 : exp(mb - M);
+                a += mom[static_cast<size_t>(q) * mom_stride + c] * r;
+                b += mom[static_cast<size_t>(q) * mom_stride + mom_k + c] * r;
+            }
+            a = block_sum(a);
+            b = block_sum(b);
+            if (threadIdx.x == 0) {
+                const double mean = a / S;
+                const double var = b / S - mean * mean;
+                out[c] = mean;
+                out[mom_k + c] = sqrt(var > 0.0 ? var : 0.0);
+            }
+        }
+    }
+    if (!sh_fire) return;
     scan_chunk(blockIdx.x, N, chunk, sc, [&](int j) { return exp(logw[j] - M) / S; });
 }
 
@@ -443,12 +470,14 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
 }
 
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
-                           double* stats, double ess_frac, const double* logw, hipStream_t s) {
+                           double* stats, double ess_frac, const double* logw, hipStream_t s,
+                           const double* mom, int mom_k, int mom_stride, double* moments) {
     const int parts = red_grid(N);
     const int chunk = cdf_chunk(N);
     const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_step_mid, dim3(nchunks), dim3(kRedBlock), 0, s, parts, static_cast<int>(N),
-                       chunk, src, t_advance, sc, stats, ess_frac, logw);
+                       chunk, src, t_advance, sc, stats, ess_frac, logw, mom, mom_k, mom_stride,
+                       moments);
     return hipGetLastError();
 }
 
