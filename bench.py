@@ -70,12 +70,12 @@ HBM_PEAK_GBS = 8000.0
 MOVE_COUNTERS = {
     "sources_sha256": "39e314e3e4f0be219cbcebd833987c218b33df88b168f28a0258f1667ff9a7ce",
     "fetch_kib": 2716.0, "fetch_scale": 2.0,
-    "write_kib": 32.38, "write_scale": 1.0,
+    "write_kib": 32.20, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": 0.862,
+    "valu_busy": 0.864,
 }
 
 
