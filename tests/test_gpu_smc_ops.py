@@ -88,7 +88,8 @@ def _resample_gpu(smc, ctx, W, u, theta=None, l=None):
     return idx, kw
 
 
-@pytest.mark.parametrize("N", [1, 2, 7, 1000, 2049, 131072, 1 << 20])
+@pytest.mark.parametrize("N", [1, 2, 7, 1000, 2049, 131072, (1 << 20) - 1, 1 << 20,
+                               (1 << 21) + 12345])
 def test_resample_bit_exact(smc, ctx, N):
     announce(f"resample N={N}")
     W = osmc.normalise(lognormal_logw(N, seed=N + 5, spread=3.0))
@@ -134,7 +135,7 @@ def test_resample_gather_and_predicate(smc, ctx):
     assert np.array_equal(idx2.cpu().numpy(), osmc.systematic_resample(W, osmc.resample_offset(3, 4)))
 
 
-@pytest.mark.parametrize("N", [1, 7, 1000, 2049, 131072, 1 << 20])
+@pytest.mark.parametrize("N", [1, 7, 1000, 2049, 131072, 1 << 20, (1 << 21) + 12345])
 @pytest.mark.parametrize("scheme", ["stratified", "multinomial", "systematic"])
 def test_resample_schemes_bit_exact(smc, ctx, scheme, N):
     """Every scheme's indices equal the oracle's bit for bit when the GPU is fed
@@ -145,6 +146,48 @@ def test_resample_schemes_bit_exact(smc, ctx, scheme, N):
     for step in (1, 5):
         smc.smc_resample(ctx, _cuda(W), scheme, 21, step, idx=idx)
         assert np.array_equal(idx.cpu().numpy(), osmc.resample_indices(W, scheme, 21, step))
+
+
+@pytest.mark.parametrize("scheme", ["systematic", "stratified"])
+def test_resample_sorted_points_large_n_degenerate_gather_predicate(smc, ctx, scheme):
+    """Past 2^20 particles (a ragged last chunk of the CDF): equal weights, one
+    particle holding all the weight (first, inside, last), every third
+    particle, zero weight on the last thousand, the gather with the logw
+    reset, and an unfired predicate (identity and copies)."""
+    N, kd = (1 << 20) + 77, 2
+    announce(f"resample sorted large N {scheme}")
+    cases = [np.full(N, 1.0 / N), np.eye(1, N, 0).ravel(), np.eye(1, N, 654321).ravel(),
+             np.eye(1, N, N - 1).ravel(), np.where(np.arange(N) % 3 == 0, 1.0, 0.0),
+             np.where(np.arange(N) < N - 1000, 1.0, 0.0)]
+    idx = torch.empty(N, dtype=torch.int32).cuda()
+    for W in cases:
+        W = W / W.sum()
+        smc.smc_resample(ctx, _cuda(W), scheme, 6, 3, idx=idx)
+        assert np.array_equal(idx.cpu().numpy(), osmc.resample_indices(W, scheme, 6, 3))
+    W = osmc.normalise(lognormal_logw(N, seed=4, spread=3.0))
+    rng = np.random.default_rng(2)
+    theta = rng.normal(size=(kd, N))
+    l = rng.normal(size=N)
+    th_out = torch.empty((kd, N), dtype=torch.float64).cuda()
+    l_out = torch.empty(N, dtype=torch.float64).cuda()
+    logw = _cuda(np.ones(N))
+    smc.smc_resample(ctx, _cuda(W), scheme, 8, 2, idx=idx, theta_in=_cuda(theta),
+                     theta_out=th_out, l_in=_cuda(l), l_out=l_out, logw=logw)
+    ref = osmc.resample_indices(W, scheme, 8, 2)
+    assert np.array_equal(idx.cpu().numpy(), ref)
+    assert np.array_equal(th_out.cpu().numpy(), theta[:, ref])
+    assert np.array_equal(l_out.cpu().numpy(), l[ref])
+    assert np.all(logw.cpu().numpy() == 0.0)
+    if scheme == "systematic":
+        ess = _cuda(np.array([osmc.ess(W)]))
+        th2 = torch.empty((kd, N), dtype=torch.float64).cuda()
+        smc.smc_resample_systematic(ctx, _cuda(W), 3, 4, ess=ess, ess_threshold=1.0, idx=idx,
+                                    theta_in=_cuda(theta), theta_out=th2)
+        assert np.array_equal(idx.cpu().numpy(), np.arange(N))
+        assert np.array_equal(th2.cpu().numpy(), theta)
+        for u in (0.0, 1.0 - 2.0 ** -32):
+            ii, _ = _resample_gpu(smc, ctx, W, u)
+            assert np.array_equal(ii.cpu().numpy(), osmc.systematic_resample(W, u))
 
 
 @pytest.mark.parametrize("scheme", ["stratified", "multinomial"])
