@@ -223,6 +223,56 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     print(f"fp32 flipped decisions: {flips} of {decisions}")
 
 
+@pytest.mark.parametrize("prec,slices", [("fp32", 4), ("fp64", 8)])
+def test_headline_size_steps_from_gpu_state(smc, ctx, prec, slices):
+    """At the headline size (N = 131072, n = 1000) in the launch shape the
+    benchmark times (4 slices per tile in FP32, 8 in FP64): the first step
+    whose ESS test fires (reweight, correctly rounded CDF, ancestor search
+    fused into the move) and a step near the posterior (t = 30, the direct FP32
+    form) are each checked against the oracle's step taken from the GPU's own
+    state. FP64 must agree in every decision; FP32 may flip near-tie accepts,
+    which are counted."""
+    cfg = CONFIGS["gmm1d_k4_n1000_N131072"]
+    announce(f"headline-size steps {prec} slices={slices}")
+    y = make_data(cfg)
+    betas = beta_schedule(cfg.T, cfg.schedule)
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2)
+    s = _sampler(smc, ctx, cfg, y, betas, prec)
+    ctx.set_slices(slices)
+    try:
+        s.init()
+        prev = _snapshot(s)
+        fired_at = None
+        for t in range(1, 30):
+            s.step(graph=False)
+            s.stream.synchronize()
+            if s.stats[2].item() > 0:
+                fired_at = t
+                break
+            prev = _snapshot(s)
+        assert fired_at is not None, "no resampling in the first 29 steps"
+        checks = [(fired_at, prev, _snapshot(s))]
+        s.advance(29 - fired_at, graph=True)
+        before = _snapshot(s)
+        s.step(graph=False)
+        checks.append((30, before, _snapshot(s)))
+    finally:
+        ctx.set_slices(0)
+    tol_l = 1e-6 if prec == "fp32" else 1e-10
+    for t, (th, l, lw, z), (th1, l1, lw1, z1) in checks:
+        rth, rl, rlw, _, inc, info = osmc.smc_step(th, l, lw, y, om, betas, t, cfg.step_sd,
+                                                   cfg.n_moves, cfg.run_seed, cfg.ess_frac)
+        assert info["resampled"] == (t == fired_at), t
+        assert abs((z1 - z) - inc) <= 1e-10 * max(1.0, abs(inc))
+        assert np.max(np.abs(lw1 - rlw)) <= 1e-12
+        same = np.all(np.abs(th1 - rth) <= 1e-12, axis=0)
+        flips = int(np.sum(~same))
+        assert flips <= (0 if prec == "fp64" else cfg.N // 1000), (t, flips)
+        assert rel_err(l1[same], rl[same]).max() <= tol_l
+        print(f"{prec} step {t}: resampled={info['resampled']} flips={flips}")
+
+
 @pytest.mark.parametrize("slices,iters_per_graph,fused", [(0, 1, False), (24, 7, False),
                                                           (0, 7, True), (3, 25, True)])
 def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph, fused):
