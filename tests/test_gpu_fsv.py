@@ -63,6 +63,16 @@ def test_fsv_paper_length_run(smc, ctx):
     assert np.corrcoef(r["mean"][:, 0], x_true[1:, 0])[0, 1] > 0.5
 
 
+@pytest.mark.parametrize("N,T", [(131072, 25), (1 << 20, 3)])
+def test_fsv_benchmark_sizes(smc, ctx, N, T):
+    """The benchmark's largest sizes (the paper's N = 131072, and 2^20) with
+    ten filter steps per graph replay, as timed."""
+    announce(f"fsv N={N} T={T}")
+    _, y = simulate(PAPER_FSV, T, 7)
+    r = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=3).run(graph=True, steps_per_graph=10)
+    _compare(r, ofsv.particle_filter(y, PAPER_FSV, N, 3), N)
+
+
 def test_fsv_rejects_bad_models(smc, ctx):
     _, y = simulate(PAPER_FSV, 5, 1)
     import dataclasses
