@@ -377,6 +377,35 @@ def test_batched_runs_match_oracle_fp64(smc, ctx, graph, scheme):
     assert r["accepted"] == acc_total
 
 
+def test_batched_full_workload_sampled_runs(smc, ctx):
+    """The benchmark's whole 256-run batch (n log-uniform in 1e2..1e5, N in
+    1024..65536) advanced three graph-replayed FP64 steps; the four cheapest
+    runs and one with long data (N = 1024, n nearest 2e4), checked one by one,
+    equal the oracle's runs alone over the same three steps."""
+    from workloads.configs import BATCHED, batched_runs
+    announce("batched full workload, sampled runs")
+    runs = batched_runs(256)
+    datas = [make_mixture_data(x.n, x.true_means, BATCHED["sigma2"], x.data_seed) for x in runs]
+    g = smc.Gmm.equal_weights(4, 1, BATCHED["sigma2"])
+    om = oracle_model(g)
+    betas = beta_schedule(BATCHED["T"], BATCHED["schedule"])
+    b = smc.BatchSampler(ctx, g, datas, [x.N for x in runs], [x.run_seed for x in runs], betas,
+                         BATCHED["step_sd"], BATCHED["n_moves"], ess_frac=BATCHED["ess_frac"],
+                         prec="fp64")
+    r = b.run(graph=True, steps=3)
+    assert r["t"] == 4
+    order = np.argsort([x.N * x.n for x in runs])
+    long_data = min((x for x in runs if x.N == 1024), key=lambda x: abs(x.n - 20000)).index
+    for i in list(order[:4]) + [long_data]:
+        x = runs[i]
+        ref = osmc.smc_run(datas[i], om, betas[:4], x.N, BATCHED["step_sd"], BATCHED["n_moves"],
+                           x.run_seed, ess_frac=BATCHED["ess_frac"])
+        assert r["resamples"][i] == int(np.sum(ref["trace"]["resampled"])), i
+        assert abs(r["logZ"][i] - ref["logZ"]) <= 1e-9 * max(1.0, abs(ref["logZ"])), i
+        assert np.max(np.abs(r["theta"][i] - ref["theta"])) <= 1e-9, i
+        assert rel_err(r["l"][i], ref["l"]).max() <= 1e-10, i
+
+
 def test_batched_fp32_two_moves_runs(smc, ctx):
     announce("batched fp32 two moves")
     datas, Ns, seeds = _batch_inputs()
