@@ -11,7 +11,9 @@ from gpu_common import announce, oracle_model, rel_err
 from oracle import gmm as ogmm
 from oracle import philox as opx
 from oracle import smc as osmc
-from workloads import lognormal_logw, make_mixture_data, pt_betas, theta_near_posterior, theta_prior_draws
+from workloads import (CONFIGS, lognormal_logw, make_data, make_mixture_data, pt_betas,
+                       theta_near_posterior, theta_prior_draws)
+from workloads.data import true_means_for
 
 pytestmark = pytest.mark.gpu
 
@@ -488,6 +490,45 @@ def test_pt_iterations_matches_oracle_and_rejects_bad_count(smc, ctx):
         smc.pt_iterations(ctx, g, s.y, s.theta, s.loglik, s.beta, s.it, 0, 0.5, 88)
     with pytest.raises(smc.SmcError):
         ctx.set_pt_single_workgroup(2)
+
+
+def test_rwmh_move_ddim_workload_size_sampled(smc, ctx):
+    """One MFMA move of the d = 8, k = 8 workload at its full size (N = 16384,
+    n = 65536), checked against the oracle's move on 96 sampled particles (each
+    particle's move depends only on its own state and counter)."""
+    cfg = CONFIGS["gmm8d_k8_n65536_N16384"]
+    announce("rwmh d=8 workload size sampled")
+    y = make_data(cfg)
+    mu = true_means_for(cfg)
+    N, kd = cfg.N, 64
+    th = np.hstack([theta_prior_draws(N // 2, 8, 8, seed=41), theta_near_posterior(N // 2, mu, seed=42)])
+    g = smc.Gmm.equal_weights(8, 8, cfg.sigma2)
+    om = oracle_model(g)
+    rng = np.random.default_rng(43)
+    idx = np.unique(np.concatenate([np.arange(16), rng.choice(N, 64, replace=False),
+                                    np.arange(N - 16, N)]))
+    l = np.full(N, -1.0e6)
+    l[idx] = ogmm.loglik(th[:, idx], y, om, chunk_elems=1 << 24)
+    tt, lt = _cuda(th), _cuda(l)
+    sd, seed, step, move, beta = 0.02, 51, 7, 0, 0.9
+    smc.smc_rwmh_move(ctx, g, _cuda(y, torch.float32), tt, lt, beta, sd, seed=seed, step=step,
+                      move=move, prec="bf16x3")
+    ctx.check()
+    uidx = idx.astype(np.uint64)
+    prop = th[:, idx] + sd * opx.normals(seed, uidx, step, opx.PROP, move, kd)
+    l_prop = ogmm.loglik(prop, y, om, chunk_elems=1 << 24)
+    la = osmc.rwmh_log_alpha(np.full(idx.size, beta), l[idx], l_prop,
+                             ogmm.log_prior(th[:, idx], om), ogmm.log_prior(prop, om))
+    acc_ref = (la >= 0.0) | (np.log(opx.uniforms_open(seed, uidx, step, opx.ACC, move)) < la)
+    got_th, got_l = tt.cpu().numpy()[:, idx], lt.cpu().numpy()[idx]
+    acc_got = np.any(got_th != th[:, idx], axis=0)
+    assert int(np.sum(acc_got != acc_ref)) <= 2
+    assert 5 < int(acc_ref.sum()) < idx.size - 5            # both outcomes occur
+    same = acc_got == acc_ref
+    want_th = np.where(acc_ref, prop, th[:, idx])
+    want_l = np.where(acc_ref, l_prop, l[idx])
+    assert np.max(np.abs(got_th[:, same] - want_th[:, same])) <= 1e-12
+    assert rel_err(got_l[same], want_l[same]).max() <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
