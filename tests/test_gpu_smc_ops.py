@@ -381,6 +381,71 @@ def test_rwmh_move_pt_size_sampled(smc, ctx, prec):
     assert rel_err(got_l[same], want_l[same]).max() <= tol
 
 
+@pytest.mark.parametrize("prec,it", [("fp32", 11), ("fp64", 12)])
+def test_pt_iteration_workload_size_sampled(smc, ctx, prec, it):
+    """One population-MCMC iteration of the 8192-chain workload (n = 10^4) in
+    the benchmark's launch shape (32 slices: each tile over two workgroups, so
+    the moves' decisions and the exchanges run in one kernel), checked on 40
+    sampled pairs of the iteration's partition: both chains' moves, then the
+    pair's exchange, against the oracle. A pair depends only on its own two
+    chains, so the sample is exact."""
+    cfg = CONFIGS["pt_k4_n10000_M8192"]
+    announce(f"pt iteration workload size {prec} it={it}")
+    y = make_data(cfg)
+    M, kd = cfg.N, 4
+    mu = np.array(cfg.true_means)
+    betas = pt_betas(M, 4)
+    g = smc.Gmm.equal_weights(4, 1, cfg.sigma2)
+    om = oracle_model(g)
+    th = np.hstack([theta_prior_draws(M // 4, 4, 1, seed=61),
+                    theta_near_posterior(M - M // 4, mu, seed=62, jitter=0.3)])
+    parity = it & 1
+    rng = np.random.default_rng(63)
+    npairs = (M - parity) // 2                 # pairs (parity + 2q, parity + 2q + 1)
+    leads = parity + 2 * np.unique(np.concatenate([[0, npairs - 1],
+                                                   rng.choice(npairs, 38, replace=False)]))
+    chains = np.unique(np.concatenate([leads, leads + 1]))
+    l = np.full(M, -1.0e6)
+    l[chains] = ogmm.loglik(th[:, chains], y, om)
+    tt, lt = _cuda(th), _cuda(l)
+    itd = torch.full((1,), it, dtype=torch.int32).cuda()
+    sd, seed = cfg.step_sd, 71
+    ctx.set_slices(32)
+    try:
+        smc.pt_iteration(ctx, g, _cuda(y, torch.float32), tt, lt, _cuda(betas), itd, sd, seed,
+                         0, False, prec)
+        ctx.check()
+    finally:
+        ctx.set_slices(0)
+    assert itd.item() == it + 1
+    # the oracle: moves of the sampled chains, then their pairs' exchanges
+    uc = chains.astype(np.uint64)
+    prop = th[:, chains] + sd * opx.normals(seed, uc, it, opx.PROP, 0, kd)
+    l_prop = ogmm.loglik(prop, y, om)
+    la = osmc.rwmh_log_alpha(betas[chains], l[chains], l_prop, ogmm.log_prior(th[:, chains], om),
+                             ogmm.log_prior(prop, om))
+    acc = (la >= 0.0) | (np.log(opx.uniforms_open(seed, uc, it, opx.ACC, 0)) < la)
+    ref_th = th.copy()
+    ref_l = l.copy()
+    ref_th[:, chains] = np.where(acc, prop, th[:, chains])
+    ref_l[chains] = np.where(acc, l_prop, l[chains])
+    swapped = 0
+    for a in leads:
+        b = a + 1
+        lx = osmc.exchange_log_alpha(betas[a], betas[b], ref_l[a], ref_l[b])
+        u = float(opx.uniforms_open(seed, int(a), it, opx.EXCH, 0))
+        if lx >= 0.0 or np.log(u) < lx:
+            ref_th[:, [a, b]] = ref_th[:, [b, a]]
+            ref_l[a], ref_l[b] = ref_l[b], ref_l[a]
+            swapped += 1
+    got_th, got_l = tt.cpu().numpy(), lt.cpu().numpy()
+    same = np.all(np.abs(got_th[:, chains] - ref_th[:, chains]) <= 1e-12, axis=0)
+    assert int(np.sum(~same)) <= (0 if prec == "fp64" else 4)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert rel_err(got_l[chains][same], ref_l[chains][same]).max() <= tol
+    assert 0 < int(acc.sum()) < chains.size and swapped > 0
+
+
 # ------------------------------------------------------------------ exchange
 
 @pytest.mark.parametrize("M,parity,wrap", [(8192, 0, False), (8192, 1, False), (64, 1, True),
