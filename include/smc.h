@@ -122,7 +122,9 @@ const char* smc_last_error(void);
  * Up to 16 slices run as the waves of one workgroup; a move with more slices
  * and N <= 32768 spreads them over up to 8 workgroups per 64 particles and
  * completes in a second, per-particle kernel. Other kernels use min(slices, 16).
- * Results depend on the slicing only through the order of FP64 additions. */
+ * Results depend on the slicing only through the order of FP64 additions and,
+ * in FP32, through which of the two equivalent per-datum forms (see
+ * smc_loglik) a wave's slice takes. */
 int smc_set_slices(smc_ctx ctx, int32_t slices);
 
 /* One entry of a context's launch table (the output of the autotuner in the
@@ -148,7 +150,11 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  *   loglik[p] = sum_j log sum_i w_i N_d(y_j; mu_{p,i}, sigma2 I).
  * y: [n][d] FP32; theta: [k*d][N] FP64; loglik: [N] FP64 out.
  * prec FP64: plain form; FP32: FP32 arithmetic with hardware exp2 and a
- * compensated FP64 sum (relative error below 1e-6); BF16X3: d = 8, k in
+ * compensated FP64 sum (relative error below 1e-6); the per-datum mixture sum
+ * is taken directly for waves whose particles sit near the data (weights of
+ * total mass <= 1) and relative to the largest term otherwise, both within the
+ * bound (the form depends on the wave, fixed for a given launch shape and
+ * population); BF16X3: d = 8, k in
  * {1,2,4,8}: the quadratic forms as one K = 64 BF16 MFMA contraction of
  * three-way (hi/mid/lo) split operands with FP32 accumulation, then the same
  * FP32 epilogue (relative error below 1e-6). */
