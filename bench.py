@@ -70,7 +70,7 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "7ce5afea2b9ce6310dfa9d28810f58234d6cbb80e980f24cede584ad4f7f0b87",
+    "sources_sha256": "077eedd91589ef7009d7df96f62cd68410720e9dc00d7b98d5af992b0879d129",
     "fetch_kib": 2716.0, "fetch_scale": 2.0,
     "write_kib": 32.20, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",

@@ -33,7 +33,8 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // runs the rest of its slice in the shifted form; otherwise it runs the
 // shifted form throughout. Both forms are within the FP32 error bound; which
 // one a particle's data went through depends on the wave it shares (fixed for
-// a given launch shape and population).
+// a given launch shape and population). j0 and j1 must be the same in every
+// lane of the wave (the data are read by scalar loads).
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const float (&nms)[K * D], float s,
