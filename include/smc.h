@@ -281,19 +281,25 @@ int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, i
  * workgroup that keeps the chains' states in LDS and takes each iteration's
  * exchanges there; this needs FP32 or FP64, M at most 1024 chains at
  * k*d <= 4 (576 at 7, 512 at 8, 256 at 16) and, by default, a small iteration
- * (64-chain tiles x n x k*d <= 2^17; see pt_set_single_workgroup). Otherwise
- * n_iters iterations are enqueued. The single launch takes smc_set_slices'
- * value (at most 16 waves in all) or its own choice. *it_dev advances by
- * n_iters; n_iters < 1 is an argument error. */
+ * (64-chain tiles x n x k*d <= 2^16; see pt_set_single_workgroup). Larger
+ * populations whose 64-chain tiles each fit one workgroup (the launch shape
+ * of pt_iteration) take one launch per iteration: each launch first takes the
+ * previous iteration's exchange, then this iteration's moves, alternating the
+ * population between (theta, loglik) and context scratch (reserve M chains of
+ * k*d first when capturing), and one closing launch takes the last exchange;
+ * the rest enqueue n_iters pt_iteration calls. The single launch takes
+ * smc_set_slices' value (at most 16 waves in all) or its own choice. *it_dev
+ * advances by n_iters; n_iters < 1 is an argument error. */
 int pt_iterations(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
                   double* theta, double* loglik, const double* beta, int32_t* it_dev,
                   int32_t n_iters, double step_sd, uint64_t seed, int32_t parity_mode,
                   int32_t wrap, smc_prec prec, unsigned long long* n_accept,
                   unsigned int* n_swap, void* stream);
 
-/* When pt_iterations uses its single-workgroup form: mode 0 (default) when
- * the population fits and the iteration is small, 1 whenever the population
- * fits, -1 never. */
+/* Which fused forms pt_iterations may use: mode 0 (default) the
+ * single-workgroup form when the population fits and the iteration is small,
+ * else the deferred-exchange form when it applies; 1 the single-workgroup
+ * form whenever the population fits; -1 neither (n_iters pt_iteration calls). */
 int pt_set_single_workgroup(smc_ctx ctx, int32_t mode);
 
 /* Record one chain's state after an iteration (graph-replayable; enqueue it

@@ -715,6 +715,26 @@ int pt_iterations(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, 
     const int kd = g.k * g.d;
     const bool local = prec != SMC_PREC_BF16X3 && M >= 2 && M <= pt_local_chains(kd) &&
                        (ctx->pt_single > 0 || (ctx->pt_single == 0 && pt_local_pays(kd, n, M)));
+    if (!local && prec != SMC_PREC_BF16X3 && ctx->pt_single >= 0) {
+        const Split sp = choose_split(ctx, g, prec, n, M, true);
+        if (sp.groups == 1) {
+            // one launch per iteration, each taking the previous iteration's exchange
+            if (!y || !theta || !loglik || !beta || !it_dev)
+                return fail(SMC_ERR_INVALID_ARG, "NULL array");
+            if (parity_mode != 0 && parity_mode != 1)
+                return fail(SMC_ERR_INVALID_ARG, "parity_mode 0 or 1");
+            if (!(step_sd >= 0.0) || !isfinite(step_sd))
+                return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+            const hipStream_t s = as_stream(stream);
+            if ((r = ensure_scratch(ctx, M, kd, s))) return r;
+            const hipError_t e = launch_pt_deferred(g, y, n, theta, loglik, M, beta, it_dev,
+                                                    n_iters, step_sd, seed, prec, parity_mode,
+                                                    wrap ? 1 : 0, sp.slices, n_accept, n_swap,
+                                                    ctx->sc, &ctx->sc.state->t, s);
+            if (e != hipSuccess) return hip_fail(e, "population MCMC launch");
+            return SMC_OK;
+        }
+    }
     if (!local) {
         for (int32_t i = 0; i < n_iters; ++i) {
             r = pt_iteration(ctx, model, y, n, M, theta, loglik, beta, it_dev, step_sd, seed,

@@ -50,6 +50,27 @@ __device__ __forceinline__ bool pt_slot(int M, int parity, int wrap, int q, int&
     return false;
 }
 
+// The pair of the partition that chain c belongs to (the pairs of pt_slot):
+// returns false when c is left single.
+__device__ __forceinline__ bool pt_pair_of(int M, int parity, int wrap, int c, int& a, int& b) {
+    if (wrap && parity == 1 && (M & 1) == 0 && (c == 0 || c == M - 1)) {
+        a = M - 1;
+        b = 0;
+        return true;
+    }
+    const int d = c - parity;
+    if (d < 0) return false;
+    if ((d & 1) == 0) {
+        if (c + 1 >= M) return false;
+        a = c;
+        b = c + 1;
+        return true;
+    }
+    a = c - 1;
+    b = c;
+    return true;
+}
+
 // log u of the exchange test of the pair led by chain a: stream (a, 0, it, EXCH, 0).
 __device__ __forceinline__ double pt_log_u(int a, uint64_t seed, uint32_t it) {
     return log(u01_open(draw(seed, static_cast<uint32_t>(a), 0, it, kExch, 0).w0));

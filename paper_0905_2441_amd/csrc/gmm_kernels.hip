@@ -318,6 +318,107 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
     if (threadIdx.x == 0) *it_dev = it0 + n_iters;
 }
 
+// One population-MCMC iteration per launch for populations spread over many
+// workgroups, with the exchange deferred: a launch reads the population after
+// the previous iteration's moves (th_in, l_in), first takes that iteration's
+// exchange for each of its chains (both chains of a pair reach the same
+// decision from the same inputs; each keeps its own side), then makes this
+// iteration's move and writes the population to the other buffer (th_out,
+// l_out). The iteration index comes from *it_in; workgroup 0 stores it + 1 in
+// *it_out (a different counter, so no workgroup reads a changed value). With
+// pending = 0 (the first iteration of a sequence) no exchange precedes the
+// move. Arithmetic and random streams are those of the move and exchange
+// kernels, so the results equal theirs bit for bit.
+template <int K, int D, int PREC>
+__global__ void __launch_bounds__(1024)
+k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_in,
+              const double* __restrict__ l_in, double* __restrict__ th_out,
+              double* __restrict__ l_out, int M, const double* __restrict__ beta,
+              const int* it_in, int* it_out, int pending, int parity_mode, int wrap, double sd,
+              uint64_t seed, GmmDev g, unsigned long long* n_acc, unsigned* n_swap, int* status) {
+    constexpr int KD = K * D;
+    __shared__ double red[kMaxSlices][kWave];
+    __shared__ double cur[KD][kWave];
+    __shared__ double prs[KD][kWave];
+    __shared__ double lcur[kWave];
+    const int S = wave_uniform(blockDim.x / kWave);
+    const int lane = lane_id();
+    const int w = wave_uniform(threadIdx.x / kWave);
+    const int p = static_cast<int>(blockIdx.x) * kWave + lane;
+    const int pc = p < M ? p : M - 1;
+    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
+    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    const uint32_t it = static_cast<uint32_t>(*it_in);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *it_out = static_cast<int>(it) + 1;
+    if (w == 0) {
+        int src = pc;
+        if (pending) {
+            const uint32_t prev = it - 1u;
+            const int parity = pt_parity(parity_mode, 0, seed, prev);
+            int a, b;
+            if (pt_pair_of(M, parity, wrap, pc, a, b)) {
+                const double la = (beta[a] - beta[b]) * (l_in[b] - l_in[a]);
+                if (la >= 0.0 || pt_log_u(a, seed, prev) < la) {
+                    src = pc == a ? b : a;
+                    if (p < M && p == a && n_swap != nullptr) atomicAdd(n_swap, 1u);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < KD; ++c) cur[c][lane] = th_in[static_cast<size_t>(c) * M + src];
+        lcur[lane] = l_in[src];
+    }
+    __syncthreads();
+    double pr[KD];
+    block_proposals<KD>(seed, static_cast<uint32_t>(pc), it, 0, &cur[0][0], kWave, lane, sd, w, S,
+                        prs, pr);
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g));
+    __syncthreads();
+    if (w != 0) return;
+    double tot = red[0][lane];
+    for (int q = 1; q < S; ++q) tot += red[q][lane];
+    const double l_prop = finish_loglik<PREC>(tot, n, g);
+    const bool acc = rwmh_decide<KD>(
+        pc, [&](int c) { return pr[c]; }, [&](int c) { return cur[c][lane]; }, lcur[lane], l_prop,
+        beta, StepSrc{}, it, seed, 0, g);
+    if (p < M) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) th_out[static_cast<size_t>(c) * M + p] = acc ? pr[c] : cur[c][lane];
+        l_out[p] = acc ? l_prop : lcur[lane];
+        if (l_prop != l_prop) atomicOr(status, kStatusNaN);
+    }
+    const unsigned long long mask = __ballot(acc && p < M);
+    if (lane == 0 && n_acc != nullptr && mask != 0ull)
+        atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
+}
+
+// The last deferred exchange of a sequence, out of place: each chain reads its
+// pair from (th_in, l_in) and writes its own side to (th_out, l_out); the
+// iteration is *it_src - 1 and *it_dst receives *it_src.
+__global__ void __launch_bounds__(256)
+k_pt_deferred_exchange(const double* __restrict__ th_in, const double* __restrict__ l_in,
+                       double* __restrict__ th_out, double* __restrict__ l_out, int M, int kd,
+                       const double* __restrict__ beta, const int* it_src, int* it_dst,
+                       int parity_mode, int wrap, uint64_t seed, unsigned* n_swap) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int itp1 = *it_src;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *it_dst = itp1;
+    if (c >= M) return;
+    const uint32_t prev = static_cast<uint32_t>(itp1) - 1u;
+    const int parity = pt_parity(parity_mode, 0, seed, prev);
+    int src = c;
+    int a, b;
+    if (pt_pair_of(M, parity, wrap, c, a, b)) {
+        const double la = (beta[a] - beta[b]) * (l_in[b] - l_in[a]);
+        if (la >= 0.0 || pt_log_u(a, seed, prev) < la) {
+            src = c == a ? b : a;
+            if (c == a && n_swap != nullptr) atomicAdd(n_swap, 1u);
+        }
+    }
+    for (int q = 0; q < kd; ++q) th_out[static_cast<size_t>(q) * M + c] = th_in[static_cast<size_t>(q) * M + src];
+    l_out[c] = l_in[src];
+}
+
 // Second half of a move whose tile data were split over G workgroups, for
 // particle p: add the G partial sums in group order, re-form the same proposal
 // (same counter, same arithmetic) and take the MH decision.
@@ -566,9 +667,10 @@ int pt_local_chains(int kd) { return kd < 1 ? 0 : pt_local_cap(kd); }
 // One workgroup runs on one compute unit, so the single-launch form pays off
 // only while an iteration's likelihood work (64-lane tiles x n data x k*d) is
 // small enough that the launches it saves cost more than the parallelism it
-// gives up: measured on the paper's population-MCMC runs (n = 100, k = 4), up
-// to 256 chains at n = 100 and about 32 at n = 1000.
-constexpr int64_t kPtLocalWork = int64_t{1} << 17;
+// gives up against the one-launch-per-iteration (deferred exchange) form:
+// measured on the paper's population-MCMC runs (n = 100, k = 4), up to 128
+// chains at n = 100.
+constexpr int64_t kPtLocalWork = int64_t{1} << 16;
 
 bool pt_local_pays(int kd, int64_t n, int64_t M) {
     const int64_t tiles = (M + kWave - 1) / kWave;
@@ -650,6 +752,45 @@ hipError_t launch_pt_iteration(const GmmDev& g, const float* y, int64_t n, doubl
 #undef SMC_CASE
 #undef SMC_PT
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_pt_deferred(const GmmDev& g, const float* y, int64_t n, double* theta,
+                              double* l, int64_t M, const double* beta, int* it_dev,
+                              int n_iters, double sd, uint64_t seed, int prec, int parity_mode,
+                              int wrap, int slices, unsigned long long* n_accept,
+                              unsigned* n_swap, const Scratch& sc, int* counter2,
+                              hipStream_t s) {
+    const int kd = g.k * g.d;
+    if (M < 2 || n_iters < 1 || slices < 1 || slices > kMaxSlices || sc.cap < M) return hipErrorInvalidValue;
+    const int64_t tiles = (M + kWave - 1) / kWave;
+    // buffers X0 = (theta, l) and X1 = scratch, counters C0 = it_dev and C1
+    double* th[2] = {theta, sc.theta_tmp};
+    double* lb[2] = {l, sc.l_tmp};
+    int* ctr[2] = {it_dev, counter2};
+    const dim3 grid(static_cast<unsigned>(tiles)), block(static_cast<unsigned>(kWave * slices));
+    for (int i = 0; i < n_iters; ++i) {
+        const int a = i & 1, b = a ^ 1;
+#define SMC_DEF(K, D, P)                                                                               hipLaunchKernelGGL((k_pt_deferred<K, D, P>), grid, block, 0, s, y, static_cast<int>(n),                             th[a], lb[a], th[b], lb[b], static_cast<int>(M), beta, ctr[a],                                  ctr[b], i > 0 ? 1 : 0, parity_mode, wrap, sd, seed, g, n_accept,                                n_swap, sc.status)
+#define SMC_CASE(K, D)                                                                                 if (g.k == K && g.d == D) {                                                                        if (prec == SMC_PREC_FP32) SMC_DEF(K, D, SMC_PREC_FP32);                                       else SMC_DEF(K, D, SMC_PREC_FP64);                                                         } else
+        SMC_KD_CASES(SMC_CASE) { return hipErrorInvalidValue; }
+#undef SMC_CASE
+#undef SMC_DEF
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // the last exchange: in place on X0 (pairs) when the population ended there,
+    // else from X1 into X0 (chains)
+    if ((n_iters & 1) == 0) {
+        StepSrc src{};
+        src.t_dev = counter2;                  // holds the last iteration's index
+        return launch_exchange(theta, l, beta, M, kd, parity_mode, 0, wrap, seed, src, it_dev,
+                               n_swap, s);
+    }
+    hipLaunchKernelGGL(k_pt_deferred_exchange, dim3(static_cast<unsigned>((M + 255) / 256)),
+                       dim3(256), 0, s, sc.theta_tmp, sc.l_tmp, theta, l, static_cast<int>(M), kd,
+                       beta, static_cast<const int*>(counter2), it_dev, parity_mode, wrap, seed,
+                       n_swap);
+    return hipGetLastError();
 }
 
 hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta,

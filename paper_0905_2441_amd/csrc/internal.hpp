@@ -186,6 +186,17 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
 // Largest population the one-workgroup population-MCMC form holds (0: none).
 int pt_local_chains(int kd);
 bool pt_local_pays(int kd, int64_t n, int64_t M);
+// n_iters population-MCMC iterations with one launch each (the exchange of an
+// iteration deferred into the next launch) plus one closing exchange; the
+// population alternates between (theta, l) and the scratch theta_tmp/l_tmp
+// (sc.cap >= M, kd rows), and the iteration index between *it_dev and
+// *counter2. Tiles of 64 chains in one workgroup of `slices` waves.
+hipError_t launch_pt_deferred(const GmmDev& g, const float* y, int64_t n, double* theta,
+                              double* l, int64_t M, const double* beta, int* it_dev,
+                              int n_iters, double sd, uint64_t seed, int prec, int parity_mode,
+                              int wrap, int slices, unsigned long long* n_accept,
+                              unsigned* n_swap, const Scratch& sc, int* counter2,
+                              hipStream_t s);
 int pt_local_slices(int64_t n, int64_t M);
 // n_iters population-MCMC iterations in one single-workgroup launch (chains in
 // LDS; M <= pt_local_chains(k*d)); `slices` data slices per 64-chain tile.

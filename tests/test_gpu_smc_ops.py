@@ -473,13 +473,20 @@ def test_exchange_matches_oracle(smc, ctx, M, parity, wrap):
     (7, 1, "fp64", 576, 1, 1, True, 5),        # k*d = 7: 576 chains in LDS
     (2, 8, "fp32", 256, 4, 0, False, 4),       # k*d = 16: 256 chains
     (1, 1, "fp32", 2, 16, 1, False, 11),       # two chains, 16 slices of one tile
-    (4, 1, "fp32", 1025, 0, 0, False, 3),      # past the single-workgroup form: per iteration
+    (4, 1, "fp32", 1025, 0, 0, False, 3),      # past the single-workgroup form
+    # one launch per iteration with the exchange deferred (odd and even counts)
+    (4, 1, "fp32", 1025, 4, 1, True, 3),
+    (4, 1, "fp64", 2048, 2, 1, True, 4),
+    (2, 8, "fp32", 700, 2, 0, False, 5),
+    (1, 1, "fp64", 1500, 8, 1, True, 1),
 ])
 def test_pt_iterations_equal_single_iterations(smc, ctx, k, d, prec, M, slices, parity, wrap,
                                                iters):
     """pt_iterations(n) leaves exactly the state, counter and tallies of n
     pt_iteration calls with the same launch shape (both sum a tile's slices in
-    the same order, so even FP32 agrees bit for bit)."""
+    the same order, so even FP32 agrees bit for bit): the single-workgroup
+    form for populations that fit, else one launch per iteration with the
+    exchange deferred into the next launch."""
     announce(f"pt_iterations k={k} d={d} {prec} M={M} slices={slices} parity={parity}")
     rng = np.random.default_rng(M + 7 * k)
     mu = rng.uniform(-4.0, 6.0, size=(k, d)) if d > 1 else np.linspace(-3.0, 6.0, k)
