@@ -303,6 +303,36 @@ def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph, fused):
     assert rel_err(r["l"], ref["l"]).max() <= 1e-10
 
 
+@pytest.mark.parametrize("M,iters,iters_per_graph,parity_mode,wrap",
+                         [(600, 15, 7, 0, False), (640, 16, 8, 1, True), (1001, 9, 9, 1, True)])
+def test_pt_deferred_exchange_graphs_match_oracle(smc, ctx, M, iters, iters_per_graph,
+                                                  parity_mode, wrap):
+    """Populations past the single-workgroup form, one launch per iteration
+    with the exchange deferred, captured in graphs of odd and even iteration
+    counts (so the population ends in either buffer), in FP64 against the
+    oracle's run."""
+    announce(f"pt deferred M={M} iters={iters}/{iters_per_graph} parity={parity_mode} wrap={wrap}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(100, mu, 0.3025, seed=5)
+    betas = pt_betas(M, 2)
+    g = smc.Gmm.equal_weights(4, 1, 0.3025, prior="box", prior_a=-10.0, prior_b=10.0)
+    om = oracle_model(g)
+    ctx.set_slices(4)
+    try:
+        s = smc.PTSampler(ctx, g, y, betas, 1.0, seed=17, parity_mode=parity_mode, wrap=wrap,
+                          prec="fp64")
+        r = s.run(iters, graph=True, iters_per_graph=iters_per_graph)
+    finally:
+        ctx.set_slices(0)
+    ref = osmc.pt_run(y, om, betas, iters, 1.0, 17,
+                      parity_mode="random" if parity_mode else "alternate", wrap=wrap)
+    assert r["it"] == iters
+    assert r["swaps"] == ref["swaps"]
+    assert r["accepted"] == ref["accepted"]
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert rel_err(r["l"], ref["l"]).max() <= 1e-10
+
+
 @pytest.mark.parametrize("M,slices,fused", [(32, 0, False), (32, 40, False), (33, 24, False),
                                             (32, 0, True), (33, 5, True)])
 def test_pt_paper_mode_random_parity_wrap(smc, ctx, M, slices, fused):
