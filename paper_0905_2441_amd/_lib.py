@@ -98,6 +98,8 @@ SIGNATURES = {
                          c_double, _P, _P, _P]),
     "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,
                          c_double, c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
+    "smc_steps": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,
+                          c_int32, c_double, c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
     "pt_iteration": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_double, c_uint64,
                              c_int32, c_int32, c_int, _P, _P, _P]),
     "smc_batch_create": (c_int, [_P, POINTER(SmcRunDesc), c_int32, c_int32, POINTER(c_void_p)]),

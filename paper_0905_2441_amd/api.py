@@ -260,6 +260,26 @@ def smc_step(ctx: Context, model: Gmm, y, theta_in, loglik_in, theta_out, loglik
         _stream(stream)))
 
 
+def smc_steps(ctx: Context, model: Gmm, y, theta_a, loglik_a, theta_b, loglik_b, logw, W, beta,
+              t_dev, n_steps, step_sd, n_moves, seed, ess_frac, prec, stats, n_accept=None,
+              stream=None):
+    """n_steps tempering steps alternating between the (a) and (b) populations
+    (even step indices read a); see smc.h."""
+    n = _data_shape(model, y)
+    N = _theta_shape(model, theta_a)
+    L.check(ctx._lib.smc_steps(
+        ctx.handle, ctypes.byref(model.struct()), _ptr(y, torch.float32, "y"), n, N,
+        _ptr(theta_a, torch.float64, "theta_a", model.kd * N),
+        _ptr(loglik_a, torch.float64, "loglik_a", N),
+        _ptr(theta_b, torch.float64, "theta_b", model.kd * N),
+        _ptr(loglik_b, torch.float64, "loglik_b", N),
+        _ptr(logw, torch.float64, "logw", N), _ptr(W, torch.float64, "W", N),
+        _ptr(beta, torch.float64, "beta"), beta.numel() - 1, _ptr(t_dev, torch.int32, "t_dev", 1),
+        int(n_steps), float(step_sd), int(n_moves), int(seed), float(ess_frac), _prec(prec),
+        _ptr(stats, torch.float64, "stats", 4), _opt(n_accept, torch.int64, "n_accept", 1),
+        _stream(stream)))
+
+
 def pt_iteration(ctx: Context, model: Gmm, y, theta, loglik, beta, it_dev, step_sd, seed,
                  parity_mode=0, wrap=False, prec="fp32", n_accept=None, n_swap=None,
                  stream=None):

@@ -655,6 +655,94 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
     return SMC_OK;
 }
 
+int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
+              double* theta_a, double* loglik_a, double* theta_b, double* loglik_b,
+              double* logw, double* W, const double* beta, int32_t T, int32_t* t_dev,
+              int32_t n_steps, double step_sd, int32_t n_moves, uint64_t seed, double ess_frac,
+              smc_prec prec, double* stats, unsigned long long* n_accept, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (n_steps < 1) return fail(SMC_ERR_INVALID_ARG, "n_steps must be >= 1");
+    if (!theta_a || !loglik_a || !theta_b || !loglik_b) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    GmmDev g;
+    if ((r = check_model(model, &g))) return r;
+    if ((r = check_prec(g, prec))) return r;
+    if ((r = check_sizes(n, N))) return r;
+    const int64_t tiles = (N + kWave - 1) / kWave;
+    constexpr int64_t kFusedTiles = static_cast<int64_t>(sizeof(double)) * kMaxGroups * kSplitCap /
+                                    static_cast<int64_t>(sizeof(RwPartial));
+    const Split sp = choose_split(ctx, g, prec, n, N, true);
+    const bool fuse = prec != SMC_PREC_BF16X3 && n_moves == 1 && sp.groups == 1 && n_steps >= 2 &&
+                      tiles <= kFusedTiles;
+    if (!fuse) {
+        for (int32_t i = 0; i < n_steps; ++i) {
+            const bool odd = (i & 1) != 0;
+            r = smc_step(ctx, model, y, n, N, odd ? theta_b : theta_a, odd ? loglik_b : loglik_a,
+                         odd ? theta_a : theta_b, odd ? loglik_a : loglik_b, logw, W, beta, T,
+                         t_dev, step_sd, n_moves, seed, ess_frac, prec, stats, n_accept, stream);
+            if (r) return r;
+        }
+        return SMC_OK;
+    }
+    // the argument checks of smc_step
+    if (!y || !logw || !W || !beta || !t_dev || !stats) return fail(SMC_ERR_INVALID_ARG, "NULL array");
+    if (theta_a == theta_b || loglik_a == loglik_b)
+        return fail(SMC_ERR_INVALID_ARG, "the steps alternate between two populations");
+    if (T < 1) return fail(SMC_ERR_INVALID_ARG, "T must be >= 1");
+    if (!(step_sd >= 0.0) || !isfinite(step_sd))
+        return fail(SMC_ERR_INVALID_ARG, "step_sd must be finite and >= 0");
+    if (!(ess_frac >= 0.0) || ess_frac > 1.0) return fail(SMC_ERR_INVALID_ARG, "ess_frac in [0,1]");
+    const hipStream_t s = as_stream(stream);
+    if ((r = ensure_scratch(ctx, N, g.k * g.d, s))) return r;
+    StepSrc src{};
+    src.t_dev = t_dev;
+    src.beta_dev = beta;
+    src.t_max = T;
+    StepSrc later = src;
+    later.t_dev = &ctx->sc.state->t;
+    int chunk, nchunks;
+    cdf_layout(N, &chunk, &nchunks);
+    double* lw_next = ctx->sc.l_tmp;
+    RwPartial* next_part = reinterpret_cast<RwPartial*>(ctx->sc.mv_part);
+    for (int32_t i = 0; i < n_steps; ++i) {
+        const bool odd = (i & 1) != 0;
+        hipError_t e;
+        if (i == 0) {
+            e = launch_reweight_partial(ctx->sc, logw, loglik_a, N, src, s);
+            if (e == hipSuccess) e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s);
+        } else {
+            // the previous move made this step's reweight and its partials
+            e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, lw_next, s, nullptr, 0,
+                                0, nullptr, next_part, static_cast<int>(tiles));
+        }
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        MoveStep ms{};
+        ms.theta_src = odd ? theta_b : theta_a;
+        ms.l_src = odd ? loglik_b : loglik_a;
+        ms.state = ctx->sc.state;
+        ms.W_out = W;
+        ms.logw = i == 0 ? logw : lw_next;
+        ms.logw_out = logw;
+        ms.cdf_hi = ctx->sc.cdf_hi;
+        ms.cdf_lo = ctx->sc.cdf_lo;
+        ms.chunk_tot = ctx->sc.dd_part;
+        ms.chunk = chunk;
+        ms.nchunks = nchunks;
+        ms.seed = seed;
+        ms.scheme = ctx->scheme;
+        if (i + 1 < n_steps) {
+            ms.lw_next = lw_next;
+            ms.next_part = next_part;
+            ms.beta_dev = beta;
+            ms.t_max = T;
+        }
+        e = launch_rwmh_moves(g, y, n, odd ? theta_a : theta_b, odd ? loglik_a : loglik_b, N, later,
+                              step_sd, seed, 1, prec, n_accept, sp, ctx->sc, ms, s);
+        if (e != hipSuccess) return hip_fail(e, "rwmh launch");
+    }
+    return SMC_OK;
+}
+
 int pt_iteration(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t M,
                  double* theta, double* loglik, const double* beta, int32_t* it_dev,
                  double step_sd, uint64_t seed, int32_t parity_mode, int32_t wrap, smc_prec prec,

@@ -328,26 +328,29 @@ __device__ __forceinline__ bool rwmh_decide(int p, PropAt pr_at, CurAt cur_at, d
 }
 
 // The step duties of a move's first launch: publish W (1/N after resampling)
-// and reset logw after resampling.
+// and reset logw after resampling (in place, or into logw_out).
 __device__ __forceinline__ void move_duties(int p, int N, const MoveStep& ms) {
     const bool rs = (ms.state != nullptr) && (ms.state->resampled != 0);
     if (ms.W_out) {
         ms.W_out[p] = rs ? 1.0 / static_cast<double>(N)
                          : exp(ms.logw[p] - ms.state->M) / ms.state->S;
     }
-    if (rs && ms.reset_logw) ms.logw[p] = 0.0;
+    if (ms.logw_out) ms.logw_out[p] = rs ? 0.0 : ms.logw[p];
+    else if (rs && ms.reset_logw) ms.logw[p] = 0.0;
 }
 
 // Decision and write-back of particle p of a random-walk move. The current
 // state is column a of (th_src, l_src) (a = p, or p's ancestor after a fused
 // resampling) and is re-read rather than held; pr_at(c) returns coordinate c of
 // the proposal. Rejected particles are copied when the move is out of place.
+// l_new (optional) receives the particle's log-likelihood after the move.
 template <int KD, class PropAt>
 __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, double l_prop,
                                             const MoveSource& srcs, double* theta, double* l,
                                             const double* beta_vec, const StepSrc& src,
                                             uint32_t step, uint64_t seed, uint32_t move,
-                                            const GmmDev& g, int* status, const MoveStep& ms) {
+                                            const GmmDev& g, int* status, const MoveStep& ms,
+                                            double* l_new = nullptr) {
     const double* th_src = srcs.th;
     const double l_cur = srcs.l[a];
     const bool acc = rwmh_decide<KD>(
@@ -365,6 +368,7 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
     }
     if (l_prop != l_prop) atomicOr(status, kStatusNaN);
     move_duties(p, N, ms);
+    if (l_new) *l_new = acc ? l_prop : l_cur;
     return acc;
 }
 

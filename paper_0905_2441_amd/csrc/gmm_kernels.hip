@@ -28,6 +28,7 @@
 // device library's exp/log for every term and a plain FP64 sum over data.
 #include "exchange.hpp"
 #include "gmm_common.hpp"
+#include "reduce.hpp"
 
 namespace smc {
 namespace {
@@ -59,7 +60,10 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
     }
 }
 
-template <int K, int D, int PREC>
+// CHAIN: the move also makes the next tempering step's reweight (ms.lw_next set,
+// one workgroup per tile); a separate instantiation keeps the plain move's code
+// free of it.
+template <int K, int D, int PREC, bool CHAIN>
 __global__ void __launch_bounds__(1024)
 k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        const double* __restrict__ beta_vec, StepSrc src, double sd, uint64_t seed,
@@ -106,17 +110,37 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         }
         return;
     }
+    // this step's log-weight, loaded while the decision is made (with a chain of
+    // steps logw and lw_next may be one array: read before it is overwritten)
+    const double lw_now = (CHAIN && p < N) ? ms.logw[p] : 0.0;
     bool acc = false;
+    double l_new = 0.0;
     if (p < N) {
         double tot = red[0][lane];
         for (int s = 1; s < S; ++s) tot += red[s][lane];
         const double l_prop = finish_loglik<PREC>(tot, n, g);
         acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
-                              beta_vec, src, step, seed, move, g, status, ms);
+                              beta_vec, src, step, seed, move, g, status, ms,
+                              CHAIN ? &l_new : nullptr);
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
         atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
+    if constexpr (CHAIN) {
+        // the next step's reweight of this tile (the pass a separate reweight
+        // kernel would make) and the log-sum-exp partials of the new weights
+        const int t1 = static_cast<int>(step) + 1 > ms.t_max ? ms.t_max : static_cast<int>(step) + 1;
+        const double dbeta = ms.beta_dev[t1] - ms.beta_dev[t1 - 1];
+        Lse3 nw = lse3_empty();
+        if (p < N) {
+            const double ln = (ms.state->resampled != 0 ? 0.0 : lw_now) + dbeta * l_new;
+            ms.lw_next[p] = ln;
+            if (ln != ln || ln == INFINITY) atomicOr(status, kStatusNaN);
+            if (ln != -INFINITY) nw = Lse3{ln, 1.0, 1.0};
+        }
+        nw = wave_lse3(nw);
+        if (lane == 0) ms.next_part[tile] = RwPartial{0.0, 0.0, nw.m, nw.s1, nw.s2, 0.0};
+    }
 }
 
 // Several consecutive moves of one tempering step in one launch (one
@@ -575,10 +599,16 @@ void launch_move_partials(const float* y, int64_t n, double* theta, double* l, i
                           uint32_t move, const GmmDev& g, unsigned long long* n_accept,
                           const Split& sp, const Scratch& sc, const MoveStep& ms, hipStream_t s) {
     const int64_t tiles = (N + kWave - 1) / kWave;
-    hipLaunchKernelGGL((k_rwmh<K, D, P>), dim3(static_cast<unsigned>(tiles * sp.groups)),
-                       dim3(static_cast<unsigned>(kWave * sp.slices)), 0, s, y,
-                       static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec, src, sd, seed,
-                       move, g, n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
+    const dim3 grid(static_cast<unsigned>(tiles * sp.groups));
+    const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+    if (ms.lw_next != nullptr)
+        hipLaunchKernelGGL((k_rwmh<K, D, P, true>), grid, block, 0, s, y, static_cast<int>(n),
+                           theta, l, static_cast<int>(N), beta_vec, src, sd, seed, move, g,
+                           n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
+    else
+        hipLaunchKernelGGL((k_rwmh<K, D, P, false>), grid, block, 0, s, y, static_cast<int>(n),
+                           theta, l, static_cast<int>(N), beta_vec, src, sd, seed, move, g,
+                           n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
 }
 
 }  // namespace
@@ -618,6 +648,8 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
                              int n_moves, int prec, unsigned long long* n_accept, Split sp,
                              const Scratch& sc, MoveStep ms, hipStream_t s) {
     if (!valid_split(sp, N) || n_moves < 1) return hipErrorInvalidValue;
+    // the next step's reweight is made by a single move of one workgroup per tile
+    if (ms.lw_next != nullptr && (n_moves != 1 || sp.groups != 1)) return hipErrorInvalidValue;
     bool one_launch = false;
     if (n_moves > 1 && sp.groups == 1) {
 #define SMC_CASE(K, D)                                                                         \

@@ -121,6 +121,17 @@ struct MoveStep {
     uint64_t seed;
     int scheme;                // resampling points (smc_resampling)
     int* t_out;                // nullable: the move records its step index here
+    // a chain of tempering steps (smc_steps): the move also writes the step's
+    // final log-weights to logw_out (0 after resampling, else logw) and, with
+    // lw_next set, the next step's reweighted ones, lw_next[p] = that value +
+    // (beta[t1] - beta[t1 - 1]) l[p] with t1 = min(t + 1, t_max), and per
+    // 64-particle tile the log-sum-exp partials of the new weights (next_part:
+    // mn, s1, s2; the old weights' log-sum-exp is known from the step state)
+    double* logw_out;
+    double* lw_next;
+    RwPartial* next_part;
+    const double* beta_dev;
+    int t_max;
 };
 
 // Launch shape of a VALU move for one 64-particle tile: `groups` workgroups of
@@ -258,10 +269,15 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
 // CDF chunks) -> moves (ancestor search fused into the first move).
 // With `mom` (a particle filter's moment partials), also the step's weighted
 // moments into moments[(t-1) * 2 mom_k ...] (means, then standard deviations).
+// With `part` (nparts per-tile partials of the new weights made by the previous
+// step's move in a chain of steps), the combine reads those instead of the
+// reweight pass's, and the old weights' log-sum-exp is the previous step's
+// (log N after a resampling) from the step state.
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
                            double* stats, double ess_frac, const double* logw, hipStream_t s,
                            const double* mom = nullptr, int mom_k = 0, int mom_stride = 0,
-                           double* moments = nullptr);
+                           double* moments = nullptr, const RwPartial* part = nullptr,
+                           int nparts = 0);
 void cdf_layout(int64_t N, int* chunk, int* nchunks);
 hipError_t launch_search_gather(const Scratch& sc, int64_t N, int scheme, uint64_t seed,
                                 StepSrc src, const StepState* pred_state, const double* theta_in,

@@ -26,6 +26,15 @@ __device__ __forceinline__ Lse3 lse3_push(Lse3 a, double x) {
                 up ? a.s2 * (e * e) + 1.0 : a.s2 + e * e};
 }
 
+// Wave (64 lanes) log-sum-exp, the same value in every lane: the wave maximum
+// first, then each lane's sums rescaled to it with one exp and added by a
+// fixed butterfly.
+__device__ __forceinline__ Lse3 wave_lse3(Lse3 v) {
+    const double m = wave_max(v.m);
+    const double r = (v.m == -INFINITY) ? 0.0 : exp(v.m - m);
+    return Lse3{m, wave_sum(v.s1 * r), wave_sum(v.s2 * (r * r))};
+}
+
 __device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
     if (b.m == -INFINITY) return a;
     if (a.m == -INFINITY) return b;
@@ -66,6 +75,19 @@ __device__ __forceinline__ Lse3 block_lse3(Lse3 v) {
     }
     __syncthreads();
     return out;
+}
+
+// Block (kRedBlock threads) maximum, valid in every thread.
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double sh[kRedBlock / kWave];
+    v = wave_max(v);
+    if (lane_id() == 0) sh[wave_id()] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kRedBlock / kWave; ++w) r = fmax(r, sh[w]);
+    __syncthreads();
+    return r;
 }
 
 __device__ __forceinline__ double block_sum(double v) {

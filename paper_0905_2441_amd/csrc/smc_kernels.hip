@@ -182,22 +182,62 @@ k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
 // exp(logw - M) / S1. With `mom` (a particle filter's per-workgroup sums of
 // w x and w x^2 over k state components, w = exp(logw - block max), stride
 // mom_stride per workgroup), workgroup 0 also writes the step's weighted means
-// and standard deviations to moments[(t-1) * 2k ...].
+// and standard deviations to moments[(t-1) * 2k ...]. With `chained`, the
+// partials are the per-tile ones of the new weights made by the previous move
+// of a chain of steps (many more than the reweight pass makes): their maximum
+// is formed first so that the loads and exps of different partials do not
+// wait on each other, and the old weights' log-sum-exp is taken from the step
+// state (the previous step's new one, or log N after its resampling).
 __global__ void __launch_bounds__(kRedBlock)
 k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
            double* stats, double ess_frac, const double* __restrict__ logw,
            const double* __restrict__ mom, int mom_k, int mom_stride,
-           double* __restrict__ moments) {
+           double* __restrict__ moments, const RwPartial* __restrict__ part, int chained) {
     __shared__ double sh_M, sh_S;
     __shared__ int sh_fire, sh_t;
     Lse3 o = lse3_empty(), nw = lse3_empty();
-    for (int b = threadIdx.x; b < parts; b += blockDim.x) {
-        const RwPartial q = sc.rw_part[b];
-        o = lse3_merge(o, Lse3{q.mo, q.so, 0.0});
-        nw = lse3_merge(nw, Lse3{q.mn, q.s1, q.s2});
+    if (chained) {
+        // kU partials per thread per round, their loads issued together
+        constexpr int kU = 8;
+        double m = -INFINITY;
+        for (int b0 = threadIdx.x; b0 < parts; b0 += kU * kRedBlock) {
+            double v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int b = b0 + u * kRedBlock;
+                v[u] = b < parts ? part[b].mn : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) m = fmax(m, v[u]);
+        }
+        m = block_max(m);
+        double a = 0.0, c = 0.0;
+        for (int b0 = threadIdx.x; b0 < parts; b0 += kU * kRedBlock) {
+            double vm[kU], v1[kU], v2[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int b = b0 + u * kRedBlock;
+                vm[u] = b < parts ? part[b].mn : -INFINITY;
+                v1[u] = b < parts ? part[b].s1 : 0.0;
+                v2[u] = b < parts ? part[b].s2 : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const double r = vm[u] == -INFINITY ? 0.0 : exp(vm[u] - m);
+                a += v1[u] * r;
+                c += v2[u] * (r * r);
+            }
+        }
+        nw = Lse3{m, block_sum(a), block_sum(c)};
+    } else {
+        for (int b = threadIdx.x; b < parts; b += blockDim.x) {
+            const RwPartial q = part[b];
+            o = lse3_merge(o, Lse3{q.mo, q.so, 0.0});
+            nw = lse3_merge(nw, Lse3{q.mn, q.s1, q.s2});
+        }
+        o = block_lse3(o);
+        nw = block_lse3(nw);
     }
-    o = block_lse3(o);
-    nw = block_lse3(nw);
     if (threadIdx.x == 0) {
         const double e = (nw.s1 * nw.s1) / nw.s2;
         const int fire = (ess_frac > 0.0) && (e < ess_frac * static_cast<double>(N));
@@ -208,10 +248,13 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
             StepState* st = sc.state;
             const int t = step_index(src);
             sh_t = t;
+            const double lse_old =
+                chained ? (st->resampled ? log(static_cast<double>(N)) : st->lse_new)
+                        : ((o.m == -INFINITY) ? -INFINITY : o.m + log(o.s1));
             st->M = nw.m;
             st->S = nw.s1;
             st->S2 = nw.s2;
-            st->lse_old = (o.m == -INFINITY) ? -INFINITY : o.m + log(o.s1);
+            st->lse_old = lse_old;
             st->lse_new = (nw.m == -INFINITY) ? -INFINITY : nw.m + log(nw.s1);
             st->ess = e;
             st->resampled = fire;
@@ -231,7 +274,7 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
         for (int c = 0; c < mom_k; ++c) {
             double a = 0.0, b = 0.0;
             for (int q = threadIdx.x; q < parts; q += blockDim.x) {
-                const double mb = sc.rw_part[q].mn;
+                const double mb = part[q].mn;
                 const double r = (mb == -INFINITY) ? 0.0 : exp(mb - M);
                 a += mom[static_cast<size_t>(q) * mom_stride + c] * r;
                 b += mom[static_cast<size_t>(q) * mom_stride + mom_k + c] * r;
@@ -471,13 +514,15 @@ hipError_t launch_exchange(double* theta, double* l, const double* beta, int64_t
 
 hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_advance,
                            double* stats, double ess_frac, const double* logw, hipStream_t s,
-                           const double* mom, int mom_k, int mom_stride, double* moments) {
-    const int parts = red_grid(N);
+                           const double* mom, int mom_k, int mom_stride, double* moments,
+                           const RwPartial* part, int nparts) {
+    const int parts = part ? nparts : red_grid(N);
     const int chunk = cdf_chunk(N);
     const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_step_mid, dim3(nchunks), dim3(kRedBlock), 0, s, parts, static_cast<int>(N),
                        chunk, src, t_advance, sc, stats, ess_frac, logw, mom, mom_k, mom_stride,
-                       moments);
+                       moments, part ? part : static_cast<const RwPartial*>(sc.rw_part),
+                       part ? 1 : 0);
     return hipGetLastError();
 }
 

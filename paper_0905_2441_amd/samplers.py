@@ -26,7 +26,7 @@ import numpy as np
 import torch
 
 from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, pt_iteration, pt_iterations,
-                  pt_record, smc_loglik, smc_prior_init, smc_step, smc_step_batched)
+                  pt_record, smc_loglik, smc_prior_init, smc_step, smc_step_batched, smc_steps)
 
 
 def _dev(x, dtype):
@@ -89,6 +89,15 @@ class SMCSampler:
                  self.step_sd, self.n_moves, self.seed, self.ess_frac, self.prec, self.stats,
                  self.n_accept, stream=self.stream)
 
+    def enqueue_steps(self, src: int, steps: int):
+        """`steps` consecutive steps from buffer `src` in one smc_steps call (each
+        move after the first step's also makes the next step's reweight)."""
+        self.ctx.set_resampling(self.scheme)
+        smc_steps(self.ctx, self.model, self.y, self.thetas[src], self.logliks[src],
+                  self.thetas[1 - src], self.logliks[1 - src], self.logw, self.W, self.beta,
+                  self.t, steps, self.step_sd, self.n_moves, self.seed, self.ess_frac, self.prec,
+                  self.stats, self.n_accept, stream=self.stream)
+
     def capture(self, src: Optional[int] = None, steps: int = 1) -> Graph:
         """The hipGraph of `steps` consecutive tempering steps starting from buffer
         `src` (replayable for every t: t, beta_t and the resampling decision live
@@ -98,34 +107,30 @@ class SMCSampler:
         if key not in self.graphs:
             g = Graph(self.ctx, self.stream)
             with g:
-                b = src
-                for _ in range(int(steps)):
-                    self.enqueue_step(b)
-                    b = 1 - b
+                self.enqueue_steps(src, int(steps))
             self.graphs[key] = g
         return self.graphs[key]
 
     def step(self, graph: bool = True, steps: int = 1):
-        """Advance `steps` tempering steps (one graph replay when graph=True)."""
+        """Advance `steps` tempering steps in one smc_steps call (replayed as one
+        graph when graph=True); a single step is exactly an smc_step call."""
         if graph:
             self.capture(self.cur, steps).launch()
+        elif int(steps) == 1:
+            self.enqueue_step(self.cur)
         else:
-            for _ in range(int(steps)):
-                self.enqueue_step(self.cur)
-                self.cur = 1 - self.cur
-            return
+            self.enqueue_steps(self.cur, int(steps))
         self.cur = self.cur ^ (int(steps) & 1)
 
     def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 10):
-        """Advance `steps` steps with graphs of `steps_per_graph` steps (plus single steps)."""
-        if not graph:
-            self.step(False, steps)
-            return
+        """Advance `steps` steps in groups of `steps_per_graph` (plus single steps),
+        each group one graph replay (graph=True) or one eager smc_steps call; the
+        same grouping gives the same results either way."""
         u = max(1, int(steps_per_graph))
         for _ in range(steps // u):
-            self.step(True, u)
+            self.step(graph, u)
         for _ in range(steps % u):
-            self.step(True, 1)
+            self.step(graph, 1)
 
     def run(self, graph: bool = True, steps: Optional[int] = None, steps_per_graph: int = 1):
         self.init()

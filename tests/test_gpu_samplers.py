@@ -49,12 +49,21 @@ def _sampler(smc, ctx, cfg, y, betas, prec):
                           ess_frac=cfg.ess_frac, prec=prec)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph):
+@pytest.mark.parametrize("graph,steps_per_call,slices", [(False, 1, 0), (True, 1, 0),
+                                                         (False, 10, 4), (True, 7, 4)])
+def test_smc_small_fp64_matches_oracle(smc, ctx, small, small_oracle, graph, steps_per_call,
+                                       slices):
+    """Single steps, and chains of 10 or 7 steps per smc_steps call (4 slices:
+    one workgroup per tile, so each move also makes the next step's reweight;
+    7 leaves a ragged last group), eager and replayed, equal the oracle."""
     cfg, y, betas = small
-    announce(f"smc small fp64 graph={graph}")
+    announce(f"smc small fp64 graph={graph} steps/call={steps_per_call} slices={slices}")
     s = _sampler(smc, ctx, cfg, y, betas, "fp64")
-    r = s.run(graph=graph)
+    ctx.set_slices(slices)
+    try:
+        r = s.run(graph=graph, steps_per_graph=steps_per_call)
+    finally:
+        ctx.set_slices(0)
     ref = small_oracle
     assert r["t"] == cfg.T + 1
     assert r["resamples"] == int(np.sum(ref["trace"]["resampled"]))
@@ -171,10 +180,18 @@ def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
     b = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True)
     assert a["logZ"] == b["logZ"]
     assert np.array_equal(a["theta"], b["theta"])
-    for spg in (2, 7, 10):              # several steps captured in one graph
-        c = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True, steps_per_graph=spg)
-        assert c["logZ"] == a["logZ"] and np.array_equal(c["theta"], a["theta"])
-        assert np.array_equal(c["W"], a["W"]) and c["t"] == cfg.T + 1
+    for spg in (2, 7, 10):              # several steps in one smc_steps call / graph
+        for slices in (0, 4):           # split tiles (plain steps) and fused reweights
+            ctx.set_slices(slices)
+            try:
+                c = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=True, steps_per_graph=spg)
+                d = _sampler(smc, ctx, cfg, y, betas, "fp32").run(graph=False, steps_per_graph=spg)
+            finally:
+                ctx.set_slices(0)
+            assert c["logZ"] == d["logZ"] and np.array_equal(c["theta"], d["theta"])
+            assert np.array_equal(c["W"], d["W"]) and c["t"] == d["t"] == cfg.T + 1
+            assert abs(c["logZ"] - a["logZ"]) <= 1e-9 * max(1.0, abs(a["logZ"]))
+            assert c["resamples"] == a["resamples"]
     # repeated replays of the same sampler give the same answer again
     s = _sampler(smc, ctx, cfg, y, betas, "fp32")
     c = s.run(graph=True)
@@ -221,6 +238,50 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     assert flips <= max(3, decisions // 1000), flips
     assert abs(sum_gpu - sum_ref) <= 1e-3
     print(f"fp32 flipped decisions: {flips} of {decisions}")
+
+
+@pytest.mark.parametrize("workload,prec,slices,n_steps,start", [
+    ("gmm1d_k4_n100_N1024", "fp64", 4, 7, 0),
+    ("gmm1d_k4_n100_N1024", "fp64", 0, 6, 0),            # split tiles: plain steps
+    ("gmm1d_k4_n1000_N131072", "fp32", 4, 10, 0),
+    ("gmm1d_k4_n1000_N131072", "fp64", 8, 5, 45)])
+def test_smc_steps_equal_single_steps(smc, ctx, workload, prec, slices, n_steps, start):
+    """smc_steps(n) against n smc_step calls from the same state: with one move
+    per step and one workgroup per tile every move after the first also makes
+    the next step's reweight, so weights, ESS and evidence may differ in the
+    last bits; populations, resampling decisions and accept counts are equal."""
+    cfg = CONFIGS[workload]
+    announce(f"smc_steps {workload} {prec} slices={slices} n={n_steps} from t={start + 1}")
+    y = make_data(cfg)
+    betas = beta_schedule(cfg.T, cfg.schedule)
+    s1 = _sampler(smc, ctx, cfg, y, betas, prec)
+    s2 = _sampler(smc, ctx, cfg, y, betas, prec)
+    ctx.set_slices(slices)
+    try:
+        # the two samplers share the context's scratch: one after the other
+        for s, chained in ((s1, True), (s2, False)):
+            s.init()
+            s.advance(start, graph=False)
+            if chained:
+                s.step(graph=False, steps=n_steps)
+            else:
+                for _ in range(n_steps):
+                    s.step(graph=False)
+            s.stream.synchronize()
+            ctx.check(s.stream)
+    finally:
+        ctx.set_slices(0)
+    st1, st2 = s1.stats.cpu().numpy(), s2.stats.cpu().numpy()
+    assert s1.t.item() == s2.t.item() == start + n_steps + 1
+    assert st1[2] == st2[2]                                   # resampling steps
+    assert abs(st1[0] - st2[0]) <= 1e-10 * max(1.0, abs(st2[0]))
+    assert abs(st1[1] - st2[1]) <= 1e-10 * st2[1]
+    assert s1.n_accept.item() == s2.n_accept.item()
+    assert np.array_equal(s1.theta.cpu().numpy(), s2.theta.cpu().numpy())
+    assert np.array_equal(s1.loglik.cpu().numpy(), s2.loglik.cpu().numpy())
+    lw1, lw2 = s1.logw.cpu().numpy(), s2.logw.cpu().numpy()
+    assert np.max(np.abs(lw1 - lw2)) <= 1e-12 * max(1.0, np.abs(lw2).max())
+    assert rel_err(s1.W.cpu().numpy(), s2.W.cpu().numpy()).max() <= 1e-12
 
 
 @pytest.mark.parametrize("prec,slices", [("fp32", 4), ("fp64", 8)])
