@@ -24,9 +24,10 @@ ARCH = "gfx950"
 # Floating-point contraction is off so that every +, -, * rounds exactly as
 # written (the double-double scan and the CPU/GPU comparisons rely on it);
 # fused multiply-adds are requested explicitly where wanted. Packed FP32
-# instructions are disabled.
+# instructions are disabled. Loop heads start on 16-byte boundaries: the FP32
+# move's likelihood loop ran about 1% slower at an unaligned 4-byte offset.
 CXXFLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-ffp-contract=off",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-falign-loops=16",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
