@@ -244,13 +244,18 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     ("gmm1d_k4_n100_N1024", "fp64", 4, 7, 0),
     ("gmm1d_k4_n100_N1024", "fp64", 0, 6, 0),            # split tiles: plain steps
     ("gmm1d_k4_n1000_N131072", "fp32", 4, 10, 0),
-    ("gmm1d_k4_n1000_N131072", "fp64", 8, 5, 45)])
+    ("gmm1d_k4_n1000_N131072", "fp64", 8, 5, 45),
+    ("ragged_N150017_n200", "fp32", 4, 6, 0)])           # 2345 tile partials, last tile of 1
 def test_smc_steps_equal_single_steps(smc, ctx, workload, prec, slices, n_steps, start):
     """smc_steps(n) against n smc_step calls from the same state: with one move
     per step and one workgroup per tile every move after the first also makes
     the next step's reweight, so weights, ESS and evidence may differ in the
     last bits; populations, resampling decisions and accept counts are equal."""
-    cfg = CONFIGS[workload]
+    if workload == "ragged_N150017_n200":
+        import dataclasses
+        cfg = dataclasses.replace(CONFIGS["gmm1d_k4_n1000_N131072"], N=150017, n=200)
+    else:
+        cfg = CONFIGS[workload]
     announce(f"smc_steps {workload} {prec} slices={slices} n={n_steps} from t={start + 1}")
     y = make_data(cfg)
     betas = beta_schedule(cfg.T, cfg.schedule)
@@ -282,6 +287,31 @@ def test_smc_steps_equal_single_steps(smc, ctx, workload, prec, slices, n_steps,
     lw1, lw2 = s1.logw.cpu().numpy(), s2.logw.cpu().numpy()
     assert np.max(np.abs(lw1 - lw2)) <= 1e-12 * max(1.0, np.abs(lw2).max())
     assert rel_err(s1.W.cpu().numpy(), s2.W.cpu().numpy()).max() <= 1e-12
+
+
+def test_smc_steps_rejects_bad_arguments(smc, ctx, small):
+    """A step count below one, or one population (or log-likelihood array)
+    passed as both buffers: an error and nothing enqueued (counter, weights and
+    populations unchanged)."""
+    cfg, y, betas = small
+    announce("smc_steps argument errors")
+    s = _sampler(smc, ctx, cfg, y, betas, "fp64")
+    s.init()
+    s.stream.synchronize()
+    before = (s.t.item(), s.logw.cpu().numpy().copy(), s.thetas[0].cpu().numpy().copy())
+    a, b = s.thetas, s.logliks
+    common = dict(n_accept=s.n_accept, stream=s.stream)
+    args = lambda ta, la, tb, lb, n_steps: (ctx, s.model, s.y, ta, la, tb, lb, s.logw, s.W,
+                                            s.beta, s.t, n_steps, s.step_sd, 1, s.seed,
+                                            s.ess_frac, "fp64", s.stats)
+    for bad in (args(a[0], b[0], a[1], b[1], 0), args(a[0], b[0], a[1], b[1], -3),
+                args(a[0], b[0], a[0], b[1], 4), args(a[0], b[0], a[1], b[0], 4)):
+        with pytest.raises(smc.SmcError):
+            smc.smc_steps(*bad, **common)
+    s.stream.synchronize()
+    assert s.t.item() == before[0]
+    assert np.array_equal(s.logw.cpu().numpy(), before[1])
+    assert np.array_equal(s.thetas[0].cpu().numpy(), before[2])
 
 
 @pytest.mark.parametrize("prec,slices", [("fp32", 4), ("fp64", 8)])
