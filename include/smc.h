@@ -266,12 +266,13 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
  * (theta_a, loglik_a) for even i and (theta_b, loglik_b) for odd i and writes
  * the other pair, so the population ends in the a pair for even n_steps and
  * the b pair for odd. Same arguments and results as those calls, except that
- * with one move per step, VALU precision and tiles of one workgroup each, every
- * move after the first step's also makes the next step's reweight (and its
- * log-sum-exp partials per 64 particles), so that step runs without its own
- * reweight pass: the weights, ESS and evidence then come from partial sums
- * grouped differently and may differ from smc_step's in the last bits. Uses
- * the context scratch (reserve N first when capturing). */
+ * with VALU precision, tiles of one workgroup each and all of a step's moves in
+ * one launch (one move, or up to k*d = 16 several), the moves of every step but
+ * the last also make the next step's reweight (and its log-sum-exp partials
+ * per 64 particles), so that step runs without its own reweight pass: the
+ * weights, ESS and evidence then come from partial sums grouped differently and
+ * may differ from smc_step's in the last bits. Uses the context scratch
+ * (reserve N first when capturing). */
 int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
               double* theta_a, double* loglik_a, double* theta_b, double* loglik_b,
               double* logw, double* W, const double* beta, int32_t T, int32_t* t_dev,

@@ -672,8 +672,8 @@ int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int6
     constexpr int64_t kFusedTiles = static_cast<int64_t>(sizeof(double)) * kMaxGroups * kSplitCap /
                                     static_cast<int64_t>(sizeof(RwPartial));
     const Split sp = choose_split(ctx, g, prec, n, N, true);
-    const bool fuse = prec != SMC_PREC_BF16X3 && n_moves == 1 && sp.groups == 1 && n_steps >= 2 &&
-                      tiles <= kFusedTiles;
+    const bool fuse = prec != SMC_PREC_BF16X3 && rwmh_moves_chainable(g, n_moves, sp) &&
+                      n_steps >= 2 && tiles <= kFusedTiles;
     if (!fuse) {
         for (int32_t i = 0; i < n_steps; ++i) {
             const bool odd = (i & 1) != 0;
@@ -737,7 +737,7 @@ int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int6
             ms.t_max = T;
         }
         e = launch_rwmh_moves(g, y, n, odd ? theta_a : theta_b, odd ? loglik_a : loglik_b, N, later,
-                              step_sd, seed, 1, prec, n_accept, sp, ctx->sc, ms, s);
+                              step_sd, seed, n_moves, prec, n_accept, sp, ctx->sc, ms, s);
         if (e != hipSuccess) return hip_fail(e, "rwmh launch");
     }
     return SMC_OK;

@@ -60,6 +60,27 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
     }
 }
 
+// The next tempering step's reweight of one 64-particle tile, made by wave 0 of
+// the tile's move after its last decision (the pass a separate reweight kernel
+// would make): lw_next[p] = (0 after resampling, else this step's log-weight
+// lw_now) + (beta[t+1] - beta[t]) l_new, and the tile's log-sum-exp partial of
+// those weights. Every lane of the wave takes part.
+__device__ __forceinline__ void chain_reweight(const MoveStep& ms, int p, int N, int tile,
+                                               uint32_t step, double lw_now, double l_new,
+                                               int* status) {
+    const int t1 = static_cast<int>(step) + 1 > ms.t_max ? ms.t_max : static_cast<int>(step) + 1;
+    const double dbeta = ms.beta_dev[t1] - ms.beta_dev[t1 - 1];
+    Lse3 nw = lse3_empty();
+    if (p < N) {
+        const double ln = (ms.state->resampled != 0 ? 0.0 : lw_now) + dbeta * l_new;
+        ms.lw_next[p] = ln;
+        if (ln != ln || ln == INFINITY) atomicOr(status, kStatusNaN);
+        if (ln != -INFINITY) nw = Lse3{ln, 1.0, 1.0};
+    }
+    nw = wave_lse3(nw);
+    if (lane_id() == 0) ms.next_part[tile] = RwPartial{0.0, 0.0, nw.m, nw.s1, nw.s2, 0.0};
+}
+
 // CHAIN: the move also makes the next tempering step's reweight (ms.lw_next set,
 // one workgroup per tile); a separate instantiation keeps the plain move's code
 // free of it.
@@ -126,29 +147,16 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
         atomicAdd(n_acc, static_cast<unsigned long long>(__popcll(mask)));
-    if constexpr (CHAIN) {
-        // the next step's reweight of this tile (the pass a separate reweight
-        // kernel would make) and the log-sum-exp partials of the new weights
-        const int t1 = static_cast<int>(step) + 1 > ms.t_max ? ms.t_max : static_cast<int>(step) + 1;
-        const double dbeta = ms.beta_dev[t1] - ms.beta_dev[t1 - 1];
-        Lse3 nw = lse3_empty();
-        if (p < N) {
-            const double ln = (ms.state->resampled != 0 ? 0.0 : lw_now) + dbeta * l_new;
-            ms.lw_next[p] = ln;
-            if (ln != ln || ln == INFINITY) atomicOr(status, kStatusNaN);
-            if (ln != -INFINITY) nw = Lse3{ln, 1.0, 1.0};
-        }
-        nw = wave_lse3(nw);
-        if (lane == 0) ms.next_part[tile] = RwPartial{0.0, 0.0, nw.m, nw.s1, nw.s2, 0.0};
-    }
+    if constexpr (CHAIN) chain_reweight(ms, p, N, tile, step, lw_now, l_new, status);
 }
 
 // Several consecutive moves of one tempering step in one launch (one
 // workgroup per 64-particle tile): the tile's state lives in LDS between moves,
 // wave 0 decides each move and updates it, and the output population, W and
 // logw are written once at the end. The moves of a particle use only its own
-// state, so this equals n_moves separate launches bit for bit.
-template <int K, int D, int PREC>
+// state, so this equals n_moves separate launches bit for bit. CHAIN: as in
+// k_rwmh, the next step's reweight after the last move.
+template <int K, int D, int PREC, bool CHAIN>
 __global__ void __launch_bounds__(1024)
 k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N, StepSrc src,
              double sd, uint64_t seed, uint32_t move0, int n_moves, GmmDev g,
@@ -204,6 +212,8 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         __syncthreads();
     }
     if (w != 0) return;
+    // with a chain of steps logw and lw_next may be one array: read it first
+    const double lw_now = (CHAIN && p < N) ? ms.logw[p] : 0.0;
     if (p < N) {
 #pragma unroll
         for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = cur[c][lane];
@@ -211,6 +221,8 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         move_duties(p, N, ms);
     }
     if (lane == 0 && n_acc != nullptr && accepted != 0ull) atomicAdd(n_acc, accepted);
+    if constexpr (CHAIN)
+        chain_reweight(ms, p, N, static_cast<int>(blockIdx.x), step, lw_now, lcur[lane], status);
 }
 
 // Data (floats) the one-launch population-MCMC kernel stages in LDS.
@@ -643,20 +655,25 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
     return hipErrorInvalidValue;
 }
 
+bool rwmh_moves_chainable(const GmmDev& g, int n_moves, const Split& sp) {
+    if (sp.groups != 1 || n_moves < 1) return false;
+    if (n_moves == 1) return true;
+    bool multi = false;
+#define SMC_CASE(K, D)                                                                         \
+    if (g.k == K && g.d == D && K * D <= 16) multi = true;
+    SMC_KD_CASES(SMC_CASE)
+#undef SMC_CASE
+    return multi;
+}
+
 hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double* theta,
                              double* l, int64_t N, StepSrc src, double sd, uint64_t seed,
                              int n_moves, int prec, unsigned long long* n_accept, Split sp,
                              const Scratch& sc, MoveStep ms, hipStream_t s) {
     if (!valid_split(sp, N) || n_moves < 1) return hipErrorInvalidValue;
-    // the next step's reweight is made by a single move of one workgroup per tile
-    if (ms.lw_next != nullptr && (n_moves != 1 || sp.groups != 1)) return hipErrorInvalidValue;
-    bool one_launch = false;
-    if (n_moves > 1 && sp.groups == 1) {
-#define SMC_CASE(K, D)                                                                         \
-        if (g.k == K && g.d == D && K * D <= 16) one_launch = true;
-        SMC_KD_CASES(SMC_CASE)
-#undef SMC_CASE
-    }
+    // the next step's reweight is made by the last move of a single launch
+    if (ms.lw_next != nullptr && !rwmh_moves_chainable(g, n_moves, sp)) return hipErrorInvalidValue;
+    const bool one_launch = n_moves > 1 && rwmh_moves_chainable(g, n_moves, sp);
     if (!one_launch) {
         for (int m = 0; m < n_moves; ++m) {
             const hipError_t e = launch_rwmh(g, y, n, theta, l, N, nullptr, src, sd, seed,
@@ -669,9 +686,16 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
     const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
     const dim3 block(static_cast<unsigned>(kWave * sp.slices));
 #define SMC_MULTI(K, D, P)                                                                     \
-    hipLaunchKernelGGL((k_rwmh_multi<K, D, P>), grid, block, 0, s, y, static_cast<int>(n),     \
-                       theta, l, static_cast<int>(N), src, sd, seed, 0u, n_moves, g, n_accept, \
-                       sc.status, ms)
+    do {                                                                                       \
+        if (ms.lw_next != nullptr)                                                             \
+            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, true>), grid, block, 0, s, y,            \
+                               static_cast<int>(n), theta, l, static_cast<int>(N), src, sd,    \
+                               seed, 0u, n_moves, g, n_accept, sc.status, ms);                 \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, false>), grid, block, 0, s, y,           \
+                               static_cast<int>(n), theta, l, static_cast<int>(N), src, sd,    \
+                               seed, 0u, n_moves, g, n_accept, sc.status, ms);                 \
+    } while (0)
 #define SMC_CASE(K, D)                                                                         \
     if constexpr (K * D <= 16) {                                                               \
         if (g.k == K && g.d == D) {                                                            \

@@ -190,6 +190,10 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
 // The n_moves moves of one tempering step (move numbers 0..n_moves-1; ms holds
 // the first move's duties): one launch with the tiles' states in LDS when a
 // tile fits one workgroup and k*d <= 16, else one launch per move.
+// Whether launch_rwmh_moves runs all n_moves in one launch of one workgroup per
+// tile (a single move, or the LDS-resident multi-move kernel at k*d <= 16), the
+// form whose last move can also make the next step's reweight (MoveStep.lw_next).
+bool rwmh_moves_chainable(const GmmDev& g, int n_moves, const Split& sp);
 hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double* theta,
                              double* l, int64_t N, StepSrc src, double sd, uint64_t seed,
                              int n_moves, int prec, unsigned long long* n_accept, Split sp,

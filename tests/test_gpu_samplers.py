@@ -245,15 +245,21 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     ("gmm1d_k4_n100_N1024", "fp64", 0, 6, 0),            # split tiles: plain steps
     ("gmm1d_k4_n1000_N131072", "fp32", 4, 10, 0),
     ("gmm1d_k4_n1000_N131072", "fp64", 8, 5, 45),
-    ("ragged_N150017_n200", "fp32", 4, 6, 0)])           # 2345 tile partials, last tile of 1
+    ("ragged_N150017_n200", "fp32", 4, 6, 0),            # 2345 tile partials, last tile of 1
+    ("paper_smc_N4000", "fp64", 2, 9, 0),                # ten moves per step in one launch
+    ("paper_smc_N4000", "fp32", 4, 8, 100)])
 def test_smc_steps_equal_single_steps(smc, ctx, workload, prec, slices, n_steps, start):
-    """smc_steps(n) against n smc_step calls from the same state: with one move
-    per step and one workgroup per tile every move after the first also makes
-    the next step's reweight, so weights, ESS and evidence may differ in the
-    last bits; populations, resampling decisions and accept counts are equal."""
+    """smc_steps(n) against n smc_step calls from the same state: with one
+    workgroup per tile and all of a step's moves in one launch (one move, or the
+    paper's ten at k*d <= 16) every step's last move but the final one also
+    makes the next step's reweight, so weights, ESS and evidence may differ in
+    the last bits; populations, resampling decisions and accept counts are equal."""
     if workload == "ragged_N150017_n200":
         import dataclasses
         cfg = dataclasses.replace(CONFIGS["gmm1d_k4_n1000_N131072"], N=150017, n=200)
+    elif workload == "paper_smc_N4000":
+        from workloads.configs import paper_mode
+        cfg = paper_mode(4000)
     else:
         cfg = CONFIGS[workload]
     announce(f"smc_steps {workload} {prec} slices={slices} n={n_steps} from t={start + 1}")
