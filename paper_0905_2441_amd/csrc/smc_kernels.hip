@@ -195,6 +195,18 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
            double* __restrict__ moments, const RwPartial* __restrict__ part, int chained) {
     __shared__ double sh_M, sh_S;
     __shared__ int sh_fire, sh_t;
+    // what thread 0 of workgroup 0 updates at the end (step counter, the
+    // previous step's state, the running statistics) is read here, so that
+    // these loads overlap the partials' instead of following the combine
+    int t_pre = 0, rs_pre = 0;
+    double lse_pre = 0.0, z_pre = 0.0, nres_pre = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        t_pre = step_index(src);
+        rs_pre = sc.state->resampled;
+        lse_pre = sc.state->lse_new;
+        z_pre = stats[0];
+        nres_pre = stats[2];
+    }
     Lse3 o = lse3_empty(), nw = lse3_empty();
     if (chained) {
         // kU partials per thread per round, their loads issued together
@@ -246,23 +258,24 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
         sh_fire = fire;
         if (blockIdx.x == 0) {
             StepState* st = sc.state;
-            const int t = step_index(src);
+            const int t = t_pre;
             sh_t = t;
             const double lse_old =
-                chained ? (st->resampled ? log(static_cast<double>(N)) : st->lse_new)
+                chained ? (rs_pre ? log(static_cast<double>(N)) : lse_pre)
                         : ((o.m == -INFINITY) ? -INFINITY : o.m + log(o.s1));
+            const double lse_new = (nw.m == -INFINITY) ? -INFINITY : nw.m + log(nw.s1);
             st->M = nw.m;
             st->S = nw.s1;
             st->S2 = nw.s2;
             st->lse_old = lse_old;
-            st->lse_new = (nw.m == -INFINITY) ? -INFINITY : nw.m + log(nw.s1);
+            st->lse_new = lse_new;
             st->ess = e;
             st->resampled = fire;
             st->t = t;
             if (nw.m == -INFINITY || !(e == e)) atomicOr(sc.status, kStatusAllZeroWeight);
-            stats[0] += st->lse_new - st->lse_old;
+            stats[0] = z_pre + (lse_new - lse_old);
             stats[1] = e;
-            if (fire) stats[2] += 1.0;
+            if (fire) stats[2] = nres_pre + 1.0;
             *t_advance = t + 1;
         }
     }
