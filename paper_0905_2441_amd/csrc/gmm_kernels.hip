@@ -504,12 +504,16 @@ k_rwmh_accept(int n, double* theta, double* l, int N, const double* __restrict__
     count_accepts(acc, n_acc);
 }
 
-// Population-MCMC iteration after a split move: one thread per slot of the
-// iteration's partition completes the moves of its chain or pair of chains
-// and then, for a pair, takes the exchange decision on the moved states (the
-// same result as all moves followed by all exchanges: the moves are
-// independent per chain and the pairs are disjoint). The iteration index comes
-// from the step state recorded by the move; the caller's counter is advanced.
+// Population-MCMC iteration after a split move: two threads per slot of the
+// iteration's partition, adjacent lanes of one wave, one for each chain of the
+// slot's pair (the odd lane idles when the slot holds a single chain). Each
+// lane completes its chain's move in registers (the proposal regenerated from
+// the same counter, the groups' partial sums added in group order); both lanes
+// then take the pair's exchange decision on the moved states, the partner's
+// fetched by a lane shuffle, and each writes its chain once. The same result as
+// all moves followed by all exchanges: the moves are independent per chain and
+// the pairs are disjoint. The iteration index comes from the step state
+// recorded by the move; the caller's counter is advanced.
 template <int KD, int PREC>
 __global__ void __launch_bounds__(256)
 k_pt_accept_exchange(int n, double* theta, double* l, int M, const double* __restrict__ beta,
@@ -520,20 +524,63 @@ k_pt_accept_exchange(int n, double* theta, double* l, int M, const double* __res
     if (t_advance != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
         *t_advance = static_cast<int>(it) + 1;
     const int parity = pt_parity(parity_mode, 0, seed, it);
-    const MoveStep ms{};
-    int a, b;
-    bool acc_a = false, acc_b = false;
-    if (pt_slot(M, parity, wrap, blockIdx.x * blockDim.x + threadIdx.x, a, b)) {
-        acc_a = complete_split_move<KD, PREC>(a, n, theta, l, M, beta, src, it, sd, seed, 0, g,
-                                              status, ms, G, part, nullptr);
-        if (b >= 0) {
-            acc_b = complete_split_move<KD, PREC>(b, n, theta, l, M, beta, src, it, sd, seed, 0, g,
-                                                  status, ms, G, part, nullptr);
-            if (pt_swap(theta, l, beta, M, KD, a, b, seed, it) && n_swap) atomicAdd(n_swap, 1u);
+    const int gt = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    const bool odd = (gt & 1) != 0;
+    int a = -1, b = -1;
+    const bool slot = pt_slot(M, parity, wrap, gt >> 1, a, b);
+    const int c = odd ? b : a;
+    const bool active = slot && c >= 0;
+    double th[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) th[k] = 0.0;
+    double lc = 0.0;
+    bool acc = false;
+    if (active) {
+        double pr[KD];
+        {
+            double z[KD];
+            normals<KD>(seed, static_cast<uint32_t>(c), it, kProp, 0, z);
+#pragma unroll
+            for (int k = 0; k < KD; ++k) {
+                th[k] = theta[static_cast<size_t>(k) * M + c];
+                pr[k] = th[k] + sd * z[k];
+            }
+        }
+        double tot = part[c];
+        for (int q = 1; q < G; ++q) tot += part[static_cast<size_t>(q) * M + c];
+        const double l_prop = finish_loglik<PREC>(tot, n, g);
+        const double l_cur = l[c];
+        acc = rwmh_decide<KD>(
+            c, [&](int k) { return pr[k]; }, [&](int k) { return th[k]; }, l_cur, l_prop, beta,
+            src, it, seed, 0u, g);
+        if (l_prop != l_prop) atomicOr(status, kStatusNaN);
+        lc = acc ? l_prop : l_cur;
+        if (acc) {
+#pragma unroll
+            for (int k = 0; k < KD; ++k) th[k] = pr[k];
         }
     }
-    count_accepts(acc_a, n_acc);
-    count_accepts(acc_b, n_acc);
+    // the partner lane's moved state (every lane takes part in the shuffles)
+    const double lp = __shfl_xor(lc, 1);
+    double tp[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) tp[k] = __shfl_xor(th[k], 1);
+    bool swap = false;
+    if (active && b >= 0) {
+        const double l_a = odd ? lp : lc;
+        const double l_b = odd ? lc : lp;
+        const double la = (beta[a] - beta[b]) * (l_b - l_a);
+        swap = la >= 0.0 || pt_log_u(a, seed, it) < la;
+    }
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < KD; ++k) theta[static_cast<size_t>(k) * M + c] = swap ? tp[k] : th[k];
+        l[c] = swap ? lp : lc;
+    }
+    count_accepts(acc, n_acc);
+    const unsigned long long sw = __ballot(swap && !odd);
+    if ((threadIdx.x & (kWave - 1)) == 0 && n_swap != nullptr && sw != 0ull)
+        atomicAdd(n_swap, static_cast<unsigned>(__popcll(sw)));
 }
 
 template <int KD>
@@ -787,8 +834,8 @@ hipError_t launch_pt_iteration(const GmmDev& g, const float* y, int64_t n, doubl
         return launch_exchange(theta, l, beta, M, g.k * g.d, parity_mode, 0, wrap, seed, later,
                                t_advance, n_swap, s);
     }
-    // slots: at most M/2 pairs plus two singles
-    const dim3 xgrid(static_cast<unsigned>((M / 2 + 2 + 255) / 256));
+    // slots: at most M/2 pairs plus two singles, two threads each
+    const dim3 xgrid(static_cast<unsigned>((2 * (M / 2 + 2) + 255) / 256));
 #define SMC_PT(K, D, P)                                                                        \
     do {                                                                                       \
         launch_move_partials<K, D, P>(y, n, theta, l, M, beta, src, sd, seed, 0, g, n_accept,  \
