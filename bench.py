@@ -71,13 +71,13 @@ HBM_PEAK_GBS = 8000.0
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
     "sources_sha256": "7d05634271c94195321747223f2c9f6cbc2153f20bef5adea9ae0d552de29d1d",
-    "fetch_kib": 2721.5, "fetch_scale": 2.0,
+    "fetch_kib": 2718.0, "fetch_scale": 2.0,
     "write_kib": 32.20, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": 0.859,
+    "valu_busy": 0.854,
 }
 
 
