@@ -51,6 +51,19 @@ int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int6
              double* x, double* x_tmp, double* logw, int32_t* t_dev, uint64_t seed,
              double ess_frac, double* stats, double* moments, void* stream);
 
+/* n_steps consecutive fsv_step calls (n_steps >= 1): the same arguments, random
+ * streams and results bit for bit (x, logw, stats and moments), except that
+ * x_tmp ends with unspecified contents. Within the call each step's
+ * propagation takes the previous step's resampling itself (the ancestor
+ * search of that step's CDF, reading the other buffer), so only the last step
+ * runs the search-and-gather pass: two kernels per step instead of three.
+ * Uses the context scratch (reserve N and k first when capturing). Errors as
+ * fsv_step, and n_steps < 1 is an invalid argument; nothing is enqueued on an
+ * argument error. */
+int fsv_steps(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int64_t N,
+              double* x, double* x_tmp, double* logw, int32_t* t_dev, int32_t n_steps,
+              uint64_t seed, double ess_frac, double* stats, double* moments, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     Gmm,
     fsv_init,
     fsv_step,
+    fsv_steps,
     PREC,
     pt_exchange,
     pt_iteration,

@@ -96,6 +96,8 @@ SIGNATURES = {
     "fsv_init": (c_int, [_P, c_int32, c_int64, _P, _P, _P]),
     "fsv_step": (c_int, [_P, POINTER(SmcFsv), _P, c_int32, c_int64, _P, _P, _P, _P, c_uint64,
                          c_double, _P, _P, _P]),
+    "fsv_steps": (c_int, [_P, POINTER(SmcFsv), _P, c_int32, c_int64, _P, _P, _P, _P, c_int32,
+                          c_uint64, c_double, _P, _P, _P]),
     "smc_step": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,
                          c_double, c_int32, c_uint64, c_double, c_int, _P, _P, _P]),
     "smc_steps": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, _P, _P, _P, c_int32, _P,

@@ -354,6 +354,20 @@ def fsv_step(ctx: Context, model, y, x, x_tmp, logw, t_dev, seed, ess_frac, stat
         _ptr(moments, torch.float64, "moments", T * 2 * k), _stream(stream)))
 
 
+def fsv_steps(ctx: Context, model, y, x, x_tmp, logw, t_dev, n_steps, seed, ess_frac, stats,
+              moments, stream=None):
+    """n_steps particle-filter steps in one call (C ABI fsv_steps: each step's
+    propagation takes the previous step's resampling itself)."""
+    T = y.shape[0]
+    k, N = x.shape
+    L.check(ctx._lib.fsv_steps(
+        ctx.handle, ctypes.byref(_fsv_struct(model)), _ptr(y, torch.float64, "y"), T, N,
+        _ptr(x, torch.float64, "x"), _ptr(x_tmp, torch.float64, "x_tmp", k * N),
+        _ptr(logw, torch.float64, "logw", N), _ptr(t_dev, torch.int32, "t_dev", 1),
+        int(n_steps), int(seed), float(ess_frac), _ptr(stats, torch.float64, "stats", 4),
+        _ptr(moments, torch.float64, "moments", T * 2 * k), _stream(stream)))
+
+
 def smc_rng_words(seed, count, block, step, purpose, move=0, out=None, stream=None):
     if out is None:
         out = torch.empty((count, 4), dtype=torch.int32, device="cuda")

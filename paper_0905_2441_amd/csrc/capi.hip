@@ -894,11 +894,12 @@ bool host_cholesky(const double* U, int k, double* L) {
 
 }  // namespace
 
-int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int64_t N,
-             double* x, double* x_tmp, double* logw, int32_t* t_dev, uint64_t seed,
-             double ess_frac, double* stats, double* moments, void* stream) {
-    int r = enter(ctx);
-    if (r) return r;
+namespace {
+
+// Argument checks of the filter calls and the device model they build.
+int fsv_prepare(const smc_fsv* model, const double* y, int32_t T, int64_t N, const double* x,
+                const double* x_tmp, const double* logw, const int32_t* t_dev,
+                const double* stats, const double* moments, double ess_frac, FsvDev* out) {
     if (!model) return fail(SMC_ERR_INVALID_ARG, "model is NULL");
     if (!fsv_supported(model->m, model->k))
         return fail(SMC_ERR_UNSUPPORTED, "(m, k) of the factor model is not compiled");
@@ -928,21 +929,95 @@ int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int6
     if (!host_cholesky(model->U, f.k, f.L))
         return fail(SMC_ERR_INVALID_ARG, "U is not symmetric positive definite");
     f.cst = -0.5 * f.m * log(2.0 * M_PI);
-    const hipStream_t s = as_stream(stream);
-    if ((r = ensure_scratch(ctx, N, f.k, s))) return r;
+    *out = f;
+    return SMC_OK;
+}
+
+// Propagate + weight (from x_in, optionally taking the previous step's
+// resampling) into x_out, then the step's combine and decision.
+hipError_t fsv_weight_mid(smc_ctx ctx, const FsvDev& f, const double* y, int32_t T, int64_t N,
+                          const double* x_in, double* x_out, double* logw, int32_t* t_dev,
+                          uint64_t seed, double ess_frac, double* stats, double* moments,
+                          const FsvAnc& anc, hipStream_t s) {
     StepSrc src{};
     src.t_dev = t_dev;
     src.t_max = T;
-    StepSrc later{};
-    later.t_dev = &ctx->sc.state->t;
-    hipError_t e = launch_fsv_weight(f, y, T, x, x_tmp, logw, N, src, seed, ctx->sc,
-                                     ctx->fsv_mom, s);
+    hipError_t e = launch_fsv_weight(f, y, T, x_in, x_out, logw, N, src, seed, ctx->sc,
+                                     ctx->fsv_mom, s, anc);
     if (e == hipSuccess)
         e = launch_step_mid(ctx->sc, N, src, t_dev, stats, ess_frac, logw, s, ctx->fsv_mom, f.k,
                             2 * SMC_FSV_KMAX, moments);
-    if (e == hipSuccess)
-        e = launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, x_tmp, x,
-                                 f.k, nullptr, nullptr, logw, 1, s);
+    return e;
+}
+
+// The step's resampling (or copy) of x_tmp into x, logw reset after resampling.
+hipError_t fsv_gather(smc_ctx ctx, int k, int64_t N, const double* x_tmp, double* x, double* logw,
+                      uint64_t seed, hipStream_t s) {
+    StepSrc later{};
+    later.t_dev = &ctx->sc.state->t;
+    return launch_search_gather(ctx->sc, N, ctx->scheme, seed, later, ctx->sc.state, x_tmp, x, k,
+                                nullptr, nullptr, logw, 1, s);
+}
+
+}  // namespace
+
+int fsv_step(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int64_t N,
+             double* x, double* x_tmp, double* logw, int32_t* t_dev, uint64_t seed,
+             double ess_frac, double* stats, double* moments, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    FsvDev f;
+    if ((r = fsv_prepare(model, y, T, N, x, x_tmp, logw, t_dev, stats, moments, ess_frac, &f)))
+        return r;
+    const hipStream_t s = as_stream(stream);
+    if ((r = ensure_scratch(ctx, N, f.k, s))) return r;
+    hipError_t e = fsv_weight_mid(ctx, f, y, T, N, x, x_tmp, logw, t_dev, seed, ess_frac, stats,
+                                  moments, FsvAnc{}, s);
+    if (e == hipSuccess) e = fsv_gather(ctx, f.k, N, x_tmp, x, logw, seed, s);
+    if (e != hipSuccess) return hip_fail(e, "particle filter launch");
+    return SMC_OK;
+}
+
+int fsv_steps(smc_ctx ctx, const smc_fsv* model, const double* y, int32_t T, int64_t N,
+              double* x, double* x_tmp, double* logw, int32_t* t_dev, int32_t n_steps,
+              uint64_t seed, double ess_frac, double* stats, double* moments, void* stream) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (n_steps < 1) return fail(SMC_ERR_INVALID_ARG, "n_steps must be >= 1");
+    FsvDev f;
+    if ((r = fsv_prepare(model, y, T, N, x, x_tmp, logw, t_dev, stats, moments, ess_frac, &f)))
+        return r;
+    const hipStream_t s = as_stream(stream);
+    if ((r = ensure_scratch(ctx, N, f.k, s))) return r;
+    int chunk, nchunks;
+    cdf_layout(N, &chunk, &nchunks);
+    FsvAnc prev{};
+    prev.state = ctx->sc.state;
+    prev.cdf_hi = ctx->sc.cdf_hi;
+    prev.cdf_lo = ctx->sc.cdf_lo;
+    prev.chunk_tot = ctx->sc.dd_part;
+    prev.chunk = chunk;
+    prev.nchunks = nchunks;
+    prev.scheme = ctx->scheme;
+    hipError_t e = hipSuccess;
+    // the chain below has an odd length, so that its last step writes x_tmp; an
+    // even count takes its first step on its own
+    int32_t m = n_steps;
+    if ((n_steps & 1) == 0) {
+        e = fsv_weight_mid(ctx, f, y, T, N, x, x_tmp, logw, t_dev, seed, ess_frac, stats, moments,
+                           FsvAnc{}, s);
+        if (e == hipSuccess) e = fsv_gather(ctx, f.k, N, x_tmp, x, logw, seed, s);
+        m = n_steps - 1;
+    }
+    // step j propagates from the previous step's states (x for j = 0, where the
+    // resampling was already applied; otherwise the other buffer, taking that
+    // step's resampling itself) into x_tmp for even j and x for odd j
+    for (int32_t j = 0; j < m && e == hipSuccess; ++j) {
+        const bool odd = (j & 1) != 0;
+        e = fsv_weight_mid(ctx, f, y, T, N, odd ? x_tmp : x, odd ? x : x_tmp, logw, t_dev, seed,
+                           ess_frac, stats, moments, j == 0 ? FsvAnc{} : prev, s);
+    }
+    if (e == hipSuccess) e = fsv_gather(ctx, f.k, N, x_tmp, x, logw, seed, s);
     if (e != hipSuccess) return hip_fail(e, "particle filter launch");
     return SMC_OK;
 }

@@ -16,6 +16,7 @@
 #include "fsv.hpp"
 #include "philox.hpp"
 #include "reduce.hpp"
+#include "cdf_search.hpp"
 
 namespace smc {
 namespace {
@@ -47,8 +48,19 @@ template <int MO, int KF>
 __global__ void __launch_bounds__(kRedBlock)
 k_fsv_weight(FsvDev f, const double* __restrict__ y, int T, const double* __restrict__ x,
              double* __restrict__ x_out, double* __restrict__ logw, int N, StepSrc src,
-             uint64_t seed, Scratch sc, double* __restrict__ mom) {
+             uint64_t seed, Scratch sc, double* __restrict__ mom, FsvAnc anc) {
+    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
     const uint32_t t = static_cast<uint32_t>(step_index(src));
+    // the previous step's resampling (one value for the whole grid), searched
+    // exactly as the standalone search-and-gather pass does
+    const bool rs = anc.state != nullptr && anc.state->resampled != 0;
+    uint32_t rs_step = 0;
+    double rs_u = 0.0;
+    if (rs) {
+        block_cdf_offsets(anc.chunk_tot, anc.nchunks, offh, offl);
+        rs_step = static_cast<uint32_t>(anc.state->t);
+        if (anc.scheme == 0) rs_u = u01_left_closed(draw(seed, 0, 0, rs_step, kResamp, 0).w0);
+    }
     const double* yt = y + static_cast<size_t>(t - 1) * MO;
     double yv[MO];
 #pragma unroll
@@ -61,12 +73,15 @@ k_fsv_weight(FsvDev f, const double* __restrict__ y, int T, const double* __rest
     for (int c = 0; c < KF; ++c) mo.sx[c] = mo.sxx[c] = 0.0;
     bool bad = false;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
+        const int a = rs ? cdf_search(resample_point(anc.scheme, seed, rs_step, p, N, rs_u), N,
+                                      anc.chunk, anc.cdf_hi, anc.cdf_lo, offh, offl)
+                         : p;
         double z[KF];
         normals<KF>(seed, static_cast<uint32_t>(p), t, kProp, 0, z);
         double xn[KF], h[KF];
 #pragma unroll
         for (int c = 0; c < KF; ++c) {
-            double v = f.phi[c] * x[static_cast<size_t>(c) * N + p];
+            double v = f.phi[c] * x[static_cast<size_t>(c) * N + a];
 #pragma unroll
             for (int j = 0; j <= c; ++j) v = fma(f.L[c * SMC_FSV_KMAX + j], z[j], v);
             xn[c] = v;
@@ -106,7 +121,7 @@ k_fsv_weight(FsvDev f, const double* __restrict__ y, int T, const double* __rest
             quad = fma(v[i], v[i], quad);
         }
         const double lg = f.cst - log(prod) - 0.5 * quad;
-        const double lo = logw[p];
+        const double lo = rs ? 0.0 : logw[p];
         const double ln = lo + lg;
         logw[p] = ln;
         bad = bad || (ln != ln) || (ln == INFINITY);
@@ -166,12 +181,12 @@ hipError_t launch_fsv_init(int k, int64_t N, double* x, double* logw, hipStream_
 
 hipError_t launch_fsv_weight(const FsvDev& f, const double* y, int T, const double* x,
                              double* x_out, double* logw, int64_t N, StepSrc src, uint64_t seed,
-                             const Scratch& sc, double* mom, hipStream_t s) {
+                             const Scratch& sc, double* mom, hipStream_t s, const FsvAnc& anc) {
     const dim3 grid(static_cast<unsigned>(fsv_parts(N)));
 #define SMC_CASE(MO, KF)                                                                      \
     if (f.m == MO && f.k == KF) {                                                             \
         hipLaunchKernelGGL((k_fsv_weight<MO, KF>), grid, dim3(kRedBlock), 0, s, f, y, T, x,   \
-                           x_out, logw, static_cast<int>(N), src, seed, sc, mom);             \
+                           x_out, logw, static_cast<int>(N), src, seed, sc, mom, anc);        \
         return hipGetLastError();                                                             \
     }
     SMC_FSV_CASES(SMC_CASE)

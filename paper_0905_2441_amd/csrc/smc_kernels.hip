@@ -24,6 +24,7 @@
 #include "philox.hpp"
 #include "exchange.hpp"
 #include "reduce.hpp"
+#include "cdf_search.hpp"
 
 namespace smc {
 namespace {
@@ -335,53 +336,14 @@ k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, in
         return;
     }
     __shared__ double offh[kMaxChunks], offl[kMaxChunks];
-    {
-        constexpr int per = kMaxChunks / kRedBlock;
-        const int c0 = threadIdx.x * per;
-        dd loc[per];
-        dd run = dd_zero();
-#pragma unroll
-        for (int q = 0; q < per; ++q) {
-            loc[q] = run;
-            if (c0 + q < nchunks)
-                run = dd_add(run, dd{sc.dd_part[2 * (c0 + q)], sc.dd_part[2 * (c0 + q) + 1]});
-        }
-        dd total;
-        const dd lead = block_dd_exclusive_scan(run, total);
-#pragma unroll
-        for (int q = 0; q < per; ++q) {
-            const dd o = dd_add(lead, loc[q]);
-            offh[c0 + q] = o.hi;
-            offl[c0 + q] = o.lo;
-        }
-        __syncthreads();
-    }
+    block_cdf_offsets(sc.dd_part, nchunks, offh, offl);
     if (i >= N) return;
-    auto cdf = [&](int j) -> double {
-        const int b = j / chunk;
-        return dd_add(dd{offh[b], offl[b]}, dd{sc.cdf_hi[j], sc.cdf_lo[j]}).hi;
-    };
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     double u = 0.0;
     if (scheme == 0)
         u = u_override ? *u_override : u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
     const double U = resample_point(scheme, seed, step, i, N, u);
-    const double clast = cdf(N - 1);
-    int lo = 0, hi = N - 1;
-    if (U < clast) {
-        while (lo < hi) {
-            const int mid = lo + ((hi - lo) >> 1);
-            if (U < cdf(mid)) hi = mid;
-            else lo = mid + 1;
-        }
-    } else {
-        while (lo < hi) {
-            const int mid = lo + ((hi - lo) >> 1);
-            if (cdf(mid) >= clast) hi = mid;
-            else lo = mid + 1;
-        }
-    }
-    const int j = lo;
+    const int j = cdf_search(U, N, chunk, sc.cdf_hi, sc.cdf_lo, offh, offl);
     if (idx_out) idx_out[i] = j;
     if (theta_in && theta_out)
         for (int c = 0; c < kd; ++c)

@@ -25,8 +25,9 @@ from typing import Dict, Optional
 import numpy as np
 import torch
 
-from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, pt_iteration, pt_iterations,
-                  pt_record, smc_loglik, smc_prior_init, smc_step, smc_step_batched, smc_steps)
+from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, fsv_steps, pt_iteration,
+                  pt_iterations, pt_record, smc_loglik, smc_prior_init, smc_step,
+                  smc_step_batched, smc_steps)
 
 
 def _dev(x, dtype):
@@ -409,30 +410,41 @@ class FSVFilter:
         fsv_step(self.ctx, self.model, self.y, self.x, self.x_tmp, self.logw, self.t, self.seed,
                  self.ess_frac, self.stats, self.moments, stream=self.stream)
 
+    def enqueue_steps(self, steps: int):
+        """`steps` consecutive steps in one fsv_steps call (each propagation
+        takes the previous step's resampling itself)."""
+        self.ctx.set_resampling(self.scheme)
+        fsv_steps(self.ctx, self.model, self.y, self.x, self.x_tmp, self.logw, self.t, steps,
+                  self.seed, self.ess_frac, self.stats, self.moments, stream=self.stream)
+
     def capture(self, steps: int = 1) -> Graph:
         g = self.graphs.get(steps)
         if g is None:
             g = Graph(self.ctx, self.stream)
             with g:
-                for _ in range(steps):
-                    self.enqueue_step()
+                self.enqueue_steps(steps)
             self.graphs[steps] = g
         return g
 
-    def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 1):
+    def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 1,
+                chained: bool = True):
+        """Groups of `steps_per_graph` steps, each one graph replay (graph=True)
+        or one eager call: fsv_steps, or (chained=False) single fsv_step calls."""
         done = 0
         while done < steps:
             c = min(int(steps_per_graph), steps - done)
             if graph:
                 self.capture(c).launch()
+            elif chained:
+                self.enqueue_steps(c)
             else:
                 for _ in range(c):
                     self.enqueue_step()
             done += c
 
-    def run(self, graph: bool = True, steps_per_graph: int = 1):
+    def run(self, graph: bool = True, steps_per_graph: int = 1, chained: bool = True):
         self.init()
-        self.advance(self.T, graph, steps_per_graph)
+        self.advance(self.T, graph, steps_per_graph, chained)
         self.stream.synchronize()
         self.ctx.check(self.stream)
         return self.results()

@@ -83,3 +83,41 @@ def test_fsv_rejects_bad_models(smc, ctx):
                            U=PAPER_FSV.U)
     with pytest.raises(smc.SmcError):
         smc.FSVFilter(ctx, unsupported, y[:, :4], 64, seed=1).run(graph=False)
+
+
+@pytest.mark.parametrize("N,T,per_call,scheme", [(5000, 40, 7, "systematic"),
+                                                 (5000, 40, 10, "systematic"),
+                                                 (3001, 23, 2, "stratified"),
+                                                 (3001, 23, 9, "multinomial"),
+                                                 (64, 12, 5, "systematic")])
+def test_fsv_steps_equal_single_steps(smc, ctx, N, T, per_call, scheme):
+    """fsv_steps in groups of per_call steps (odd and even, a ragged last
+    group; eager and graph-replayed), each propagation taking the previous
+    step's resampling itself, equals single fsv_step calls bit for bit: the
+    population, log-weights, log-likelihood, ESS, resample count and moments."""
+    announce(f"fsv_steps N={N} T={T} per_call={per_call} {scheme}")
+    _, y = simulate(PAPER_FSV, T, 13)
+    runs = []
+    for graph, chained in ((False, False), (False, True), (True, True)):
+        f = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=21, scheme=scheme)
+        f.run(graph=graph, steps_per_graph=per_call, chained=chained)
+        runs.append((f.x.cpu().numpy(), f.logw.cpu().numpy(), f.stats.cpu().numpy(),
+                     f.moments.cpu().numpy(), int(f.t.item())))
+    base = runs[0]
+    assert base[2][2] > 0                                # some steps resampled
+    for r in runs[1:]:
+        for a, b in zip(r[:4], base[:4]):
+            assert np.array_equal(a, b)
+        assert r[4] == base[4] == T + 1
+
+
+def test_fsv_steps_rejects_bad_arguments(smc, ctx):
+    _, y = simulate(PAPER_FSV, 6, 1)
+    f = smc.FSVFilter(ctx, PAPER_FSV, y, 500, seed=2)
+    f.init()
+    for n_steps, x_tmp in ((0, f.x_tmp), (-1, f.x_tmp), (3, f.x)):
+        with pytest.raises(smc.SmcError):
+            smc.fsv_steps(ctx, PAPER_FSV, f.y, f.x, x_tmp, f.logw, f.t, n_steps, 2, 0.5,
+                          f.stats, f.moments, stream=f.stream)
+    f.stream.synchronize()
+    assert f.t.item() == 1 and f.stats.cpu().numpy()[2] == 0.0
