@@ -102,6 +102,29 @@ __device__ __forceinline__ double block_sum(double v) {
     return r;
 }
 
+// Block (kRedBlock threads) sums of n values per thread, each added as
+// block_sum adds one (wave butterfly, then the waves in order); the results
+// are valid in thread 0.
+template <int n>
+__device__ __forceinline__ void block_sum_n(double (&v)[n]) {
+    __shared__ double sh[n][kRedBlock / kWave];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        v[i] = wave_sum(v[i]);
+        if (lane_id() == 0) sh[i][wave_id()] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            double r = 0.0;
+            for (int w = 0; w < kRedBlock / kWave; ++w) r += sh[i][w];
+            v[i] = r;
+        }
+    }
+    __syncthreads();
+}
+
 // Exclusive scan of one dd value per thread over the block (thread order);
 // also returns the block total in `total` (valid in every thread).
 __device__ __forceinline__ dd block_dd_exclusive_scan(dd v, dd& total) {

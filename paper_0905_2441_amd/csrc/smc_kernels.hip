@@ -29,6 +29,8 @@
 namespace smc {
 namespace {
 
+constexpr int kMaxMomK = 4;    // state components of a particle filter's step moments
+
 // ---------------------------------------------------------------- reweight
 
 __global__ void __launch_bounds__(kRedBlock)
@@ -283,21 +285,29 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
     __syncthreads();
     const double M = sh_M, S = sh_S;
     if (mom != nullptr && blockIdx.x == 0) {
-        // each workgroup's sums rescaled from its own maximum to M, added in order
+        // each workgroup's sums rescaled from its own maximum to M, added in
+        // order; all 2 mom_k sums in one pass and one block reduction
         double* out = moments + static_cast<size_t>(sh_t - 1) * 2 * mom_k;
-        for (int c = 0; c < mom_k; ++c) {
-            double a = 0.0, b = 0.0;
-            for (int q = threadIdx.x; q < parts; q += blockDim.x) {
-                const double mb = part[q].mn;
-                const double r = (mb == -INFINITY) ? 0.0 : exp(mb - M);
-                a += mom[static_cast<size_t>(q) * mom_stride + c] * r;
-                b += mom[static_cast<size_t>(q) * mom_stride + mom_k + c] * r;
+        double acc[2 * kMaxMomK];
+#pragma unroll
+        for (int c = 0; c < 2 * kMaxMomK; ++c) acc[c] = 0.0;
+        for (int q = threadIdx.x; q < parts; q += blockDim.x) {
+            const double mb = part[q].mn;
+            const double r = (mb == -INFINITY) ? 0.0 : exp(mb - M);
+            const double* mq = mom + static_cast<size_t>(q) * mom_stride;
+#pragma unroll
+            for (int c = 0; c < kMaxMomK; ++c) {
+                if (c < mom_k) {
+                    acc[c] += mq[c] * r;
+                    acc[kMaxMomK + c] += mq[mom_k + c] * r;
+                }
             }
-            a = block_sum(a);
-            b = block_sum(b);
-            if (threadIdx.x == 0) {
-                const double mean = a / S;
-                const double var = b / S - mean * mean;
+        }
+        block_sum_n<2 * kMaxMomK>(acc);
+        if (threadIdx.x == 0) {
+            for (int c = 0; c < mom_k; ++c) {
+                const double mean = acc[c] / S;
+                const double var = acc[kMaxMomK + c] / S - mean * mean;
                 out[c] = mean;
                 out[mom_k + c] = sqrt(var > 0.0 ? var : 0.0);
             }
@@ -491,6 +501,7 @@ hipError_t launch_step_mid(const Scratch& sc, int64_t N, StepSrc src, int* t_adv
                            double* stats, double ess_frac, const double* logw, hipStream_t s,
                            const double* mom, int mom_k, int mom_stride, double* moments,
                            const RwPartial* part, int nparts) {
+    if (mom != nullptr && (mom_k < 1 || mom_k > kMaxMomK)) return hipErrorInvalidValue;
     const int parts = part ? nparts : red_grid(N);
     const int chunk = cdf_chunk(N);
     const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
