@@ -77,7 +77,7 @@ MOVE_COUNTERS = {
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": 0.854,
+    "valu_busy": 0.858,
 }
 
 
@@ -115,7 +115,11 @@ def move_traffic():
     if c["fetch_kib"] is None or c["sources_sha256"] != kernel_sources_sha256():
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
-STEPS_PER_GRAPH = 10    # tempering steps per hipGraph replay
+STEPS_PER_GRAPH = 50    # tempering steps (filter steps, PT iterations) per hipGraph replay
+# measured best groupings that differ from it: the headline's whole 100-step run
+# in one replay (per step 90.1 us against 92.6 at 50 and 95.5 at 10 on one box);
+# the small run's 25 us steps in replays of 10 (39-41 us per step at 50)
+GRAPH_STEPS = {"gmm1d_k4_n1000_N131072": 100, "gmm1d_k4_n100_N1024": 10}
 PT_ITERS_PER_GRAPH = 64  # population-MCMC iterations per replay in the paper's runs
 
 
@@ -185,7 +189,7 @@ def cpu_baseline(cfg, y, betas, budget_s=12.0):
 
 def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
     """Population-MCMC iterations (one RW-MH move per chain, then exchanges),
-    ten iterations per hipGraph replay."""
+    STEPS_PER_GRAPH iterations per hipGraph replay."""
     from workloads import pt_betas
     betas = pt_betas(cfg.N, 4)
     s = smc.PTSampler(ctx, g, y, betas, cfg.step_sd, cfg.run_seed, parity_mode=0, wrap=False,
@@ -246,12 +250,16 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
 
 
 def main():
+    global STEPS_PER_GRAPH
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--steps-per-graph", type=int, default=None,
+                    help="tempering steps (filter steps, PT iterations) per hipGraph replay "
+                         f"(default: {GRAPH_STEPS} by workload, else {STEPS_PER_GRAPH})")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in launch shape instead of autotuning it first")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -259,6 +267,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD, choices=(WORKLOAD,) + OTHER_WORKLOADS,
                     help="the headline workload (default) or another measured configuration")
     args = ap.parse_args()
+    STEPS_PER_GRAPH = max(1, int(args.steps_per_graph if args.steps_per_graph is not None
+                                 else GRAPH_STEPS.get(args.workload, STEPS_PER_GRAPH)))
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

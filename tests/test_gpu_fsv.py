@@ -66,10 +66,10 @@ def test_fsv_paper_length_run(smc, ctx):
 @pytest.mark.parametrize("N,T", [(131072, 25), (1 << 20, 3)])
 def test_fsv_benchmark_sizes(smc, ctx, N, T):
     """The benchmark's largest sizes (the paper's N = 131072, and 2^20) with
-    ten filter steps per graph replay, as timed."""
+    all steps of the run in one chained graph replay (the benchmark replays 50)."""
     announce(f"fsv N={N} T={T}")
     _, y = simulate(PAPER_FSV, T, 7)
-    r = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=3).run(graph=True, steps_per_graph=10)
+    r = smc.FSVFilter(ctx, PAPER_FSV, y, N, seed=3).run(graph=True, steps_per_graph=50)
     _compare(r, ofsv.particle_filter(y, PAPER_FSV, N, 3), N)
 
 

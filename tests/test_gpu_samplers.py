@@ -244,6 +244,7 @@ def test_smc_small_fp32_stepwise_replay(smc, ctx, small):
     ("gmm1d_k4_n100_N1024", "fp64", 4, 7, 0),
     ("gmm1d_k4_n100_N1024", "fp64", 0, 6, 0),            # split tiles: plain steps
     ("gmm1d_k4_n1000_N131072", "fp32", 4, 10, 0),
+    ("gmm1d_k4_n1000_N131072", "fp32", 4, 100, 0),         # the benchmark's whole-run chain
     ("gmm1d_k4_n1000_N131072", "fp64", 8, 5, 45),
     ("ragged_N150017_n200", "fp32", 4, 6, 0),            # 2345 tile partials, last tile of 1
     ("paper_smc_N4000", "fp64", 2, 9, 0),                # ten moves per step in one launch
