@@ -194,13 +194,16 @@ def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
     betas = pt_betas(cfg.N, 4)
     s = smc.PTSampler(ctx, g, y, betas, cfg.step_sd, cfg.run_seed, parity_mode=0, wrap=False,
                       prec=prec)
+    u = min(STEPS_PER_GRAPH, steps)
     s.init()
-    s.advance(warmup + STEPS_PER_GRAPH + 1, graph=True, iters_per_graph=STEPS_PER_GRAPH)
-    s.stream.synchronize()                 # graphs captured and warm
+    s.advance(warmup, graph=True, iters_per_graph=u)
+    s.init()
+    s.advance(steps, graph=True, iters_per_graph=u)    # the timed sequence's graphs captured
+    s.stream.synchronize()
     s.init()
     s.stream.synchronize()
     t0 = time.perf_counter()
-    s.advance(steps, graph=True, iters_per_graph=STEPS_PER_GRAPH)
+    s.advance(steps, graph=True, iters_per_graph=u)
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
@@ -225,13 +228,16 @@ def tune(ctx, cfg, precs, no_tune):
 def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
                        ess_frac=cfg.ess_frac, prec=prec)
+    u = min(STEPS_PER_GRAPH, steps)
     s.init()
-    s.advance(warmup + STEPS_PER_GRAPH + 1, graph=True, steps_per_graph=STEPS_PER_GRAPH)
-    s.stream.synchronize()                 # graphs captured and warm
+    s.advance(warmup, graph=True, steps_per_graph=u)
+    s.init()
+    s.advance(steps, graph=True, steps_per_graph=u)    # the timed sequence's graphs captured
+    s.stream.synchronize()
     s.init()                               # a fresh run from the prior for the timed steps
     s.stream.synchronize()
     t0 = time.perf_counter()
-    s.advance(steps, graph=True, steps_per_graph=STEPS_PER_GRAPH)
+    s.advance(steps, graph=True, steps_per_graph=u)
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
@@ -344,7 +350,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "k": cfg.k, "d": cfg.d, "n": cfg.n, "N": cfg.N,
                    "T": cfg.T, "schedule": "(t/T)^2", "moves_per_step": cfg.n_moves,
-                   "ess_threshold": "N/2", "graph": f"{STEPS_PER_GRAPH} tempering steps per hipGraph replay",
+                   "ess_threshold": "N/2", "graph": f"{min(STEPS_PER_GRAPH, args.steps)} tempering steps per hipGraph replay",
                    "launch": launch},
         "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
         "fp32_over_fp64_speedup": (r64["ms_per_step"] / r32["ms_per_step"]) if r64 else None,

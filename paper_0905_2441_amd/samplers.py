@@ -124,14 +124,14 @@ class SMCSampler:
         self.cur = self.cur ^ (int(steps) & 1)
 
     def advance(self, steps: int, graph: bool = True, steps_per_graph: int = 10):
-        """Advance `steps` steps in groups of `steps_per_graph` (plus single steps),
-        each group one graph replay (graph=True) or one eager smc_steps call; the
-        same grouping gives the same results either way."""
+        """Advance `steps` steps in groups of `steps_per_graph` (the last group
+        holds the remainder), each group one graph replay (graph=True) or one
+        eager smc_steps call; the same grouping gives the same results either way."""
         u = max(1, int(steps_per_graph))
         for _ in range(steps // u):
             self.step(graph, u)
-        for _ in range(steps % u):
-            self.step(graph, 1)
+        if steps % u:
+            self.step(graph, steps % u)
 
     def run(self, graph: bool = True, steps: Optional[int] = None, steps_per_graph: int = 1):
         self.init()
