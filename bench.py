@@ -77,7 +77,7 @@ MOVE_COUNTERS = {
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": 0.858,
+    "valu_busy": 0.848,
 }
 
 
