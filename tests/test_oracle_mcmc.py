@@ -106,3 +106,103 @@ def test_pt_run_small_moves_hot_chain_between_modes():
     lbest = gmm.loglik(mu[:, None], y, m)[0]
     assert out["l"][-1] > lbest - 15.0
     assert out["swaps"] > 0
+
+
+# ---------------------------------------------------------------------------
+# The prior term of the Metropolis ratio. Under a strong prior, or at beta = 0
+# where the prior is the whole target, a move that drops log p0(theta') -
+# log p0(theta) or flips its sign leaves the target at once; these checks start
+# from exact draws of the target (particles are independent chains, so after the
+# moves they are still independent exact draws and the standard errors are the
+# plain ones) and fail for either mistake (shown below by planting each one).
+
+def _moments_off(th, mean, var, z=5.0):
+    """Reasons the particle cloud's mean or variance is more than z standard
+    errors from (mean, var); empty if both agree."""
+    N = th.size
+    out = []
+    if abs(th.mean() - mean) > z * math.sqrt(var / N):
+        out.append(f"mean {th.mean():.5f} vs {mean:.5f}")
+    if abs(th.var() / var - 1.0) > z * math.sqrt(2.0 / N):
+        out.append(f"variance {th.var():.5f} vs {var:.5f}")
+    return out
+
+
+def _check_strong_gauss_prior():
+    """k = 1, prior N(1, 0.2^2), beta = 0.01, n = 50: the prior precision (25)
+    is about 27 times the tempered likelihood's (0.91). Start from exact draws
+    of p0 L^beta (closed form); after 12 moves the draws keep its moments."""
+    y = make_mixture_data(50, np.array([2.0]), 0.55, seed=3)
+    m = Model.equal_weights(1, 1, 0.55, prior="gauss", prior_a=1.0, prior_b=0.2)
+    beta = 0.01
+    mean, var = evidence.posterior_k1(y, 0.55, beta, prior_a=1.0, prior_b=0.2)
+    rng = np.random.default_rng(11)
+    N = 1 << 14
+    th = rng.normal(mean, math.sqrt(var), size=(1, N))
+    l = gmm.loglik(th, y, m)
+    acc = 0
+    for mv in range(12):
+        th, l, a = smc.rwmh_move(th, l, y, m, beta, 0.3, seed=21, step=4, move=mv)
+        acc += int(a.sum())
+    out = _moments_off(th[0], mean, var)
+    if not 0.2 < acc / (12 * N) < 0.8:
+        out.append(f"acceptance {acc / (12 * N):.3f}")
+    return out
+
+
+def _check_beta0_gauss_prior():
+    """beta = 0: the target is the prior N(3, 2^2) on each of the k = 4 means.
+    Prior draws moved 20 times keep mean 3 and variance 4 in every coordinate."""
+    y = make_mixture_data(50, np.array([-3.0, 0.0, 3.0, 6.0]), 0.55, seed=4)
+    m = Model.equal_weights(4, 1, 0.55, prior="gauss", prior_a=3.0, prior_b=2.0)
+    N = 1 << 14
+    th = smc.prior_init(m, N, seed=31)
+    l = gmm.loglik(th, y, m)
+    for mv in range(20):
+        th, l, _ = smc.rwmh_move(th, l, y, m, 0.0, 1.0, seed=32, step=1, move=mv)
+    out = []
+    for c in range(4):
+        out += [f"coordinate {c}: {r}" for r in _moments_off(th[c], 3.0, 4.0)]
+    return out
+
+
+def _check_beta0_box_prior():
+    """beta = 0 under the paper's box prior U[-10, 10]^4: uniform draws moved 20
+    times with sd 3 never leave the box and keep the uniform's moments."""
+    y = make_mixture_data(50, np.array([-3.0, 0.0, 3.0, 6.0]), 0.3025, seed=5)
+    m = Model.equal_weights(4, 1, 0.3025, prior="box", prior_a=-10.0, prior_b=10.0)
+    N = 1 << 14
+    th = smc.prior_init(m, N, seed=41)
+    l = gmm.loglik(th, y, m)
+    for mv in range(20):
+        th, l, _ = smc.rwmh_move(th, l, y, m, 0.0, 3.0, seed=42, step=1, move=mv)
+    out = []
+    if np.any(np.abs(th) > 10.0):
+        out.append(f"{int(np.sum(np.any(np.abs(th) > 10.0, axis=0)))} particles left the box")
+    for c in range(4):
+        out += [f"coordinate {c}: {r}" for r in _moments_off(th[c], 0.0, 400.0 / 12.0)]
+    return out
+
+
+_PRIOR_CHECKS = (_check_strong_gauss_prior, _check_beta0_gauss_prior, _check_beta0_box_prior)
+
+
+def test_rwmh_prior_term_strong_prior_and_beta0():
+    for check in _PRIOR_CHECKS:
+        assert check() == [], check.__name__
+
+
+def test_rwmh_prior_term_checks_catch_planted_mistakes(monkeypatch):
+    """Each planted mistake in the oracle's prior term (dropped, or with its sign
+    flipped) makes every one of the three checks above fail."""
+    planted = {
+        "dropped": lambda beta, l_cur, l_prop, lp_cur, lp_prop: beta * (l_prop - l_cur),
+        "sign flipped": lambda beta, l_cur, l_prop, lp_cur, lp_prop:
+            beta * (l_prop - l_cur) - (lp_prop - lp_cur),
+    }
+    for name, wrong in planted.items():
+        with monkeypatch.context() as mp, np.errstate(invalid="ignore"):
+            # (outside the box both priors are -inf: the flipped term is NaN there)
+            mp.setattr(smc, "rwmh_log_alpha", wrong)
+            for check in _PRIOR_CHECKS:
+                assert check() != [], (name, check.__name__)
