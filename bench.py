@@ -187,6 +187,220 @@ def cpu_baseline(cfg, y, betas, budget_s=12.0):
     }
 
 
+# ---------------------------------------------------------------------------
+# The oracle leg: the FP64 CPU oracle timed on a bounded sample (cpu_baseline)
+# and the error of the measured GPU results against it (oracle_error). This is
+# the only part of the benchmark that runs the oracle; --no-cpu-baseline skips it.
+
+LOGLIK_SAMPLE = 512         # particles whose log-likelihood the oracle recomputes
+REPLAY_SAMPLE = 4096        # positions whose moves a replayed step checks
+
+
+def _oracle_model(k, d, sigma2, prior="gauss", prior_a=0.0, prior_b=10.0):
+    from oracle.gmm import Model
+    return Model.equal_weights(k, d, sigma2, prior=prior, prior_a=prior_a, prior_b=prior_b)
+
+
+def _positions(N, count, seed):
+    import numpy as np
+    if N <= count:
+        return np.arange(N)
+    return np.sort(np.random.default_rng(seed).choice(N, size=count, replace=False))
+
+
+def _oracle_loglik(theta, y, om, workers=8):
+    """The oracle's log-likelihood of every column, columns split over threads."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import gmm as ogmm
+    parts = np.array_split(np.arange(theta.shape[1]), workers)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return np.concatenate(list(ex.map(lambda ix: ogmm.loglik(theta[:, ix], y, om), parts)))
+
+
+def loglik_error(theta, l, y, om, count=LOGLIK_SAMPLE, seed=0):
+    """Largest relative error of the GPU log-likelihoods `l` of parameters
+    `theta` against the oracle's, over `count` sampled particles."""
+    import numpy as np
+    from oracle import gmm as ogmm
+    pos = _positions(theta.shape[1], count, seed)
+    ref = ogmm.loglik(theta[:, pos], y, om)
+    return float(np.max(np.abs(l[pos] - ref) / np.abs(ref)))
+
+
+def _sampler_state(s):
+    s.stream.synchronize()
+    st = s.stats.cpu().numpy()
+    return dict(theta=s.theta.cpu().numpy(), l=s.loglik.cpu().numpy(), logw=s.logw.cpu().numpy(),
+                logZ=float(st[0]), resamples=int(st[2]))
+
+
+def replay_step(t, s0, s1, y, om, betas, step_sd, n_moves, seed, ess_frac, count, fp64_l):
+    """Tempering step t taken by the oracle from the GPU's state s0 and compared
+    with the GPU's result s1 (replay mode): the evidence increment, log-weights
+    and decision over the whole population, the moves on `count` sampled
+    positions (FP32 near-tie accept flips counted), and with fp64_l the
+    increment from the oracle's FP64 log-likelihoods of the same particles."""
+    import numpy as np
+    from oracle import smc as osmc
+    pos = _positions(s0["l"].size, count, seed=t)
+    rth, rl, rlw, _, inc, info = osmc.smc_step_sampled(
+        s0["theta"], s0["l"], s0["logw"], y, om, betas, t, step_sd, n_moves, seed, pos, ess_frac)
+    inc_gpu = s1["logZ"] - s0["logZ"]
+    same = np.all(np.abs(s1["theta"][:, pos] - rth) <= 1e-12, axis=0)
+    out = {"t": t, "resampled": bool(info["resampled"]),
+           "decision_equal": bool(info["resampled"] == (s1["resamples"] > s0["resamples"])),
+           "logZ_increment": inc_gpu,
+           "logZ_increment_abs_err": abs(inc_gpu - inc),
+           "logw_max_abs_err": float(np.max(np.abs(s1["logw"] - rlw))),
+           "flips": int(np.sum(~same)), "decisions": int(pos.size * n_moves),
+           "moved_loglik_max_rel_err": float(np.max(np.abs(s1["l"][pos][same] - rl[same])
+                                                    / np.abs(rl[same]))) if same.any() else None}
+    if fp64_l:
+        l_o = _oracle_loglik(s0["theta"], y, om)
+        out["loglik_all_max_rel_err"] = float(np.max(np.abs(s0["l"] - l_o) / np.abs(l_o)))
+        inc_o = osmc.reweight(s0["logw"], l_o, betas[t] - betas[t - 1])[2]
+        out["logZ_increment_abs_err_fp64_l"] = abs(inc_gpu - inc_o)
+    return out
+
+
+def headline_oracle_error(smc, ctx, cfg, g, y, betas, runs):
+    """oracle_error of the headline line: the final populations of the timed
+    runs (log-likelihoods of sampled particles against the oracle's) and two
+    steps of a fresh FP32 run replayed by the oracle from the GPU's state: the
+    first step that resamples and the step at t = T/2."""
+    om = _oracle_model(cfg.k, cfg.d, cfg.sigma2, cfg.prior, cfg.prior_a, cfg.prior_b)
+    out = {"against": "FP64 CPU oracle (oracle/), same inputs and random streams",
+           "final_population_loglik_max_rel_err": {
+               p: loglik_error(r["theta"], r["l"], y, om) for p, r in runs.items()},
+           "loglik_sample": LOGLIK_SAMPLE}
+    s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac, prec="fp32")
+    s.init()
+    replays = []
+    before, done, mid = _sampler_state(s), 0, cfg.T // 2
+    while done < mid - 1:
+        s.step(graph=False)
+        done += 1
+        after = _sampler_state(s)
+        if after["resamples"] > before["resamples"]:
+            replays.append(replay_step(done, before, after, y, om, betas, cfg.step_sd,
+                                       cfg.n_moves, cfg.run_seed, cfg.ess_frac, REPLAY_SAMPLE,
+                                       True))
+            break
+        before = after
+    if mid - 1 - done > 0:
+        s.advance(mid - 1 - done, graph=True, steps_per_graph=cfg.T)
+    before = _sampler_state(s)
+    s.step(graph=False)
+    replays.append(replay_step(mid, before, _sampler_state(s), y, om, betas, cfg.step_sd,
+                               cfg.n_moves, cfg.run_seed, cfg.ess_frac, REPLAY_SAMPLE, True))
+    ctx.check(s.stream)
+    out["replayed_steps_fp32"] = replays
+    out["bounds"] = {"loglik_rel": 1e-6, "logZ_abs": 1e-3, "flips_per_decision": 1e-3}
+    return out
+
+
+def small_run_oracle_error(smc, ctx, cfg, g, y, betas, prec):
+    """The oracle-sized run in full: a fresh GPU run of all T steps (ten steps
+    per graph replay) against the oracle's run with the same seeds."""
+    import numpy as np
+    from oracle import smc as osmc
+    om = _oracle_model(cfg.k, cfg.d, cfg.sigma2, cfg.prior, cfg.prior_a, cfg.prior_b)
+    s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac, prec=prec)
+    r = s.run(graph=True, steps_per_graph=10)
+    ref = osmc.smc_run(y, om, betas, cfg.N, cfg.step_sd, cfg.n_moves, cfg.run_seed,
+                       ess_frac=cfg.ess_frac)
+    return {"against": "the oracle's whole run (same seeds)",
+            "logZ_abs_err": abs(r["logZ"] - ref["logZ"]),
+            "theta_max_abs_err": float(np.max(np.abs(r["theta"] - ref["theta"]))),
+            "loglik_max_rel_err": float(np.max(np.abs(r["l"] - ref["l"]) / np.abs(ref["l"]))),
+            "W_max_abs_err": float(np.max(np.abs(r["W"] - ref["W"]))),
+            "resamples": [r["resamples"], int(np.sum(ref["trace"]["resampled"]))],
+            "accepted": [r["accepted"], int(np.sum(ref["trace"]["accepted"]))]}
+
+
+def pt_oracle_error(smc, ctx, cfg, g, y, prec, final, pairs=40, it=10):
+    """Population MCMC: the timed run's final chains (log-likelihoods of sampled
+    chains against the oracle's) and iteration `it` of a fresh run replayed by
+    the oracle from the GPU's state on sampled pairs of its partition (both
+    chains' moves, then the pair's exchange: exact for a sample of pairs)."""
+    import numpy as np
+    from oracle import smc as osmc
+    from workloads import pt_betas
+    om = _oracle_model(cfg.k, cfg.d, cfg.sigma2, cfg.prior, cfg.prior_a, cfg.prior_b)
+    betas = pt_betas(cfg.N, 4)
+    s = smc.PTSampler(ctx, g, y, betas, cfg.step_sd, cfg.run_seed, parity_mode=0, wrap=False,
+                      prec=prec)
+    s.init()
+    s.advance(it, graph=True, iters_per_graph=it)
+    r0 = s.results()
+    s.advance(1, graph=False)
+    r1 = s.results()
+    ctx.check(s.stream)
+    all_pairs = osmc.exchange_pairs(cfg.N, it & 1, False)
+    rng = np.random.default_rng(it)
+    pick = [all_pairs[0], all_pairs[-1]] + [all_pairs[i] for i in
+                                            rng.choice(len(all_pairs), pairs, replace=False)]
+    th, ll, chains = osmc.pt_iteration_pairs(r0["theta"], r0["l"], y, om, betas, it,
+                                             cfg.step_sd, cfg.run_seed, pick)
+    same = np.all(np.abs(r1["theta"][:, chains] - th) <= 1e-12, axis=0)
+    return {"against": "FP64 CPU oracle (oracle/), same inputs and random streams",
+            "final_population_loglik_max_rel_err": loglik_error(final["theta"], final["l"], y,
+                                                                om),
+            "loglik_sample": LOGLIK_SAMPLE,
+            "replayed_iteration": {
+                "it": it, "chains": int(chains.size), "flips": int(np.sum(~same)),
+                "loglik_max_rel_err": float(np.max(np.abs(r1["l"][chains][same] - ll[same])
+                                                   / np.abs(ll[same])))}}
+
+
+def ddim_oracle_error(y, cfg, res, count=128):
+    """d-dimensional mixture: each precision's final population (its own
+    log-likelihoods) against the oracle on `count` sampled particles."""
+    import numpy as np
+    om = _oracle_model(cfg.k, cfg.d, cfg.sigma2, cfg.prior, cfg.prior_a, cfg.prior_b)
+    out = {"against": "FP64 CPU oracle (oracle/), same inputs", "loglik_sample": count,
+           "final_population_loglik_max_rel_err": {}}
+    for p, r in res.items():
+        pos = _positions(r["theta"].shape[1], count, seed=1)
+        ref = _oracle_loglik(r["theta"][:, pos], y, om)
+        out["final_population_loglik_max_rel_err"][p] = float(
+            np.max(np.abs(r["l"][pos] - ref) / np.abs(ref)))
+    return out
+
+
+def batched_oracle_error(b, datas, betas, final, replay_state, replay_runs, per_run=64):
+    """Batched runs: the timed final populations (sampled particles of every
+    eighth run against the oracle) and one further step replayed by the oracle
+    from the GPU's state for a few runs (moves on sampled positions)."""
+    import numpy as np
+    from oracle import smc as osmc
+    om = _oracle_model(b.model.k, b.model.d, b.model.sigma2)
+    kd = b.model.kd
+    worst = 0.0
+    for r in range(0, b.R, 8):
+        a, N = int(b.p_off[r]), b.Ns[r]
+        th = final["theta"][kd * a:kd * (a + N)].reshape(kd, N)
+        worst = max(worst, loglik_error(th, final["l"][a:a + N], datas[r], om, per_run, seed=r))
+    t, s0, s1 = replay_state
+    steps = []
+    for r in replay_runs:
+        a, N = int(b.p_off[r]), b.Ns[r]
+        view = lambda st: dict(theta=st["theta"][kd * a:kd * (a + N)].reshape(kd, N),
+                               l=st["l"][a:a + N], logw=st["logw"][a:a + N],
+                               logZ=float(st["stats"][r, 0]), resamples=int(st["stats"][r, 2]))
+        rep = replay_step(t, view(s0), view(s1), datas[r], om, betas, b.step_sd, b.n_moves,
+                          b.seeds[r], b.ess_frac, 256, False)
+        rep["run"] = int(r)
+        steps.append(rep)
+    return {"against": "FP64 CPU oracle (oracle/), same inputs and random streams",
+            "final_population_loglik_max_rel_err": worst,
+            "loglik_sample": f"{per_run} particles of each of {len(range(0, b.R, 8))} runs",
+            "replayed_step": steps}
+
+
 def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
     """Population-MCMC iterations (one RW-MH move per chain, then exchanges),
     STEPS_PER_GRAPH iterations per hipGraph replay."""
@@ -208,7 +422,8 @@ def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
     t1 = time.perf_counter()
     ctx.check(s.stream)
     r = s.results()
-    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, swaps=r["swaps"], accepted=r["accepted"])
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, swaps=r["swaps"], accepted=r["accepted"],
+                theta=r["theta"], l=r["l"])
 
 
 def tune(ctx, cfg, precs, no_tune):
@@ -241,7 +456,7 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
-    res = s.results()
+    res = s.results()          # the timed run's final population (before the kernel timing)
     ms_step = (t1 - t0) * 1e3 / steps
     # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept)
     # launched back to back, timed with HIP events recorded on the stream it
@@ -252,7 +467,8 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
         stream=s.stream), reps)
     ctx.check(s.stream)
     return dict(ms_per_step=ms_step, kernel_ms=kern_ms, resamples=res["resamples"],
-                accepted=res["accepted"], logZ=res["logZ"])
+                accepted=res["accepted"], logZ=res["logZ"], theta=res["theta"], l=res["l"],
+                t=res["t"])
 
 
 def main():
@@ -261,7 +477,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the error against the oracle)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--steps-per-graph", type=int, default=None,
                     help="tempering steps (filter steps, PT iterations) per hipGraph replay "
@@ -328,11 +545,15 @@ def main():
         "kernel_ms": r32["kernel_ms"],
         "kernel_evals_per_s": kern_evals,
     }
-    cpu = None
+    cpu = oracle_error = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(cfg, y, betas)
         log(f"[bench] oracle {cpu['value']:.3e} evals/s")
+        log("[bench] error of the measured runs against the oracle ...")
+        oracle_error = headline_oracle_error(
+            smc, ctx, cfg, g, y, betas, {"fp32": r32, **({"fp64": r64} if r64 else {})})
+        log(f"[bench] oracle error: {json.dumps(oracle_error)}")
 
     value = evals_per_step / (r32["ms_per_step"] * 1e-3)
     out = {
@@ -357,11 +578,13 @@ def main():
         "fp64_move_kernel_ms": r64["kernel_ms"] if r64 else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_error": oracle_error,
     }
     print(json.dumps(out), flush=True)
 
 
-def time_batched(smc, torch, ctx, prec, steps, warmup, R=256):
+def time_batched(smc, torch, ctx, prec, steps, warmup, R=256, keep_state=False,
+                 tune_batch=True):
     """256 independent 1-D k = 4 runs (n log-uniform in [100, 1e5], N in
     {1024, ..., 65536}) advanced by one graph-replayed batched step."""
     from workloads import beta_schedule, make_mixture_data
@@ -370,6 +593,14 @@ def time_batched(smc, torch, ctx, prec, steps, warmup, R=256):
     datas = [make_mixture_data(r.n, r.true_means, BATCHED["sigma2"], r.data_seed) for r in runs]
     g = smc.Gmm.equal_weights(4, 1, BATCHED["sigma2"])
     betas = beta_schedule(BATCHED["T"], BATCHED["schedule"])
+    table = None
+    if tune_batch:
+        # per range of n, the waves per tile of the persistent move (untimed)
+        from paper_0905_2441_amd import autotune
+        table = autotune.tune_batched(ctx, g, datas, [r.N for r in runs],
+                                      [r.run_seed for r in runs], betas, BATCHED["step_sd"],
+                                      BATCHED["n_moves"], BATCHED["ess_frac"], prec, log=log)
+        ctx.set_launch_table(table)
     b = smc.BatchSampler(ctx, g, datas, [r.N for r in runs], [r.run_seed for r in runs], betas,
                          BATCHED["step_sd"], BATCHED["n_moves"], ess_frac=BATCHED["ess_frac"],
                          prec=prec)
@@ -387,8 +618,23 @@ def time_batched(smc, torch, ctx, prec, steps, warmup, R=256):
     t1 = time.perf_counter()
     ctx.check(b.stream)
     evals = sum(r.N * r.n for r in runs) * BATCHED["n_moves"]
-    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, evals_per_step=evals, R=R,
-                N_total=sum(r.N for r in runs), n_total=sum(r.n for r in runs))
+    out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, evals_per_step=evals, R=R,
+               N_total=sum(r.N for r in runs), n_total=sum(r.n for r in runs),
+               launch_table=table)
+    if keep_state:
+        # the timed run's final state, then one more (untimed) step with the
+        # states around it, for the oracle leg
+        def state():
+            b.stream.synchronize()
+            return dict(theta=b.theta.cpu().numpy(), l=b.loglik.cpu().numpy(),
+                        logw=b.logw.cpu().numpy(),
+                        stats=b.stats.cpu().numpy().reshape(b.R, 4).copy())
+        t = min(int(b.t.cpu().item()), b.T)
+        s0 = state()
+        graph.launch()
+        out.update(sampler=b, datas=datas, betas=betas, final=s0, replay=(t, s0, state()))
+        ctx.check(b.stream)
+    return out
 
 
 def copy_calibration(nbytes=1 << 28, reps=4):
@@ -616,17 +862,32 @@ def other_workload(args):
     if args.workload == "batched_256runs":
         torch.cuda.set_device(0)
         ctx = smc.Context(0)
-        r = time_batched(smc, torch, ctx, "fp32", args.steps, args.warmup)
-        r64 = time_batched(smc, torch, ctx, "fp64", max(2, args.steps // 5), 1)
+        r = time_batched(smc, torch, ctx, "fp32", args.steps, args.warmup,
+                         keep_state=not args.no_cpu_baseline, tune_batch=not args.no_tune)
+        oracle_error = None
+        if not args.no_cpu_baseline:
+            log("[bench] error of the batched runs against the oracle ...")
+            b = r["sampler"]
+            order = sorted(range(b.R), key=lambda i: b.Ns[i] * b.ns[i])
+            big = max(range(b.R), key=lambda i: b.Ns[i] * b.ns[i])
+            oracle_error = batched_oracle_error(b, r["datas"], r["betas"], r["final"],
+                                                r["replay"], order[:3] + [big])
+            log(f"[bench] oracle error: {json.dumps(oracle_error)}")
+            del r["sampler"], b
+        r64 = time_batched(smc, torch, ctx, "fp64", max(2, args.steps // 5), 1,
+                           tune_batch=not args.no_tune)
         out = {"metric": "particle×datum loglik evals/s; ms per SMC tempering step, FP32/batched vs FP64",
                "value": r["evals_per_step"] / (r["ms_per_step"] * 1e-3), "unit": "evals/s",
                "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                "config": {"workload": "batched_256runs", "R": r["R"], "N_total": r["N_total"],
-                          "n_total": r["n_total"], "evals_per_step": r["evals_per_step"]},
+                          "n_total": r["n_total"], "evals_per_step": r["evals_per_step"],
+                          "launch": {"fp32": r["launch_table"] or "built-in",
+                                     "fp64": r64["launch_table"] or "built-in"}},
                "fp64_ms_per_step": r64["ms_per_step"],
-               "fp32_over_fp64_speedup": r64["ms_per_step"] / r["ms_per_step"]}
+               "fp32_over_fp64_speedup": r64["ms_per_step"] / r["ms_per_step"],
+               "oracle_error": oracle_error}
         print(json.dumps(out), flush=True)
         return
 
@@ -650,6 +911,10 @@ def other_workload(args):
                    fp32_over_fp64_speedup=r64["ms_per_step"] / r["ms_per_step"],
                    swaps=r["swaps"], accepted=r["accepted"])
         out["config"]["step"] = "one PT iteration: RW-MH per chain + exchanges (alternating parity)"
+        if not args.no_cpu_baseline:
+            log("[bench] error of the population-MCMC run against the oracle ...")
+            out["oracle_error"] = pt_oracle_error(smc, ctx, cfg, g, y, "fp32", r)
+            log(f"[bench] oracle error: {json.dumps(out['oracle_error'])}")
     else:
         betas = beta_schedule(cfg.T, cfg.schedule)
         precs = list(cfg.precisions)
@@ -672,6 +937,13 @@ def other_workload(args):
         if "fp64" in res and fast != "fp64":
             out["fp64_ms_per_step"] = res["fp64"]["ms_per_step"]
             out["fast_over_fp64_speedup"] = res["fp64"]["ms_per_step"] / res[fast]["ms_per_step"]
+        if not args.no_cpu_baseline:
+            log(f"[bench] error of the {cfg.name} runs against the oracle ...")
+            if cfg.d > 1:
+                out["oracle_error"] = ddim_oracle_error(y, cfg, res)
+            else:
+                out["oracle_error"] = small_run_oracle_error(smc, ctx, cfg, g, y, betas, fast)
+            log(f"[bench] oracle error: {json.dumps(out['oracle_error'])}")
     print(json.dumps(out), flush=True)
 
 

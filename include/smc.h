@@ -63,7 +63,9 @@ enum {
 
 typedef enum {
     SMC_PREC_FP64 = 0,        /* plain FP64 arithmetic with device-library exp/log */
-    SMC_PREC_FP32 = 1,        /* FP32 + hardware exp2, compensated FP64 accumulation */
+    SMC_PREC_FP32 = 1,        /* FP32 terms + hardware exp2, per-datum sums multiplied into a
+                                 renormalised FP32 product (exponents kept as integers),
+                                 FP64 total */
     SMC_PREC_BF16X3 = 2       /* d-dim: split-BF16 MFMA cross term, FP32 accumulation */
 } smc_prec;
 
@@ -106,7 +108,9 @@ int smc_destroy(smc_ctx ctx);
 /* [sync] Size the context scratch for up to N particles of up to kd = k*d
  * parameters each and, when n > 0, for the MFMA form over up to n observations,
  * so that later calls (in particular inside hipGraph stream capture) never
- * allocate. */
+ * allocate. Scratch that a larger reservation (or a call needing more room)
+ * supersedes is kept until smc_destroy, so graphs captured before the growth
+ * stay valid; a graph must be destroyed before its context. */
 int smc_reserve(smc_ctx ctx, int64_t N, int32_t kd, int64_t n);
 
 /* [sync] Synchronise `stream`, then read and clear the device status flag:
@@ -127,34 +131,51 @@ const char* smc_last_error(void);
  * smc_loglik) a wave's slice takes. */
 int smc_set_slices(smc_ctx ctx, int32_t slices);
 
+/* Which launches a rule of the launch table shapes. */
+enum {
+    SMC_RULE_CALL = 0,    /* the likelihood and move kernels of every per-call entry point */
+    SMC_RULE_BATCH = 1    /* the persistent move of smc_step_batched, per run */
+};
+
 /* One entry of a context's launch table (the output of the autotuner in the
- * Python package): calls whose model, precision and sizes fall in the rule's
- * ranges use `slices` data slices per 64-particle tile (same meaning and range
- * as smc_set_slices; the MFMA form uses min(slices, 16)). k, d = 0 and
- * prec = -1 match anything; ranges are inclusive. */
+ * Python package). kind SMC_RULE_CALL: calls whose model, precision and sizes
+ * fall in the rule's ranges use `slices` data slices per 64-particle tile
+ * (same meaning and range as smc_set_slices; the MFMA form uses
+ * min(slices, 16)). kind SMC_RULE_BATCH: in a batch created while the rule is
+ * in force, every run whose (n, N) fall in its ranges has each 64-particle tile
+ * moved by `slices` waves (1, 2, 4 or 8) of the persistent move's 8-wave
+ * workgroups, which therefore take 8 / slices tiles of the run at once.
+ * k, d = 0 and prec = -1 match anything; ranges are inclusive. */
 typedef struct {
     int32_t k, d, prec;
+    int32_t kind;
     int32_t slices;
     int64_t n_lo, n_hi;
     int64_t N_lo, N_hi;
 } smc_launch_rule;
 
 /* Replace the context's launch table with a copy of `rules[0..count-1]`
- * (count = 0 clears it). The first matching rule wins; an explicit
- * smc_set_slices override takes precedence over the table, and calls that
- * match no rule use the built-in choice. Invalid rules (slices outside 1..128,
- * empty ranges) reject the whole table and leave the old one in place. */
+ * (count = 0 clears it). The first matching rule of the call's kind wins; an
+ * explicit smc_set_slices override takes precedence over the table for
+ * per-call launches, and launches that match no rule use the built-in choice.
+ * Invalid rules (unknown kind, slices outside 1..128 or, for a batch rule, not
+ * 1, 2, 4 or 8, empty ranges) reject the whole table and leave the old one in
+ * place. */
 int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t count);
 
 /* Per-particle log-likelihood (Mixture Modelling section):
  *   loglik[p] = sum_j log sum_i w_i N_d(y_j; mu_{p,i}, sigma2 I).
  * y: [n][d] FP32; theta: [k*d][N] FP64; loglik: [N] FP64 out.
- * prec FP64: plain form; FP32: FP32 arithmetic with hardware exp2 and a
- * compensated FP64 sum (relative error below 1e-6); the per-datum mixture sum
- * is taken directly for waves whose particles sit near the data (weights of
- * total mass <= 1) and relative to the largest term otherwise, both within the
- * bound (the form depends on the wave, fixed for a given launch shape and
- * population); BF16X3: d = 8, k in
+ * prec FP64: plain form (device-library exp and log per datum, plain sum);
+ * FP32: FP32 arithmetic in base 2 with hardware exp2, no per-datum log: each
+ * datum's mixture sum is multiplied into a running FP32 product that is
+ * renormalised by frexp after every block of 8 or 16 data, its exponents added
+ * as integers, and one FP64 log2 of the product per particle finishes (relative
+ * error below 1e-6). The per-datum sum is taken directly for waves whose
+ * particles sit near the data (weights of total mass <= 1) and relative to its
+ * largest term otherwise (those maxima added in 16-term FP32 blocks promoted to
+ * FP64), both within the bound (the form depends on the wave, fixed for a given
+ * launch shape and population); BF16X3: d = 8, k in
  * {1,2,4,8}: the quadratic forms as one K = 64 BF16 MFMA contraction of
  * three-way (hi/mid/lo) split operands with FP32 accumulation, then the same
  * FP32 epilogue (relative error below 1e-6). */
@@ -168,7 +189,10 @@ int smc_loglik(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
 int smc_prior_init(smc_ctx ctx, const smc_gmm* model, int64_t N, uint64_t seed,
                    double* theta, void* stream);
 
-/* One random-walk Metropolis-Hastings move of every particle, in place.
+/* One random-walk Metropolis-Hastings move of every particle, in place
+ * (Population-Based MCMC subsection: the stage-one move of each chain is an
+ * N(0, I) random walk; SMC Sampler subsection: the same move keeps each
+ * tempered target invariant; Mixture Modelling section: the prior p0).
  * Proposal theta' = theta + step_sd * xi, xi ~ N(0, I_{kd}) jointly (normal c
  * of stream (p, c/4, step, PROP, move)). Accept iff log alpha >= 0 or
  * log u < log alpha, with log alpha = b_p (l' - l) + log p0(theta') - log p0(theta),
@@ -193,7 +217,9 @@ int smc_rwmh_move(smc_ctx ctx, const smc_gmm* model, const float* y, int64_t n,
 int smc_reweight(smc_ctx ctx, double* logw, const double* loglik, int64_t N, double dbeta,
                  double* W, double* logZ, double* ess, void* stream);
 
-/* Effective sample size 1 / sum_p W[p]^2 of normalised weights W [N]. */
+/* Effective sample size 1 / sum_p W[p]^2 of normalised weights W [N]
+ * (Sequential Monte Carlo subsection: the ESS criterion that decides when to
+ * resample). ess: device scalar out. One pass plus a fixed-order combine. */
 int smc_ess(smc_ctx ctx, const double* W, int64_t N, double* ess, void* stream);
 
 /* Systematic resampling (Sequential Monte Carlo subsection: build the
@@ -343,8 +369,11 @@ typedef struct {
 typedef struct smc_batch_s* smc_batch;
 
 /* [sync] Upload R run descriptors (host array) and size the batch scratch for
- * runs of kd = k*d parameters; the work list (run, 64-particle tile) is ordered
- * by decreasing n (longest first). d must be 1. */
+ * runs of kd = k*d parameters (d must be 1). The move's work list holds units
+ * of 8 / S consecutive 64-particle tiles of one run, each tile moved by S
+ * waves, ordered by decreasing n (longest first); S per run comes from the
+ * context's SMC_RULE_BATCH launch rules in force now (one list per precision),
+ * else the largest power of two <= min(8, n / 32) (at least 1). */
 int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t kd,
                      smc_batch* out);
 int smc_batch_destroy(smc_batch b);
@@ -354,9 +383,11 @@ int smc_batch_destroy(smc_batch b);
  *   one workgroup per run: reweight, log-sum-exp, ESS and the resampling
  *   decision (ESS < ess_frac * N_r); one workgroup per resampling run:
  *   systematic resampling and gather; then n_moves (>= 1) RW-MH moves as one
- *   persistent launch over the work list (workgroups pull items from a device
+ *   persistent launch over the work list (workgroups pull units from a device
  *   counter). run_stats: device FP64 [R][4] = {log Z (accumulated), last ESS,
- *   resample count, unused}. prec: FP32 or FP64. */
+ *   resample count, unused}. prec: FP32 or FP64. A run's results depend on its
+ *   S only through the order of its FP64 slice sums and, in FP32, through which
+ *   of the two per-datum forms a wave takes (see smc_loglik). */
 int smc_step_batched(smc_ctx ctx, smc_batch b, const smc_gmm* model, const float* y,
                      double* theta, double* loglik, double* logw, double* W, const double* beta,
                      int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, double ess_frac,

@@ -256,14 +256,17 @@ def rwmh_log_alpha(beta, l_cur, l_prop, lp_cur, lp_prop):
     return beta * (l_prop - l_cur) + (lp_prop - lp_cur)
 
 
-def rwmh_move(theta, l, y, model: Model, beta, step_sd, seed, step, move):
+def rwmh_move(theta, l, y, model: Model, beta, step_sd, seed, step, move, index=None):
     """One random-walk MH move of every particle, N(0, I) scaled by step_sd,
     jointly over all k*d coordinates. ``beta`` is a scalar or one value per
-    particle (per chain, for parallel tempering). Returns (theta, l, accepted)."""
+    particle (per chain, for parallel tempering). Column p is particle
+    ``index[p]`` of the population (default: p), whose number selects its
+    random streams. Returns (theta, l, accepted)."""
     theta = np.array(theta, dtype=np.float64, copy=True)
     l = np.array(l, dtype=np.float64, copy=True)
     kd, N = theta.shape
-    idx = np.arange(N, dtype=np.uint64)
+    idx = (np.arange(N, dtype=np.uint64) if index is None
+           else np.asarray(index, dtype=np.uint64))
     z = px.normals(seed, idx, step, px.PROP, move, kd)
     prop = theta + step_sd * z
     l_prop = loglik(prop, y, model)
@@ -279,17 +282,17 @@ def rwmh_move(theta, l, y, model: Model, beta, step_sd, seed, step, move):
 # ---------------------------------------------------------------------------
 # SMC sampler
 
-def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
-             ess_frac=0.5, resample=True, scheme="systematic"):
-    """Tempering step t >= 1: reweight by L^(beta_t - beta_{t-1}); if
-    ESS < ess_frac * N resample (systematic by default; points from the streams
-    of step t) and reset the log-weights; then n_moves RW-MH moves at beta_t
-    (move m uses stream move m). Returns (theta, l, logw, W, logZ_increment, info)."""
+def _reweight_resample(theta, l, logw, betas, t, seed, ess_frac, resample, scheme):
+    """The first part of tempering step t: reweight by L^(beta_t - beta_{t-1});
+    if ESS < ess_frac * N resample (points from the streams of step t) and reset
+    the log-weights. Returns (theta, l, logw, W, logZ_increment, info, idx)
+    with idx the ancestor of each position (None without resampling)."""
     N = l.size
     dbeta = betas[t] - betas[t - 1]
     logw, W, inc, e = reweight(logw, l, dbeta)
     did = bool(resample and e < ess_frac * N)
     u = None
+    idx = None
     if did:
         u = resample_offset(seed, t) if scheme == "systematic" else None
         idx = resample_indices(W, scheme, seed, t)
@@ -297,12 +300,46 @@ def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
         l = l[idx]
         logw = np.zeros(N)
         W = np.full(N, 1.0 / N)
+    return theta, l, logw, W, inc, dict(ess=e, resampled=did, u=u), idx
+
+
+def smc_step(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
+             ess_frac=0.5, resample=True, scheme="systematic"):
+    """Tempering step t >= 1: reweight by L^(beta_t - beta_{t-1}); if
+    ESS < ess_frac * N resample (systematic by default; points from the streams
+    of step t) and reset the log-weights; then n_moves RW-MH moves at beta_t
+    (move m uses stream move m). Returns (theta, l, logw, W, logZ_increment, info)."""
+    theta, l, logw, W, inc, info, _ = _reweight_resample(theta, l, logw, betas, t, seed,
+                                                         ess_frac, resample, scheme)
     accepted = []
     for m in range(n_moves):
         theta, l, a = rwmh_move(theta, l, y, model, betas[t], step_sd, seed, t, m)
         accepted.append(a)
-    info = dict(ess=e, resampled=did, u=u, accepted=accepted)
+    info["accepted"] = accepted
     return theta, l, logw, W, inc, info
+
+
+def smc_step_sampled(theta, l, logw, y, model: Model, betas, t, step_sd, n_moves, seed,
+                     sample, ess_frac=0.5, resample=True, scheme="systematic"):
+    """smc_step with the moves taken only by the particles at positions
+    ``sample`` of the (resampled) population. A particle's moves depend on its
+    own state and its own streams only, so these are exactly the corresponding
+    columns of smc_step's result; the reweight, evidence, ESS and resampling
+    are over the whole population as there. Returns (theta_s [kd][len(sample)],
+    l_s, logw, W, logZ_increment, info); info["ancestor"] holds the ancestor of
+    each sampled position (the position itself without resampling)."""
+    sample = np.asarray(sample, dtype=np.int64)
+    theta, l, logw, W, inc, info, idx = _reweight_resample(theta, l, logw, betas, t, seed,
+                                                           ess_frac, resample, scheme)
+    th_s, l_s = theta[:, sample], l[sample]
+    accepted = []
+    for m in range(n_moves):
+        th_s, l_s, a = rwmh_move(th_s, l_s, y, model, betas[t], step_sd, seed, t, m,
+                                 index=sample)
+        accepted.append(a)
+    info["accepted"] = accepted
+    info["ancestor"] = sample if idx is None else idx[sample]
+    return th_s, l_s, logw, W, inc, info
 
 
 def smc_run(y, model: Model, betas, N, step_sd, n_moves, seed, ess_frac=0.5,
@@ -358,21 +395,45 @@ def pt_parity(seed, it, mode):
     return int(w0) >> 31
 
 
+def exchange_accepts(beta_a, beta_b, l_a, l_b, seed, it, a) -> bool:
+    """The exchange decision of pair (a, b) at iteration `it`: accept iff
+    log alpha >= 0 or log u < log alpha, u from the stream of the pair's first
+    index a."""
+    la = exchange_log_alpha(beta_a, beta_b, l_a, l_b)
+    u = float(px.uniforms_open(seed, a, it, px.EXCH, 0))
+    return bool(la >= 0.0 or math.log(u) < la)
+
+
 def pt_exchange(theta, l, betas, parity, wrap, seed, it):
     """Exchange moves on the current partition; each pair draws its uniform from
-    the stream of its lower index a. Returns (theta, l, swapped pairs count)."""
+    the stream of its first index a. Returns (theta, l, swapped pairs count)."""
     theta = np.array(theta, dtype=np.float64, copy=True)
     l = np.array(l, dtype=np.float64, copy=True)
     M = l.size
     nswap = 0
     for a, b in exchange_pairs(M, parity, wrap):
-        la = exchange_log_alpha(betas[a], betas[b], l[a], l[b])
-        u = float(px.uniforms_open(seed, a, it, px.EXCH, 0))
-        if la >= 0.0 or math.log(u) < la:
+        if exchange_accepts(betas[a], betas[b], l[a], l[b], seed, it, a):
             theta[:, [a, b]] = theta[:, [b, a]]
             l[a], l[b] = l[b], l[a]
             nswap += 1
     return theta, l, nswap
+
+
+def pt_iteration_pairs(theta, l, y, model: Model, betas, it, step_sd, seed, pairs):
+    """One population-MCMC iteration restricted to the chains of `pairs` (pairs
+    of the iteration's partition): each chain's RW-MH move at its own beta, then
+    each pair's exchange. A pair depends only on its own two chains, so these
+    are exactly the corresponding columns of the whole iteration.
+    Returns (theta [kd][2P], l [2P], chains [2P]) with chains = (a0, b0, a1, b1, ...)."""
+    betas = np.asarray(betas, dtype=np.float64)
+    chains = np.array([c for p in pairs for c in p], dtype=np.int64)
+    th, ll, _ = rwmh_move(np.asarray(theta)[:, chains], np.asarray(l)[chains], y, model,
+                          betas[chains], step_sd, seed, it, 0, index=chains)
+    for q, (a, b) in enumerate(pairs):
+        if exchange_accepts(betas[a], betas[b], ll[2 * q], ll[2 * q + 1], seed, it, a):
+            th[:, [2 * q, 2 * q + 1]] = th[:, [2 * q + 1, 2 * q]]
+            ll[2 * q], ll[2 * q + 1] = ll[2 * q + 1], ll[2 * q]
+    return th, ll, chains
 
 
 def pt_run(y, model: Model, betas, iters, step_sd, seed, parity_mode="alternate",

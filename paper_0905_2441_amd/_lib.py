@@ -36,6 +36,9 @@ SMC_RESAMPLE_MULTINOMIAL = 2
 SMC_PRIOR_GAUSS = 0
 SMC_PRIOR_BOX = 1
 
+SMC_RULE_CALL = 0
+SMC_RULE_BATCH = 1
+
 
 class SmcGmm(Structure):
     _fields_ = [("k", c_int32), ("d", c_int32), ("sigma2", c_double),
@@ -59,8 +62,9 @@ class SmcFsv(Structure):
 
 
 class SmcLaunchRule(Structure):
-    _fields_ = [("k", c_int32), ("d", c_int32), ("prec", c_int32), ("slices", c_int32),
-                ("n_lo", c_int64), ("n_hi", c_int64), ("N_lo", c_int64), ("N_hi", c_int64)]
+    _fields_ = [("k", c_int32), ("d", c_int32), ("prec", c_int32), ("kind", c_int32),
+                ("slices", c_int32), ("n_lo", c_int64), ("n_hi", c_int64), ("N_lo", c_int64),
+                ("N_hi", c_int64)]
 
 
 _P = c_void_p

@@ -105,6 +105,7 @@ class Context:
         L.check(self._lib.smc_create(ctypes.byref(h), int(device)))
         self.handle = h
         self.device = device
+        self.rules: list = []          # the launch table last installed
 
     def reserve(self, N: int, kd: int = 8, n: int = 0) -> None:
         L.check(self._lib.smc_reserve(self.handle, int(N), int(kd), int(n)))
@@ -125,15 +126,18 @@ class Context:
         L.check(self._lib.smc_set_resampling(self.handle, SCHEME[scheme]))
 
     def set_launch_table(self, rules: Sequence[dict]) -> None:
-        """Install launch rules (dicts with k, d, prec, slices, n_lo, n_hi, N_lo,
-        N_hi; prec is a name of PREC or "any"); an empty list clears the table."""
+        """Install launch rules (dicts with k, d, prec, kind, slices, n_lo, n_hi,
+        N_lo, N_hi; prec is a name of PREC or "any"; kind is "call" (default)
+        or "batch"); an empty list clears the table."""
         arr = (L.SmcLaunchRule * max(1, len(rules)))()
         for i, r in enumerate(rules):
             prec = r.get("prec", "any")
+            kind = {"call": L.SMC_RULE_CALL, "batch": L.SMC_RULE_BATCH}[r.get("kind", "call")]
             arr[i] = L.SmcLaunchRule(int(r.get("k", 0)), int(r.get("d", 0)),
-                                     -1 if prec == "any" else PREC[prec], int(r["slices"]),
+                                     -1 if prec == "any" else PREC[prec], kind, int(r["slices"]),
                                      int(r["n_lo"]), int(r["n_hi"]), int(r["N_lo"]), int(r["N_hi"]))
         L.check(self._lib.smc_set_launch_table(self.handle, arr, len(rules)))
+        self.rules = [dict(r) for r in rules]
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -9,6 +9,12 @@ candidate on the device, with HIP events on its own stream, and keeps the
 fastest; the result is a list of launch rules for ``Context.set_launch_table``
 (C ABI ``smc_set_launch_table``), which can be saved as JSON and reloaded.
 
+Batched runs (``tune_batched``): the persistent move gives every tile of a run
+S of its workgroup's 8 waves (so 8 / S tiles share a workgroup). For each
+power-of-two range of n among the runs, the tuner times graph-replayed batched
+steps of just those runs for S = 1, 2, 4, 8 and keeps the fastest, giving one
+batch rule per range.
+
 Usage: python -m paper_0905_2441_amd.autotune --shape 4,1,1000,131072,fp32 [--out table.json]
 """
 
@@ -19,6 +25,7 @@ import json
 import math
 from typing import Dict, Iterable, List, Optional, Sequence
 
+import numpy as np
 import torch
 
 from .api import Context, Gmm, smc_rwmh_move
@@ -99,6 +106,69 @@ def make_rules(ctx: Context, shapes: Iterable[tuple], reps: int = 20, exact: boo
             log(f"[autotune] k={k} d={d} n={n} N={N} {prec}: slices {r['best']} "
                 f"({r['ms'][r['best']]:.4f} ms/move)")
     return rules
+
+
+BATCH_CANDIDATES = (1, 2, 4, 8)
+
+
+def time_batched_step(ctx: Context, model: Gmm, datas, Ns, seeds, betas, step_sd: float,
+                      n_moves: int, ess_frac: float, prec: str, reps: int) -> float:
+    """Mean device time (ms) of one graph-replayed batched step of these runs
+    under the context's current launch table: the runs start from the prior,
+    one step warms the graph, then `reps` steps are timed with HIP events."""
+    from .samplers import BatchSampler
+    b = BatchSampler(ctx, model, datas, Ns, seeds, betas, step_sd, n_moves, ess_frac=ess_frac,
+                     prec=prec)
+    try:
+        b.init()
+        g = b.capture()
+        g.launch()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        for _ in range(reps):
+            g.launch()
+        e1.record(b.stream)
+        e1.synchronize()
+        ctx.check(b.stream)
+        return e0.elapsed_time(e1) / reps
+    finally:
+        if b.graph is not None:
+            b.graph.close()
+        b.batch.close()
+
+
+def tune_batched(ctx: Context, model: Gmm, datas, Ns, seeds, betas, step_sd: float,
+                 n_moves: int, ess_frac: float = 0.5, prec: str = "fp32", reps: int = 3,
+                 log=None) -> List[dict]:
+    """Batch rules (kind "batch") for the runs' power-of-two ranges of n: for
+    each range, graph-replayed batched steps of the runs in it are timed with
+    every S in BATCH_CANDIDATES and the fastest is kept. Other rules of the
+    context's table are kept while tuning and the batch rules are returned (the
+    caller installs them)."""
+    base = [r for r in ctx.rules if r.get("kind", "call") != "batch"]
+    ns = [int(np.asarray(y).size) for y in datas]
+    buckets = sorted({bucket(n) for n in ns})
+    out = []
+    for lo, hi in buckets:
+        sel = [i for i, n in enumerate(ns) if lo <= n <= hi]
+        times = {}
+        for S in BATCH_CANDIDATES:
+            rule = dict(k=model.k, d=1, prec=prec, kind="batch", slices=S, n_lo=lo, n_hi=hi,
+                        N_lo=1, N_hi=(1 << 31) - 1)
+            ctx.set_launch_table(list(base) + [rule])
+            times[S] = time_batched_step(ctx, model, [datas[i] for i in sel],
+                                         [Ns[i] for i in sel], [seeds[i] for i in sel], betas,
+                                         step_sd, n_moves, ess_frac, prec, reps)
+        best = min(times, key=times.get)
+        out.append(dict(k=model.k, d=1, prec=prec, kind="batch", slices=best, n_lo=lo, n_hi=hi,
+                        N_lo=1, N_hi=(1 << 31) - 1, runs=len(sel),
+                        ms={str(t): round(v, 4) for t, v in times.items()}))
+        if log:
+            log(f"[autotune] batch n in [{lo}, {hi}] ({len(sel)} runs): S = {best} "
+                f"({', '.join(f'{t}: {v:.3f}' for t, v in times.items())} ms/step)")
+    ctx.set_launch_table(list(base))
+    return out
 
 
 def save(rules: Sequence[dict], path: str) -> None:

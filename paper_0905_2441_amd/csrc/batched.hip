@@ -14,11 +14,15 @@
 //   k_b_resample  one workgroup per run that resamples: double-double CDF scan
 //                 of the run's weights, then search and gather of all N_r
 //                 offspring (runs that keep their weights exit at once);
-//   k_b_move      persistent: a grid sized to the GPU pulls work items
-//                 (run, tile of 64 particles) from an atomic counter. Items are
-//                 listed longest data first (LPT), each is one proposal + mixture
-//                 likelihood over the run's n_r observations (waves split the
-//                 data) + accept, so runs whose work differs by 10^3 balance.
+//   k_b_move      persistent: a grid sized to the GPU pulls work units from an
+//                 atomic counter. A unit is 8 / S consecutive 64-particle tiles
+//                 of one run, each moved by S of the workgroup's 8 waves
+//                 (proposal + mixture likelihood over the run's n_r
+//                 observations, the S waves splitting the data + accept). S is
+//                 per run (launch table or built-in rule), so short-data runs
+//                 fill the workgroup with several tiles instead of leaving waves
+//                 idle. Units are listed longest data first (LPT), so runs whose
+//                 work differs by 10^3 balance.
 // and a one-thread kernel that advances the step counter and rewinds the work
 // counter for the next replay.
 #include "gmm_common.hpp"
@@ -27,7 +31,6 @@
 namespace smc {
 namespace {
 
-constexpr int kBatchWaves = 8;                 // data slices per move workgroup
 constexpr int kBatchBlock = kBatchWaves * kWave;
 
 __global__ void __launch_bounds__(kRedBlock)
@@ -134,7 +137,7 @@ k_b_resample(const BatchRun* __restrict__ runs, const StepState* __restrict__ st
 
 template <int K, int PREC>
 __global__ void __launch_bounds__(kBatchBlock)
-k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items, int n_items,
+k_b_move(const BatchRun* __restrict__ runs, const BatchUnit* __restrict__ units, int n_units,
          unsigned* work, const float* __restrict__ y, double* theta, double* l,
          const double* __restrict__ logw, double* __restrict__ W,
          const double* __restrict__ theta_tmp, const double* __restrict__ l_tmp,
@@ -142,48 +145,51 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchItem* __restrict__ items,
          GmmDev g, unsigned long long* n_acc, int* status) {
     constexpr int KD = K;
     __shared__ double red[kBatchWaves][kWave];
-    __shared__ double prs[KD][kWave];
-    __shared__ int item_sh;
+    __shared__ double prs[kBatchWaves][KD][kWave];
+    __shared__ int unit_sh;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
     for (;;) {
-        if (threadIdx.x == 0) item_sh = static_cast<int>(atomicAdd(work, 1u));
+        if (threadIdx.x == 0) unit_sh = static_cast<int>(atomicAdd(work, 1u));
         __syncthreads();
-        const int it = item_sh;
+        const int u = unit_sh;
         __syncthreads();
-        if (it >= n_items) break;
-        const BatchItem itm = items[it];
-        const BatchRun rd = runs[itm.run];
+        if (u >= n_units) break;
+        const BatchUnit un = units[u];
+        const BatchRun rd = runs[un.run];
+        const int S = wave_uniform(un.slices);
+        const int grp = w / S;                       // this wave's tile within the unit
+        const int sl = w - grp * S;                  // and its data slice
+        const bool active = grp < un.ntiles;
         const int N = rd.N;
         const int n = rd.n;
-        const int p = itm.tile * kWave + lane;
+        const int p = (un.tile0 + (active ? grp : 0)) * kWave + lane;
         const int pc = p < N ? p : N - 1;
-        const StepState* sr = st + itm.run;
+        const StepState* sr = st + un.run;
         const uint32_t step = static_cast<uint32_t>(sr->t);
         const bool use_alt = first && sr->resampled;
         double* th_run = theta + static_cast<size_t>(KD) * rd.p_off;
         double* l_run = l + rd.p_off;
         const double* th_src = use_alt ? theta_tmp + static_cast<size_t>(KD) * rd.p_off : th_run;
         const double l_src = use_alt ? l_tmp[rd.p_off + pc] : l_run[pc];
-        // active slices: at least 32 observations each
-        int S = n / 32;
-        S = S < 1 ? 1 : (S > kBatchWaves ? kBatchWaves : S);
+        // the tile's Box-Muller pairs shared out over its S waves (an idle
+        // wave of a short last unit draws none but meets the barrier)
         double pr[KD];
-        block_proposals<KD>(rd.seed, static_cast<uint32_t>(pc), step, move, th_src, N, pc, sd, w,
-                            kBatchWaves, prs, pr);
+        block_proposals<KD>(rd.seed, static_cast<uint32_t>(pc), step, move, th_src, N, pc, sd,
+                            active ? sl : (KD + 1) / 2, S, prs[grp], pr);
         double part = 0.0;
-        if (w < S) {
-            const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
-            const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+        if (active) {
+            const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / S));
+            const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / S));
             part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g));
         }
         red[w][lane] = part;
         __syncthreads();
-        if (w == 0) {
+        if (active && sl == 0) {
             bool acc = false;
             if (p < N) {
-                double tot = red[0][lane];
-                for (int s = 1; s < S; ++s) tot += red[s][lane];
+                double tot = red[w][lane];
+                for (int q = 1; q < S; ++q) tot += red[w + q][lane];
                 const double l_prop = finish_loglik<PREC>(tot, n, g);
                 MoveStep ms{};
                 if (first) {
@@ -247,7 +253,10 @@ hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y,
                        theta, l, b.cdf, b.theta_tmp, b.l_tmp, g.k * g.d, src, scheme);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int grid = b.n_items < b.move_grid ? b.n_items : b.move_grid;
+    const int pi = prec == SMC_PREC_FP32 ? 1 : 0;
+    const BatchUnit* units = b.units[pi];
+    const int n_units = b.n_units[pi];
+    const int grid = n_units < b.move_grid ? n_units : b.move_grid;
     for (int m = 0; m < n_moves; ++m) {
         if (m > 0) {
             hipLaunchKernelGGL(k_b_rewind, dim3(1), dim3(64), 0, s, b.work);
@@ -258,12 +267,12 @@ hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y,
         if (g.k == KK) {                                                                        \
             if (prec == SMC_PREC_FP32)                                                          \
                 hipLaunchKernelGGL((k_b_move<KK, SMC_PREC_FP32>), dim3(grid), dim3(kBatchBlock), 0, s, \
-                                   b.runs, b.items, b.n_items, b.work, y, theta, l, logw, W,    \
+                                   b.runs, units, n_units, b.work, y, theta, l, logw, W,    \
                                    b.theta_tmp, b.l_tmp, b.state, src, sd, static_cast<uint32_t>(m), \
                                    m == 0 ? 1 : 0, g, n_acc, status);                           \
             else                                                                                \
                 hipLaunchKernelGGL((k_b_move<KK, SMC_PREC_FP64>), dim3(grid), dim3(kBatchBlock), 0, s, \
-                                   b.runs, b.items, b.n_items, b.work, y, theta, l, logw, W,    \
+                                   b.runs, units, n_units, b.work, y, theta, l, logw, W,    \
                                    b.theta_tmp, b.l_tmp, b.state, src, sd, static_cast<uint32_t>(m), \
                                    m == 0 ? 1 : 0, g, n_acc, status);                           \
         }

@@ -27,6 +27,10 @@ struct smc_ctx_s {
     int64_t grow_kd = 0;
     void* mm = nullptr;          // MFMA form: data rows, columns, proposals, partials
     double* fsv_mom = nullptr;   // particle filter: per-block moment sums (in `fixed`)
+    // Scratch superseded by a larger allocation. Graphs captured earlier hold
+    // its addresses as kernel arguments, so it stays allocated (and those
+    // graphs valid) until the context is destroyed.
+    std::vector<void*> retired;
 };
 
 struct smc_graph_s {
@@ -124,15 +128,30 @@ int check_sizes(int64_t n, int64_t N) {
     return SMC_OK;
 }
 
-// Slices per tile from the launch table (0 when no rule matches).
-int64_t table_slices(const smc_ctx_s* ctx, const GmmDev& g, int prec, int64_t n, int64_t N) {
+// Slices per tile from the first launch rule of `kind` that matches (0 when none).
+int64_t table_slices(const smc_ctx_s* ctx, int k, int d, int prec, int64_t n, int64_t N,
+                     int kind = SMC_RULE_CALL) {
     for (const smc_launch_rule& r : ctx->table) {
-        if ((r.k == 0 || r.k == g.k) && (r.d == 0 || r.d == g.d) &&
+        if (r.kind == kind && (r.k == 0 || r.k == k) && (r.d == 0 || r.d == d) &&
             (r.prec < 0 || r.prec == prec) && n >= r.n_lo && n <= r.n_hi && N >= r.N_lo &&
             N <= r.N_hi)
             return r.slices;
     }
     return 0;
+}
+
+int64_t table_slices(const smc_ctx_s* ctx, const GmmDev& g, int prec, int64_t n, int64_t N) {
+    return table_slices(ctx, g.k, g.d, prec, n, N);
+}
+
+// Waves per 64-particle tile of a batched run: its SMC_RULE_BATCH rule, else
+// the largest power of two <= min(kBatchWaves, n / 32), at least 1.
+int batch_slices(const smc_ctx_s* ctx, int k, int prec, int64_t n, int64_t N) {
+    const int64_t t = table_slices(ctx, k, 1, prec, n, N, SMC_RULE_BATCH);
+    if (t > 0) return static_cast<int>(t);
+    int S = 1;
+    while (2 * S <= kBatchWaves && 2 * S <= n / 32) S *= 2;
+    return S;
 }
 
 // Data slices per 64-particle tile: the explicit override, else the launch
@@ -184,7 +203,7 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
     SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     SMC_CHECK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize before scratch growth");
     if (ctx->grow) {
-        SMC_CHECK_HIP(hipFree(ctx->grow), "hipFree");
+        ctx->retired.push_back(ctx->grow);
         ctx->grow = nullptr;
     }
     void* p = nullptr;
@@ -220,7 +239,7 @@ int ensure_mm_scratch(smc_ctx ctx, int64_t n, int64_t N, hipStream_t s) {
     SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     SMC_CHECK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize before scratch growth");
     if (ctx->mm) {
-        SMC_CHECK_HIP(hipFree(ctx->mm), "hipFree");
+        ctx->retired.push_back(ctx->mm);
         ctx->mm = nullptr;
     }
     void* p = nullptr;
@@ -313,6 +332,7 @@ int smc_destroy(smc_ctx ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->grow) (void)hipFree(ctx->grow);
     if (ctx->mm) (void)hipFree(ctx->mm);
+    for (void* p : ctx->retired) (void)hipFree(p);
     if (ctx->fixed) (void)hipFree(ctx->fixed);
     delete ctx;
     return SMC_OK;
@@ -368,8 +388,12 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
     if (count < 0 || (count > 0 && !rules)) return fail(SMC_ERR_INVALID_ARG, "bad rule array");
     for (int32_t i = 0; i < count; ++i) {
         const smc_launch_rule& r = rules[i];
+        if (r.kind != SMC_RULE_CALL && r.kind != SMC_RULE_BATCH)
+            return fail(SMC_ERR_INVALID_ARG, "rule kind is SMC_RULE_CALL or SMC_RULE_BATCH");
         if (r.slices < 1 || r.slices > kMaxSlices * kMaxGroups)
             return fail(SMC_ERR_INVALID_ARG, "rule slices in 1..128");
+        if (r.kind == SMC_RULE_BATCH && (r.slices > kBatchWaves || (r.slices & (r.slices - 1))))
+            return fail(SMC_ERR_INVALID_ARG, "batch rule slices must be 1, 2, 4 or 8");
         if (r.n_lo > r.n_hi || r.N_lo > r.N_hi || r.k < 0 || r.d < 0 || r.prec < -1)
             return fail(SMC_ERR_INVALID_ARG, "rule ranges are empty or fields negative");
     }
@@ -1116,33 +1140,42 @@ int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t k
     *out = nullptr;
     if (R < 1) return fail(SMC_ERR_INVALID_ARG, "R must be >= 1");
     if (kd < 1 || kd > SMC_KMAX) return fail(SMC_ERR_INVALID_ARG, "batched runs need d = 1, k <= 8");
-    int64_t N_total = 0, n_total = 0, n_items = 0;
+    int64_t N_total = 0, n_total = 0, n_tiles = 0;
     for (int i = 0; i < R; ++i) {
         const smc_run_desc& d = runs[i];
         if (d.N < 1 || d.n < 1 || d.p_off < 0 || d.y_off < 0)
             return fail(SMC_ERR_INVALID_ARG, "run needs N >= 1, n >= 1, offsets >= 0");
         if (d.p_off + d.N > N_total) N_total = d.p_off + d.N;
         if (d.y_off + d.n > n_total) n_total = d.y_off + d.n;
-        n_items += (d.N + 63) / 64;
+        n_tiles += (d.N + 63) / 64;
     }
-    if (N_total > INT32_MAX || n_items > INT32_MAX)
+    if (N_total > INT32_MAX || n_tiles > INT32_MAX)
         return fail(SMC_ERR_INVALID_ARG, "batch too large");
-    // work list: runs by decreasing data length (ties: larger N first), tiles in order
+    // work lists (FP64, FP32): runs by decreasing data length (ties: larger N
+    // first), each run's tiles in units of kBatchWaves / S tiles
     std::vector<int> order(R);
     for (int i = 0; i < R; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         if (runs[a].n != runs[b].n) return runs[a].n > runs[b].n;
         return runs[a].N > runs[b].N;
     });
-    std::vector<BatchItem> items;
-    items.reserve(static_cast<size_t>(n_items));
-    for (int i : order)
-        for (int t = 0; t < (runs[i].N + 63) / 64; ++t) items.push_back(BatchItem{i, t});
+    std::vector<BatchUnit> units[2];
+    for (int pi = 0; pi < 2; ++pi) {
+        const int prec = pi == 1 ? SMC_PREC_FP32 : SMC_PREC_FP64;
+        for (int i : order) {
+            const int S = batch_slices(ctx, kd, prec, runs[i].n, runs[i].N);
+            const int per = kBatchWaves / S;
+            const int tiles = (runs[i].N + 63) / 64;
+            for (int t = 0; t < tiles; t += per)
+                units[pi].push_back(BatchUnit{i, t, std::min(per, tiles - t), S});
+        }
+    }
     std::vector<BatchRun> rd(R);
     for (int i = 0; i < R; ++i)
         rd[i] = BatchRun{runs[i].p_off, runs[i].y_off, runs[i].N, runs[i].n, runs[i].seed};
     const size_t b_runs = align_up(sizeof(BatchRun) * R);
-    const size_t b_items = align_up(sizeof(BatchItem) * items.size());
+    const size_t b_u0 = align_up(sizeof(BatchUnit) * units[0].size());
+    const size_t b_items = b_u0 + align_up(sizeof(BatchUnit) * units[1].size());
     const size_t b_work = align_up(sizeof(unsigned));
     const size_t b_state = align_up(sizeof(StepState) * R);
     const size_t b_cdf = align_up(sizeof(double) * N_total);
@@ -1165,8 +1198,10 @@ int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t k
     BatchDev& d = b->dev;
     d.R = R;
     d.runs = reinterpret_cast<BatchRun*>(c);
-    d.items = reinterpret_cast<BatchItem*>(c + b_runs);
-    d.n_items = static_cast<int>(items.size());
+    d.units[0] = reinterpret_cast<BatchUnit*>(c + b_runs);
+    d.units[1] = reinterpret_cast<BatchUnit*>(c + b_runs + b_u0);
+    d.n_units[0] = static_cast<int>(units[0].size());
+    d.n_units[1] = static_cast<int>(units[1].size());
     d.work = reinterpret_cast<unsigned*>(c + b_runs + b_items);
     d.state = reinterpret_cast<StepState*>(c + b_runs + b_items + b_work);
     d.cdf = reinterpret_cast<double*>(c + b_runs + b_items + b_work + b_state);
@@ -1175,8 +1210,9 @@ int smc_batch_create(smc_ctx ctx, const smc_run_desc* runs, int32_t R, int32_t k
     d.move_grid = batch_move_grid();
     hipError_t e = hipMemset(p, 0, total);
     if (e == hipSuccess) e = hipMemcpy(d.runs, rd.data(), sizeof(BatchRun) * R, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(d.items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    for (int pi = 0; pi < 2 && e == hipSuccess; ++pi)
+        e = hipMemcpy(d.units[pi], units[pi].data(), sizeof(BatchUnit) * units[pi].size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(p);

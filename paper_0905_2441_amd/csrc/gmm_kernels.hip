@@ -21,8 +21,10 @@
 // (partial_fp32). Instead of one log per datum, the e's are multiplied into a
 // running FP32 product whose exponent is extracted exactly after each block
 // of data (frexp), and the m's are summed in blocks in FP32 and promoted into
-// an FP64 accumulator. Both are compensated schemes: the relative error of
-// the particle's log-likelihood stays below 1e-6 for n up to 10^5.
+// an FP64 accumulator. Neither is a Kahan sum: the product loses no exponent
+// range (the integer exponents are exact), the block sums round at most 16
+// FP32 terms, and the relative error of the particle's log-likelihood stays
+// below 1e-6 for n up to 10^5.
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.

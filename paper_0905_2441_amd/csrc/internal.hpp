@@ -157,14 +157,18 @@ struct BatchRun {
     int N, n;
     uint64_t seed;
 };
-struct BatchItem {
-    int run, tile;             // tile of 64 particles of run `run`
+constexpr int kBatchWaves = 8;          // waves per workgroup of the persistent batched move
+// Work unit of the persistent batched move: ntiles consecutive 64-particle
+// tiles of run `run` from tile0 on, each moved by `slices` waves (slices *
+// ntiles <= kBatchWaves).
+struct BatchUnit {
+    int run, tile0, ntiles, slices;
 };
 struct BatchDev {
     int R;
     BatchRun* runs;            // [R]
-    BatchItem* items;          // [n_items], longest data first
-    int n_items;
+    BatchUnit* units[2];       // work lists of the FP64 [0] and FP32 [1] moves, longest data first
+    int n_units[2];
     unsigned* work;            // work-queue counter, zero between launches
     StepState* state;          // [R]
     double* cdf;               // [N_total]

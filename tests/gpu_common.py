@@ -19,3 +19,31 @@ def rel_err(got, want):
 
 def announce(msg):
     print(f"[gpu-case] {msg}", flush=True)
+
+
+def loglik_threads(theta, y, model, workers=8):
+    """The oracle's FP64 log-likelihood of every column of theta, the columns
+    split over a thread pool (NumPy releases the GIL in its array loops). The
+    arithmetic is the oracle's own; NumPy's summation blocking follows the
+    array shapes, so values may differ from one call over all columns in the
+    last bits (a few 1e-15 relative)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import gmm as ogmm
+
+    theta = np.asarray(theta, dtype=np.float64)
+    N = theta.shape[1]
+    parts = np.array_split(np.arange(N), max(1, min(workers, N // 256 or 1)))
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        outs = list(ex.map(lambda ix: ogmm.loglik(theta[:, ix], y, model), parts))
+    return np.concatenate(outs)
+
+
+def replay_positions(N, count, seed):
+    """Sorted positions for a sampled replay: `count` random ones plus the first
+    and last 64 (a whole first and last tile)."""
+    if N <= count + 128:
+        return np.arange(N)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(N, size=count, replace=False)
+    return np.unique(np.concatenate([pick, np.arange(64), np.arange(N - 64, N)]))

@@ -39,10 +39,17 @@ def test_binding_signature_table_matches_header():
     assert sorted(_lib.SIGNATURES) == declared_functions()
 
 
-def test_last_error_is_callable_without_gpu():
+def test_last_error_names_the_rejected_argument():
+    """After an argument error the thread's last-error text says what was wrong
+    (no GPU call is made: the checks run before any device work)."""
     from paper_0905_2441_amd import _lib
     lib = _lib.load()
-    assert lib.smc_last_error() is not None or lib.smc_last_error() is None
+    assert lib.smc_create(None, 0) == _lib.SMC_ERR_INVALID_ARG
+    assert b"out" in lib.smc_last_error()
+    assert lib.smc_rng_words(1, 0, 0, 0, 0, 0, None, None) == _lib.SMC_ERR_INVALID_ARG
+    assert b"count" in lib.smc_last_error()
+    assert lib.smc_set_slices(None, 4) == _lib.SMC_ERR_INVALID_ARG
+    assert b"context" in lib.smc_last_error()
 
 
 def test_invalid_arguments_are_rejected_before_any_gpu_work():

@@ -25,7 +25,23 @@ def test_buckets_are_power_of_two_ranges():
     assert autotune.bucket(131072) == (131072, 262143)
 
 
-def test_launch_rule_layout_matches_header():
-    # int32 k, d, prec, slices; int64 n_lo, n_hi, N_lo, N_hi
-    assert ctypes.sizeof(L.SmcLaunchRule) == 4 * 4 + 4 * 8
-    assert L.SmcLaunchRule.n_lo.offset == 16
+def test_launch_rule_layout_matches_header(tmp_path):
+    """The binding's struct has the size and field offsets that a C compiler
+    gives smc_launch_rule from include/smc.h."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = [f[0] for f in L.SmcLaunchRule._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "smc.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(smc_launch_rule));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(smc_launch_rule, {f}));\n'
+                             for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(L.SmcLaunchRule)
+    assert got[1:] == [getattr(L.SmcLaunchRule, f).offset for f in fields]

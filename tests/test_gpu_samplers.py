@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import announce, oracle_model, rel_err
+from gpu_common import announce, loglik_threads, oracle_model, rel_err, replay_positions
 from oracle import gmm as ogmm
 from oracle import smc as osmc
 from workloads import CONFIGS, beta_schedule, make_data, pt_betas, make_mixture_data
@@ -199,6 +199,33 @@ def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
     assert c["logZ"] == d["logZ"] and np.array_equal(c["theta"], d["theta"])
 
 
+def test_graphs_captured_before_scratch_growth_stay_valid(smc, small, small_oracle):
+    """Graphs of both step directions are captured on a fresh context, then a
+    larger reservation regrows its scratch (VALU and MFMA forms) to new
+    addresses. The context keeps the superseded scratch, so replaying the old
+    graphs still runs the small FP64 run exactly as the oracle does."""
+    cfg, y, betas = small
+    announce("graphs replayed after the context scratch grew")
+    c2 = smc.Context(0)
+    s = _sampler(smc, c2, cfg, y, betas, "fp64")
+    try:
+        s.capture(0, 1)
+        s.capture(1, 1)
+        c2.reserve(1 << 20, 8, 1 << 16)
+        r = s.run(graph=True)
+    finally:
+        for g in s.graphs.values():
+            g.close()
+        s.graphs.clear()
+        s.stream.synchronize()
+        c2.close()
+    ref = small_oracle
+    assert r["resamples"] == int(np.sum(ref["trace"]["resampled"]))
+    assert r["accepted"] == int(np.sum(ref["trace"]["accepted"]))
+    assert np.max(np.abs(r["theta"] - ref["theta"])) <= 1e-9
+    assert abs(r["logZ"] - ref["logZ"]) <= 1e-3
+
+
 def _snapshot(s):
     s.stream.synchronize()
     return (s.theta.cpu().numpy().copy(), s.loglik.cpu().numpy().copy(),
@@ -371,6 +398,88 @@ def test_headline_size_steps_from_gpu_state(smc, ctx, prec, slices):
         print(f"{prec} step {t}: resampled={info['resampled']} flips={flips}")
 
 
+def _full_state(s):
+    s.stream.synchronize()
+    st = s.stats.cpu().numpy()
+    return dict(theta=s.theta.cpu().numpy().copy(), l=s.loglik.cpu().numpy().copy(),
+                logw=s.logw.cpu().numpy().copy(), logZ=float(st[0]), resamples=int(st[2]),
+                accepted=int(s.n_accept.cpu().item()))
+
+
+def test_headline_fp32_run_replayed_by_oracle(smc, ctx):
+    """The benchmark's FP32 run (N = 131072, n = 1000, 100 steps, 4 slices per
+    tile) in replay mode.
+    (1) The whole run as one 100-step chain in one graph replay, as timed.
+    (2) The same run as alternating one-step and nine-step chains (one graph
+        replay each), keeping the state before and after every step
+        t = 10k + 1; its final population equals (1)'s and its evidence
+        agrees to 1e-9.
+    (3) The oracle takes each kept step from the GPU's state before it:
+        - the GPU's FP32 log-likelihoods of all N particles are within 1e-6 of
+          the oracle's FP64 values on the same parameters;
+        - from the GPU's log-likelihoods the oracle gives the GPU's evidence
+          increment (1e-10 relative), log-weights (1e-12) and resampling
+          decision; on about 4200 sampled positions the moved particles equal
+          the oracle's except FP32 near-tie accept flips (at most one per
+          thousand decisions) and their log-likelihoods agree to 1e-6;
+        - from the oracle's FP64 log-likelihoods the increments move by the
+          FP32 likelihood error only: summed over the ten steps, the GPU's
+          increments are within 1e-3 of the oracle's."""
+    cfg = CONFIGS["gmm1d_k4_n1000_N131072"]
+    y = make_data(cfg)
+    betas = beta_schedule(cfg.T, cfg.schedule)
+    from oracle.gmm import Model
+    om = Model.equal_weights(cfg.k, cfg.d, cfg.sigma2)
+    ctx.set_slices(4)
+    try:
+        announce("headline fp32: 100-step chain in one graph")
+        a = _sampler(smc, ctx, cfg, y, betas, "fp32")
+        a.run(graph=True, steps_per_graph=cfg.T)
+        whole = _full_state(a)
+        announce("headline fp32: chains of 1 and 9 steps with saved states")
+        b = _sampler(smc, ctx, cfg, y, betas, "fp32")
+        b.init()
+        kept = []
+        for k in range(cfg.T // 10):
+            before = _full_state(b)
+            b.step(graph=True, steps=1)
+            kept.append((10 * k + 1, before, _full_state(b)))
+            b.step(graph=True, steps=9)
+        split = _full_state(b)
+        ctx.check(b.stream)
+    finally:
+        ctx.set_slices(0)
+    assert whole["resamples"] == split["resamples"] > 0
+    assert whole["accepted"] == split["accepted"]
+    assert np.array_equal(whole["theta"], split["theta"])
+    assert np.array_equal(whole["l"], split["l"])
+    assert abs(whole["logZ"] - split["logZ"]) <= 1e-9 * max(1.0, abs(whole["logZ"]))
+    flips = decisions = 0
+    drift = []
+    for t, s0, s1 in kept:
+        l_o = loglik_threads(s0["theta"], y, om)
+        assert rel_err(s0["l"], l_o).max() <= 1e-6, t
+        pos = replay_positions(cfg.N, 4096, seed=t)
+        rth, rl, rlw, _, inc, info = osmc.smc_step_sampled(
+            s0["theta"], s0["l"], s0["logw"], y, om, betas, t, cfg.step_sd, cfg.n_moves,
+            cfg.run_seed, pos, cfg.ess_frac)
+        inc_gpu = s1["logZ"] - s0["logZ"]
+        assert info["resampled"] == (s1["resamples"] == s0["resamples"] + 1), t
+        assert abs(inc_gpu - inc) <= 1e-10 * max(1.0, abs(inc)), t
+        assert np.max(np.abs(s1["logw"] - rlw)) <= 1e-12, t
+        same = np.all(np.abs(s1["theta"][:, pos] - rth) <= 1e-12, axis=0)
+        flips += int(np.sum(~same))
+        decisions += pos.size * cfg.n_moves
+        assert rel_err(s1["l"][pos][same], rl[same]).max() <= 1e-6, t
+        inc_fp64 = osmc.reweight(s0["logw"], l_o, betas[t] - betas[t - 1])[2]
+        drift.append(inc_gpu - inc_fp64)
+        print(f"step {t}: resampled={info['resampled']} increment {inc_gpu:.9f} "
+              f"(oracle on FP64 l: {inc_fp64:.9f}) flips={int(np.sum(~same))}")
+    assert flips <= max(3, decisions // 1000), flips
+    assert abs(sum(drift)) <= 1e-3 and max(abs(x) for x in drift) <= 1e-4, drift
+    print(f"summed increment error {sum(drift):.3e}; flips {flips} of {decisions}")
+
+
 @pytest.mark.parametrize("slices,iters_per_graph,fused", [(0, 1, False), (24, 7, False),
                                                           (0, 7, True), (3, 25, True)])
 def test_pt_matches_oracle(smc, ctx, slices, iters_per_graph, fused):
@@ -505,21 +614,38 @@ def test_batched_runs_match_oracle_fp64(smc, ctx, graph, scheme):
     assert r["accepted"] == acc_total
 
 
-def test_batched_full_workload_sampled_runs(smc, ctx):
+# launch tables of the batched move: the built-in rule, and one that gives
+# short-data runs a single wave per tile and long-data runs two
+BATCH_TABLES = {
+    "built-in": [],
+    "one-two": [dict(k=4, d=1, prec="any", kind="batch", slices=1, n_lo=1, n_hi=999,
+                     N_lo=1, N_hi=1 << 30),
+                dict(k=4, d=1, prec="any", kind="batch", slices=2, n_lo=1000, n_hi=1 << 30,
+                     N_lo=1, N_hi=1 << 30)],
+}
+
+
+@pytest.mark.parametrize("table", sorted(BATCH_TABLES))
+def test_batched_full_workload_sampled_runs(smc, ctx, table):
     """The benchmark's whole 256-run batch (n log-uniform in 1e2..1e5, N in
-    1024..65536) advanced three graph-replayed FP64 steps; the four cheapest
-    runs and one with long data (N = 1024, n nearest 2e4), checked one by one,
-    equal the oracle's runs alone over the same three steps."""
+    1024..65536) advanced three graph-replayed FP64 steps, under two launch
+    tables of the persistent move; the four cheapest runs and one with long
+    data (N = 1024, n nearest 2e4), checked one by one, equal the oracle's runs
+    alone over the same three steps."""
     from workloads.configs import BATCHED, batched_runs
-    announce("batched full workload, sampled runs")
+    announce(f"batched full workload, sampled runs, table {table}")
     runs = batched_runs(256)
     datas = [make_mixture_data(x.n, x.true_means, BATCHED["sigma2"], x.data_seed) for x in runs]
     g = smc.Gmm.equal_weights(4, 1, BATCHED["sigma2"])
     om = oracle_model(g)
     betas = beta_schedule(BATCHED["T"], BATCHED["schedule"])
-    b = smc.BatchSampler(ctx, g, datas, [x.N for x in runs], [x.run_seed for x in runs], betas,
-                         BATCHED["step_sd"], BATCHED["n_moves"], ess_frac=BATCHED["ess_frac"],
-                         prec="fp64")
+    ctx.set_launch_table(BATCH_TABLES[table])
+    try:
+        b = smc.BatchSampler(ctx, g, datas, [x.N for x in runs], [x.run_seed for x in runs],
+                             betas, BATCHED["step_sd"], BATCHED["n_moves"],
+                             ess_frac=BATCHED["ess_frac"], prec="fp64")
+    finally:
+        ctx.set_launch_table([])
     r = b.run(graph=True, steps=3)
     assert r["t"] == 4
     order = np.argsort([x.N * x.n for x in runs])
@@ -534,18 +660,102 @@ def test_batched_full_workload_sampled_runs(smc, ctx):
         assert rel_err(r["l"][i], ref["l"]).max() <= 1e-10, i
 
 
-def test_batched_fp32_two_moves_runs(smc, ctx):
-    announce("batched fp32 two moves")
+def _batch_state(b):
+    b.stream.synchronize()
+    return dict(theta=b.theta.cpu().numpy().copy(), l=b.loglik.cpu().numpy().copy(),
+                logw=b.logw.cpu().numpy().copy(),
+                stats=b.stats.cpu().numpy().reshape(b.R, 4).copy())
+
+
+def _run_view(b, st, r):
+    """Run r's (theta [kd][N_r], l, logw, logZ, resamples) from a batch state."""
+    kd, N, a = b.model.kd, b.Ns[r], int(b.p_off[r])
+    return (st["theta"][kd * a:kd * (a + N)].reshape(kd, N), st["l"][a:a + N],
+            st["logw"][a:a + N], float(st["stats"][r, 0]), int(st["stats"][r, 2]))
+
+
+def _replay_batched(b, states, runs, datas, om, betas, max_evals):
+    """Each listed run's steps taken by the oracle from the GPU's state before
+    each step (replay mode); moves on all particles, or on sampled positions
+    when the run is large. Returns (flips, decisions)."""
+    flips = decisions = 0
+    for r in runs:
+        y = datas[r]
+        N, n = b.Ns[r], b.ns[r]
+        pos = np.arange(N) if N * n <= max_evals else replay_positions(N, 512, seed=r)
+        th0, l0, _, _, _ = _run_view(b, states[0], r)
+        assert rel_err(l0[pos], ogmm.loglik(th0[:, pos], y, om)).max() <= 1e-6, r
+        for t in range(1, len(states)):
+            th0, l0, lw0, z0, c0 = _run_view(b, states[t - 1], r)
+            th1, l1, lw1, z1, c1 = _run_view(b, states[t], r)
+            rth, rl, rlw, _, inc, info = osmc.smc_step_sampled(
+                th0, l0, lw0, y, om, betas, t, b.step_sd, b.n_moves, b.seeds[r], pos,
+                b.ess_frac)
+            assert info["resampled"] == (c1 == c0 + 1), (r, t)
+            assert abs((z1 - z0) - inc) <= 1e-10 * max(1.0, abs(inc)), (r, t)
+            assert np.max(np.abs(lw1 - rlw)) <= 1e-12, (r, t)
+            same = np.all(np.abs(th1[:, pos] - rth) <= 1e-12, axis=0)
+            flips += int(np.sum(~same))
+            decisions += pos.size * b.n_moves
+            if same.any():
+                assert rel_err(l1[pos][same], rl[same]).max() <= 1e-6, (r, t)
+    return flips, decisions
+
+
+def test_batched_fp32_runs_replayed_by_oracle(smc, ctx):
+    """Six uneven FP32 runs with two moves per step, one graph replay per step:
+    replaying the whole batch gives the same results, and every step of every
+    run, taken by the oracle from the GPU's state before it, gives the GPU's
+    evidence increment, log-weights and decision, and its population except
+    FP32 near-tie accept flips (at most one per thousand decisions)."""
+    announce("batched fp32 two moves, replay mode")
     datas, Ns, seeds = _batch_inputs()
     betas = beta_schedule(8, "linear")
     g = smc.Gmm.equal_weights(4, 1, 0.55)
+    om = oracle_model(g)
     b = smc.BatchSampler(ctx, g, datas, Ns, seeds, betas, 0.5, 2, ess_frac=0.5, prec="fp32")
     r1 = b.run(graph=True)
-    r2 = b.run(graph=True)
-    assert np.array_equal(r1["logZ"], r2["logZ"])
-    assert all(np.isfinite(r1["logZ"]))
+    b.init()
+    states = [_batch_state(b)]
+    for _ in range(b.T):
+        b.capture().launch()
+        states.append(_batch_state(b))
+    ctx.check(b.stream)
+    assert np.array_equal(states[-1]["stats"][:, 0], r1["logZ"])
+    flips, decisions = _replay_batched(b, states, range(b.R), datas, om, betas, 10 ** 9)
+    assert flips <= max(3, decisions // 1000), (flips, decisions)
+    print(f"batched fp32 flips {flips} of {decisions}")
+
+
+def test_batched_full_workload_fp32_replayed_by_oracle(smc, ctx):
+    """The benchmark's whole 256-run batch in FP32 (the benchmarked form),
+    three graph-replayed steps with the state kept after each. The oracle
+    replays seven runs step by step from the GPU's state: the four cheapest,
+    one with long data (N = 1024, n nearest 2e4), the largest N with the
+    shortest data and the largest N x n (moves on 512 sampled positions where
+    N x n exceeds 2e7). Increments to 1e-10 relative, log-weights to 1e-12,
+    decisions equal, flips at most one per thousand decisions, and the
+    log-likelihoods of unflipped particles to 1e-6."""
+    from workloads.configs import BATCHED, batched_runs
+    announce("batched full workload fp32, replay mode")
+    runs = batched_runs(256)
+    datas = [make_mixture_data(x.n, x.true_means, BATCHED["sigma2"], x.data_seed) for x in runs]
+    g = smc.Gmm.equal_weights(4, 1, BATCHED["sigma2"])
     om = oracle_model(g)
-    for i in range(len(Ns)):
-        ref = osmc.smc_run(datas[i], om, betas, Ns[i], 0.5, 2, seeds[i], ess_frac=0.5)
-        # same path unless an FP32 near-tie accept decision flipped
-        assert abs(r1["logZ"][i] - ref["logZ"]) <= max(1e-3, 0.5 * abs(ref["logZ"]) * 1e-2), i
+    betas = beta_schedule(BATCHED["T"], BATCHED["schedule"])
+    b = smc.BatchSampler(ctx, g, datas, [x.N for x in runs], [x.run_seed for x in runs], betas,
+                         BATCHED["step_sd"], BATCHED["n_moves"], ess_frac=BATCHED["ess_frac"],
+                         prec="fp32")
+    b.init()
+    states = [_batch_state(b)]
+    for _ in range(3):
+        b.capture().launch()
+        states.append(_batch_state(b))
+    ctx.check(b.stream)
+    order = list(np.argsort([x.N * x.n for x in runs]))
+    long_data = min((x for x in runs if x.N == 1024), key=lambda x: abs(x.n - 20000)).index
+    big_N = min((x for x in runs if x.N == 65536), key=lambda x: x.n).index
+    picked = list(dict.fromkeys(order[:4] + [long_data, big_N, order[-1]]))
+    flips, decisions = _replay_batched(b, states, picked, datas, om, betas, 2 * 10 ** 7)
+    assert flips <= max(3, decisions // 1000), (flips, decisions)
+    print(f"batched full workload fp32: runs {picked}, flips {flips} of {decisions}")

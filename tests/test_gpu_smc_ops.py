@@ -314,8 +314,17 @@ def test_launch_table_selects_slices(smc, ctx):
             ctx.set_launch_table([dict(rule, slices=129)])
         with pytest.raises(smc.SmcError):
             ctx.set_launch_table([dict(rule, N_lo=6000)])
+        # a batch rule (persistent batched move) is not a per-call rule, and
+        # its slices must divide the workgroup's 8 waves
+        ctx.set_launch_table([dict(rule, kind="batch", slices=4)])
+        batch_only = run()
+        with pytest.raises(smc.SmcError):
+            ctx.set_launch_table([dict(rule, kind="batch", slices=3)])
+        with pytest.raises(smc.SmcError):
+            ctx.set_launch_table([dict(rule, kind="batch", slices=16)])
     finally:
         ctx.set_launch_table([])
+    assert all(np.array_equal(a, b) for a, b in zip(batch_only, base))
     assert all(np.array_equal(a, b) for a, b in zip(tabled, forced))
     assert all(np.array_equal(a, b) for a, b in zip(missed, base))
     assert not np.array_equal(forced[1], base[1])          # the slicing changed the sums

@@ -206,3 +206,50 @@ def test_rwmh_prior_term_checks_catch_planted_mistakes(monkeypatch):
             mp.setattr(smc, "rwmh_log_alpha", wrong)
             for check in _PRIOR_CHECKS:
                 assert check() != [], (name, check.__name__)
+
+
+def test_sampled_step_equals_whole_step_columns():
+    """The oracle's step with moves on a sample of positions gives exactly the
+    sampled columns of the whole step (with and without resampling)."""
+    y = make_mixture_data(60, np.array([-3.0, 0.0, 3.0, 6.0]), 0.55, seed=8)
+    m = Model.equal_weights(4, 1, 0.55)
+    N = 700
+    th = smc.prior_init(m, N, seed=9)
+    l = gmm.loglik(th, y, m)
+    betas = np.array([0.0, 0.002, 0.01, 0.05])
+    sample = np.array([0, 5, 77, 300, 699, 5])
+    lw = np.zeros(N)
+    fired = []
+    for t in (1, 2, 3):
+        a = smc.smc_step(th, l, lw, y, m, betas, t, 0.5, 2, 12)
+        fired.append(a[5]["resampled"])
+        b = smc.smc_step_sampled(th, l, lw, y, m, betas, t, 0.5, 2, 12, sample)
+        assert np.array_equal(a[0][:, sample], b[0]) and np.array_equal(a[1][sample], b[1])
+        assert np.array_equal(a[2], b[2]) and a[4] == b[4]
+        assert a[5]["resampled"] == b[5]["resampled"]
+        for am, bm in zip(a[5]["accepted"], b[5]["accepted"]):
+            assert np.array_equal(am[sample], bm)
+        th, l, lw = a[0], a[1], a[2]
+    assert any(fired) and not all(fired), fired
+
+
+def test_pt_iteration_pairs_equal_whole_iteration_columns():
+    """The oracle's population-MCMC iteration restricted to sampled pairs gives
+    exactly those chains' columns of the whole iteration (move, then exchange),
+    for both partitions and the wrap pair."""
+    y = make_mixture_data(40, np.array([-3.0, 0.0, 3.0, 6.0]), 0.3025, seed=2)
+    m = Model.equal_weights(4, 1, 0.3025, prior="box", prior_a=-10.0, prior_b=10.0)
+    M = 64
+    betas = pt_betas(M, 2)
+    th = smc.prior_init(m, M, seed=5)
+    l = gmm.loglik(th, y, m)
+    for it, wrap in ((0, False), (1, False), (3, True)):
+        parity = it & 1
+        th1, l1, _ = smc.rwmh_move(th, l, y, m, betas, 1.0, 13, it, 0)
+        th1, l1, nsw = smc.pt_exchange(th1, l1, betas, parity, wrap, 13, it)
+        pairs = smc.exchange_pairs(M, parity, wrap)
+        pick = [pairs[0], pairs[len(pairs) // 2], pairs[-1]]
+        ths, ls, chains = smc.pt_iteration_pairs(th, l, y, m, betas, it, 1.0, 13, pick)
+        assert np.array_equal(ths, th1[:, chains]) and np.array_equal(ls, l1[chains])
+        assert nsw > 0
+        th, l = th1, l1
