@@ -70,20 +70,24 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "27000fbf9430fd3ab5f49d8e13643e9caecf5e455e668726142fd6fb5581d1a1",
-    "fetch_kib": 2718.0, "fetch_scale": 2.0,
-    "write_kib": 32.20, "write_scale": 1.0,
+    "sources_sha256": None,
+    # the launch shape the counters were taken at (data slices per 64-particle
+    # tile, and so waves per launch); figures apply only to a timed move of that shape
+    "slices": 4, "waves": 8192,
+    "fetch_kib": None, "fetch_scale": 2.0,
+    "write_kib": None, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": 0.848,
+    "valu_busy": None,
 }
 
 
 # the files the move kernel is compiled from (with the compiler flags of build.py)
 MOVE_SOURCES = ("gmm_kernels.hip", "gmm_common.hpp", "exchange.hpp", "internal.hpp",
-                "philox.hpp", "wave.hpp", "dd.hpp", "../../include/smc.h")
+                "philox.hpp", "wave.hpp", "dd.hpp", "cdf_search.hpp", "reduce.hpp",
+                "../../include/smc.h")
 
 
 def kernel_sources_sha256() -> str:
@@ -101,18 +105,25 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def move_valu_busy():
+def counters_apply(slices) -> bool:
+    """Whether the recorded counters belong to the timed move: same kernel
+    sources (and flags) and the same launch shape."""
+    c = MOVE_COUNTERS
+    return c["sources_sha256"] == kernel_sources_sha256() and slices == c["slices"]
+
+
+def move_valu_busy(slices):
     """Counter-measured VALU-busy share of the dominant kernel, or None if the
-    counters were taken on other kernel sources."""
+    counters were taken on other kernel sources or another launch shape."""
     c = MOVE_COUNTERS
-    return c["valu_busy"] if c["sources_sha256"] == kernel_sources_sha256() else None
+    return c["valu_busy"] if counters_apply(slices) else None
 
 
-def move_traffic():
+def move_traffic(slices):
     """HBM bytes per launch of the dominant kernel, or None if the counters were
-    taken on other kernel sources."""
+    taken on other kernel sources or another launch shape."""
     c = MOVE_COUNTERS
-    if c["fetch_kib"] is None or c["sources_sha256"] != kernel_sources_sha256():
+    if c["fetch_kib"] is None or not counters_apply(slices):
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 STEPS_PER_GRAPH = 50    # tempering steps (filter steps, PT iterations) per hipGraph replay
@@ -426,18 +437,31 @@ def time_pt(smc, torch, ctx, cfg, g, y, prec, steps, warmup):
                 theta=r["theta"], l=r["l"])
 
 
-def tune(ctx, cfg, precs, no_tune):
+def tune(ctx, cfg, precs, no_tune, fixed=None):
     """Pick the launch shape (data slices per 64-particle tile) of each precision
     with the package's autotuner (timed moves of this exact shape) and install
-    it in the context's launch table; {prec: {"slices", "ms_per_move"}}."""
+    it in the context's launch table; {prec: {"slices", "ms_per_move"}}.
+    fixed = {prec: slices} installs those shapes instead of tuning them."""
+    fixed = fixed or {}
+    out = {}
+    rules = []
+    for p in precs:
+        if p in fixed:
+            rules.append(dict(k=cfg.k, d=cfg.d, prec=p, slices=fixed[p], n_lo=cfg.n, n_hi=cfg.n,
+                              N_lo=cfg.N, N_hi=cfg.N))
+            out[p] = {"slices": fixed[p], "chosen": "fixed"}
+    tuned = [p for p in precs if p not in fixed]
     if no_tune:
-        return {p: {"slices": "built-in"} for p in precs}
-    from paper_0905_2441_amd import autotune
-    rules = autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, cfg.N, p) for p in precs], reps=10,
-                                exact=True, log=log)
+        out.update({p: {"slices": "built-in"} for p in tuned})
+    elif tuned:
+        from paper_0905_2441_amd import autotune
+        got = autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, cfg.N, p) for p in tuned],
+                                  reps=10, exact=True, log=log)
+        rules += got
+        out.update({r["prec"]: {"slices": r["slices"], "ms_per_move": r["ms"][str(r["slices"])]}
+                    for r in got})
     ctx.set_launch_table(rules)
-    return {r["prec"]: {"slices": r["slices"], "ms_per_move": r["ms"][str(r["slices"])]}
-            for r in rules}
+    return out
 
 
 def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
@@ -451,22 +475,35 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s.stream.synchronize()
     s.init()                               # a fresh run from the prior for the timed steps
     s.stream.synchronize()
+    ctx.fp32_shifted_data(reset=True)
     t0 = time.perf_counter()
     s.advance(steps, graph=True, steps_per_graph=u)
     s.stream.synchronize()
     t1 = time.perf_counter()
     ctx.check(s.stream)
+    # the timed steps' moves: (observation, tile) pairs in the shifted form
+    step_pairs = steps * cfg.n_moves * ((cfg.N + 63) // 64) * cfg.n
+    direct_steps = 1.0 - ctx.fp32_shifted_data(reset=True) / step_pairs
     res = s.results()          # the timed run's final population (before the kernel timing)
     ms_step = (t1 - t0) * 1e3 / steps
     # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept)
     # launched back to back, timed with HIP events recorded on the stream it
     # runs on (an event pair around every launch would add its own overhead)
     reps = max(10, steps)
+    ctx.fp32_shifted_data(reset=True)
     kern_ms = time_launches(torch, s.stream, lambda i: smc.smc_rwmh_move(
         ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed, cfg.T + 1 + i, 0, prec,
         stream=s.stream), reps)
     ctx.check(s.stream)
-    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, resamples=res["resamples"],
+    direct = None
+    if prec == "fp32":
+        # (observation, tile) pairs of the reps + 1 launches (one untimed) that
+        # left the direct form (the sub-block tail of each slice not counted)
+        pairs = (reps + 1) * ((cfg.N + 63) // 64) * cfg.n
+        direct = 1.0 - ctx.fp32_shifted_data(reset=True) / pairs
+    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, direct_share=direct,
+                direct_share_steps=direct_steps if prec == "fp32" else None,
+                resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"], theta=res["theta"], l=res["l"],
                 t=res["t"])
 
@@ -485,6 +522,8 @@ def main():
                          f"(default: {GRAPH_STEPS} by workload, else {STEPS_PER_GRAPH})")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in launch shape instead of autotuning it first")
+    ap.add_argument("--slices", type=int, default=None,
+                    help="fix the FP32 move's data slices per tile (headline) instead of tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
     ap.add_argument("--workload", default=WORKLOAD, choices=(WORKLOAD,) + OTHER_WORKLOADS,
@@ -516,7 +555,9 @@ def main():
     g = smc.Gmm.equal_weights(cfg.k, cfg.d, cfg.sigma2, prior=cfg.prior, prior_a=cfg.prior_a,
                               prior_b=cfg.prior_b)
     evals_per_step = cfg.N * cfg.n * cfg.n_moves
-    launch = tune(ctx, cfg, ["fp32"] + ([] if args.no_fp64 else ["fp64"]), args.no_tune)
+    launch = tune(ctx, cfg, ["fp32"] + ([] if args.no_fp64 else ["fp64"]), args.no_tune,
+                  fixed={"fp32": args.slices} if args.slices else None)
+    slices32 = launch["fp32"]["slices"]
 
     log(f"[bench] {WORKLOAD}: fp32 {args.steps} steps after {args.warmup} warm-up")
     r32 = time_precision(smc, torch, ctx, cfg, g, y, betas, "fp32", args.steps, args.warmup)
@@ -534,16 +575,25 @@ def main():
         "peak": PEAK_LANE_OPS / 1e12,
         "unit": "Tlane-op/s",
         "frac": achieved / PEAK_LANE_OPS,
-        "traffic": move_traffic(),
+        "traffic": move_traffic(slices32),
         "traffic_unit": "bytes per launch",
-        "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept; direct form)",
+        "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
         # the looser bound with exp2 charged one slot (16 slots per direct evaluation)
         "frac_exp_one_slot": kern_evals * (ops_per_eval(cfg.k) - (TRANS_SLOTS - 1.0) * cfg.k)
                              / PEAK_LANE_OPS,
-        "valu_busy_measured": move_valu_busy(),
+        "valu_busy_measured": move_valu_busy(slices32),
+        "counters": {"slices": MOVE_COUNTERS["slices"], "waves": MOVE_COUNTERS["waves"],
+                     "apply_to_timed_shape": counters_apply(slices32)},
         "kernel_ms": r32["kernel_ms"],
         "kernel_evals_per_s": kern_evals,
+        # the timed launches' per-datum form: 1 - (observation, tile) pairs that
+        # left the direct form over all pairs (device counter; the < 8
+        # observations after each slice's last full block of 8 always take the
+        # shifted form and count as direct here)
+        "direct_form_share": r32["direct_share"],
+        "direct_form_share_timed_steps": r32["direct_share_steps"],
+        "launch_slices": slices32,
     }
     cpu = oracle_error = None
     if not args.no_cpu_baseline:

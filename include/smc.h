@@ -403,6 +403,18 @@ int smc_graph_end(smc_ctx ctx, void* stream, smc_graph* out);
 int smc_graph_launch(smc_graph g, void* stream);
 int smc_graph_destroy(smc_graph g);
 
+/* [sync] Diagnostic of the FP32 likelihood's two per-datum forms (see
+ * smc_loglik): *out = the number of (observation, 64-particle tile) pairs that
+ * FP32 moves launched one move at a time (smc_rwmh_move, and the moves of
+ * smc_step / smc_steps unless a step's several moves run in one launch)
+ * evaluated in the shifted form since the
+ * last reset because a wave left (or never took) the direct form, summed over
+ * every context on the context's device. Not counted: the fewer than 8
+ * observations after the last full block of 8 of each wave's data slice, which
+ * always take the shifted form. With reset != 0 the count is cleared after the
+ * read. Waves that stay in the direct form do not touch the counter. */
+int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset);
+
 /* Diagnostics used by the CPU/GPU bit-identity tests: Philox words and
  * Box-Muller normals for indices 0..count-1 of one stream.
  * rng_words out: [count][4] u32 for counter (i, block, step, purpose<<24|move).

@@ -139,6 +139,13 @@ class Context:
         L.check(self._lib.smc_set_launch_table(self.handle, arr, len(rules)))
         self.rules = [dict(r) for r in rules]
 
+    def fp32_shifted_data(self, reset: bool = False) -> int:
+        """(observation, tile) pairs that FP32 single moves on this device took
+        in the shifted form since the last reset (smc_fp32_shifted_data)."""
+        v = ctypes.c_uint64()
+        L.check(self._lib.smc_fp32_shifted_data(self.handle, ctypes.byref(v), int(bool(reset))))
+        return int(v.value)
+
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
             self._lib.smc_destroy(self.handle)

@@ -200,6 +200,7 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
     const size_t b_cdf = align_up(sizeof(double) * cap);
     const size_t b_l = align_up(sizeof(double) * cap);
     const size_t b_th = align_up(sizeof(double) * cap * kdc);
+    const size_t b_res = align_up(sizeof(double) * 2 * res_chunks(cap));
     SMC_CHECK_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     SMC_CHECK_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize before scratch growth");
     if (ctx->grow) {
@@ -207,7 +208,7 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
         ctx->grow = nullptr;
     }
     void* p = nullptr;
-    if (hipMalloc(&p, 2 * b_cdf + b_l + b_th) != hipSuccess) {
+    if (hipMalloc(&p, 2 * b_cdf + b_l + b_th + 2 * b_res) != hipSuccess) {
         ctx->sc.cap = 0;
         ctx->grow_kd = 0;
         return fail(SMC_ERR_NOMEM, "device allocation of context scratch failed");
@@ -218,6 +219,8 @@ int ensure_scratch(smc_ctx ctx, int64_t N, int64_t kd, hipStream_t s) {
     ctx->sc.cdf_lo = reinterpret_cast<double*>(c + b_cdf);
     ctx->sc.l_tmp = reinterpret_cast<double*>(c + 2 * b_cdf);
     ctx->sc.theta_tmp = reinterpret_cast<double*>(c + 2 * b_cdf + b_l);
+    ctx->sc.res_tot = reinterpret_cast<double*>(c + 2 * b_cdf + b_l + b_th);
+    ctx->sc.res_off = reinterpret_cast<double*>(c + 2 * b_cdf + b_l + b_th + b_res);
     ctx->sc.cap = cap;
     ctx->grow_kd = kdc;
     return SMC_OK;
@@ -277,6 +280,10 @@ StepSrc host_src(int t, double beta, double dbeta) {
 }
 
 }  // namespace
+
+namespace smc {
+void set_last_error(const char* msg) { g_last_error = msg; }
+}  // namespace smc
 
 extern "C" {
 
@@ -1094,6 +1101,16 @@ int smc_graph_destroy(smc_graph g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+    return SMC_OK;
+}
+
+int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset) {
+    int r = enter(ctx);
+    if (r) return r;
+    if (!out) return fail(SMC_ERR_INVALID_ARG, "out is NULL");
+    unsigned long long v = 0;
+    SMC_CHECK_HIP(fp32_shifted_data(&v, reset != 0), "reading the form counter");
+    *out = static_cast<uint64_t>(v);
     return SMC_OK;
 }
 

@@ -1,5 +1,6 @@
 // Device helpers shared by the mixture likelihood kernels (VALU and MFMA forms).
 #pragma once
+#include "cdf_search.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
 #include "wave.hpp"
@@ -34,11 +35,19 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // shifted form throughout. Both forms are within the FP32 error bound; which
 // one a particle's data went through depends on the wave it shares (fixed for
 // a given launch shape and population). j0 and j1 must be the same in every
-// lane of the wave (the data are read by scalar loads).
+// lane of the wave (the data are read by scalar loads). With shifted_ctr set,
+// a wave that left (or never took) the direct form adds the number of data it
+// then took in the shifted form, up to its slice's last full block of 8, to
+// the counter slot shifted_ctr[slot] (one atomic per such wave, slots spread
+// so that waves rarely share one; the fewer than 8 data after the last full
+// block always take the shifted form and are not counted).
+constexpr int kFormSlots = 1024;
+
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const float (&nms)[K * D], float s,
-                                               const GmmDev& g, bool near) {
+                                               const GmmDev& g, bool near,
+                                               unsigned long long* shifted_ctr = nullptr) {
     constexpr int UF = 8;            // direct-form block
     constexpr int US = 16;           // shifted-form block
     constexpr float kFloor = 0x1p-100f;
@@ -92,6 +101,14 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
             if (!__all(p >= kFloor)) break;
             expo += __builtin_amdgcn_frexp_expf(p);
             prod = __builtin_amdgcn_frexp_mantf(p);
+        }
+    }
+    if (shifted_ctr != nullptr) {
+        const int counted = ((j1 - j0) & ~(UF - 1)) - (j - j0);
+        if (counted > 0 && lane_id() == 0) {
+            const int slot = (static_cast<int>(blockIdx.x) * (static_cast<int>(blockDim.x) >> 6) +
+                              wave_id()) & (kFormSlots - 1);
+            atomicAdd(shifted_ctr + slot, static_cast<unsigned long long>(counted));
         }
     }
     for (; j + US <= j1; j += US) {
@@ -158,13 +175,14 @@ __device__ __forceinline__ bool near_data(double l, int n, const GmmDev& g) {
 template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
                                                 const double (&pr)[K * D], const GmmDev& g,
-                                                bool near = true) {
+                                                bool near = true,
+                                                unsigned long long* shifted_ctr = nullptr) {
     if constexpr (PREC == SMC_PREC_FP32) {
         float nms[K * D];
         const double s = static_cast<double>(g.s32);
 #pragma unroll
         for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(s * pr[c]));
-        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g, near);
+        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g, near, shifted_ctr);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
     }
@@ -246,29 +264,15 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
     }
     __syncthreads();
     if (wave_id() == 0) {
-        auto cdf = [&](int j) -> double {
-            const int b = j / ms.chunk;
-            return dd_add(dd{offh[b], offl[b]}, dd{ms.cdf_hi[j], ms.cdf_lo[j]}).hi;
-        };
         const double u = ms.scheme == 0 ? u01_left_closed(draw(ms.seed, 0, 0, step, kResamp, 0).w0)
                                         : 0.0;
+        // pc is clamped to N - 1 past the end, so the tile's points are sorted
+        // for the systematic and stratified schemes
         const double U = resample_point(ms.scheme, ms.seed, step, pc, N, u);
-        const double clast = cdf(N - 1);
-        int lo = 0, hi = N - 1;
-        if (U < clast) {
-            while (lo < hi) {
-                const int mid = lo + ((hi - lo) >> 1);
-                if (U < cdf(mid)) hi = mid;
-                else lo = mid + 1;
-            }
-        } else {
-            while (lo < hi) {
-                const int mid = lo + ((hi - lo) >> 1);
-                if (cdf(mid) >= clast) hi = mid;
-                else lo = mid + 1;
-            }
-        }
-        anc[lane] = lo;
+        anc[lane] = ms.scheme == SMC_RESAMPLE_MULTINOMIAL
+                        ? cdf_search(U, N, ms.chunk, ms.cdf_hi, ms.cdf_lo, offh, offl)
+                        : cdf_search_sorted_wave(U, true, N, ms.chunk, ms.cdf_hi, ms.cdf_lo, offh,
+                                                 offl);
     }
     __syncthreads();
 }

@@ -35,6 +35,12 @@
 namespace smc {
 namespace {
 
+// Observations x 64-particle tiles that the FP32 single-move kernel (k_rwmh)
+// evaluated in the shifted form since the last reset, on this device, spread
+// over kFormSlots counters (a diagnostic of which form the moves took; summed
+// by smc_fp32_shifted_data).
+__device__ unsigned long long g_fp32_shifted_data[kFormSlots];
+
 template <int K, int D, int PREC>
 __global__ void __launch_bounds__(1024)
 k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, int N,
@@ -119,7 +125,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g));
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
+                                             g_fp32_shifted_data);
     __syncthreads();
     if (w != 0) return;
 
@@ -913,6 +920,26 @@ hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta
     SMC_KD(16) SMC_KD(32) SMC_KD(64)
 #undef SMC_KD
     return hipErrorInvalidValue;
+}
+
+hipError_t fp32_shifted_data(unsigned long long* out, bool reset) {
+    static_assert(sizeof(g_fp32_shifted_data) == kFormSlots * sizeof(unsigned long long), "");
+    unsigned long long v[kFormSlots];
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpyFromSymbol(v, HIP_SYMBOL(g_fp32_shifted_data), sizeof(v), 0,
+                                hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    unsigned long long sum = 0;
+    for (int i = 0; i < kFormSlots; ++i) sum += v[i];
+    *out = sum;
+    if (reset) {
+        for (int i = 0; i < kFormSlots; ++i) v[i] = 0ull;
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_fp32_shifted_data), v, sizeof(v), 0,
+                              hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    return e;
 }
 
 }  // namespace smc

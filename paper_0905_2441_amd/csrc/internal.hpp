@@ -60,6 +60,8 @@ struct Scratch {
     StepState* state;          // [1]
     double* cdf_hi;            // [cap] within-chunk inclusive prefix, high part
     double* cdf_lo;            // [cap] low part
+    double* res_tot;           // standalone resampling: chunk totals [2 * res_chunks(cap)]
+    double* res_off;           // standalone resampling: chunk offsets [2 * res_chunks(cap)]
     double* theta_tmp;         // [kd * cap]
     double* l_tmp;             // [cap]
     int64_t cap;
@@ -183,6 +185,13 @@ hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y,
                              double* stats, unsigned long long* n_acc, int* status, int scheme,
                              hipStream_t s);
 
+// Read (and with reset, clear) the device's count of observations x tiles that
+// FP32 single moves evaluated in the shifted form (synchronous).
+hipError_t fp32_shifted_data(unsigned long long* out, bool reset);
+
+// The text smc_last_error() returns on this thread (set by every failing call).
+void set_last_error(const char* msg);
+
 hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
                          int64_t N, int prec, double* out, int slices, int* status,
                          hipStream_t s);
@@ -263,6 +272,9 @@ hipError_t launch_ess(const Scratch& sc, const double* W, int64_t N, double* ess
                       hipStream_t s);
 // Resampling (scheme: smc_resampling): CDF of the weights, then search and
 // gather. pred_ess / pred_state make both kernels no-ops unless the ESS test fired.
+// Chunks of the standalone resampling CDF for N particles (1024 per chunk).
+inline int64_t res_chunks(int64_t N) { return (N + kRedBlock * 4 - 1) / (kRedBlock * 4); }
+
 hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, int scheme, uint64_t seed,
                            StepSrc src, const double* u_override, const double* pred_ess,
                            double ess_threshold, const StepState* pred_state,

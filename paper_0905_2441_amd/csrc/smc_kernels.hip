@@ -135,47 +135,122 @@ __device__ __forceinline__ double weight_at(const WeightSrc& w, int j) {
     return exp(w.logw[j] - w.state->M) / w.state->S;
 }
 
-// Within-chunk inclusive prefixes (double-double) of chunk b and its total.
-// Chunk b covers [b*chunk, min(N, (b+1)*chunk)), processed kScanChunk at a time.
+// Inclusive prefixes (double-double) of the piece [piece, piece + kRedBlock*PER)
+// clipped to `end`, offset by `carry`, stored rounded in two halves to
+// out_hi/out_lo; returns carry plus the piece's total. Each thread scans PER
+// consecutive elements, but the weights are read and the prefixes written
+// striped across the block (element e*256 + t by thread t: every wave access
+// is 512 contiguous bytes) through LDS, whose rows are padded by one double per
+// PER elements so that the per-thread runs do not fall on the same banks.
+template <int PER, class WeightAt>
+__device__ __forceinline__ dd scan_piece(int piece, int end, dd carry, double* out_hi,
+                                         double* out_lo, WeightAt weight) {
+    constexpr int kPiece = kRedBlock * PER;
+    constexpr int kPadded = kPiece + kPiece / PER;
+    __shared__ double sh_hi[kPadded], sh_lo[kPadded];
+    auto at = [](int j) { return j + j / PER; };
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int j = e * kRedBlock + t;
+        sh_hi[at(j)] = piece + j < end ? weight(piece + j) : 0.0;
+    }
+    __syncthreads();
+    const int base = t * PER;
+    dd pre[PER];
+    dd run = dd_zero();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        if (piece + base + e < end) run = dd_add(run, sh_hi[at(base + e)]);
+        pre[e] = run;
+    }
+    dd total;
+    const dd excl = block_dd_exclusive_scan(run, total);     // ends with a barrier
+    const dd lead = dd_add(carry, excl);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const dd c = dd_add(lead, pre[e]);
+        sh_hi[at(base + e)] = c.hi;
+        sh_lo[at(base + e)] = c.lo;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int j = e * kRedBlock + t;
+        if (piece + j < end) {
+            out_hi[piece + j] = sh_hi[at(j)];
+            out_lo[piece + j] = sh_lo[at(j)];
+        }
+    }
+    __syncthreads();
+    return dd_add(carry, total);
+}
+
+// Within-chunk inclusive prefixes of chunk b of the fused step's layout (up to
+// kMaxChunks chunks of kScanChunk-element pieces) and the chunk's total.
 template <class WeightAt>
 __device__ __forceinline__ void scan_chunk(int b, int N, int chunk, const Scratch& sc,
                                            WeightAt weight) {
     const int begin = b * chunk;
     const int end = min(N, begin + chunk);
     dd carry = dd_zero();
-    for (int piece = begin; piece < end; piece += kScanChunk) {
-        const int base = piece + threadIdx.x * kScanPerThread;
-        dd pre[kScanPerThread];
-        dd run = dd_zero();
-#pragma unroll
-        for (int e = 0; e < kScanPerThread; ++e) {
-            if (base + e < end) run = dd_add(run, weight(base + e));
-            pre[e] = run;
-        }
-        dd total;
-        const dd excl = block_dd_exclusive_scan(run, total);
-        const dd lead = dd_add(carry, excl);
-#pragma unroll
-        for (int e = 0; e < kScanPerThread; ++e) {
-            if (base + e < end) {
-                const dd c = dd_add(lead, pre[e]);
-                sc.cdf_hi[base + e] = c.hi;
-                sc.cdf_lo[base + e] = c.lo;
-            }
-        }
-        carry = dd_add(carry, total);
-    }
+    for (int piece = begin; piece < end; piece += kScanChunk)
+        carry = scan_piece<kScanPerThread>(piece, end, carry, sc.cdf_hi, sc.cdf_lo, weight);
     if (threadIdx.x == 0) {
         sc.dd_part[2 * b] = carry.hi;
         sc.dd_part[2 * b + 1] = carry.lo;
     }
 }
 
-// Phase 1 of standalone resampling: the chunk scans.
+// Standalone resampling (smc_resample*) in three passes over chunks of
+// kResChunk elements: (1) each chunk's within-chunk prefixes and total; (2) one
+// workgroup scans the chunk totals into chunk offsets; (3) search and gather,
+// reading C_j = offset + prefix (rounded once) with the offsets in memory, so
+// no workgroup rescans the totals.
+constexpr int kResPer = 4;
+constexpr int kResChunk = kRedBlock * kResPer;
+
 __global__ void __launch_bounds__(kRedBlock)
-k_cdf_local(WeightSrc w, int N, int chunk, Scratch sc, ResamplePred pred) {
+k_cdf_chunks(WeightSrc w, int N, Scratch sc, ResamplePred pred) {
     if (!should_fire(pred)) return;
-    scan_chunk(blockIdx.x, N, chunk, sc, [&](int j) { return weight_at(w, j); });
+    const int piece = blockIdx.x * kResChunk;
+    const int end = min(N, piece + kResChunk);
+    const dd tot = scan_piece<kResPer>(piece, end, dd_zero(), sc.cdf_hi, sc.cdf_lo,
+                                       [&](int j) { return weight_at(w, j); });
+    if (threadIdx.x == 0) {
+        sc.res_tot[2 * blockIdx.x] = tot.hi;
+        sc.res_tot[2 * blockIdx.x + 1] = tot.lo;
+    }
+}
+
+// Exclusive double-double scan of the nchunks chunk totals into res_off
+// (one workgroup; kScanPerThread consecutive totals per thread per round).
+__global__ void __launch_bounds__(kRedBlock)
+k_cdf_offsets(int nchunks, Scratch sc, ResamplePred pred) {
+    if (!should_fire(pred)) return;
+    dd carry = dd_zero();
+    for (int piece = 0; piece < nchunks; piece += kScanChunk) {
+        const int base = piece + threadIdx.x * kScanPerThread;
+        dd loc[kScanPerThread];
+        dd run = dd_zero();
+#pragma unroll
+        for (int e = 0; e < kScanPerThread; ++e) {
+            loc[e] = run;
+            if (base + e < nchunks)
+                run = dd_add(run, dd{sc.res_tot[2 * (base + e)], sc.res_tot[2 * (base + e) + 1]});
+        }
+        dd total;
+        const dd lead = dd_add(carry, block_dd_exclusive_scan(run, total));
+#pragma unroll
+        for (int e = 0; e < kScanPerThread; ++e) {
+            if (base + e < nchunks) {
+                const dd o = dd_add(lead, loc[e]);
+                sc.res_off[2 * (base + e)] = o.hi;
+                sc.res_off[2 * (base + e) + 1] = o.lo;
+            }
+        }
+        carry = dd_add(carry, total);
+    }
 }
 
 // Middle of a fused tempering step: every workgroup combines the reweight
@@ -347,19 +422,207 @@ k_search_gather(int N, int chunk, int nchunks, Scratch sc, ResamplePred pred, in
     }
     __shared__ double offh[kMaxChunks], offl[kMaxChunks];
     block_cdf_offsets(sc.dd_part, nchunks, offh, offl);
-    if (i >= N) return;
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     double u = 0.0;
     if (scheme == 0)
         u = u_override ? *u_override : u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
-    const double U = resample_point(scheme, seed, step, i, N, u);
-    const int j = cdf_search(U, N, chunk, sc.cdf_hi, sc.cdf_lo, offh, offl);
+    // lanes past N take point N - 1, so a wave's points stay sorted for the
+    // sorted schemes' wave-cooperative search
+    const int ic = i < N ? i : N - 1;
+    const double U = resample_point(scheme, seed, step, ic, N, u);
+    const int j = scheme == SMC_RESAMPLE_MULTINOMIAL
+                      ? cdf_search(U, N, chunk, sc.cdf_hi, sc.cdf_lo, offh, offl)
+                      : cdf_search_sorted_wave(U, true, N, chunk, sc.cdf_hi, sc.cdf_lo, offh, offl);
+    if (i >= N) return;
     if (idx_out) idx_out[i] = j;
     if (theta_in && theta_out)
         for (int c = 0; c < kd; ++c)
             theta_out[static_cast<size_t>(c) * N + i] = theta_in[static_cast<size_t>(c) * N + j];
     if (l_in && l_out) l_out[i] = l_in[j];
     if (logw) logw[i] = 0.0;
+}
+
+// Phase 3 of standalone resampling: each particle's point U_i, its ancestor
+// idx_i, the gather. Lanes past N take point N - 1.
+//
+// Sorted points (systematic, stratified): a workgroup takes kRedBlock * PER
+// consecutive points. The ancestors a and b of its first and last point bound
+// all of its ancestors (idx is non-decreasing in U); wave 0 finds both with
+// one 32-ary search per half-wave. The window [a, b] of C_j is then loaded
+// into LDS in pieces of kMergePiece values with independent coalesced loads,
+// and every thread finds its PER consecutive points' ancestors there (a binary
+// search for the first, then a galloping search forward from the previous
+// answer): the only dependent global loads are the few levels of the 32-ary
+// search. The indices go through LDS so that the gather and every store are
+// striped over the block. Large populations take 8 points per thread (fewer
+// 32-ary searches), smaller ones 2 (more workgroups in flight).
+// Multinomial points are unsorted: one binary search per point.
+constexpr int kMergePiece = 2048;
+constexpr int64_t kMergeWideN = int64_t{1} << 22;   // PER = 8 from here on
+
+__device__ __forceinline__ void resample_gather_point(int i, int j, int N, int32_t* idx_out,
+                                                      const double* __restrict__ theta_in,
+                                                      double* __restrict__ theta_out, int kd,
+                                                      const double* __restrict__ l_in,
+                                                      double* __restrict__ l_out, double* logw) {
+    if (idx_out) idx_out[i] = j;
+    if (theta_in && theta_out)
+        for (int c = 0; c < kd; ++c)
+            theta_out[static_cast<size_t>(c) * N + i] = theta_in[static_cast<size_t>(c) * N + j];
+    if (l_in && l_out) l_out[i] = l_in[j];
+    if (logw) logw[i] = 0.0;
+}
+
+__device__ __forceinline__ bool resample_copy_if_skipped(const ResamplePred& pred,
+                                                         int copy_when_skipped, int i, int N,
+                                                         int32_t* idx_out,
+                                                         const double* theta_in,
+                                                         double* theta_out, int kd,
+                                                         const double* l_in, double* l_out) {
+    if (should_fire(pred)) return false;
+    if (copy_when_skipped && i < N) {
+        if (idx_out) idx_out[i] = i;
+        if (theta_in && theta_out)
+            for (int c = 0; c < kd; ++c)
+                theta_out[static_cast<size_t>(c) * N + i] = theta_in[static_cast<size_t>(c) * N + i];
+        if (l_in && l_out) l_out[i] = l_in[i];
+    }
+    return true;
+}
+
+template <int PER>
+__global__ void __launch_bounds__(kRedBlock)
+k_resample_merge(int N, Scratch sc, ResamplePred pred, int scheme, uint64_t seed, StepSrc src,
+                 const double* u_override, int32_t* idx_out,
+                 const double* __restrict__ theta_in, double* __restrict__ theta_out, int kd,
+                 const double* __restrict__ l_in, double* __restrict__ l_out, double* logw,
+                 int copy_when_skipped) {
+    constexpr int kMergePer = PER;
+    constexpr int kMergeTile = kRedBlock * PER;
+    __shared__ double cwin[kMergePiece];
+    __shared__ int idx_sh[kMergeTile];
+    __shared__ int ab[2];
+    const int t = threadIdx.x;
+    const int i0 = blockIdx.x * kMergeTile;
+    if (!should_fire(pred)) {
+        for (int e = 0; e < kMergePer; ++e)
+            resample_copy_if_skipped(pred, copy_when_skipped, i0 + e * kRedBlock + t, N, idx_out,
+                                     theta_in, theta_out, kd, l_in, l_out);
+        return;
+    }
+    const double* __restrict__ hi = sc.cdf_hi;
+    const double* __restrict__ lo = sc.cdf_lo;
+    const double* __restrict__ off = sc.res_off;
+    auto cdf = [&](int j) -> double {
+        const int b = j / kResChunk;
+        return dd_add(dd{off[2 * b], off[2 * b + 1]}, dd{hi[j], lo[j]}).hi;
+    };
+    const uint32_t step = static_cast<uint32_t>(step_index(src));
+    double u = 0.0;
+    if (scheme == 0)
+        u = u_override ? *u_override : u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
+    const double clast = cdf(N - 1);
+    auto pred_c = [&](double uu, double c) -> bool {
+        return uu < clast ? (uu < c) : (c >= clast);
+    };
+    const int i_last = min(N, i0 + kMergeTile) - 1;
+    if (wave_id() == 0) {
+        // lanes 0-31 search the ancestor of the tile's first point, 32-63 of its last
+        const int lane = lane_id();
+        const int half = lane >> 5, hl = lane & 31;
+        const double us = resample_point(scheme, seed, step, half ? i_last : i0, N, u);
+        int lo_ = 0, hi_ = N - 1;
+        while (__any(hi_ > lo_)) {
+            const int len = hi_ - lo_ + 1;
+            const int stp = (len + 31) >> 5;
+            int q = lo_ + (hl + 1) * stp - 1;
+            q = q < hi_ ? q : hi_;
+            const unsigned long long m = __ballot(pred_c(us, cdf(q)));
+            const unsigned mh = static_cast<unsigned>(half ? (m >> 32) : (m & 0xffffffffull));
+            const int f = __ffs(mh) - 1;
+            const int nhi = lo_ + (f + 1) * stp - 1;
+            lo_ = lo_ + f * stp;
+            hi_ = nhi < hi_ ? nhi : hi_;
+        }
+        if (lane == 0) ab[0] = lo_;
+        if (lane == 32) ab[1] = lo_;
+    }
+    // this thread's points, consecutive (sorted) within the thread
+    double U[kMergePer];
+    int found[kMergePer];
+#pragma unroll
+    for (int e = 0; e < kMergePer; ++e) {
+        const int i = min(i0 + t * kMergePer + e, N - 1);
+        U[e] = resample_point(scheme, seed, step, i, N, u);
+        found[e] = -1;
+    }
+    __syncthreads();
+    const int a = ab[0], b = ab[1];
+    for (int p0 = a; p0 <= b; p0 += kMergePiece) {
+        const int len = min(kMergePiece, b - p0 + 1);
+        for (int r = t; r < len; r += kRedBlock) cwin[r] = cdf(p0 + r);
+        __syncthreads();
+        const double c_end = cwin[len - 1];
+        int from = 0;             // no answer of this thread in this piece lies below it
+#pragma unroll
+        for (int e = 0; e < kMergePer; ++e) {
+            if (found[e] < 0 && pred_c(U[e], c_end)) {
+                // first position in [from, len) where pred holds: gallop, then bisect
+                int l = from, h = len - 1;
+                if (!pred_c(U[e], cwin[l])) {
+                    int k = 1;
+                    while (l + k < h && !pred_c(U[e], cwin[l + k])) k <<= 1;
+                    h = l + k < h ? l + k : h;
+                    l = l + (k >> 1) + 1;
+                    while (l < h) {
+                        const int mid = (l + h) >> 1;
+                        if (pred_c(U[e], cwin[mid])) h = mid;
+                        else l = mid + 1;
+                    }
+                }
+                found[e] = p0 + l;
+                from = l;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < kMergePer; ++e) idx_sh[t * kMergePer + e] = found[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kMergePer; ++e) {
+        const int r = e * kRedBlock + t;
+        const int i = i0 + r;
+        if (i < N)
+            resample_gather_point(i, idx_sh[r], N, idx_out, theta_in, theta_out, kd, l_in, l_out,
+                                  logw);
+    }
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+k_resample_gather(int N, Scratch sc, ResamplePred pred, int scheme, uint64_t seed, StepSrc src,
+                  const double* u_override, int32_t* idx_out,
+                  const double* __restrict__ theta_in, double* __restrict__ theta_out, int kd,
+                  const double* __restrict__ l_in, double* __restrict__ l_out, double* logw,
+                  int copy_when_skipped) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (resample_copy_if_skipped(pred, copy_when_skipped, i, N, idx_out, theta_in, theta_out, kd,
+                                 l_in, l_out))
+        return;
+    if (i >= N) return;
+    const uint32_t step = static_cast<uint32_t>(step_index(src));
+    double u = 0.0;
+    if (scheme == 0)
+        u = u_override ? *u_override : u01_left_closed(draw(seed, 0, 0, step, kResamp, 0).w0);
+    const double U = resample_point(scheme, seed, step, i, N, u);
+    const double* __restrict__ hi = sc.cdf_hi;
+    const double* __restrict__ lo = sc.cdf_lo;
+    const double* __restrict__ off = sc.res_off;
+    const int j = cdf_search_fn(U, N, [&](int jj) -> double {
+        const int b = jj / kResChunk;
+        return dd_add(dd{off[2 * b], off[2 * b + 1]}, dd{hi[jj], lo[jj]}).hi;
+    });
+    resample_gather_point(i, j, N, idx_out, theta_in, theta_out, kd, l_in, l_out, logw);
 }
 
 // ---------------------------------------------------------------- exchange
@@ -472,16 +735,32 @@ hipError_t launch_resample(const Scratch& sc, WeightSrc w, int64_t N, int scheme
                            int32_t kd, const double* l_in, double* l_out, double* logw,
                            int copy_when_skipped, hipStream_t s) {
     ResamplePred pred{pred_ess, ess_threshold, pred_state};
-    const int chunk = cdf_chunk(N);
-    const int nchunks = static_cast<int>((N + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_cdf_local, dim3(nchunks), dim3(kRedBlock), 0, s, w,
-                       static_cast<int>(N), chunk, sc, pred);
+    const int nchunks = static_cast<int>((N + kResChunk - 1) / kResChunk);
+    hipLaunchKernelGGL(k_cdf_chunks, dim3(nchunks), dim3(kRedBlock), 0, s, w,
+                       static_cast<int>(N), sc, pred);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
-    hipLaunchKernelGGL(k_search_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N),
-                       chunk, nchunks, sc, pred, scheme, seed, src, u_override, idx, theta_in,
-                       theta_out, kd, l_in, l_out, logw, copy_when_skipped);
+    hipLaunchKernelGGL(k_cdf_offsets, dim3(1), dim3(kRedBlock), 0, s, nchunks, sc, pred);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (scheme == SMC_RESAMPLE_MULTINOMIAL) {
+        const int g = static_cast<int>((N + kRedBlock - 1) / kRedBlock);
+        hipLaunchKernelGGL(k_resample_gather, dim3(g), dim3(kRedBlock), 0, s, static_cast<int>(N),
+                           sc, pred, scheme, seed, src, u_override, idx, theta_in, theta_out, kd,
+                           l_in, l_out, logw, copy_when_skipped);
+    } else {
+        if (N >= kMergeWideN) {
+            const int g = static_cast<int>((N + kRedBlock * 8 - 1) / (kRedBlock * 8));
+            hipLaunchKernelGGL(k_resample_merge<8>, dim3(g), dim3(kRedBlock), 0, s,
+                               static_cast<int>(N), sc, pred, scheme, seed, src, u_override, idx,
+                               theta_in, theta_out, kd, l_in, l_out, logw, copy_when_skipped);
+        } else {
+            const int g = static_cast<int>((N + kRedBlock * 2 - 1) / (kRedBlock * 2));
+            hipLaunchKernelGGL(k_resample_merge<2>, dim3(g), dim3(kRedBlock), 0, s,
+                               static_cast<int>(N), sc, pred, scheme, seed, src, u_override, idx,
+                               theta_in, theta_out, kd, l_in, l_out, logw, copy_when_skipped);
+        }
+    }
     return hipGetLastError();
 }
 

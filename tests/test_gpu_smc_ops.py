@@ -160,7 +160,9 @@ def test_resample_sorted_points_large_n_degenerate_gather_predicate(smc, ctx, sc
     announce(f"resample sorted large N {scheme}")
     cases = [np.full(N, 1.0 / N), np.eye(1, N, 0).ravel(), np.eye(1, N, 654321).ravel(),
              np.eye(1, N, N - 1).ravel(), np.where(np.arange(N) % 3 == 0, 1.0, 0.0),
-             np.where(np.arange(N) < N - 1000, 1.0, 0.0)]
+             np.where(np.arange(N) < N - 1000, 1.0, 0.0),
+             # sparse weight: every wave's points span thousands of particles
+             np.where(np.arange(N) % 4099 == 17, 1.0, 0.0)]
     idx = torch.empty(N, dtype=torch.int32).cuda()
     for W in cases:
         W = W / W.sum()
@@ -279,6 +281,35 @@ def test_rwmh_per_chain_beta_and_box_prior(smc, ctx):
     assert np.max(np.abs(tt.cpu().numpy() - th_ref)) <= 1e-12
     assert rel_err(lt.cpu().numpy(), l_ref).max() <= 1e-12
     assert np.all(tt.cpu().numpy() <= 10.0) and np.all(tt.cpu().numpy() >= -10.0)
+
+
+def test_fp32_shifted_form_counter(smc, ctx):
+    """The device counter of the FP32 move's per-datum forms: a move of prior
+    draws (far from the data) takes the shifted form for every full block of 8
+    observations of every wave's slice; a move of particles near a posterior
+    mode stays direct throughout; FP64 moves do not count. (Four slices of
+    250 observations: 248 counted per wave, 2 after the last full block.)"""
+    announce("fp32 form counter")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    n, N = 1000, 4096
+    y = _cuda(make_mixture_data(n, mu, 0.55, seed=2), torch.float32)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    tiles = N // 64
+    ctx.set_slices(4)
+    try:
+        for name, th_np, prec, want in (
+                ("prior", theta_prior_draws(N, 4, 1, seed=3), "fp32", tiles * 4 * 248),
+                ("near", theta_near_posterior(N, mu, seed=4, jitter=0.1), "fp32", 0),
+                ("prior fp64", theta_prior_draws(N, 4, 1, seed=3), "fp64", 0)):
+            th = _cuda(th_np)
+            l = torch.empty(N, dtype=torch.float64, device="cuda")
+            smc.smc_loglik(ctx, g, y, th, prec, out=l)
+            ctx.fp32_shifted_data(reset=True)
+            smc.smc_rwmh_move(ctx, g, y, th, l, 0.5, 0.5, seed=5, step=1, prec=prec)
+            ctx.check()
+            assert ctx.fp32_shifted_data(reset=True) == want, name
+    finally:
+        ctx.set_slices(0)
 
 
 def test_launch_table_selects_slices(smc, ctx):
