@@ -247,6 +247,22 @@ int smc_resample(smc_ctx ctx, smc_resampling scheme, const double* W, int64_t N,
                  const double* theta_in, double* theta_out, int32_t kd, const double* l_in,
                  double* l_out, double* logw, void* stream);
 
+/* smc_resample for callers that cannot allocate device memory (code under
+ * hipGraph stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments (no context), kernels and results, but the
+ * scratch (correctly rounded CDF halves and chunk totals) lives in a fixed
+ * 16 MiB device array of the library, one per GPU, held until the process
+ * ends; the call itself allocates nothing (the array's device address is
+ * looked up once per GPU, on the first call with that GPU current). N is
+ * limited to 2^20 (larger N: SMC_ERR_INVALID_ARG, nothing enqueued). Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from several threads) race; calls in one stream order
+ * do not. Errors are reported by smc_last_error(). */
+int smc_resample_noalloc(smc_resampling scheme, const double* W, int64_t N, uint64_t seed,
+                         uint64_t step, const double* ess, double ess_threshold, int32_t* idx,
+                         const double* theta_in, double* theta_out, int32_t kd,
+                         const double* l_in, double* l_out, double* logw, void* stream);
+
 /* The scheme used by later smc_step and smc_step_batched calls on this
  * context (default SYSTEMATIC); a captured graph keeps the scheme it was
  * captured with. */

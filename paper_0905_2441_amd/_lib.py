@@ -93,6 +93,8 @@ SIGNATURES = {
     "smc_resample": (c_int, [_P, c_int, _P, c_int64, c_uint64, c_uint64, _P, c_double, _P, _P,
                              _P, c_int32, _P, _P, _P, _P]),
     "smc_set_resampling": (c_int, [_P, c_int]),
+    "smc_resample_noalloc": (c_int, [c_int, _P, c_int64, c_uint64, c_uint64, _P, c_double, _P,
+                                     _P, _P, c_int32, _P, _P, _P, _P]),
     "pt_exchange": (c_int, [_P, _P, _P, _P, c_int64, c_int32, c_int32, c_int32, c_uint64,
                             c_uint64, _P, _P]),
     "pt_iterations": (c_int, [_P, _GP, _P, c_int64, c_int64, _P, _P, _P, _P, c_int32, c_double,
