@@ -70,17 +70,19 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": None,
+    "sources_sha256": "c72c669d10dc992dd2146a60a93e181b4aef970a5a0804ddbfa549d90df98e65",
     # the launch shape the counters were taken at (data slices per 64-particle
-    # tile, and so waves per launch); figures apply only to a timed move of that shape
-    "slices": 4, "waves": 8192,
-    "fetch_kib": None, "fetch_scale": 2.0,
-    "write_kib": None, "write_scale": 1.0,
+    # tile, and so waves per launch); figures apply only to a timed move of that
+    # shape. The standalone moves run from the population after `steps` timed
+    # steps, whose acceptance rate sets the bytes written.
+    "slices": 4, "waves": 8192, "steps": 20,
+    "fetch_kib": 2719.0, "fetch_scale": 2.0,
+    "write_kib": 1351.0, "write_scale": 1.0,
     "summary": "profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_hbm_counters.txt",
     # SQ_ACTIVE_INST_VALU x 4 cycles / (1024 SIMDs x GRBM_GUI_ACTIVE / 8 XCDs) of the
     # same launches: the share of SIMD cycles the VALU pipeline was issuing
     # (profiles/k_rwmh_fp32_gmm1d_k4_n1000_N131072_valu_counters.txt)
-    "valu_busy": None,
+    "valu_busy": 0.872,
 }
 
 
@@ -119,11 +121,12 @@ def move_valu_busy(slices):
     return c["valu_busy"] if counters_apply(slices) else None
 
 
-def move_traffic(slices):
+def move_traffic(slices, steps):
     """HBM bytes per launch of the dominant kernel, or None if the counters were
-    taken on other kernel sources or another launch shape."""
+    taken on other kernel sources, another launch shape or after another number
+    of steps (another population, so another acceptance rate)."""
     c = MOVE_COUNTERS
-    if c["fetch_kib"] is None or not counters_apply(slices):
+    if c["fetch_kib"] is None or not counters_apply(slices) or steps != c["steps"]:
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 STEPS_PER_GRAPH = 50    # tempering steps (filter steps, PT iterations) per hipGraph replay
@@ -464,6 +467,39 @@ def tune(ctx, cfg, precs, no_tune, fixed=None):
     return out
 
 
+def moves_of_steps(smc, torch, ctx, cfg, g, s, betas, prec, steps):
+    """Average time (ms) of the moves of the timed steps on their own: the run is
+    taken again from the prior one step at a time, each step's input population
+    is copied before the step, and then the step's move (same temperature and
+    random streams) is launched on every copy back to back between two HIP
+    events on the sampler's stream. A step that resampled moved its ancestors
+    rather than this copy, at the same cost per particle."""
+    s.init()
+    copies = []
+    for t in range(1, steps + 1):
+        with torch.cuda.stream(s.stream):
+            copies.append((min(t, cfg.T), s.theta.clone(), s.loglik.clone()))
+        s.step(graph=False)
+    s.stream.synchronize()
+
+    def move(c):
+        t, th, l = c
+        smc.smc_rwmh_move(ctx, g, s.y, th, l, float(betas[t]), cfg.step_sd, cfg.run_seed, t, 0,
+                          prec, stream=s.stream)
+
+    move(tuple(x.clone() if hasattr(x, "clone") else x for x in copies[0]))   # warm, untimed
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for c in copies:
+        move(c)
+    e1.record(s.stream)
+    e1.synchronize()
+    ctx.check(s.stream)
+    del copies
+    return e0.elapsed_time(e1) / steps
+
+
 def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s = smc.SMCSampler(ctx, g, y, cfg.N, betas, cfg.step_sd, cfg.n_moves, cfg.run_seed,
                        ess_frac=cfg.ess_frac, prec=prec)
@@ -490,18 +526,22 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     # launched back to back, timed with HIP events recorded on the stream it
     # runs on (an event pair around every launch would add its own overhead)
     reps = max(10, steps)
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
     ctx.fp32_shifted_data(reset=True)
     kern_ms = time_launches(torch, s.stream, lambda i: smc.smc_rwmh_move(
         ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed, cfg.T + 1 + i, 0, prec,
-        stream=s.stream), reps)
+        n_accept=acc, stream=s.stream), reps)
     ctx.check(s.stream)
+    accept_rate = acc.item() / ((reps + 1) * cfg.N)
     direct = None
     if prec == "fp32":
         # (observation, tile) pairs of the reps + 1 launches (one untimed) that
         # left the direct form (the sub-block tail of each slice not counted)
         pairs = (reps + 1) * ((cfg.N + 63) // 64) * cfg.n
         direct = 1.0 - ctx.fp32_shifted_data(reset=True) / pairs
+    move_steps_ms = moves_of_steps(smc, torch, ctx, cfg, g, s, betas, prec, steps)
     return dict(ms_per_step=ms_step, kernel_ms=kern_ms, direct_share=direct,
+                accept_rate=accept_rate, move_steps_ms=move_steps_ms,
                 direct_share_steps=direct_steps if prec == "fp32" else None,
                 resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"], theta=res["theta"], l=res["l"],
@@ -575,7 +615,9 @@ def main():
         "peak": PEAK_LANE_OPS / 1e12,
         "unit": "Tlane-op/s",
         "frac": achieved / PEAK_LANE_OPS,
-        "traffic": move_traffic(slices32),
+        "traffic": move_traffic(slices32, args.steps),
+        # read theta, l (40 B) per particle, write theta, l (40 B) per accepted one
+        "traffic_algorithmic": cfg.N * 40.0 * (1.0 + r32["accept_rate"]),
         "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
@@ -591,6 +633,7 @@ def main():
         # left the direct form over all pairs (device counter; the < 8
         # observations after each slice's last full block of 8 always take the
         # shifted form and count as direct here)
+        "accept_rate": r32["accept_rate"],
         "direct_form_share": r32["direct_share"],
         "direct_form_share_timed_steps": r32["direct_share_steps"],
         "launch_slices": slices32,
@@ -626,6 +669,13 @@ def main():
         "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
         "fp32_over_fp64_speedup": (r64["ms_per_step"] / r32["ms_per_step"]) if r64 else None,
         "fp64_move_kernel_ms": r64["kernel_ms"] if r64 else None,
+        # the timed steps' moves launched alone on each step's input population,
+        # and what the step spends besides (k_step_mid, the chain's first
+        # reweight pass, launch gaps)
+        "step_split": {"ms_per_step": r32["ms_per_step"],
+                       "move_ms": r32["move_steps_ms"],
+                       "other_ms": r32["ms_per_step"] - r32["move_steps_ms"],
+                       "other_share": 1.0 - r32["move_steps_ms"] / r32["ms_per_step"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_error": oracle_error,
