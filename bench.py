@@ -139,15 +139,21 @@ PT_ITERS_PER_GRAPH = 64  # population-MCMC iterations per replay in the paper's 
 
 def ops_per_eval(k: int, form: str = "direct") -> float:
     """Algorithmic VALU issue slots of one particle x datum evaluation in the
-    FP32 form (exp2 counted as TRANS_SLOTS slots).
+    FP32 form for 1-D data, which runs in the expanded split about a data centre
+    c (exp2 counted as TRANS_SLOTS slots):
     direct (waves whose particles sit near the data, as in a population that
-    has reached the posterior): per component a distance FMA, a
-    square-and-weight FMA and one exp2; per datum k-1 adds and the product
-    update: 3k VALU + k transcendental (20 slots for k = 4; 16 with exp2 at one).
-    shifted (waves holding a particle far from the data): per component also a
-    shift subtract; per datum k-1 max and the max accumulation: 5k VALU + k
-    transcendental (28 slots for k = 4; 24 with exp2 at one)."""
-    return (3.0 if form == "direct" else 5.0) * k + TRANS_SLOTS * k
+    has reached the posterior): per component one FMA (x = C + B (y - c)) and
+    one exp2; per datum k-1 adds, the multiply by the datum's factor 2^-q and
+    the product update: 2k + 1 VALU + k transcendental (17 slots for k = 4; 13
+    with exp2 at one).
+    shifted (waves holding a particle far from the data): per component the FMA,
+    a shift subtract and the exp2; per datum the maximum (v_max3 folds two
+    comparisons), k-1 adds, the product update and the block sum of max - q:
+    3k + ceil((k-1)/2) + 2 VALU + k transcendental (24 slots for k = 4; 20 with
+    exp2 at one)."""
+    if form == "direct":
+        return 2.0 * k + 1.0 + TRANS_SLOTS * k
+    return 3.0 * k + (k // 2) + 2.0 + TRANS_SLOTS * k
 
 
 def log(msg):
@@ -621,7 +627,7 @@ def main():
         "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
-        # the looser bound with exp2 charged one slot (16 slots per direct evaluation)
+        # the looser bound with exp2 charged one slot (13 slots per direct evaluation)
         "frac_exp_one_slot": kern_evals * (ops_per_eval(cfg.k) - (TRANS_SLOTS - 1.0) * cfg.k)
                              / PEAK_LANE_OPS,
         "valu_busy_measured": move_valu_busy(slices32),

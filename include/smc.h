@@ -127,8 +127,8 @@ const char* smc_last_error(void);
  * and N <= 32768 spreads them over up to 8 workgroups per 64 particles and
  * completes in a second, per-particle kernel. Other kernels use min(slices, 16).
  * Results depend on the slicing only through the order of FP64 additions and,
- * in FP32, through which of the two equivalent per-datum forms (see
- * smc_loglik) a wave's slice takes. */
+ * in FP32, through which of the equivalent per-datum forms (see smc_loglik) a
+ * wave's slice takes and the data centre of its expanded form. */
 int smc_set_slices(smc_ctx ctx, int32_t slices);
 
 /* Which launches a rule of the launch table shapes. */
@@ -174,8 +174,13 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  * error below 1e-6). The per-datum sum is taken directly for waves whose
  * particles sit near the data (weights of total mass <= 1) and relative to its
  * largest term otherwise (those maxima added in 16-term FP32 blocks promoted to
- * FP64), both within the bound (the form depends on the wave, fixed for a given
- * launch shape and population); BF16X3: d = 8, k in
+ * FP64). For d = 1 both are evaluated in an expanded form: with c the midrange
+ * of the first 64 data of a wave's slice, the squared distance splits into a
+ * per-particle affine function of y - c (one FMA per component) and a
+ * per-datum term s^2 (y - c)^2 that the wave forms once for all its particles;
+ * data farther from c than that split's range bound go through the plain form.
+ * All forms are within the bound (the form, and for d = 1 the centre, depend on
+ * the wave, fixed for a given launch shape and population); BF16X3: d = 8, k in
  * {1,2,4,8}: the quadratic forms as one K = 64 BF16 MFMA contraction of
  * three-way (hi/mid/lo) split operands with FP32 accumulation, then the same
  * FP32 epilogue (relative error below 1e-6). */
@@ -403,7 +408,7 @@ int smc_batch_destroy(smc_batch b);
  *   counter). run_stats: device FP64 [R][4] = {log Z (accumulated), last ESS,
  *   resample count, unused}. prec: FP32 or FP64. A run's results depend on its
  *   S only through the order of its FP64 slice sums and, in FP32, through which
- *   of the two per-datum forms a wave takes (see smc_loglik). */
+ *   of the per-datum forms a wave takes and its data centre (see smc_loglik). */
 int smc_step_batched(smc_ctx ctx, smc_batch b, const smc_gmm* model, const float* y,
                      double* theta, double* loglik, double* logw, double* W, const double* beta,
                      int32_t T, int32_t* t_dev, double step_sd, int32_t n_moves, double ess_frac,
@@ -419,12 +424,12 @@ int smc_graph_end(smc_ctx ctx, void* stream, smc_graph* out);
 int smc_graph_launch(smc_graph g, void* stream);
 int smc_graph_destroy(smc_graph g);
 
-/* [sync] Diagnostic of the FP32 likelihood's two per-datum forms (see
+/* [sync] Diagnostic of the FP32 likelihood's per-datum forms (see
  * smc_loglik): *out = the number of (observation, 64-particle tile) pairs that
  * FP32 moves launched one move at a time (smc_rwmh_move, and the moves of
  * smc_step / smc_steps unless a step's several moves run in one launch)
- * evaluated in the shifted form since the
- * last reset because a wave left (or never took) the direct form, summed over
+ * evaluated in a shifted form (plain or expanded) since the last reset because
+ * a wave left (or never took) the direct forms, summed over
  * every context on the context's device. Not counted: the fewer than 8
  * observations after the last full block of 8 of each wave's data slice, which
  * always take the shifted form. With reset != 0 the count is cleared after the

@@ -20,31 +20,198 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij}, a_ij = log2 w_i - s^2 ||y_j - mu_i||^2
 // (FP32 arithmetic, FP64 result). The per-datum sums are multiplied into a
 // running product that is renormalised (frexp) after each block of data, its
-// exponents summed as integers. Two forms:
+// exponents summed as integers. Three forms:
 //  - direct (weights of total mass <= 1): e_j = sum_i 2^{a_ij}. Every factor
 //    is then <= 1, so the partial products only fall, and a block of 8 whose
 //    product ends at or above 2^-100 had no factor or partial product in the
 //    FP32 subnormal range: it is as accurate as the shifted form;
+//  - expanded direct (1-D data, for the windows of 64 data whose every datum
+//    keeps s^2 (y - c)^2 <= kExpQmax, c the midrange of the slice's first 64
+//    data): the same e_j, computed from the split a_ij = x_ij - q_j
+//    (expanded_direct below), one FMA and one exp2 per component instead of
+//    two FMAs and an exp2; the direct form takes over from the first window
+//    that does not keep it;
 //  - shifted: each datum's sum is taken relative to its largest term
 //    m_j = max_i a_ij (blocks of 16), and the m_j are added apart.
-// A wave starts in the direct form when every lane's `near` hint holds (the
+// A wave starts in a direct form when every lane's `near` hint holds (the
 // caller's guess that the particle sits near the data, from its current
 // log-likelihood) and, at the first block where any of its lanes ends below
 // 2^-100 (a particle far from these data, or a NaN), drops that block and
 // runs the rest of its slice in the shifted form; otherwise it runs the
-// shifted form throughout. Both forms are within the FP32 error bound; which
+// shifted form throughout. All forms are within the FP32 error bound; which
 // one a particle's data went through depends on the wave it shares (fixed for
 // a given launch shape and population). j0 and j1 must be the same in every
-// lane of the wave (the data are read by scalar loads). With shifted_ctr set,
-// a wave that left (or never took) the direct form adds the number of data it
-// then took in the shifted form, up to its slice's last full block of 8, to
-// the counter slot shifted_ctr[slot] (one atomic per such wave, slots spread
-// so that waves rarely share one; the fewer than 8 data after the last full
-// block always take the shifted form and are not counted).
+// lane of the wave, and every lane of the wave must take part (the data are
+// read by scalar loads, or staged by the wave's lanes in LDS). With
+// shifted_ctr set, a wave that left (or never took) the direct forms adds the
+// number of data it then took in the shifted form, up to its slice's last
+// full block of 8, to the counter slot shifted_ctr[slot] (one atomic per such
+// wave, slots spread so that waves rarely share one; the fewer than 8 data
+// after the last full block always take the shifted form and are not
+// counted).
 constexpr int kFormSlots = 1024;
+// Data staged per window of the expanded direct form (one per lane).
+constexpr int kExpWin = kWave;
+// Largest s^2 (y - c)^2 over a slice for which the expanded form runs: its
+// terms 2^{x_ij} then stay below 2^96 and its data factors above 2^-96.
+constexpr double kExpQmax = 96.0;
+
+// The expanded forms (1-D data). With c a data centre, y' = y - c (FP32) and
+// m_i = mu_i - c,
+//   a_ij = log2 w_i - s2 (y'_j - m_i)^2 = x_ij - q_j,
+//   x_ij = C_i + B_i y'_j,  B_i = 2 s2 m_i,  C_i = log2 w_i - s2 m_i^2,
+//   q_j = s2 y'_j^2,
+// and q_j does not depend on the particle: one FMA per component gives x_ij,
+// and each datum's log2 sum_i 2^{a_ij} follows from the x_ij and q_j.
+// B_i and C_i are formed in FP64 and rounded once, C_i with B_i's rounding
+// error at y' = m_i folded in, so that x_ij is exact up to its own rounding at
+// the component's centre. The wave stages its data 64 at a time, one datum per
+// lane (q in FP64), in its own row of LDS (`row`, 2 * kExpWin floats), and
+// reads them back as broadcasts; each lane fetches its datum of the next
+// window while the current one is consumed. A window holding a datum with
+// q_j > kExpQmax (or not finite) ends a form at its start: this bounds the
+// magnitude of x_ij and so its rounding error (and, in the direct form, keeps
+// 2^{x_ij} finite and g_j normal).
+template <int K>
+struct Expanded {
+    double s2;                 // s^2 = log2(e) / (2 sigma2)
+    float c;
+    float B[K], C[K];
+};
+
+// c = the midrange of the data in [j0, jlim) (at most 64 of them) and the
+// lane's B_i, C_i. False when those data are not all finite.
+template <int K>
+__device__ __forceinline__ bool expanded_setup(const float* __restrict__ y, int j0, int jlim,
+                                               const double (&mu)[K], const GmmDev& g,
+                                               Expanded<K>& f) {
+    constexpr double kLog2eD = 1.4426950408889634;
+    const int jj = j0 + lane_id();
+    const float v = jj < jlim ? y[jj] : 0.0f;
+    const float lo = wave_min(jj < jlim ? v : INFINITY);
+    const float hi = wave_max(jj < jlim ? v : -INFINITY);
+    f.s2 = g.inv2s2 * kLog2eD;
+    f.c = 0.5f * lo + 0.5f * hi;
+    if (!(fabsf(f.c) <= 3.0e38f)) return false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const double m = mu[i] - static_cast<double>(f.c);
+        const double b = 2.0 * f.s2 * m;
+        f.B[i] = static_cast<float>(b);
+        f.C[i] = static_cast<float>(g.lw[i] * kLog2eD - f.s2 * m * m +
+                                    (b - static_cast<double>(f.B[i])) * m);
+    }
+    return true;
+}
+
+// The expanded direct form over the blocks of 8 data from j to jend:
+// e_j = g_j sum_i 2^{x_ij} with g_j = 2^{-q_j} (= 2^-round(q) times the
+// hardware exp2 of the small remainder), staged as (y'_j, g_j) pairs. Updates
+// prod and expo over the blocks it took and moves j past them; returns true
+// when it stopped for the range (the caller goes on in the scalar-load direct
+// form from j), false when it took every block or a block failed the 2^-100
+// check (the caller goes on in the shifted forms).
+template <int K>
+__device__ __forceinline__ bool expanded_direct(const float* __restrict__ y, int jend,
+                                                const Expanded<K>& f, float* row, float& prod,
+                                                int& expo, int& j) {
+    constexpr float kFloor = 0x1p-100f;
+    const int lane = lane_id();
+    float ycur = j + lane < jend ? y[j + lane] : 0.0f;
+    for (int wb = j; wb < jend; wb += kExpWin) {
+        const int jj = wb + lane;
+        bool ok = true;
+        wave_sync();                          // the previous window's reads come first
+        if (jj < jend) {
+            const float yp = ycur - f.c;
+            const double q = f.s2 * static_cast<double>(yp) * static_cast<double>(yp);
+            ok = q <= kExpQmax;
+            const double qi = rint(q);
+            row[2 * lane] = yp;
+            row[2 * lane + 1] = __builtin_amdgcn_ldexpf(
+                __builtin_amdgcn_exp2f(static_cast<float>(qi - q)), -static_cast<int>(qi));
+        }
+        // the next window's datum, in flight while this window is consumed
+        ycur = jj + kExpWin < jend ? y[jj + kExpWin] : 0.0f;
+        if (!__all(ok)) return true;
+        wave_sync();                          // the window is written before it is read
+        const int we = wb + kExpWin < jend ? wb + kExpWin : jend;
+        for (; j < we; j += 8) {
+            float p = prod;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float yp = row[2 * (j - wb + u)];
+                const float gj = row[2 * (j - wb + u) + 1];
+                float e = __builtin_amdgcn_exp2f(__builtin_fmaf(yp, f.B[0], f.C[0]));
+#pragma unroll
+                for (int i = 1; i < K; ++i)
+                    e += __builtin_amdgcn_exp2f(__builtin_fmaf(yp, f.B[i], f.C[i]));
+                p *= e * gj;
+            }
+            if (!__all(p >= kFloor)) return false;
+            expo += __builtin_amdgcn_frexp_expf(p);
+            prod = __builtin_amdgcn_frexp_mantf(p);
+        }
+    }
+    return false;
+}
+
+// The expanded shifted form over the blocks of 16 data from j to jend:
+// log2 e_j = (M_j - q_j) + log2 sum_i 2^{x_ij - M_j} with M_j = max_i x_ij,
+// staged as (y'_j, q_j) pairs (q_j rounded to FP32). The M_j - q_j are summed
+// in FP32 per block and added to msum in FP64, as in the shifted form.
+// Updates prod, expo and msum and moves j past the blocks it took; stops at
+// the first window out of range.
+template <int K>
+__device__ __forceinline__ void expanded_shifted(const float* __restrict__ y, int jend,
+                                                 const Expanded<K>& f, float* row, float& prod,
+                                                 int& expo, double& msum, int& j) {
+    constexpr int US = 16;
+    const int lane = lane_id();
+    float ycur = j + lane < jend ? y[j + lane] : 0.0f;
+    for (int wb = j; wb < jend; wb += kExpWin) {
+        const int jj = wb + lane;
+        bool ok = true;
+        wave_sync();                          // the previous window's reads come first
+        if (jj < jend) {
+            const float yp = ycur - f.c;
+            const double q = f.s2 * static_cast<double>(yp) * static_cast<double>(yp);
+            ok = q <= kExpQmax;
+            row[2 * lane] = yp;
+            row[2 * lane + 1] = static_cast<float>(q);
+        }
+        ycur = jj + kExpWin < jend ? y[jj + kExpWin] : 0.0f;
+        if (!__all(ok)) return;
+        wave_sync();                          // the window is written before it is read
+        const int we = wb + kExpWin < jend ? wb + kExpWin : jend;
+        for (; j < we; j += US) {
+            float mblk = 0.0f;
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                const float yp = row[2 * (j - wb + u)];
+                const float qj = row[2 * (j - wb + u) + 1];
+                float x[K];
+#pragma unroll
+                for (int i = 0; i < K; ++i) x[i] = __builtin_fmaf(yp, f.B[i], f.C[i]);
+                float m = x[0];
+#pragma unroll
+                for (int i = 1; i < K; ++i) m = fmaxf(m, x[i]);
+                float e = __builtin_amdgcn_exp2f(x[0] - m);
+#pragma unroll
+                for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(x[i] - m);
+                prod *= e;
+                mblk += m - qj;
+            }
+            msum += static_cast<double>(mblk);
+            expo += __builtin_amdgcn_frexp_expf(prod);
+            prod = __builtin_amdgcn_frexp_mantf(prod);
+        }
+    }
+}
 
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
+                                               const double (&mu)[K * D],
                                                const float (&nms)[K * D], float s,
                                                const GmmDev& g, bool near,
                                                unsigned long long* shifted_ctr = nullptr) {
@@ -92,15 +259,32 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(a[i]);
         return e;
     };
+    // the expanded forms' setup (1-D data): the centre of the slice's first 64 data
+    float* row = nullptr;
+    Expanded<K> xf;
+    bool xok = false;
+    if constexpr (D == 1) {
+        __shared__ float win[kMaxSlices][2 * kExpWin];
+        row = win[wave_id()];
+        const int jlim = j0 + kExpWin < j1 ? j0 + kExpWin : j1;
+        xok = j1 - j0 >= UF && expanded_setup<K>(y, j0, jlim, mu, g, xf);
+    }
     if (g.unit_mass != 0 && __all(near)) {
-        for (; j + UF <= j1; j += UF) {
-            const float* yb = y + (size_t)wave_uniform(j) * D;    // wave-uniform: scalar loads
-            float p = prod;
+        bool plain = true;                    // whether the scalar-load direct form runs from j
+        if constexpr (D == 1) {
+            if (xok) plain = expanded_direct<K>(y, j0 + ((j1 - j0) & ~(UF - 1)), xf, row, prod,
+                                                expo, j);
+        }
+        if (plain) {
+            for (; j + UF <= j1; j += UF) {
+                const float* yb = y + (size_t)wave_uniform(j) * D;    // wave-uniform: scalar loads
+                float p = prod;
 #pragma unroll
-            for (int u = 0; u < UF; ++u) p *= direct(yb + u * D);
-            if (!__all(p >= kFloor)) break;
-            expo += __builtin_amdgcn_frexp_expf(p);
-            prod = __builtin_amdgcn_frexp_mantf(p);
+                for (int u = 0; u < UF; ++u) p *= direct(yb + u * D);
+                if (!__all(p >= kFloor)) break;
+                expo += __builtin_amdgcn_frexp_expf(p);
+                prod = __builtin_amdgcn_frexp_mantf(p);
+            }
         }
     }
     if (shifted_ctr != nullptr) {
@@ -110,6 +294,10 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
                               wave_id()) & (kFormSlots - 1);
             atomicAdd(shifted_ctr + slot, static_cast<unsigned long long>(counted));
         }
+    }
+    if constexpr (D == 1) {
+        if (xok && j + US <= j1)
+            expanded_shifted<K>(y, j + ((j1 - j) & ~(US - 1)), xf, row, prod, expo, msum, j);
     }
     for (; j + US <= j1; j += US) {
         float mblk = 0.0f;
@@ -182,7 +370,7 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
         const double s = static_cast<double>(g.s32);
 #pragma unroll
         for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(s * pr[c]));
-        return partial_fp32<K, D>(y, j0, j1, nms, g.s32, g, near, shifted_ctr);
+        return partial_fp32<K, D>(y, j0, j1, pr, nms, g.s32, g, near, shifted_ctr);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
     }

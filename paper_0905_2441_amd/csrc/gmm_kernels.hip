@@ -18,7 +18,10 @@
 //   a_i = log2 w_i - t_i^2        (one FMA)
 // and the datum's mixture sum e = sum_i 2^(a_i) (hardware v_exp_f32), taken
 // directly for waves near the data or relative to m = max_i a_i otherwise
-// (partial_fp32). Instead of one log per datum, the e's are multiplied into a
+// (partial_fp32). For 1-D data both run in an expanded form: about a data
+// centre c, a_i = x_i - q with x_i = C_i + B_i (y - c) (one FMA) and the
+// particle-free q = s^2 (y - c)^2, which each wave forms once per datum for
+// all 64 of its particles. Instead of one log per datum, the e's are multiplied into a
 // running FP32 product whose exponent is extracted exactly after each block
 // of data (frexp), and the m's are summed in blocks in FP32 and promoted into
 // an FP64 accumulator. Neither is a Kahan sum: the product loses no exponent

@@ -190,7 +190,11 @@ def test_smc_graph_replay_is_bit_identical_to_eager(smc, ctx, small):
                 ctx.set_slices(0)
             assert c["logZ"] == d["logZ"] and np.array_equal(c["theta"], d["theta"])
             assert np.array_equal(c["W"], d["W"]) and c["t"] == d["t"] == cfg.T + 1
-            assert abs(c["logZ"] - a["logZ"]) <= 1e-9 * max(1.0, abs(a["logZ"]))
+            # other slicings round each datum's FP32 term differently (the
+            # expanded forms centre each slice's data on its own midrange):
+            # log Z moves by at most the largest change of a particle's
+            # log-likelihood, each within the FP32 form's 1e-6 relative bound
+            assert abs(c["logZ"] - a["logZ"]) <= 1e-6 * max(1.0, abs(a["logZ"]))
             assert c["resamples"] == a["resamples"]
     # repeated replays of the same sampler give the same answer again
     s = _sampler(smc, ctx, cfg, y, betas, "fp32")
