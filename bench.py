@@ -467,8 +467,8 @@ def tune(ctx, cfg, precs, no_tune, fixed=None):
         got = autotune.make_rules(ctx, [(cfg.k, cfg.d, cfg.n, cfg.N, p) for p in tuned],
                                   reps=10, exact=True, log=log)
         rules += got
-        out.update({r["prec"]: {"slices": r["slices"], "ms_per_move": r["ms"][str(r["slices"])]}
-                    for r in got})
+        out.update({r["prec"]: {"slices": r["slices"], "ms_per_move": r["ms"][str(r["slices"])],
+                                "ms_by_slices": r["ms"]} for r in got})
     ctx.set_launch_table(rules)
     return out
 

@@ -104,7 +104,8 @@ def make_rules(ctx: Context, shapes: Iterable[tuple], reps: int = 20, exact: boo
                           ms={str(t): round(v, 5) for t, v in r["ms"].items()}))
         if log:
             log(f"[autotune] k={k} d={d} n={n} N={N} {prec}: slices {r['best']} "
-                f"({r['ms'][r['best']]:.4f} ms/move)")
+                f"({r['ms'][r['best']]:.4f} ms/move; "
+                + ", ".join(f"{t}: {v:.4f}" for t, v in r["ms"].items()) + ")")
     return rules
 
 

@@ -136,7 +136,7 @@ k_b_resample(const BatchRun* __restrict__ runs, const StepState* __restrict__ st
 }
 
 template <int K, int PREC>
-__global__ void __launch_bounds__(kBatchBlock)
+__global__ void __launch_bounds__(kBatchBlock, 4)
 k_b_move(const BatchRun* __restrict__ runs, const BatchUnit* __restrict__ units, int n_units,
          unsigned* work, const float* __restrict__ y, double* theta, double* l,
          const double* __restrict__ logw, double* __restrict__ W,
@@ -181,7 +181,8 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchUnit* __restrict__ units,
         if (active) {
             const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / S));
             const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / S));
-            part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g));
+            part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g),
+                                             expanded_row<PREC, 1, kBatchWaves>());
         }
         red[w][lane] = part;
         __syncthreads();

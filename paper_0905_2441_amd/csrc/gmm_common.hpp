@@ -50,11 +50,15 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // after the last full block always take the shifted form and are not
 // counted).
 constexpr int kFormSlots = 1024;
-// Data staged per window of the expanded direct form (one per lane).
+// Data staged per window of the expanded forms (one per lane).
 constexpr int kExpWin = kWave;
-// Largest s^2 (y - c)^2 over a slice for which the expanded form runs: its
-// terms 2^{x_ij} then stay below 2^96 and its data factors above 2^-96.
-constexpr double kExpQmax = 96.0;
+// Shortest slice that takes the expanded forms (below it their per-wave
+// set-up, the centre and the FP64 B and C, costs more than they save).
+constexpr int kExpMinData = 128;
+// Largest s^2 (y - c)^2 for which a datum takes the expanded forms: their
+// terms 2^{x_ij} then stay below 2^120 and the data factors above 2^-120, and
+// |x_ij| < 128 bounds x_ij's rounding error by 2^-18.
+constexpr double kExpQmax = 120.0;
 
 // The expanded forms (1-D data). With c a data centre, y' = y - c (FP32) and
 // m_i = mu_i - c,
@@ -88,10 +92,10 @@ __device__ __forceinline__ bool expanded_setup(const float* __restrict__ y, int 
     constexpr double kLog2eD = 1.4426950408889634;
     const int jj = j0 + lane_id();
     const float v = jj < jlim ? y[jj] : 0.0f;
-    const float lo = wave_min(jj < jlim ? v : INFINITY);
-    const float hi = wave_max(jj < jlim ? v : -INFINITY);
+    const float lo = wave_min_dpp(jj < jlim ? v : INFINITY);
+    const float hi = wave_max_dpp(jj < jlim ? v : -INFINITY);
     f.s2 = g.inv2s2 * kLog2eD;
-    f.c = 0.5f * lo + 0.5f * hi;
+    f.c = 0.5f * lo + 0.5f * hi;          // the same in every lane
     if (!(fabsf(f.c) <= 3.0e38f)) return false;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -186,7 +190,7 @@ __device__ __forceinline__ void expanded_shifted(const float* __restrict__ y, in
         const int we = wb + kExpWin < jend ? wb + kExpWin : jend;
         for (; j < we; j += US) {
             float mblk = 0.0f;
-#pragma unroll
+#pragma unroll 8
             for (int u = 0; u < US; ++u) {
                 const float yp = row[2 * (j - wb + u)];
                 const float qj = row[2 * (j - wb + u) + 1];
@@ -211,17 +215,25 @@ __device__ __forceinline__ void expanded_shifted(const float* __restrict__ y, in
 
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
-                                               const double (&mu)[K * D],
-                                               const float (&nms)[K * D], float s,
-                                               const GmmDev& g, bool near,
+                                               const double (&mu)[K * D], const GmmDev& g,
+                                               bool near, float* row,
                                                unsigned long long* shifted_ctr = nullptr) {
     constexpr int UF = 8;            // direct-form block
     constexpr int US = 16;           // shifted-form block
     constexpr float kFloor = 0x1p-100f;
+    const float s = g.s32;
     double msum = 0.0;
     float prod = 1.0f;
     int expo = 0;
     int j = j0;
+    // -s mu in FP32 for the plain forms, formed where they run (not held
+    // through the expanded forms)
+    float nms[K * D];
+    auto form_nms = [&]() {
+#pragma unroll
+        for (int c = 0; c < K * D; ++c)
+            nms[c] = static_cast<float>(-(static_cast<double>(s) * mu[c]));
+    };
     auto exponents = [&](const float* yj, float (&a)[K]) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -259,15 +271,13 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(a[i]);
         return e;
     };
-    // the expanded forms' setup (1-D data): the centre of the slice's first 64 data
-    float* row = nullptr;
+    // the expanded forms' setup (1-D data, a staging row given): the centre of
+    // the slice's first 64 data
     Expanded<K> xf;
     bool xok = false;
     if constexpr (D == 1) {
-        __shared__ float win[kMaxSlices][2 * kExpWin];
-        row = win[wave_id()];
         const int jlim = j0 + kExpWin < j1 ? j0 + kExpWin : j1;
-        xok = j1 - j0 >= UF && expanded_setup<K>(y, j0, jlim, mu, g, xf);
+        xok = row != nullptr && j1 - j0 >= kExpMinData && expanded_setup<K>(y, j0, jlim, mu, g, xf);
     }
     if (g.unit_mass != 0 && __all(near)) {
         bool plain = true;                    // whether the scalar-load direct form runs from j
@@ -276,6 +286,7 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
                                                 expo, j);
         }
         if (plain) {
+            form_nms();
             for (; j + UF <= j1; j += UF) {
                 const float* yb = y + (size_t)wave_uniform(j) * D;    // wave-uniform: scalar loads
                 float p = prod;
@@ -299,9 +310,10 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         if (xok && j + US <= j1)
             expanded_shifted<K>(y, j + ((j1 - j) & ~(US - 1)), xf, row, prod, expo, msum, j);
     }
+    if (j < j1) form_nms();
     for (; j + US <= j1; j += US) {
         float mblk = 0.0f;
-#pragma unroll
+#pragma unroll 8
         for (int u = 0; u < US; ++u) {
             float m, e;
             shifted(y + (size_t)(j + u) * D, m, e);
@@ -359,20 +371,31 @@ __device__ __forceinline__ bool near_data(double l, int n, const GmmDev& g) {
 }
 
 // The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values);
-// `near` is the hint of partial_fp32 (unused in FP64).
+// `near` is the hint of partial_fp32 and `row` the wave's LDS staging row of
+// 2 * kExpWin floats for the expanded forms (nullptr: plain forms only); both
+// unused in FP64.
 template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
                                                 const double (&pr)[K * D], const GmmDev& g,
-                                                bool near = true,
+                                                bool near = true, float* row = nullptr,
                                                 unsigned long long* shifted_ctr = nullptr) {
     if constexpr (PREC == SMC_PREC_FP32) {
-        float nms[K * D];
-        const double s = static_cast<double>(g.s32);
-#pragma unroll
-        for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(s * pr[c]));
-        return partial_fp32<K, D>(y, j0, j1, pr, nms, g.s32, g, near, shifted_ctr);
+        return partial_fp32<K, D>(y, j0, j1, pr, g, near, row, shifted_ctr);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
+    }
+}
+
+// This wave's staging row for the expanded forms in a kernel of at most W
+// waves per workgroup (a static LDS array of that kernel), or nullptr where the
+// forms do not apply (FP64, d > 1).
+template <int PREC, int D, int W>
+__device__ __forceinline__ float* expanded_row() {
+    if constexpr (PREC == SMC_PREC_FP32 && D == 1) {
+        __shared__ float win[W][2 * kExpWin];
+        return win[wave_id()];
+    } else {
+        return nullptr;
     }
 }
 
@@ -419,17 +442,17 @@ __device__ __forceinline__ MoveSource move_source(const MoveStep& ms, double* th
 
 // Ancestors of the 64 particles of this workgroup after systematic resampling
 // (cooperative: every thread of the block must call it). Wave 0 forms the chunk
-// offsets in LDS (exclusive double-double scan of the chunk totals), then each
-// of its lanes takes the scheme's point U_i for particle i and finds
-// idx = min{j : U < C_j} (or the first j with C_j = C_{N-1}), C_j = offset +
-// within-chunk prefix rounded once.
+// offsets in LDS (exclusive double-double scan of the chunk totals; offh and
+// offl hold ms.nchunks entries each), then each of its lanes takes the
+// scheme's point U_i for particle i and finds idx = min{j : U < C_j} (or the
+// first j with C_j = C_{N-1}), C_j = offset + within-chunk prefix rounded once.
 __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint32_t step, int pc,
                                                 int* anc, double* offh, double* offl) {
     const int lane = lane_id();
     if (wave_id() == 0) {
         // two passes over the lane's chunk totals (sum, then running offsets)
         // keep the register footprint of this prologue small
-        constexpr int per = kMaxChunks / kWave;
+        const int per = wave_uniform((ms.nchunks + kWave - 1) / kWave);
         dd run = dd_zero();
         for (int q = 0; q < per; ++q) {
             const int c = lane * per + q;
@@ -445,9 +468,11 @@ __device__ __forceinline__ void fused_ancestors(const MoveStep& ms, int N, uint3
         if (lane == 0) excl = dd_zero();
         for (int q = 0; q < per; ++q) {
             const int c = lane * per + q;
-            offh[c] = excl.hi;
-            offl[c] = excl.lo;
-            if (c < ms.nchunks) excl = dd_add(excl, dd{ms.chunk_tot[2 * c], ms.chunk_tot[2 * c + 1]});
+            if (c < ms.nchunks) {
+                offh[c] = excl.hi;
+                offl[c] = excl.lo;
+                excl = dd_add(excl, dd{ms.chunk_tot[2 * c], ms.chunk_tot[2 * c + 1]});
+            }
         }
     }
     __syncthreads();

@@ -60,7 +60,8 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
     double pr[KD];
 #pragma unroll
     for (int c = 0; c < KD; ++c) pr[c] = theta[static_cast<size_t>(c) * N + pc];
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g);
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, true,
+                                             expanded_row<PREC, D, kMaxSlices>());
     __syncthreads();
     if (w == 0 && p < N) {
         double acc = red[0][lane];
@@ -102,13 +103,21 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        uint32_t move, GmmDev g, unsigned long long* n_acc, int* status, MoveStep ms, int G,
        double* __restrict__ part, int* __restrict__ anc_out) {
     constexpr int KD = K * D;
+    constexpr bool kRows = PREC == SMC_PREC_FP32 && D == 1;
     __shared__ double red[kMaxSlices][kWave];
     __shared__ int anc[kWave];
-    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
     __shared__ double prs[KD][kWave];
+    // LDS sized by the launch (rwmh_dyn_lds_bytes): for the FP32 1-D form the
+    // waves' staging rows [S][2 kExpWin] floats, then offh, offl [nch] (nch =
+    // ms.nchunks when the move can resample, else 0)
+    extern __shared__ double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
+    const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
+    double* offh = lds + (kRows ? S * kExpWin : 0);
+    double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin : nullptr;
     const int tile = static_cast<int>(blockIdx.x) / G;
     const int grp = static_cast<int>(blockIdx.x) - tile * G;
     const int p = tile * kWave + lane;
@@ -128,7 +137,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g), row,
                                              g_fp32_shifted_data);
     __syncthreads();
     if (w != 0) return;
@@ -204,7 +213,8 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         double pr[KD];
         block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, mv, &cur[0][0], kWave, lane, sd,
                             w, S, prs, pr);
-        red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g));
+        red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
+                                                 expanded_row<PREC, D, kMaxSlices>());
         __syncthreads();
         if (w == 0) {
             double tot = red[0][lane];
@@ -323,7 +333,8 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
         double pr[KD];
 #pragma unroll
         for (int c = 0; c < KD; ++c) pr[c] = cur[c][col] + sd * zs[c][col];
-        red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g, near_data(lcur[col], n, g));
+        red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g, near_data(lcur[col], n, g),
+                                                 expanded_row<PREC, D, kMaxSlices>());
         __syncthreads();
         if (sl == 0) {
             double tot = red[w][lane];
@@ -420,7 +431,8 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), it, 0, &cur[0][0], kWave, lane, sd, w, S,
                         prs, pr);
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g));
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
+                                             expanded_row<PREC, D, kMaxSlices>());
     __syncthreads();
     if (w != 0) return;
     double tot = red[0][lane];
@@ -663,23 +675,39 @@ bool valid_split(const Split& sp, int64_t N) {
            sp.slices <= kMaxSlices && (sp.groups == 1 || N <= kSplitCap);
 }
 
+// Largest dynamic LDS a k_rwmh launch asks for (the static part is at most
+// 8 KB + 32 KB + 256 B).
+constexpr size_t kMaxRwmhLds = 24 * 1024;
+
+// Dynamic LDS bytes of one k_rwmh workgroup (the layout at the top of k_rwmh).
+size_t rwmh_dyn_lds_bytes(int slices, int nchunks, bool rows) {
+    return (rows ? sizeof(float) * slices * 2 * kExpWin : 0) +
+           sizeof(double) * 2 * static_cast<size_t>(nchunks);
+}
+
 // The likelihood half of a move (with the decision when groups == 1).
 template <int K, int D, int P>
-void launch_move_partials(const float* y, int64_t n, double* theta, double* l, int64_t N,
-                          const double* beta_vec, const StepSrc& src, double sd, uint64_t seed,
-                          uint32_t move, const GmmDev& g, unsigned long long* n_accept,
-                          const Split& sp, const Scratch& sc, const MoveStep& ms, hipStream_t s) {
+hipError_t launch_move_partials(const float* y, int64_t n, double* theta, double* l, int64_t N,
+                                const double* beta_vec, const StepSrc& src, double sd,
+                                uint64_t seed, uint32_t move, const GmmDev& g,
+                                unsigned long long* n_accept, const Split& sp, const Scratch& sc,
+                                const MoveStep& ms, hipStream_t s) {
     const int64_t tiles = (N + kWave - 1) / kWave;
     const dim3 grid(static_cast<unsigned>(tiles * sp.groups));
     const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+    const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
+    if (nch < 0 || nch > kMaxChunks) return hipErrorInvalidValue;
+    const size_t lds = rwmh_dyn_lds_bytes(sp.slices, nch, P == SMC_PREC_FP32 && D == 1);
+    if (lds > kMaxRwmhLds) return hipErrorInvalidValue;
     if (ms.lw_next != nullptr)
-        hipLaunchKernelGGL((k_rwmh<K, D, P, true>), grid, block, 0, s, y, static_cast<int>(n),
+        hipLaunchKernelGGL((k_rwmh<K, D, P, true>), grid, block, lds, s, y, static_cast<int>(n),
                            theta, l, static_cast<int>(N), beta_vec, src, sd, seed, move, g,
                            n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
     else
-        hipLaunchKernelGGL((k_rwmh<K, D, P, false>), grid, block, 0, s, y, static_cast<int>(n),
+        hipLaunchKernelGGL((k_rwmh<K, D, P, false>), grid, block, lds, s, y, static_cast<int>(n),
                            theta, l, static_cast<int>(N), beta_vec, src, sd, seed, move, g,
                            n_accept, sc.status, ms, sp.groups, sc.mv_part, sc.mv_anc);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -693,8 +721,10 @@ hipError_t launch_rwmh(const GmmDev& g, const float* y, int64_t n, double* theta
     const dim3 agrid(static_cast<unsigned>((N + 255) / 256));
 #define SMC_MOVE(K, D, P)                                                                      \
     do {                                                                                       \
-        launch_move_partials<K, D, P>(y, n, theta, l, N, beta_vec, src, sd, seed, move, g,     \
-                                      n_accept, sp, sc, ms, s);                                \
+        const hipError_t e0 = launch_move_partials<K, D, P>(y, n, theta, l, N, beta_vec, src,  \
+                                                            sd, seed, move, g, n_accept, sp,   \
+                                                            sc, ms, s);                        \
+        if (e0 != hipSuccess) return e0;                                                       \
         if (sp.groups > 1)                                                                     \
             hipLaunchKernelGGL((k_rwmh_accept<K * D, P>), agrid, dim3(256), 0, s,              \
                                static_cast<int>(n), theta, l, static_cast<int>(N), beta_vec,   \
@@ -850,8 +880,10 @@ hipError_t launch_pt_iteration(const GmmDev& g, const float* y, int64_t n, doubl
     const dim3 xgrid(static_cast<unsigned>((2 * (M / 2 + 2) + 255) / 256));
 #define SMC_PT(K, D, P)                                                                        \
     do {                                                                                       \
-        launch_move_partials<K, D, P>(y, n, theta, l, M, beta, src, sd, seed, 0, g, n_accept,  \
-                                      sp, sc, ms, s);                                          \
+        const hipError_t e0 = launch_move_partials<K, D, P>(y, n, theta, l, M, beta, src, sd,  \
+                                                            seed, 0, g, n_accept, sp, sc, ms,  \
+                                                            s);                                \
+        if (e0 != hipSuccess) return e0;                                                       \
         hipLaunchKernelGGL((k_pt_accept_exchange<K * D, P>), xgrid, dim3(256), 0, s,           \
                            static_cast<int>(n), theta, l, static_cast<int>(M), beta, later,    \
                            sd, seed, g, sp.groups, static_cast<const double*>(sc.mv_part),     \

@@ -34,6 +34,37 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// The largest and smallest of the wave's 64 values of v, in every lane, by
+// DPP row shifts and row broadcasts (no LDS round trips). Floats are compared
+// through integer keys that keep their order (a NaN comes out largest or
+// smallest, by its sign bit).
+__device__ __forceinline__ int float_order_key(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    return b >= 0 ? b : b ^ 0x7fffffff;
+}
+__device__ __forceinline__ float float_of_order_key(int k) {
+    return __builtin_bit_cast(float, k >= 0 ? k : k ^ 0x7fffffff);
+}
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme_key(int v) {
+    // a lane whose DPP source is outside its row, or whose row is masked off,
+    // keeps its own value (the operation is idempotent)
+    auto step = [&](int o) { return MAX ? (v > o ? v : o) : (v < o ? v : o); };
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = step(__builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    return float_of_order_key(wave_extreme_key<true>(float_order_key(v)));
+}
+__device__ __forceinline__ float wave_min_dpp(float v) {
+    return float_of_order_key(wave_extreme_key<false>(float_order_key(v)));
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
