@@ -179,10 +179,10 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchUnit* __restrict__ units,
                             active ? sl : (KD + 1) / 2, S, prs[grp], pr);
         double part = 0.0;
         if (active) {
-            const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / S));
-            const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / S));
+            int j0, j1;
+            slice_bounds(n, sl, S, j0, j1);
             part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g),
-                                             expanded_row<PREC, 1, kBatchWaves>());
+                                             ExpStage{expanded_row<PREC, 1, kBatchWaves>()});
         }
         red[w][lane] = part;
         __syncthreads();

@@ -76,6 +76,27 @@ constexpr double kExpQmax = 120.0;
 // q_j > kExpQmax (or not finite) ends a form at its start: this bounds the
 // magnitude of x_ij and so its rounding error (and, in the direct form, keeps
 // 2^{x_ij} finite and g_j normal).
+// A wave's staging for the expanded forms: its LDS row of 2 * kExpWin floats
+// (nullptr: plain forms only) and, when `pre` is set, each lane's datum
+// y[j0 + lane] of its slice already loaded (a caller may issue that load early,
+// ahead of other work).
+struct ExpStage {
+    float* row = nullptr;
+    float y0 = 0.0f;
+    bool pre = false;
+};
+
+// The data slice [j0, j1) of slice sl out of nsl over n data (the same in
+// every lane). Slices of at least 64 data start on multiples of 8, the FP32
+// forms' blocks, so that only a slice ending at n can end in a partial block.
+__device__ __forceinline__ void slice_bounds(int n, int sl, int nsl, int& j0, int& j1) {
+    const int a = static_cast<int>((static_cast<int64_t>(n) * sl) / nsl);
+    const int b = static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / nsl);
+    const bool blocks = static_cast<int64_t>(n) >= static_cast<int64_t>(64) * nsl;
+    j0 = wave_uniform(blocks ? a & ~7 : a);
+    j1 = wave_uniform(blocks && sl + 1 < nsl ? b & ~7 : b);
+}
+
 template <int K>
 struct Expanded {
     double s2;                 // s^2 = log2(e) / (2 sigma2)
@@ -85,13 +106,13 @@ struct Expanded {
 
 // c = the midrange of the data in [j0, jlim) (at most 64 of them) and the
 // lane's B_i, C_i. False when those data are not all finite.
+// v: the lane's datum y[j0 + lane] (unused past jlim).
 template <int K>
-__device__ __forceinline__ bool expanded_setup(const float* __restrict__ y, int j0, int jlim,
+__device__ __forceinline__ bool expanded_setup(float v, int j0, int jlim,
                                                const double (&mu)[K], const GmmDev& g,
                                                Expanded<K>& f) {
     constexpr double kLog2eD = 1.4426950408889634;
     const int jj = j0 + lane_id();
-    const float v = jj < jlim ? y[jj] : 0.0f;
     const float lo = wave_min_dpp(jj < jlim ? v : INFINITY);
     const float hi = wave_max_dpp(jj < jlim ? v : -INFINITY);
     f.s2 = g.inv2s2 * kLog2eD;
@@ -114,14 +135,14 @@ __device__ __forceinline__ bool expanded_setup(const float* __restrict__ y, int 
 // prod and expo over the blocks it took and moves j past them; returns true
 // when it stopped for the range (the caller goes on in the scalar-load direct
 // form from j), false when it took every block or a block failed the 2^-100
-// check (the caller goes on in the shifted forms).
+// check (the caller goes on in the shifted forms). ycur: the lane's datum
+// y[j + lane] (unused past jend).
 template <int K>
 __device__ __forceinline__ bool expanded_direct(const float* __restrict__ y, int jend,
                                                 const Expanded<K>& f, float* row, float& prod,
-                                                int& expo, int& j) {
+                                                int& expo, int& j, float ycur) {
     constexpr float kFloor = 0x1p-100f;
     const int lane = lane_id();
-    float ycur = j + lane < jend ? y[j + lane] : 0.0f;
     for (int wb = j; wb < jend; wb += kExpWin) {
         const int jj = wb + lane;
         bool ok = true;
@@ -216,7 +237,7 @@ __device__ __forceinline__ void expanded_shifted(const float* __restrict__ y, in
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const double (&mu)[K * D], const GmmDev& g,
-                                               bool near, float* row,
+                                               bool near, const ExpStage& st,
                                                unsigned long long* shifted_ctr = nullptr) {
     constexpr int UF = 8;            // direct-form block
     constexpr int US = 16;           // shifted-form block
@@ -273,17 +294,22 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
     };
     // the expanded forms' setup (1-D data, a staging row given): the centre of
     // the slice's first 64 data
+    float* row = st.row;
     Expanded<K> xf;
     bool xok = false;
+    float y0 = 0.0f;
     if constexpr (D == 1) {
-        const int jlim = j0 + kExpWin < j1 ? j0 + kExpWin : j1;
-        xok = row != nullptr && j1 - j0 >= kExpMinData && expanded_setup<K>(y, j0, jlim, mu, g, xf);
+        if (row != nullptr && j1 - j0 >= kExpMinData) {
+            // j1 - j0 >= 64: every lane's datum y[j0 + lane] is in the slice
+            y0 = st.pre ? st.y0 : y[j0 + lane_id()];
+            xok = expanded_setup<K>(y0, j0, j0 + kExpWin, mu, g, xf);
+        }
     }
     if (g.unit_mass != 0 && __all(near)) {
         bool plain = true;                    // whether the scalar-load direct form runs from j
         if constexpr (D == 1) {
             if (xok) plain = expanded_direct<K>(y, j0 + ((j1 - j0) & ~(UF - 1)), xf, row, prod,
-                                                expo, j);
+                                                expo, j, y0);
         }
         if (plain) {
             form_nms();
@@ -371,16 +397,15 @@ __device__ __forceinline__ bool near_data(double l, int n, const GmmDev& g) {
 }
 
 // The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values);
-// `near` is the hint of partial_fp32 and `row` the wave's LDS staging row of
-// 2 * kExpWin floats for the expanded forms (nullptr: plain forms only); both
-// unused in FP64.
+// `near` is the hint of partial_fp32 and `st` the wave's staging for the
+// expanded forms; both unused in FP64.
 template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
                                                 const double (&pr)[K * D], const GmmDev& g,
-                                                bool near = true, float* row = nullptr,
+                                                bool near = true, const ExpStage& st = {},
                                                 unsigned long long* shifted_ctr = nullptr) {
     if constexpr (PREC == SMC_PREC_FP32) {
-        return partial_fp32<K, D>(y, j0, j1, pr, g, near, row, shifted_ctr);
+        return partial_fp32<K, D>(y, j0, j1, pr, g, near, st, shifted_ctr);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
     }

@@ -49,19 +49,24 @@ __global__ void __launch_bounds__(1024)
 k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, int N,
          GmmDev g, double* __restrict__ out, int* status) {
     constexpr int KD = K * D;
-    __shared__ double red[kMaxSlices][kWave];
+    // LDS sized by the launch (loglik_dyn_lds_bytes): red [S][64] doubles, then
+    // for the FP32 1-D form the waves' staging rows [S][2 kExpWin] floats
+    extern __shared__ double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
+    double (*red)[kWave] = reinterpret_cast<double (*)[kWave]>(lds);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
+    float* row = (PREC == SMC_PREC_FP32 && D == 1)
+                     ? reinterpret_cast<float*>(lds + S * kWave) + w * 2 * kExpWin
+                     : nullptr;
     const int p = blockIdx.x * kWave + lane;
     const int pc = p < N ? p : N - 1;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    int j0, j1;
+    slice_bounds(n, w, S, j0, j1);
     double pr[KD];
 #pragma unroll
     for (int c = 0; c < KD; ++c) pr[c] = theta[static_cast<size_t>(c) * N + pc];
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, true,
-                                             expanded_row<PREC, D, kMaxSlices>());
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, true, ExpStage{row});
     __syncthreads();
     if (w == 0 && p < N) {
         double acc = red[0][lane];
@@ -122,10 +127,15 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int grp = static_cast<int>(blockIdx.x) - tile * G;
     const int p = tile * kWave + lane;
     const int pc = p < N ? p : N - 1;
-    const int64_t nsl = static_cast<int64_t>(S) * G;
+    const int nsl = S * G;
     const int sl = grp * S + w;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / nsl));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / nsl));
+    int j0, j1;
+    slice_bounds(n, sl, nsl, j0, j1);
+    // the lane's first datum of the slice for the expanded forms, loaded ahead
+    // of the ancestor search and the proposals (their barriers and Box-Muller
+    // work hide its latency)
+    const bool y_pre = kRows && j1 - j0 >= kExpMinData;
+    const float y_first = y_pre ? y[j0 + lane] : 0.0f;
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     if (ms.t_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
         *ms.t_out = static_cast<int>(step);
@@ -137,8 +147,8 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g), row,
-                                             g_fp32_shifted_data);
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
+                                             ExpStage{row, y_first, y_pre}, g_fp32_shifted_data);
     __syncthreads();
     if (w != 0) return;
 
@@ -183,19 +193,25 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
              double sd, uint64_t seed, uint32_t move0, int n_moves, GmmDev g,
              unsigned long long* n_acc, int* status, MoveStep ms) {
     constexpr int KD = K * D;
+    constexpr bool kRows = PREC == SMC_PREC_FP32 && D == 1;
     __shared__ double red[kMaxSlices][kWave];
     __shared__ int anc[kWave];
-    __shared__ double offh[kMaxChunks], offl[kMaxChunks];
     __shared__ double prs[KD][kWave];
     __shared__ double cur[KD][kWave];
     __shared__ double lcur[kWave];
+    // LDS sized by the launch (rwmh_dyn_lds_bytes), as in k_rwmh
+    extern __shared__ double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
+    const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
+    double* offh = lds + (kRows ? S * kExpWin : 0);
+    double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < N ? p : N - 1;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    int j0, j1;
+    slice_bounds(n, w, S, j0, j1);
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     const bool fused = (ms.cdf_hi != nullptr) && (ms.state != nullptr) && (ms.state->resampled != 0);
     if (fused) fused_ancestors(ms, N, step, pc, anc, offh, offl);
@@ -214,7 +230,7 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, mv, &cur[0][0], kWave, lane, sd,
                             w, S, prs, pr);
         red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
-                                                 expanded_row<PREC, D, kMaxSlices>());
+                                                 ExpStage{row});
         __syncthreads();
         if (w == 0) {
             double tot = red[0][lane];
@@ -291,8 +307,8 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
     const int sl = w - tile * S;
     const int col = tile * kWave + lane;          // chain held by this lane
     const int cc = col < M ? col : M - 1;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * sl) / S));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (sl + 1)) / S));
+    int j0, j1;
+    slice_bounds(n, sl, S, j0, j1);
     // random items of chain col for iteration it, items first, first + stride, ...
     auto draw_items = [&](uint32_t it, int buf, int first, int stride) {
         for (int i = first; i < NITEM; i += stride) {
@@ -333,8 +349,10 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
         double pr[KD];
 #pragma unroll
         for (int c = 0; c < KD; ++c) pr[c] = cur[c][col] + sd * zs[c][col];
+        // the same per-datum forms as the one-launch-per-iteration path, so the
+        // two agree bit for bit
         red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g, near_data(lcur[col], n, g),
-                                                 expanded_row<PREC, D, kMaxSlices>());
+                                                 ExpStage{expanded_row<PREC, D, kMaxSlices>()});
         __syncthreads();
         if (sl == 0) {
             double tot = red[w][lane];
@@ -400,13 +418,19 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     __shared__ double cur[KD][kWave];
     __shared__ double prs[KD][kWave];
     __shared__ double lcur[kWave];
+    // LDS sized by the launch: for the FP32 1-D form the waves' staging rows
+    // [S][2 kExpWin] floats
+    extern __shared__ double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
+    float* row = (PREC == SMC_PREC_FP32 && D == 1)
+                     ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin
+                     : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < M ? p : M - 1;
-    const int j0 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * w) / S));
-    const int j1 = wave_uniform(static_cast<int>((static_cast<int64_t>(n) * (w + 1)) / S));
+    int j0, j1;
+    slice_bounds(n, w, S, j0, j1);
     const uint32_t it = static_cast<uint32_t>(*it_in);
     if (blockIdx.x == 0 && threadIdx.x == 0) *it_out = static_cast<int>(it) + 1;
     if (w == 0) {
@@ -432,7 +456,7 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), it, 0, &cur[0][0], kWave, lane, sd, w, S,
                         prs, pr);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
-                                             expanded_row<PREC, D, kMaxSlices>());
+                                             ExpStage{row});
     __syncthreads();
     if (w != 0) return;
     double tot = red[0][lane];
@@ -636,6 +660,25 @@ __global__ void k_prior(int N, uint64_t seed, GmmDev g, double* __restrict__ the
 #define SMC_KD_CASES(X) \
     X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(1, 8) X(2, 8) X(4, 8) X(8, 8)
 
+namespace {
+
+// Largest dynamic LDS a k_rwmh or k_rwmh_multi launch asks for (their static
+// part is at most 8 KB + 64 KB + 768 B).
+constexpr size_t kMaxRwmhLds = 24 * 1024;
+
+// LDS bytes of the expanded forms' staging rows of `slices` waves (FP32, d = 1).
+size_t rows_lds_bytes(int slices, bool rows) {
+    return rows ? sizeof(float) * slices * 2 * kExpWin : 0;
+}
+
+// Dynamic LDS bytes of one k_rwmh / k_rwmh_multi workgroup (the layout at the
+// top of k_rwmh).
+size_t rwmh_dyn_lds_bytes(int slices, int nchunks, bool rows) {
+    return rows_lds_bytes(slices, rows) + sizeof(double) * 2 * static_cast<size_t>(nchunks);
+}
+
+}  // namespace
+
 bool supported_kd(int k, int d, int prec) {
     if (prec == SMC_PREC_BF16X3) return dd_supported(k, d);
     if (prec != SMC_PREC_FP32 && prec != SMC_PREC_FP64) return false;
@@ -649,16 +692,20 @@ bool supported_kd(int k, int d, int prec) {
 hipError_t launch_loglik(const GmmDev& g, const float* y, int64_t n, const double* theta,
                          int64_t N, int prec, double* out, int slices, int* status,
                          hipStream_t s) {
+    if (slices < 1 || slices > kMaxSlices) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
     const dim3 block(static_cast<unsigned>(kWave * slices));
+    // LDS of k_loglik: red [slices][64] doubles, then the staging rows
+    const size_t red_bytes = sizeof(double) * kWave * slices;
 #define SMC_CASE(K, D)                                                                        \
     if (g.k == K && g.d == D) {                                                               \
         if (prec == SMC_PREC_FP32)                                                            \
-            hipLaunchKernelGGL((k_loglik<K, D, SMC_PREC_FP32>), grid, block, 0, s, y,         \
+            hipLaunchKernelGGL((k_loglik<K, D, SMC_PREC_FP32>), grid, block,                  \
+                               red_bytes + rows_lds_bytes(slices, D == 1), s, y,              \
                                static_cast<int>(n), theta, static_cast<int>(N), g, out,       \
                                status);                                                       \
         else                                                                                  \
-            hipLaunchKernelGGL((k_loglik<K, D, SMC_PREC_FP64>), grid, block, 0, s, y,         \
+            hipLaunchKernelGGL((k_loglik<K, D, SMC_PREC_FP64>), grid, block, red_bytes, s, y, \
                                static_cast<int>(n), theta, static_cast<int>(N), g, out,       \
                                status);                                                       \
         return hipGetLastError();                                                             \
@@ -673,16 +720,6 @@ namespace {
 bool valid_split(const Split& sp, int64_t N) {
     return sp.groups >= 1 && sp.groups <= kMaxGroups && sp.slices >= 1 &&
            sp.slices <= kMaxSlices && (sp.groups == 1 || N <= kSplitCap);
-}
-
-// Largest dynamic LDS a k_rwmh launch asks for (the static part is at most
-// 8 KB + 32 KB + 256 B).
-constexpr size_t kMaxRwmhLds = 24 * 1024;
-
-// Dynamic LDS bytes of one k_rwmh workgroup (the layout at the top of k_rwmh).
-size_t rwmh_dyn_lds_bytes(int slices, int nchunks, bool rows) {
-    return (rows ? sizeof(float) * slices * 2 * kExpWin : 0) +
-           sizeof(double) * 2 * static_cast<size_t>(nchunks);
 }
 
 // The likelihood half of a move (with the decision when groups == 1).
@@ -774,14 +811,18 @@ hipError_t launch_rwmh_moves(const GmmDev& g, const float* y, int64_t n, double*
     }
     const dim3 grid(static_cast<unsigned>((N + kWave - 1) / kWave));
     const dim3 block(static_cast<unsigned>(kWave * sp.slices));
+    const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
+    if (nch < 0 || nch > kMaxChunks) return hipErrorInvalidValue;
 #define SMC_MULTI(K, D, P)                                                                     \
     do {                                                                                       \
+        const size_t lds = rwmh_dyn_lds_bytes(sp.slices, nch, P == SMC_PREC_FP32 && D == 1);   \
+        if (lds > kMaxRwmhLds) return hipErrorInvalidValue;                                    \
         if (ms.lw_next != nullptr)                                                             \
-            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, true>), grid, block, 0, s, y,            \
+            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, true>), grid, block, lds, s, y,          \
                                static_cast<int>(n), theta, l, static_cast<int>(N), src, sd,    \
                                seed, 0u, n_moves, g, n_accept, sc.status, ms);                 \
         else                                                                                   \
-            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, false>), grid, block, 0, s, y,           \
+            hipLaunchKernelGGL((k_rwmh_multi<K, D, P, false>), grid, block, lds, s, y,         \
                                static_cast<int>(n), theta, l, static_cast<int>(N), src, sd,    \
                                seed, 0u, n_moves, g, n_accept, sc.status, ms);                 \
     } while (0)
@@ -917,7 +958,12 @@ hipError_t launch_pt_deferred(const GmmDev& g, const float* y, int64_t n, double
     const dim3 grid(static_cast<unsigned>(tiles)), block(static_cast<unsigned>(kWave * slices));
     for (int i = 0; i < n_iters; ++i) {
         const int a = i & 1, b = a ^ 1;
-#define SMC_DEF(K, D, P)                                                                               hipLaunchKernelGGL((k_pt_deferred<K, D, P>), grid, block, 0, s, y, static_cast<int>(n),                             th[a], lb[a], th[b], lb[b], static_cast<int>(M), beta, ctr[a],                                  ctr[b], i > 0 ? 1 : 0, parity_mode, wrap, sd, seed, g, n_accept,                                n_swap, sc.status)
+#define SMC_DEF(K, D, P)                                                                       \
+    hipLaunchKernelGGL((k_pt_deferred<K, D, P>), grid, block,                                  \
+                       rows_lds_bytes(slices, P == SMC_PREC_FP32 && D == 1), s, y,             \
+                       static_cast<int>(n), th[a], lb[a], th[b], lb[b], static_cast<int>(M),   \
+                       beta, ctr[a], ctr[b], i > 0 ? 1 : 0, parity_mode, wrap, sd, seed, g,    \
+                       n_accept, n_swap, sc.status)
 #define SMC_CASE(K, D)                                                                                 if (g.k == K && g.d == D) {                                                                        if (prec == SMC_PREC_FP32) SMC_DEF(K, D, SMC_PREC_FP32);                                       else SMC_DEF(K, D, SMC_PREC_FP64);                                                         } else
         SMC_KD_CASES(SMC_CASE) { return hipErrorInvalidValue; }
 #undef SMC_CASE

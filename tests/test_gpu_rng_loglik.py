@@ -230,6 +230,45 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
             ctx.set_slices(0)
 
 
+@pytest.mark.parametrize("case", ["range_exit_late", "range_exit_early", "far_particles",
+                                  "slice_127", "slice_128", "slice_129"])
+def test_loglik_fp32_expanded_forms(smc, ctx, case):
+    """The FP32 forms for 1-D data in their expanded split about a centre c
+    (the midrange of a slice's first 64 data), at 4 slices: a window holding a
+    datum with s^2 (y - c)^2 above the split's range bound hands the rest of
+    the slice to the plain forms (late: at the slice's last window; early: at
+    its second); prior draws take the expanded shifted form; slices of 127,
+    128 and 129 data sit on either side of the shortest slice the split takes.
+    Every case agrees with the oracle."""
+    announce(f"loglik fp32 expanded {case}")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    rng = np.random.default_rng(41)
+    near = theta_near_posterior(500, mu, seed=42)
+    th = near
+    if case.startswith("range_exit"):
+        # 4 slices of 256: the first 64 data of each cluster near 0.5 (c near
+        # 0.5); the rest come from the mixture, with 10.5 (s^2 100 = 131 > 120)
+        # planted in the last window (late) or the second one (early)
+        n = 1024
+        y = make_mixture_data(n, mu, 0.55, seed=43).copy()
+        at = 200 if case.endswith("late") else 70
+        for sl in range(4):
+            y[256 * sl: 256 * sl + 64] = 0.5 + 0.2 * rng.standard_normal(64).astype(np.float32)
+            y[256 * sl + at] = 10.5
+    elif case == "far_particles":
+        y = make_mixture_data(1000, mu, 0.55, seed=44)
+        th = theta_prior_draws(500, 4, 1, seed=45)
+    else:
+        per = int(case.split("_")[1])
+        y = make_mixture_data(4 * per, mu, 0.55, seed=per)
+    ctx.set_slices(4)
+    try:
+        _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)
+    finally:
+        ctx.set_slices(0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_loglik_nan_raises_status(smc, ctx, prec):
     announce(f"loglik NaN status {prec}")

@@ -287,8 +287,9 @@ def test_fp32_shifted_form_counter(smc, ctx):
     """The device counter of the FP32 move's per-datum forms: a move of prior
     draws (far from the data) takes the shifted form for every full block of 8
     observations of every wave's slice; a move of particles near a posterior
-    mode stays direct throughout; FP64 moves do not count. (Four slices of
-    250 observations: 248 counted per wave, 2 after the last full block.)"""
+    mode stays direct throughout; FP64 moves do not count. (Four slices whose
+    boundaries fall on multiples of 8: 248, 248, 248 and 256 observations, all
+    in full blocks, so every observation of every tile is counted.)"""
     announce("fp32 form counter")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     n, N = 1000, 4096
@@ -298,7 +299,7 @@ def test_fp32_shifted_form_counter(smc, ctx):
     ctx.set_slices(4)
     try:
         for name, th_np, prec, want in (
-                ("prior", theta_prior_draws(N, 4, 1, seed=3), "fp32", tiles * 4 * 248),
+                ("prior", theta_prior_draws(N, 4, 1, seed=3), "fp32", tiles * n),
                 ("near", theta_near_posterior(N, mu, seed=4, jitter=0.1), "fp32", 0),
                 ("prior fp64", theta_prior_draws(N, 4, 1, seed=3), "fp64", 0)):
             th = _cuda(th_np)
