@@ -70,7 +70,7 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "48e3c34d1042b20661af52d8f0fea30176bdf04f3640e8def65a3b43390a6675",
+    "sources_sha256": "c2e907de20cbc909bfaf694a8f404176f81aa647f0c46518aeb36711f9e43ac7",
     # the launch shape the counters were taken at (data slices per 64-particle
     # tile, and so waves per launch); figures apply only to a timed move of that
     # shape. The standalone moves run from the population after `steps` timed

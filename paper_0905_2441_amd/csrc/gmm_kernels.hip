@@ -3,10 +3,12 @@
 // Decomposition (one workgroup = 64 particles x S data slices):
 //   * lane l of every wave owns particle blockIdx.x*64 + l and keeps that
 //     particle's k*d means in registers (as FP32 scaled offsets, or FP64);
-//   * wave w of the workgroup owns the data slice [w*n/S, (w+1)*n/S); its index
-//     is made wave-uniform, so every observation is fetched by a scalar load
-//     into SGPRs and broadcast to all 64 lanes with no LDS traffic, no VGPR
-//     copies and no barriers inside the data loop;
+//   * wave w of the workgroup owns a data slice of about n/S observations
+//     (slice_bounds); its bounds are made wave-uniform, so in the plain forms
+//     every observation is fetched by a scalar load into SGPRs and broadcast
+//     to all 64 lanes, and in the expanded forms (1-D data) the wave stages
+//     its observations with their particle-free terms in its own LDS row and
+//     reads them back as broadcasts; no barrier inside the data loop;
 //   * the S per-slice partial sums of a particle meet in LDS and wave 0 adds
 //     them in slice order (bit-reproducible for a given S).
 // The paper evaluated one likelihood per thread over data in shared memory
