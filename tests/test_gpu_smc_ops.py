@@ -91,7 +91,7 @@ def _resample_gpu(smc, ctx, W, u, theta=None, l=None):
 
 
 @pytest.mark.parametrize("N", [1, 2, 7, 1000, 2049, 131072, (1 << 20) - 1, 1 << 20,
-                               (1 << 21) + 12345])
+                               (1 << 21) + 12345, (1 << 22) + 4321])
 def test_resample_bit_exact(smc, ctx, N):
     announce(f"resample N={N}")
     W = osmc.normalise(lognormal_logw(N, seed=N + 5, spread=3.0))
@@ -137,11 +137,13 @@ def test_resample_gather_and_predicate(smc, ctx):
     assert np.array_equal(idx2.cpu().numpy(), osmc.systematic_resample(W, osmc.resample_offset(3, 4)))
 
 
-@pytest.mark.parametrize("N", [1, 7, 1000, 2049, 131072, 1 << 20, (1 << 21) + 12345])
+@pytest.mark.parametrize("N", [1, 7, 1000, 2049, 131072, 1 << 20, (1 << 21) + 12345,
+                               (1 << 22) + 4321])
 @pytest.mark.parametrize("scheme", ["stratified", "multinomial", "systematic"])
 def test_resample_schemes_bit_exact(smc, ctx, scheme, N):
     """Every scheme's indices equal the oracle's bit for bit when the GPU is fed
-    the oracle's weights; the points come from each side's own Philox."""
+    the oracle's weights; the points come from each side's own Philox. From
+    N = 2^22 on a workgroup of the sorted schemes' search takes 2048 points."""
     announce(f"resample {scheme} N={N}")
     W = osmc.normalise(lognormal_logw(N, seed=N % 97))
     idx = torch.empty(N, dtype=torch.int32).cuda()
