@@ -137,23 +137,33 @@ GRAPH_STEPS = {"gmm1d_k4_n1000_N131072": 100, "gmm1d_k4_n100_N1024": 10}
 PT_ITERS_PER_GRAPH = 64  # population-MCMC iterations per replay in the paper's runs
 
 
-def ops_per_eval(k: int, form: str = "direct") -> float:
-    """Algorithmic VALU issue slots of one particle x datum evaluation in the
-    FP32 form for 1-D data, which runs in the expanded split about a data centre
-    c (exp2 counted as TRANS_SLOTS slots):
-    direct (waves whose particles sit near the data, as in a population that
-    has reached the posterior): per component one FMA (x = C + B (y - c)) and
-    one exp2; per datum k-1 adds, the multiply by the datum's factor 2^-q and
-    the product update: 2k + 1 VALU + k transcendental (17 slots for k = 4; 13
-    with exp2 at one).
-    shifted (waves holding a particle far from the data): per component the FMA,
-    a shift subtract and the exp2; per datum the maximum (v_max3 folds two
-    comparisons), k-1 adds, the product update and the block sum of max - q:
-    3k + ceil((k-1)/2) + 2 VALU + k transcendental (24 slots for k = 4; 20 with
-    exp2 at one)."""
+def ops_per_eval(k: int, form: str = "pivot") -> float:
+    """Algorithmic VALU issue slots of one particle x datum evaluation in an
+    FP32 form for 1-D data (exp2 counted as TRANS_SLOTS slots):
+    pivot (the form the samplers' data in ascending order take): per
+    component other than the particle's pivot one FMA (its exponent offset,
+    linear in the datum) and one exp2; per datum k-2 adds and one FMA into the
+    running product: 2k - 2 VALU + k - 1 transcendental (12 slots for k = 4;
+    9 with exp2 at one). The pivot's own terms come per window of 64 data from
+    sums the wave shares, outside the per-datum count.
+    direct (plain form, waves near the data): per component two FMAs and one
+    exp2; per datum k-1 adds and the product update: 3k VALU + k
+    transcendental (20 slots for k = 4).
+    shifted (plain form, waves holding a particle far from the data): per
+    component two FMAs, a shift subtract and the exp2; per datum the maximum
+    (v_max3 folds two comparisons), k-1 adds, the product update and the block
+    sum of maxima: 4k + ceil((k-1)/2) + 1 VALU + k transcendental (27 slots for
+    k = 4)."""
+    if form == "pivot":
+        return 2.0 * k - 2.0 + TRANS_SLOTS * (k - 1)
     if form == "direct":
-        return 2.0 * k + 1.0 + TRANS_SLOTS * k
-    return 3.0 * k + (k // 2) + 2.0 + TRANS_SLOTS * k
+        return 3.0 * k + TRANS_SLOTS * k
+    return 4.0 * k + (k // 2) + 1.0 + TRANS_SLOTS * k
+
+
+def trans_per_eval(k: int, form: str = "pivot") -> int:
+    """exp2 instructions per evaluation in the form of ops_per_eval."""
+    return k - 1 if form == "pivot" else k
 
 
 def log(msg):
@@ -525,7 +535,7 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     ctx.check(s.stream)
     # the timed steps' moves: (observation, tile) pairs in the shifted form
     step_pairs = steps * cfg.n_moves * ((cfg.N + 63) // 64) * cfg.n
-    direct_steps = 1.0 - ctx.fp32_shifted_data(reset=True) / step_pairs
+    shifted_steps = ctx.fp32_shifted_data(reset=True) / step_pairs
     res = s.results()          # the timed run's final population (before the kernel timing)
     ms_step = (t1 - t0) * 1e3 / steps
     # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept)
@@ -539,16 +549,16 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
         n_accept=acc, stream=s.stream), reps)
     ctx.check(s.stream)
     accept_rate = acc.item() / ((reps + 1) * cfg.N)
-    direct = None
+    shifted = None
     if prec == "fp32":
         # (observation, tile) pairs of the reps + 1 launches (one untimed) that
-        # left the direct form (the sub-block tail of each slice not counted)
+        # went through the plain shifted form
         pairs = (reps + 1) * ((cfg.N + 63) // 64) * cfg.n
-        direct = 1.0 - ctx.fp32_shifted_data(reset=True) / pairs
+        shifted = ctx.fp32_shifted_data(reset=True) / pairs
     move_steps_ms = moves_of_steps(smc, torch, ctx, cfg, g, s, betas, prec, steps)
-    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, direct_share=direct,
+    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, shifted_share=shifted,
                 accept_rate=accept_rate, move_steps_ms=move_steps_ms,
-                direct_share_steps=direct_steps if prec == "fp32" else None,
+                shifted_share_steps=shifted_steps if prec == "fp32" else None,
                 resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"], theta=res["theta"], l=res["l"],
                 t=res["t"])
@@ -627,21 +637,24 @@ def main():
         "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
         "ops_per_eval": ops_per_eval(cfg.k),
-        # the looser bound with exp2 charged one slot (13 slots per direct evaluation)
-        "frac_exp_one_slot": kern_evals * (ops_per_eval(cfg.k) - (TRANS_SLOTS - 1.0) * cfg.k)
+        "form": "pivot",
+        # the looser bound with exp2 charged one slot (9 slots per evaluation)
+        "frac_exp_one_slot": kern_evals * (ops_per_eval(cfg.k)
+                                           - (TRANS_SLOTS - 1.0) * trans_per_eval(cfg.k))
                              / PEAK_LANE_OPS,
         "valu_busy_measured": move_valu_busy(slices32),
         "counters": {"slices": MOVE_COUNTERS["slices"], "waves": MOVE_COUNTERS["waves"],
                      "apply_to_timed_shape": counters_apply(slices32)},
         "kernel_ms": r32["kernel_ms"],
         "kernel_evals_per_s": kern_evals,
-        # the timed launches' per-datum form: 1 - (observation, tile) pairs that
-        # left the direct form over all pairs (device counter; the < 8
-        # observations after each slice's last full block of 8 always take the
-        # shifted form and count as direct here)
+        # the timed launches' per-datum forms: the share of (observation, tile)
+        # pairs that went through the plain shifted form (device counter; the
+        # rest took the pivot form, or the plain direct form in windows the
+        # pivot form refused; the < 8 observations after the last full block of
+        # 8 of each range the plain forms take are not counted)
         "accept_rate": r32["accept_rate"],
-        "direct_form_share": r32["direct_share"],
-        "direct_form_share_timed_steps": r32["direct_share_steps"],
+        "shifted_form_share": r32["shifted_share"],
+        "shifted_form_share_timed_steps": r32["shifted_share_steps"],
         "launch_slices": slices32,
     }
     cpu = oracle_error = None
@@ -785,6 +798,7 @@ def probes(smc, torch, ctx, reps):
     N, n = 1 << 20, 4096
     with torch.cuda.stream(s):
         y = torch.as_tensor(make_mixture_data(n, np.array([-3.0, 0.0, 3.0, 6.0]), 0.55, 7)).cuda()
+        smc.smc_sort_data(y, stream=s)
         th = torch.as_tensor(theta_prior_draws(N, 4, 1, seed=8)).cuda()
         l = torch.empty(N, dtype=torch.float64, device="cuda")
     ms = time_launches(torch, s, lambda i: smc.smc_loglik(ctx, g, y, th, "fp32", out=l, stream=s),
@@ -792,8 +806,8 @@ def probes(smc, torch, ctx, reps):
     evals = N * n / (ms * 1e-3)
     out["loglik_fp32_N1048576_n4096"] = {
         "us": ms * 1e3, "evals_per_s": evals,
-        "form": "shifted (prior draws, far from the data)",
-        "frac_issue_slots": evals * ops_per_eval(4, "shifted") / PEAK_LANE_OPS}
+        "form": "pivot (prior draws, far from the data; data in ascending order)",
+        "frac_issue_slots": evals * ops_per_eval(4, "pivot") / PEAK_LANE_OPS}
     del th, l
     for logN in (17, 20, 24):
         N = 1 << logN

@@ -128,7 +128,7 @@ const char* smc_last_error(void);
  * completes in a second, per-particle kernel. Other kernels use min(slices, 16).
  * Results depend on the slicing only through the order of FP64 additions and,
  * in FP32, through which of the equivalent per-datum forms (see smc_loglik) a
- * wave's slice takes and the data centre of its expanded form. */
+ * wave's slice takes and, in the pivot form, through its windows. */
 int smc_set_slices(smc_ctx ctx, int32_t slices);
 
 /* Which launches a rule of the launch table shapes. */
@@ -174,13 +174,19 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  * error below 1e-6). The per-datum sum is taken directly for waves whose
  * particles sit near the data (weights of total mass <= 1) and relative to its
  * largest term otherwise (those maxima added in 16-term FP32 blocks promoted to
- * FP64). For d = 1 both are evaluated in an expanded form: with c the midrange
- * of the first 64 data of a wave's slice, the squared distance splits into a
- * per-particle affine function of y - c (one FMA per component) and a
- * per-datum term s^2 (y - c)^2 that the wave forms once for all its particles;
- * data farther from c than that split's range bound go through the plain form.
- * All forms are within the bound (the form, and for d = 1 the centre, depend on
- * the wave, fixed for a given launch shape and population); BF16X3: d = 8, k in
+ * FP64). For d = 1 a third form, the pivot form, runs first: a wave's slice
+ * goes in windows of 64 data; in a window with midpoint c each particle's
+ * component p with the largest exponent at c is its pivot, each other
+ * component's exponent difference to it is linear in y (one FMA and one exp2
+ * per datum and component), every per-datum factor is at least 1, and the
+ * pivot's own exponents summed over the window come in FP64 from two data sums
+ * the wave forms once for all its particles. A window is taken when none of
+ * the wave's particles can see an exponent difference above 12 in it
+ * (narrow windows; data in ascending order, see smc_sort_data, give them);
+ * other windows, and windows holding a datum or parameter that is not finite,
+ * go through the plain forms. All forms are within the bound (the form
+ * depends on the wave and the data order, fixed for a given launch shape,
+ * population and data array); BF16X3: d = 8, k in
  * {1,2,4,8}: the quadratic forms as one K = 64 BF16 MFMA contraction of
  * three-way (hi/mid/lo) split operands with FP32 accumulation, then the same
  * FP32 epilogue (relative error below 1e-6). */
@@ -428,13 +434,26 @@ int smc_graph_destroy(smc_graph g);
  * smc_loglik): *out = the number of (observation, 64-particle tile) pairs that
  * FP32 moves launched one move at a time (smc_rwmh_move, and the moves of
  * smc_step / smc_steps unless a step's several moves run in one launch)
- * evaluated in a shifted form (plain or expanded) since the last reset because
- * a wave left (or never took) the direct forms, summed over
- * every context on the context's device. Not counted: the fewer than 8
- * observations after the last full block of 8 of each wave's data slice, which
- * always take the shifted form. With reset != 0 the count is cleared after the
- * read. Waves that stay in the direct form do not touch the counter. */
+ * evaluated in the plain shifted form since the last reset, summed over every
+ * context on the context's device: the data of a wave's slice (d > 1, or
+ * slices shorter than 32) or of a window the pivot form refused (d = 1) from
+ * where the wave left, or never took, the plain direct form. Not counted: the
+ * fewer than 8 observations after the last full block of 8 of each such range,
+ * which always take the shifted form. With reset != 0 the count is cleared
+ * after the read. Waves that take only the pivot and direct forms do not touch
+ * the counter. */
 int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset);
+
+/* Sort n FP32 values of the device array y in place into ascending order
+ * (Mixture Modelling section: the data are independent draws, so the
+ * likelihood, a sum over data, does not depend on their order; the 1-D FP32
+ * likelihood's pivot form wants them ascending). The order is that of the
+ * values' bit patterns read as sign-magnitude integers: -NaN < -inf < ... <
+ * -0 < +0 < ... < +inf < +NaN. Device-side bitonic network, enqueued on
+ * stream; no allocation. n in [0, 2^30] (0 and 1: nothing to do); y may be
+ * NULL only when n is 0. The samplers of the Python binding sort their own
+ * copy of 1-D data once when they are created. */
+int smc_sort_data(float* y, int64_t n, void* stream);
 
 /* Diagnostics used by the CPU/GPU bit-identity tests: Philox words and
  * Box-Muller normals for indices 0..count-1 of one stream.

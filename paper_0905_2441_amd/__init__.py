@@ -27,6 +27,7 @@ from .api import (  # noqa: F401
     smc_rng_normals,
     smc_rng_words,
     smc_rwmh_move,
+    smc_sort_data,
     smc_step,
     smc_steps,
     smc_step_batched,

@@ -119,6 +119,7 @@ SIGNATURES = {
     "smc_graph_end": (c_int, [_P, _P, POINTER(c_void_p)]),
     "smc_graph_launch": (c_int, [_P, _P]),
     "smc_graph_destroy": (c_int, [_P]),
+    "smc_sort_data": (c_int, [_P, c_int64, _P]),
     "smc_rng_words": (c_int, [c_uint64, c_int64, c_uint32, c_uint32, c_uint32, c_uint32, _P, _P]),
     "smc_rng_normals": (c_int, [c_uint64, c_int64, c_int32, c_uint32, c_uint32, c_uint32, _P,
                                 _P]),

@@ -379,6 +379,13 @@ def fsv_steps(ctx: Context, model, y, x, x_tmp, logw, t_dev, n_steps, seed, ess_
         _ptr(moments, torch.float64, "moments", T * 2 * k), _stream(stream)))
 
 
+def smc_sort_data(y: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sort the FP32 device tensor y in place into ascending order
+    (smc_sort_data) and return it."""
+    L.check(L.load().smc_sort_data(_ptr(y, torch.float32, "y"), int(y.numel()), _stream(stream)))
+    return y
+
+
 def smc_rng_words(seed, count, block, step, purpose, move=0, out=None, stream=None):
     if out is None:
         out = torch.empty((count, 4), dtype=torch.int32, device="cuda")

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build", "libsmcgpu")
 LIB = os.path.join(PKG, "libsmcgpu.so")
 SOURCES = ["gmm_kernels.hip", "ddim_mfma.hip", "smc_kernels.hip", "batched.hip", "fsv.hip",
-           "noalloc.hip", "capi.hip"]
+           "noalloc.hip", "sort.hip", "capi.hip"]
 ARCH = "gfx950"
 
 # Floating-point contraction is off so that every +, -, * rounds exactly as

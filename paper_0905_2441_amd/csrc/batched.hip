@@ -182,7 +182,7 @@ k_b_move(const BatchRun* __restrict__ runs, const BatchUnit* __restrict__ units,
             int j0, j1;
             slice_bounds(n, sl, S, j0, j1);
             part = slice_partial<K, 1, PREC>(y + rd.y_off, j0, j1, pr, g, near_data(l_src, n, g),
-                                             ExpStage{expanded_row<PREC, 1, kBatchWaves>()});
+                                             PivotStage{pivot_row<PREC, 1, kBatchWaves>()});
         }
         red[w][lane] = part;
         __syncthreads();

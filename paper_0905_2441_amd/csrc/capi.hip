@@ -1114,6 +1114,14 @@ int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset) {
     return SMC_OK;
 }
 
+int smc_sort_data(float* y, int64_t n, void* stream) {
+    if (n < 0 || n > (int64_t{1} << 30) || (n > 0 && !y))
+        return fail(SMC_ERR_INVALID_ARG, "n must be in [0, 2^30] and y set when n > 0");
+    const hipError_t e = launch_sort_data(y, n, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "sort launch");
+    return SMC_OK;
+}
+
 int smc_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step, uint32_t purpose,
                   uint32_t move, uint32_t* out, void* stream) {
     if (count < 1 || count > INT32_MAX || !out) return fail(SMC_ERR_INVALID_ARG, "bad count or out");

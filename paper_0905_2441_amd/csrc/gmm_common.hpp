@@ -18,69 +18,66 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 }
 
 // Sum over data j in [j0, j1) of log2 sum_i 2^{a_ij}, a_ij = log2 w_i - s^2 ||y_j - mu_i||^2
-// (FP32 arithmetic, FP64 result). The per-datum sums are multiplied into a
-// running product that is renormalised (frexp) after each block of data, its
-// exponents summed as integers. Three forms:
+// (FP32 per-datum arithmetic, FP64 result). Per-datum factors are multiplied
+// into a running FP32 product that is renormalised (frexp) after each block of
+// data, its exponents summed as integers. Three forms:
+//  - pivot (1-D data with a staging row, slices of at least kPivotMinData
+//    data): the slice goes window by window, 64 data at a time. In a window
+//    with midpoint c and half-width h, each particle takes as its pivot p the
+//    component with the largest exponent at c. The difference of two
+//    exponents is linear in y, so
+//      log2 sum_i 2^{a_ij} = a_pj + log2(1 + sum_{i != p} 2^{t_ij}),
+//      t_ij = dX_i + dB_i (y_j - c),  dX_i = a_i(c) - a_p(c) <= 0,
+//      dB_i = 2 s^2 (mu_i - mu_p),
+//    and sum_j a_pj over the window follows in FP64 from two sums over the
+//    window's data (of y_j - c and of its square) that every particle shares.
+//    Per datum and particle that is K-1 FMAs, K-1 exp2, K-2 adds and one FMA
+//    into the product. Every factor is at least 1, so the product cannot
+//    underflow; a window is taken when, for every particle of the wave, every
+//    dX_i + |dB_i| h (the largest t_ij the window can hold) is at most
+//    kPivotOverMax, which keeps a block of 8 factors below 2^120. A window
+//    that some particle fails (components far apart across a wide window, a
+//    datum or parameter not finite) goes through the plain forms below. On
+//    data in ascending order the windows are narrow and nearly all are
+//    taken; on unordered data nearly none are;
 //  - direct (weights of total mass <= 1): e_j = sum_i 2^{a_ij}. Every factor
 //    is then <= 1, so the partial products only fall, and a block of 8 whose
 //    product ends at or above 2^-100 had no factor or partial product in the
 //    FP32 subnormal range: it is as accurate as the shifted form;
-//  - expanded direct (1-D data, for the windows of 64 data whose every datum
-//    keeps s^2 (y - c)^2 <= kExpQmax, c the midrange of the slice's first 64
-//    data): the same e_j, computed from the split a_ij = x_ij - q_j
-//    (expanded_direct below), one FMA and one exp2 per component instead of
-//    two FMAs and an exp2; the direct form takes over from the first window
-//    that does not keep it;
 //  - shifted: each datum's sum is taken relative to its largest term
 //    m_j = max_i a_ij (blocks of 16), and the m_j are added apart.
-// A wave starts in a direct form when every lane's `near` hint holds (the
-// caller's guess that the particle sits near the data, from its current
-// log-likelihood) and, at the first block where any of its lanes ends below
-// 2^-100 (a particle far from these data, or a NaN), drops that block and
-// runs the rest of its slice in the shifted form; otherwise it runs the
-// shifted form throughout. All forms are within the FP32 error bound; which
-// one a particle's data went through depends on the wave it shares (fixed for
-// a given launch shape and population). j0 and j1 must be the same in every
-// lane of the wave, and every lane of the wave must take part (the data are
-// read by scalar loads, or staged by the wave's lanes in LDS). With
-// shifted_ctr set, a wave that left (or never took) the direct forms adds the
-// number of data it then took in the shifted form, up to its slice's last
-// full block of 8, to the counter slot shifted_ctr[slot] (one atomic per such
-// wave, slots spread so that waves rarely share one; the fewer than 8 data
-// after the last full block always take the shifted form and are not
-// counted).
+// The plain forms: a wave starts in the direct form when every lane's `near`
+// hint holds (the caller's guess that the particle sits near the data, from
+// its current log-likelihood) and, at the first block where any of its lanes
+// ends below 2^-100 (a particle far from these data, or a NaN), drops that
+// block and takes the shifted form for the rest of its slice; otherwise it
+// takes the shifted form throughout. All forms are within the FP32 error
+// bound; which one a particle's data went through depends on the wave it
+// shares (fixed for a given launch shape, population and data order). j0 and
+// j1 must be the same in every lane of the wave, and every lane of the wave
+// must take part (the forms use cross-lane operations, scalar loads and the
+// wave's LDS row). With shifted_ctr set, a wave adds the number of data it
+// took in the shifted form, counted up to the last full block of 8 of each
+// range the plain forms took (a whole slice, or a refused window), to the
+// counter slot shifted_ctr[slot] (one atomic per such wave, slots spread so
+// that waves rarely share one; the fewer than 8 data after such a range's
+// last full block always take the shifted form and are not counted).
 constexpr int kFormSlots = 1024;
-// Data staged per window of the expanded forms (one per lane).
-constexpr int kExpWin = kWave;
-// Shortest slice that takes the expanded forms (below it their per-wave
-// set-up, the centre and the FP64 B and C, costs more than they save).
-constexpr int kExpMinData = 128;
-// Largest s^2 (y - c)^2 for which a datum takes the expanded forms: their
-// terms 2^{x_ij} then stay below 2^120 and the data factors above 2^-120, and
-// |x_ij| < 128 bounds x_ij's rounding error by 2^-18.
-constexpr double kExpQmax = 120.0;
+// Data per window of the pivot form (one per lane).
+constexpr int kPivotWin = kWave;
+// Shortest slice that takes the pivot form (below it the per-window set-up
+// costs more than it saves).
+constexpr int kPivotMinData = 32;
+// Largest t_ij a window of the pivot form may hold: with K <= 8 components a
+// factor is then below 1 + 7 * 2^12 < 2^15 and a block of 8 below 2^120.
+constexpr float kPivotOverMax = 12.0f;
+static_assert(SMC_KMAX <= 8, "kPivotOverMax assumes at most 8 components");
 
-// The expanded forms (1-D data). With c a data centre, y' = y - c (FP32) and
-// m_i = mu_i - c,
-//   a_ij = log2 w_i - s2 (y'_j - m_i)^2 = x_ij - q_j,
-//   x_ij = C_i + B_i y'_j,  B_i = 2 s2 m_i,  C_i = log2 w_i - s2 m_i^2,
-//   q_j = s2 y'_j^2,
-// and q_j does not depend on the particle: one FMA per component gives x_ij,
-// and each datum's log2 sum_i 2^{a_ij} follows from the x_ij and q_j.
-// B_i and C_i are formed in FP64 and rounded once, C_i with B_i's rounding
-// error at y' = m_i folded in, so that x_ij is exact up to its own rounding at
-// the component's centre. The wave stages its data 64 at a time, one datum per
-// lane (q in FP64), in its own row of LDS (`row`, 2 * kExpWin floats), and
-// reads them back as broadcasts; each lane fetches its datum of the next
-// window while the current one is consumed. A window holding a datum with
-// q_j > kExpQmax (or not finite) ends a form at its start: this bounds the
-// magnitude of x_ij and so its rounding error (and, in the direct form, keeps
-// 2^{x_ij} finite and g_j normal).
-// A wave's staging for the expanded forms: its LDS row of 2 * kExpWin floats
+// A wave's staging for the pivot form: its LDS row of kPivotWin floats
 // (nullptr: plain forms only) and, when `pre` is set, each lane's datum
-// y[j0 + lane] of its slice already loaded (a caller may issue that load early,
-// ahead of other work).
-struct ExpStage {
+// y[j0 + lane] of its slice already loaded where j0 + lane < j1 (a caller may
+// issue that load early, ahead of other work).
+struct PivotStage {
     float* row = nullptr;
     float y0 = 0.0f;
     bool pre = false;
@@ -97,147 +94,123 @@ __device__ __forceinline__ void slice_bounds(int n, int sl, int nsl, int& j0, in
     j1 = wave_uniform(blocks && sl + 1 < nsl ? b & ~7 : b);
 }
 
-template <int K>
-struct Expanded {
-    double s2;                 // s^2 = log2(e) / (2 sigma2)
-    float c;
-    float B[K], C[K];
-};
-
-// c = the midrange of the data in [j0, jlim) (at most 64 of them) and the
-// lane's B_i, C_i. False when those data are not all finite.
-// v: the lane's datum y[j0 + lane] (unused past jlim).
-template <int K>
-__device__ __forceinline__ bool expanded_setup(float v, int j0, int jlim,
-                                               const double (&mu)[K], const GmmDev& g,
-                                               Expanded<K>& f) {
+// The pivot form over the 1-D slice [j0, j1) (see partial_fp32): adds the
+// slice's terms to prod, expo and msum and returns the count of data the
+// plain forms took in the shifted form. nms[i] = -s mu_i in FP32; plain(ja, jb)
+// runs the plain forms over [ja, jb) and returns its own such count.
+template <int K, class Plain>
+__device__ __forceinline__ int pivot_slice(const float* __restrict__ y, int j0, int j1,
+                                           const double (&mu)[K], const GmmDev& g,
+                                           const float (&nms)[K], const PivotStage& st,
+                                           float& prod, int& expo, double& msum,
+                                           Plain&& plain) {
     constexpr double kLog2eD = 1.4426950408889634;
-    const int jj = j0 + lane_id();
-    const float lo = wave_min_dpp(jj < jlim ? v : INFINITY);
-    const float hi = wave_max_dpp(jj < jlim ? v : -INFINITY);
-    f.s2 = g.inv2s2 * kLog2eD;
-    f.c = 0.5f * lo + 0.5f * hi;          // the same in every lane
-    if (!(fabsf(f.c) <= 3.0e38f)) return false;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const double m = mu[i] - static_cast<double>(f.c);
-        const double b = 2.0 * f.s2 * m;
-        f.B[i] = static_cast<float>(b);
-        f.C[i] = static_cast<float>(g.lw[i] * kLog2eD - f.s2 * m * m +
-                                    (b - static_cast<double>(f.B[i])) * m);
-    }
-    return true;
-}
-
-// The expanded direct form over the blocks of 8 data from j to jend:
-// e_j = g_j sum_i 2^{x_ij} with g_j = 2^{-q_j} (= 2^-round(q) times the
-// hardware exp2 of the small remainder), staged as (y'_j, g_j) pairs. Updates
-// prod and expo over the blocks it took and moves j past them; returns true
-// when it stopped for the range (the caller goes on in the scalar-load direct
-// form from j), false when it took every block or a block failed the 2^-100
-// check (the caller goes on in the shifted forms). ycur: the lane's datum
-// y[j + lane] (unused past jend).
-template <int K>
-__device__ __forceinline__ bool expanded_direct(const float* __restrict__ y, int jend,
-                                                const Expanded<K>& f, float* row, float& prod,
-                                                int& expo, int& j, float ycur) {
-    constexpr float kFloor = 0x1p-100f;
+    constexpr int KO = K > 1 ? K - 1 : 1;
     const int lane = lane_id();
-    for (int wb = j; wb < jend; wb += kExpWin) {
-        const int jj = wb + lane;
-        bool ok = true;
+    const float s = g.s32;
+    const double s2 = g.inv2s2 * kLog2eD;
+    float* row = st.row;
+    float beta[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) beta[i] = static_cast<float>(2.0 * s2 * mu[i]);
+    int counted = 0;
+    float ycur = st.pre ? st.y0 : (j0 + lane < j1 ? y[j0 + lane] : 0.0f);
+    for (int wb = j0; wb < j1; wb += kPivotWin) {
+        const int nw = wave_uniform(j1 - wb < kPivotWin ? j1 - wb : kPivotWin);
+        const bool in = lane < nw;
+        const float v = ycur;
+        const int jn = wb + kPivotWin + lane;
+        ycur = jn < j1 ? y[jn] : 0.0f;        // the next window's datum, in flight
+        // the window's range and its data sums about the midpoint (all lanes)
+        const float lo = wave_min_dpp(in ? v : INFINITY);
+        const float hi = wave_max_dpp(in ? v : -INFINITY);
+        const float c = 0.5f * lo + 0.5f * hi;
+        const float h = 0.5f * hi - 0.5f * lo;
+        const float dv = in ? v - c : 0.0f;
+        const float S1 = wave_sum_dpp(dv);
+        const float S2 = wave_sum_dpp(dv * dv);
         wave_sync();                          // the previous window's reads come first
-        if (jj < jend) {
-            const float yp = ycur - f.c;
-            const double q = f.s2 * static_cast<double>(yp) * static_cast<double>(yp);
-            ok = q <= kExpQmax;
-            const double qi = rint(q);
-            row[2 * lane] = yp;
-            row[2 * lane + 1] = __builtin_amdgcn_ldexpf(
-                __builtin_amdgcn_exp2f(static_cast<float>(qi - q)), -static_cast<int>(qi));
-        }
-        // the next window's datum, in flight while this window is consumed
-        ycur = jj + kExpWin < jend ? y[jj + kExpWin] : 0.0f;
-        if (!__all(ok)) return true;
+        row[lane] = dv;
         wave_sync();                          // the window is written before it is read
-        const int we = wb + kExpWin < jend ? wb + kExpWin : jend;
-        for (; j < we; j += 8) {
-            float p = prod;
+        // the lane's pivot and the others' offsets and slopes
+        float a[K];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const float yp = row[2 * (j - wb + u)];
-                const float gj = row[2 * (j - wb + u) + 1];
-                float e = __builtin_amdgcn_exp2f(__builtin_fmaf(yp, f.B[0], f.C[0]));
+        for (int i = 0; i < K; ++i) {
+            const float t = __builtin_fmaf(c, s, nms[i]);
+            a[i] = __builtin_fmaf(-t, t, g.lw2[i]);
+        }
+        int piv = 0;
+        float best = a[0];
 #pragma unroll
-                for (int i = 1; i < K; ++i)
-                    e += __builtin_amdgcn_exp2f(__builtin_fmaf(yp, f.B[i], f.C[i]));
-                p *= e * gj;
+        for (int i = 1; i < K; ++i) {
+            const bool up = a[i] > best;
+            best = up ? a[i] : best;
+            piv = up ? i : piv;
+        }
+        float bp = beta[0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) bp = piv == i ? beta[i] : bp;
+        float dX[KO], dB[KO];
+        bool ok = h <= 3.0e38f;               // false for a datum not finite
+#pragma unroll
+        for (int o = 0; o + 1 < K; ++o) {
+            const bool up = o >= piv;
+            dX[o] = (up ? a[o + 1] : a[o]) - best;
+            dB[o] = (up ? beta[o + 1] : beta[o]) - bp;
+            ok &= __builtin_fmaf(fabsf(dB[o]), h, dX[o]) <= kPivotOverMax;
+        }
+        if (!__all(ok)) {
+            counted += plain(wb, wb + nw);
+            continue;
+        }
+        if constexpr (K > 1) {
+            auto factor = [&](float p, float d) {
+                float e = __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[0], dX[0]));
+#pragma unroll
+                for (int o = 1; o + 1 < K; ++o)
+                    e += __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[o], dX[o]));
+                return __builtin_fmaf(p, e, p);
+            };
+            int u = 0;
+            for (; u + 8 <= nw; u += 8) {
+                float p = prod;
+#pragma unroll
+                for (int q = 0; q < 8; q += 4) {
+                    const float4 d4 = *reinterpret_cast<const float4*>(row + u + q);
+                    p = factor(p, d4.x);
+                    p = factor(p, d4.y);
+                    p = factor(p, d4.z);
+                    p = factor(p, d4.w);
+                }
+                expo += __builtin_amdgcn_frexp_expf(p);
+                prod = __builtin_amdgcn_frexp_mantf(p);
             }
-            if (!__all(p >= kFloor)) return false;
-            expo += __builtin_amdgcn_frexp_expf(p);
-            prod = __builtin_amdgcn_frexp_mantf(p);
-        }
-    }
-    return false;
-}
-
-// The expanded shifted form over the blocks of 16 data from j to jend:
-// log2 e_j = (M_j - q_j) + log2 sum_i 2^{x_ij - M_j} with M_j = max_i x_ij,
-// staged as (y'_j, q_j) pairs (q_j rounded to FP32). The M_j - q_j are summed
-// in FP32 per block and added to msum in FP64, as in the shifted form.
-// Updates prod, expo and msum and moves j past the blocks it took; stops at
-// the first window out of range.
-template <int K>
-__device__ __forceinline__ void expanded_shifted(const float* __restrict__ y, int jend,
-                                                 const Expanded<K>& f, float* row, float& prod,
-                                                 int& expo, double& msum, int& j) {
-    constexpr int US = 16;
-    const int lane = lane_id();
-    float ycur = j + lane < jend ? y[j + lane] : 0.0f;
-    for (int wb = j; wb < jend; wb += kExpWin) {
-        const int jj = wb + lane;
-        bool ok = true;
-        wave_sync();                          // the previous window's reads come first
-        if (jj < jend) {
-            const float yp = ycur - f.c;
-            const double q = f.s2 * static_cast<double>(yp) * static_cast<double>(yp);
-            ok = q <= kExpQmax;
-            row[2 * lane] = yp;
-            row[2 * lane + 1] = static_cast<float>(q);
-        }
-        ycur = jj + kExpWin < jend ? y[jj + kExpWin] : 0.0f;
-        if (!__all(ok)) return;
-        wave_sync();                          // the window is written before it is read
-        const int we = wb + kExpWin < jend ? wb + kExpWin : jend;
-        for (; j < we; j += US) {
-            float mblk = 0.0f;
-#pragma unroll 8
-            for (int u = 0; u < US; ++u) {
-                const float yp = row[2 * (j - wb + u)];
-                const float qj = row[2 * (j - wb + u) + 1];
-                float x[K];
-#pragma unroll
-                for (int i = 0; i < K; ++i) x[i] = __builtin_fmaf(yp, f.B[i], f.C[i]);
-                float m = x[0];
-#pragma unroll
-                for (int i = 1; i < K; ++i) m = fmaxf(m, x[i]);
-                float e = __builtin_amdgcn_exp2f(x[0] - m);
-#pragma unroll
-                for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(x[i] - m);
-                prod *= e;
-                mblk += m - qj;
+            if (u < nw) {
+                float p = prod;
+                for (; u < nw; ++u) p = factor(p, row[u]);
+                expo += __builtin_amdgcn_frexp_expf(p);
+                prod = __builtin_amdgcn_frexp_mantf(p);
             }
-            msum += static_cast<double>(mblk);
-            expo += __builtin_amdgcn_frexp_expf(prod);
-            prod = __builtin_amdgcn_frexp_mantf(prod);
         }
+        // the pivots' own terms over the window, in FP64
+        double mp = mu[0], lwp = g.lw[0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) {
+            mp = piv == i ? mu[i] : mp;
+            lwp = piv == i ? g.lw[i] : lwp;
+        }
+        const double d = static_cast<double>(c) - mp;
+        const double sq = static_cast<double>(S2) +
+                          d * (2.0 * static_cast<double>(S1) + static_cast<double>(nw) * d);
+        msum += static_cast<double>(nw) * lwp * kLog2eD - s2 * sq;
     }
+    return counted;
 }
 
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const double (&mu)[K * D], const GmmDev& g,
-                                               bool near, const ExpStage& st,
+                                               bool near, const PivotStage& st,
                                                unsigned long long* shifted_ctr = nullptr) {
     constexpr int UF = 8;            // direct-form block
     constexpr int US = 16;           // shifted-form block
@@ -246,15 +219,9 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
     double msum = 0.0;
     float prod = 1.0f;
     int expo = 0;
-    int j = j0;
-    // -s mu in FP32 for the plain forms, formed where they run (not held
-    // through the expanded forms)
-    float nms[K * D];
-    auto form_nms = [&]() {
+    float nms[K * D];                // -s mu in FP32
 #pragma unroll
-        for (int c = 0; c < K * D; ++c)
-            nms[c] = static_cast<float>(-(static_cast<double>(s) * mu[c]));
-    };
+    for (int c = 0; c < K * D; ++c) nms[c] = static_cast<float>(-(static_cast<double>(s) * mu[c]));
     auto exponents = [&](const float* yj, float (&a)[K]) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -292,70 +259,62 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         for (int i = 1; i < K; ++i) e += __builtin_amdgcn_exp2f(a[i]);
         return e;
     };
-    // the expanded forms' setup (1-D data, a staging row given): the centre of
-    // the slice's first 64 data
-    float* row = st.row;
-    Expanded<K> xf;
-    bool xok = false;
-    float y0 = 0.0f;
-    if constexpr (D == 1) {
-        if (row != nullptr && j1 - j0 >= kExpMinData) {
-            // j1 - j0 >= 64: every lane's datum y[j0 + lane] is in the slice
-            y0 = st.pre ? st.y0 : y[j0 + lane_id()];
-            xok = expanded_setup<K>(y0, j0, j0 + kExpWin, mu, g, xf);
-        }
-    }
-    if (g.unit_mass != 0 && __all(near)) {
-        bool plain = true;                    // whether the scalar-load direct form runs from j
-        if constexpr (D == 1) {
-            if (xok) plain = expanded_direct<K>(y, j0 + ((j1 - j0) & ~(UF - 1)), xf, row, prod,
-                                                expo, j, y0);
-        }
-        if (plain) {
-            form_nms();
-            for (; j + UF <= j1; j += UF) {
+    // the plain forms over [ja, jb); the direct form, once left, is not taken
+    // again in this slice. Returns the data taken in the shifted form up to
+    // the range's last full block of 8.
+    bool take_direct = g.unit_mass != 0 && __all(near);
+    auto plain = [&](int ja, int jb) {
+        int j = ja;
+        if (take_direct) {
+            for (; j + UF <= jb; j += UF) {
                 const float* yb = y + (size_t)wave_uniform(j) * D;    // wave-uniform: scalar loads
                 float p = prod;
 #pragma unroll
                 for (int u = 0; u < UF; ++u) p *= direct(yb + u * D);
-                if (!__all(p >= kFloor)) break;
+                if (!__all(p >= kFloor)) {
+                    take_direct = false;
+                    break;
+                }
                 expo += __builtin_amdgcn_frexp_expf(p);
                 prod = __builtin_amdgcn_frexp_mantf(p);
             }
         }
-    }
-    if (shifted_ctr != nullptr) {
-        const int counted = ((j1 - j0) & ~(UF - 1)) - (j - j0);
-        if (counted > 0 && lane_id() == 0) {
-            const int slot = (static_cast<int>(blockIdx.x) * (static_cast<int>(blockDim.x) >> 6) +
-                              wave_id()) & (kFormSlots - 1);
-            atomicAdd(shifted_ctr + slot, static_cast<unsigned long long>(counted));
-        }
-    }
-    if constexpr (D == 1) {
-        if (xok && j + US <= j1)
-            expanded_shifted<K>(y, j + ((j1 - j) & ~(US - 1)), xf, row, prod, expo, msum, j);
-    }
-    if (j < j1) form_nms();
-    for (; j + US <= j1; j += US) {
-        float mblk = 0.0f;
+        const int counted = ((jb - ja) & ~(UF - 1)) - (j - ja);
+        for (; j + US <= jb; j += US) {
+            float mblk = 0.0f;
 #pragma unroll 8
-        for (int u = 0; u < US; ++u) {
-            float m, e;
-            shifted(y + (size_t)(j + u) * D, m, e);
-            prod *= e;
-            mblk += m;
+            for (int u = 0; u < US; ++u) {
+                float m, e;
+                shifted(y + (size_t)(j + u) * D, m, e);
+                prod *= e;
+                mblk += m;
+            }
+            msum += static_cast<double>(mblk);
+            expo += __builtin_amdgcn_frexp_expf(prod);
+            prod = __builtin_amdgcn_frexp_mantf(prod);
         }
-        msum += static_cast<double>(mblk);
-        expo += __builtin_amdgcn_frexp_expf(prod);
-        prod = __builtin_amdgcn_frexp_mantf(prod);
-    }
 #pragma unroll 4
-    for (; j < j1; ++j) {
-        float m, e;
-        shifted(y + (size_t)j * D, m, e);
-        prod *= e;
-        msum += static_cast<double>(m);
+        for (; j < jb; ++j) {
+            float m, e;
+            shifted(y + (size_t)j * D, m, e);
+            prod *= e;
+            msum += static_cast<double>(m);
+        }
+        return counted;
+    };
+    int counted;
+    if constexpr (D == 1) {
+        if (st.row != nullptr && j1 - j0 >= kPivotMinData)
+            counted = pivot_slice<K>(y, j0, j1, mu, g, nms, st, prod, expo, msum, plain);
+        else
+            counted = plain(j0, j1);
+    } else {
+        counted = plain(j0, j1);
+    }
+    if (shifted_ctr != nullptr && counted > 0 && lane_id() == 0) {
+        const int slot = (static_cast<int>(blockIdx.x) * (static_cast<int>(blockDim.x) >> 6) +
+                          wave_id()) & (kFormSlots - 1);
+        atomicAdd(shifted_ctr + slot, static_cast<unsigned long long>(counted));
     }
     return msum + static_cast<double>(expo) + log2(static_cast<double>(prod));
 }
@@ -398,11 +357,11 @@ __device__ __forceinline__ bool near_data(double l, int n, const GmmDev& g) {
 
 // The slice partial of one lane for parameters pr[0..K*D-1] (FP64 values);
 // `near` is the hint of partial_fp32 and `st` the wave's staging for the
-// expanded forms; both unused in FP64.
+// pivot form; both unused in FP64.
 template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
                                                 const double (&pr)[K * D], const GmmDev& g,
-                                                bool near = true, const ExpStage& st = {},
+                                                bool near = true, const PivotStage& st = {},
                                                 unsigned long long* shifted_ctr = nullptr) {
     if constexpr (PREC == SMC_PREC_FP32) {
         return partial_fp32<K, D>(y, j0, j1, pr, g, near, st, shifted_ctr);
@@ -411,13 +370,13 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
     }
 }
 
-// This wave's staging row for the expanded forms in a kernel of at most W
-// waves per workgroup (a static LDS array of that kernel), or nullptr where the
-// forms do not apply (FP64, d > 1).
+// This wave's staging row for the pivot form in a kernel of at most W waves
+// per workgroup (a static LDS array of that kernel), or nullptr where the form
+// does not apply (FP64, d > 1).
 template <int PREC, int D, int W>
-__device__ __forceinline__ float* expanded_row() {
+__device__ __forceinline__ float* pivot_row() {
     if constexpr (PREC == SMC_PREC_FP32 && D == 1) {
-        __shared__ float win[W][2 * kExpWin];
+        __shared__ __align__(16) float win[W][kPivotWin];
         return win[wave_id()];
     } else {
         return nullptr;

@@ -6,30 +6,32 @@
 //   * wave w of the workgroup owns a data slice of about n/S observations
 //     (slice_bounds); its bounds are made wave-uniform, so in the plain forms
 //     every observation is fetched by a scalar load into SGPRs and broadcast
-//     to all 64 lanes, and in the expanded forms (1-D data) the wave stages
-//     its observations with their particle-free terms in its own LDS row and
-//     reads them back as broadcasts; no barrier inside the data loop;
+//     to all 64 lanes, and in the pivot form (1-D data) the wave stages its
+//     observations, 64 at a time, in its own LDS row and reads them back as
+//     broadcasts; no barrier inside the data loop;
 //   * the S per-slice partial sums of a particle meet in LDS and wave 0 adds
 //     them in slice order (bit-reproducible for a given S).
 // The paper evaluated one likelihood per thread over data in shared memory
 // and remarked that long data can be split over several threads (Comparison
 // subsection); here both are combined: lanes over particles, waves over data.
 //
-// FP32 form, per datum y and component i, in base-2 units:
-//   t_i = s*y - s*mu_i            (s = sqrt(log2(e)/(2 sigma2)); one FMA)
-//   a_i = log2 w_i - t_i^2        (one FMA)
-// and the datum's mixture sum e = sum_i 2^(a_i) (hardware v_exp_f32), taken
-// directly for waves near the data or relative to m = max_i a_i otherwise
-// (partial_fp32). For 1-D data both run in an expanded form: about a data
-// centre c, a_i = x_i - q with x_i = C_i + B_i (y - c) (one FMA) and the
-// particle-free q = s^2 (y - c)^2, which each wave forms once per datum for
-// all 64 of its particles. Instead of one log per datum, the e's are multiplied into a
+// FP32 forms, in base-2 units, a_i = log2 w_i - s^2 (y - mu_i)^2 with
+// s = sqrt(log2(e)/(2 sigma2)) (partial_fp32):
+//   * pivot (1-D data): per window of 64 data about its midpoint c, each
+//     particle's component p with the largest a_p(c) is its pivot; the
+//     others enter through t_i = a_i - a_p, which is linear in y (one FMA),
+//     as 2^(t_i) (hardware v_exp_f32), and the pivot's own a_p summed over
+//     the window comes from two data sums shared by the wave's particles;
+//   * plain: t_i = s*y - s*mu_i (one FMA), a_i = log2 w_i - t_i^2 (one FMA),
+//     and the datum's mixture sum e = sum_i 2^(a_i), taken directly for
+//     waves near the data or relative to m = max_i a_i otherwise.
+// Instead of one log per datum, the per-datum factors are multiplied into a
 // running FP32 product whose exponent is extracted exactly after each block
-// of data (frexp), and the m's are summed in blocks in FP32 and promoted into
-// an FP64 accumulator. Neither is a Kahan sum: the product loses no exponent
-// range (the integer exponents are exact), the block sums round at most 16
-// FP32 terms, and the relative error of the particle's log-likelihood stays
-// below 1e-6 for n up to 10^5.
+// of data (frexp), and the m's and the pivot terms are summed apart and
+// promoted into an FP64 accumulator. Neither is a Kahan sum: the product
+// loses no exponent range (the integer exponents are exact), the block sums
+// round at most 16 FP32 terms, and the relative error of the particle's
+// log-likelihood stays below 1e-6 for n up to 10^5.
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.
@@ -52,14 +54,14 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
          GmmDev g, double* __restrict__ out, int* status) {
     constexpr int KD = K * D;
     // LDS sized by the launch (loglik_dyn_lds_bytes): red [S][64] doubles, then
-    // for the FP32 1-D form the waves' staging rows [S][2 kExpWin] floats
-    extern __shared__ double lds[];
+    // for the FP32 1-D form the waves' staging rows [S][kPivotWin] floats
+    extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     double (*red)[kWave] = reinterpret_cast<double (*)[kWave]>(lds);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
     float* row = (PREC == SMC_PREC_FP32 && D == 1)
-                     ? reinterpret_cast<float*>(lds + S * kWave) + w * 2 * kExpWin
+                     ? reinterpret_cast<float*>(lds + S * kWave) + w * kPivotWin
                      : nullptr;
     const int p = blockIdx.x * kWave + lane;
     const int pc = p < N ? p : N - 1;
@@ -68,7 +70,7 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
     double pr[KD];
 #pragma unroll
     for (int c = 0; c < KD; ++c) pr[c] = theta[static_cast<size_t>(c) * N + pc];
-    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, true, ExpStage{row});
+    red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, true, PivotStage{row});
     __syncthreads();
     if (w == 0 && p < N) {
         double acc = red[0][lane];
@@ -115,16 +117,16 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     __shared__ int anc[kWave];
     __shared__ double prs[KD][kWave];
     // LDS sized by the launch (rwmh_dyn_lds_bytes): for the FP32 1-D form the
-    // waves' staging rows [S][2 kExpWin] floats, then offh, offl [nch] (nch =
+    // waves' staging rows [S][kPivotWin] floats, then offh, offl [nch] (nch =
     // ms.nchunks when the move can resample, else 0)
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
-    double* offh = lds + (kRows ? S * kExpWin : 0);
+    double* offh = lds + (kRows ? S * (kPivotWin / 2) : 0);
     double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
-    float* row = kRows ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin : nullptr;
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotWin : nullptr;
     const int tile = static_cast<int>(blockIdx.x) / G;
     const int grp = static_cast<int>(blockIdx.x) - tile * G;
     const int p = tile * kWave + lane;
@@ -133,11 +135,11 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     const int sl = grp * S + w;
     int j0, j1;
     slice_bounds(n, sl, nsl, j0, j1);
-    // the lane's first datum of the slice for the expanded forms, loaded ahead
+    // the lane's first datum of the slice for the pivot form, loaded ahead
     // of the ancestor search and the proposals (their barriers and Box-Muller
     // work hide its latency)
-    const bool y_pre = kRows && j1 - j0 >= kExpMinData;
-    const float y_first = y_pre ? y[j0 + lane] : 0.0f;
+    const bool y_pre = kRows && j1 - j0 >= kPivotMinData;
+    const float y_first = y_pre && j0 + lane < j1 ? y[j0 + lane] : 0.0f;
     const uint32_t step = static_cast<uint32_t>(step_index(src));
     if (ms.t_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
         *ms.t_out = static_cast<int>(step);
@@ -150,7 +152,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
-                                             ExpStage{row, y_first, y_pre}, g_fp32_shifted_data);
+                                             PivotStage{row, y_first, y_pre}, g_fp32_shifted_data);
     __syncthreads();
     if (w != 0) return;
 
@@ -202,14 +204,14 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
     __shared__ double cur[KD][kWave];
     __shared__ double lcur[kWave];
     // LDS sized by the launch (rwmh_dyn_lds_bytes), as in k_rwmh
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
-    double* offh = lds + (kRows ? S * kExpWin : 0);
+    double* offh = lds + (kRows ? S * (kPivotWin / 2) : 0);
     double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
-    float* row = kRows ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin : nullptr;
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotWin : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < N ? p : N - 1;
     int j0, j1;
@@ -232,7 +234,7 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
         block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, mv, &cur[0][0], kWave, lane, sd,
                             w, S, prs, pr);
         red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
-                                                 ExpStage{row});
+                                                 PivotStage{row});
         __syncthreads();
         if (w == 0) {
             double tot = red[0][lane];
@@ -354,7 +356,7 @@ k_pt_local(const float* __restrict__ y, int n, double* theta, double* l, int M,
         // the same per-datum forms as the one-launch-per-iteration path, so the
         // two agree bit for bit
         red[w][lane] = slice_partial<K, D, PREC>(yl, j0, j1, pr, g, near_data(lcur[col], n, g),
-                                                 ExpStage{expanded_row<PREC, D, kMaxSlices>()});
+                                                 PivotStage{pivot_row<PREC, D, kMaxSlices>()});
         __syncthreads();
         if (sl == 0) {
             double tot = red[w][lane];
@@ -421,13 +423,13 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     __shared__ double prs[KD][kWave];
     __shared__ double lcur[kWave];
     // LDS sized by the launch: for the FP32 1-D form the waves' staging rows
-    // [S][2 kExpWin] floats
-    extern __shared__ double lds[];
+    // [S][kPivotWin] floats
+    extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
     float* row = (PREC == SMC_PREC_FP32 && D == 1)
-                     ? reinterpret_cast<float*>(lds) + w * 2 * kExpWin
+                     ? reinterpret_cast<float*>(lds) + w * kPivotWin
                      : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < M ? p : M - 1;
@@ -458,7 +460,7 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), it, 0, &cur[0][0], kWave, lane, sd, w, S,
                         prs, pr);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(lcur[lane], n, g),
-                                             ExpStage{row});
+                                             PivotStage{row});
     __syncthreads();
     if (w != 0) return;
     double tot = red[0][lane];
@@ -668,9 +670,9 @@ namespace {
 // part is at most 8 KB + 64 KB + 768 B).
 constexpr size_t kMaxRwmhLds = 24 * 1024;
 
-// LDS bytes of the expanded forms' staging rows of `slices` waves (FP32, d = 1).
+// LDS bytes of the pivot form's staging rows of `slices` waves (FP32, d = 1).
 size_t rows_lds_bytes(int slices, bool rows) {
-    return rows ? sizeof(float) * slices * 2 * kExpWin : 0;
+    return rows ? sizeof(float) * slices * kPivotWin : 0;
 }
 
 // Dynamic LDS bytes of one k_rwmh / k_rwmh_multi workgroup (the layout at the

@@ -309,6 +309,7 @@ hipError_t launch_reweight_partial(const Scratch& sc, double* logw, const double
                                    StepSrc src, hipStream_t s);
 hipError_t launch_pt_record(const double* theta, int64_t M, int32_t kd, int64_t chain,
                             const int32_t* it_dev, double* out, int64_t max_iters, hipStream_t s);
+hipError_t launch_sort_data(float* y, int64_t n, hipStream_t s);
 hipError_t launch_rng_words(uint64_t seed, int64_t count, uint32_t block, uint32_t step,
                             uint32_t purpose, uint32_t move, uint32_t* out, hipStream_t s);
 hipError_t launch_rng_normals(uint64_t seed, int64_t count, int32_t per_index, uint32_t step,

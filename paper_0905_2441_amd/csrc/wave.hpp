@@ -65,6 +65,26 @@ __device__ __forceinline__ float wave_min_dpp(float v) {
     return float_of_order_key(wave_extreme_key<false>(float_order_key(v)));
 }
 
+// The sum of the wave's 64 values of v, in every lane: an inclusive scan within
+// each row of 16 lanes by DPP row shifts (a source outside the row reads 0),
+// then the row totals carried up by row broadcasts, so lane 63 ends with the
+// total. The order of the additions is fixed.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add_step(float v) {
+    const int o = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                              true);
+    return v + __builtin_bit_cast(float, o);
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v = dpp_add_step<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_add_step<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_add_step<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_add_step<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_add_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));

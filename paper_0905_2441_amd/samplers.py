@@ -15,6 +15,11 @@ the whole batch.
 PTSampler: population MCMC with tempered chains (Population-Based MCMC
 subsection): per iteration one RW-MH move per chain at its own beta, then
 exchange moves on one partition of adjacent pairs.
+
+The mixture samplers hold their own device copy of the data; 1-D data are
+sorted into ascending order once, on the device (smc_sort_data), which leaves
+the likelihood unchanged up to rounding and lets the FP32 likelihood take its
+pivot form.
 """
 
 from __future__ import annotations
@@ -26,8 +31,8 @@ import numpy as np
 import torch
 
 from .api import (Batch, Context, Gmm, Graph, fsv_init, fsv_step, fsv_steps, pt_iteration,
-                  pt_iterations, pt_record, smc_loglik, smc_prior_init, smc_step,
-                  smc_step_batched, smc_steps)
+                  pt_iterations, pt_record, smc_loglik, smc_prior_init, smc_sort_data,
+                  smc_step, smc_step_batched, smc_steps)
 
 
 def _dev(x, dtype):
@@ -45,6 +50,8 @@ class SMCSampler:
         self.stream = stream or torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.y = _dev(y, torch.float32)
+            if model.d == 1:
+                smc_sort_data(self.y, stream=self.stream)
             self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
             kd = model.kd
             self.thetas = [torch.empty((kd, self.N), dtype=torch.float64, device="cuda")
@@ -162,6 +169,8 @@ class PTSampler:
         self.stream = stream or torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.y = _dev(y, torch.float32)
+            if model.d == 1:
+                smc_sort_data(self.y, stream=self.stream)
             self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
             self.theta = torch.empty((model.kd, self.M), dtype=torch.float64, device="cuda")
             self.loglik = torch.empty(self.M, dtype=torch.float64, device="cuda")
@@ -262,6 +271,8 @@ class BatchSampler:
         with torch.cuda.stream(self.stream):
             self.y = _dev(np.concatenate([np.asarray(y, dtype=np.float32).ravel() for y in datas]),
                           torch.float32)
+            for r in range(self.R):                  # each run's data in ascending order
+                smc_sort_data(self.y[self.y_off[r]:self.y_off[r] + self.ns[r]], stream=self.stream)
             self.beta = _dev(np.asarray(betas, dtype=np.float64), torch.float64)
             self.theta = torch.empty(kd * self.N_total, dtype=torch.float64, device="cuda")
             self.loglik = torch.empty(self.N_total, dtype=torch.float64, device="cuda")

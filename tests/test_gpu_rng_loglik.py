@@ -230,38 +230,54 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
             ctx.set_slices(0)
 
 
-@pytest.mark.parametrize("case", ["range_exit_late", "range_exit_early", "far_particles",
-                                  "slice_127", "slice_128", "slice_129"])
-def test_loglik_fp32_expanded_forms(smc, ctx, case):
-    """The FP32 forms for 1-D data in their expanded split about a centre c
-    (the midrange of a slice's first 64 data), at 4 slices: a window holding a
-    datum with s^2 (y - c)^2 above the split's range bound hands the rest of
-    the slice to the plain forms (late: at the slice's last window; early: at
-    its second); prior draws take the expanded shifted form; slices of 127,
-    128 and 129 data sit on either side of the shortest slice the split takes.
+@pytest.mark.parametrize("case", ["sorted_near", "sorted_far", "sorted_mixed", "sorted_k1",
+                                  "sorted_k2", "sorted_k3", "sorted_k8", "unsorted",
+                                  "sorted_outliers", "wide_clusters", "zero_weights",
+                                  "slice_31", "slice_32", "slice_33", "slice_63", "slice_65",
+                                  "slice_129"])
+def test_loglik_fp32_pivot_form(smc, ctx, case):
+    """The FP32 pivot form (1-D data, windows of 64 data, each particle's
+    largest component at the window's midpoint as its pivot) at 4 slices:
+    on ascending data near and far particles and every k take it (k = 1
+    leaves only the pivot's own terms); unordered data, windows that span
+    far-apart clusters or hold a jump to outliers at +40 are refused for some
+    or all particles and go through the plain forms; components of zero
+    weight never become pivots; slices of 31 to 129 data sit on either side
+    of the shortest slice the form takes (32) and of a window's length.
     Every case agrees with the oracle."""
-    announce(f"loglik fp32 expanded {case}")
+    announce(f"loglik fp32 pivot {case}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     g = smc.Gmm.equal_weights(4, 1, 0.55)
-    rng = np.random.default_rng(41)
-    near = theta_near_posterior(500, mu, seed=42)
-    th = near
-    if case.startswith("range_exit"):
-        # 4 slices of 256: the first 64 data of each cluster near 0.5 (c near
-        # 0.5); the rest come from the mixture, with 10.5 (s^2 100 = 131 > 120)
-        # planted in the last window (late) or the second one (early)
-        n = 1024
-        y = make_mixture_data(n, mu, 0.55, seed=43).copy()
-        at = 200 if case.endswith("late") else 70
-        for sl in range(4):
-            y[256 * sl: 256 * sl + 64] = 0.5 + 0.2 * rng.standard_normal(64).astype(np.float32)
-            y[256 * sl + at] = 10.5
-    elif case == "far_particles":
-        y = make_mixture_data(1000, mu, 0.55, seed=44)
+    n = 1000
+    y = make_mixture_data(n, mu, 0.55, seed=43)
+    th = theta_near_posterior(500, mu, seed=42)
+    if case == "sorted_far":
         th = theta_prior_draws(500, 4, 1, seed=45)
-    else:
+    elif case == "sorted_mixed":
+        far = theta_prior_draws(500, 4, 1, seed=45)
+        th = np.where(np.arange(500) % 5 == 2, far, th)
+    elif case.startswith("sorted_k"):
+        k = int(case[len("sorted_k"):])
+        mu = np.linspace(-4.0, 7.0, k) if k > 1 else np.array([1.5])
+        g = smc.Gmm.equal_weights(k, 1, 0.55)
+        y = make_mixture_data(n, mu, 0.55, seed=46 + k)
+        th = np.hstack([theta_near_posterior(300, mu, seed=47), theta_prior_draws(200, k, 1, 48)])
+    elif case == "sorted_outliers":
+        y = y.copy()
+        y[-40:] = 40.0 + np.arange(40, dtype=np.float32) * 0.01
+    elif case == "wide_clusters":
+        mu = np.array([-30.0, -10.0, 10.0, 30.0])
+        y = make_mixture_data(n, mu, 0.55, seed=49)
+        th = np.hstack([theta_near_posterior(300, mu, seed=50), theta_prior_draws(200, 4, 1, 51)])
+    elif case == "zero_weights":
+        g = smc.Gmm(k=4, d=1, sigma2=0.55,
+                    log_w=(math.log(0.5), float("-inf"), math.log(0.5), float("-inf")))
+        y = make_mixture_data(n, np.array([-3.0, 3.0]), 0.55, seed=52)
+    elif case.startswith("slice_"):
         per = int(case.split("_")[1])
         y = make_mixture_data(4 * per, mu, 0.55, seed=per)
+    if case != "unsorted":
+        y = np.sort(y)
     ctx.set_slices(4)
     try:
         _check_loglik(smc, ctx, g, y, th, "fp32", FP32_TOL)

@@ -286,33 +286,106 @@ def test_rwmh_per_chain_beta_and_box_prior(smc, ctx):
 
 
 def test_fp32_shifted_form_counter(smc, ctx):
-    """The device counter of the FP32 move's per-datum forms: a move of prior
-    draws (far from the data) takes the shifted form for every full block of 8
-    observations of every wave's slice; a move of particles near a posterior
-    mode stays direct throughout; FP64 moves do not count. (Four slices whose
-    boundaries fall on multiples of 8: 248, 248, 248 and 256 observations, all
-    in full blocks, so every observation of every tile is counted.)"""
+    """The device counter of the FP32 move's per-datum forms. On data in their
+    generated (unordered) order the pivot form refuses every window: a move of
+    prior draws (far from the data) then takes the plain shifted form for
+    every full block of 8 observations of every wave's slice, and a move of
+    particles near a posterior mode stays in the plain direct form. On the
+    same data in ascending order the near particles take the pivot form
+    throughout and the prior draws take it in most windows. FP64 moves do not
+    count. (Four slices whose boundaries fall on multiples of 8: 248, 248, 248
+    and 256 observations, all in full blocks.)"""
     announce("fp32 form counter")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     n, N = 1000, 4096
-    y = _cuda(make_mixture_data(n, mu, 0.55, seed=2), torch.float32)
+    y_np = make_mixture_data(n, mu, 0.55, seed=2)
     g = smc.Gmm.equal_weights(4, 1, 0.55)
     tiles = N // 64
+    prior = theta_prior_draws(N, 4, 1, seed=3)
+    near = theta_near_posterior(N, mu, seed=4, jitter=0.1)
     ctx.set_slices(4)
     try:
-        for name, th_np, prec, want in (
-                ("prior", theta_prior_draws(N, 4, 1, seed=3), "fp32", tiles * n),
-                ("near", theta_near_posterior(N, mu, seed=4, jitter=0.1), "fp32", 0),
-                ("prior fp64", theta_prior_draws(N, 4, 1, seed=3), "fp64", 0)):
+        for name, y_in, th_np, prec, want in (
+                ("prior", y_np, prior, "fp32", lambda c: c == tiles * n),
+                ("near", y_np, near, "fp32", lambda c: c == 0),
+                ("prior fp64", y_np, prior, "fp64", lambda c: c == 0),
+                ("prior sorted", np.sort(y_np), prior, "fp32", lambda c: 0 < c < tiles * n // 2),
+                ("near sorted", np.sort(y_np), near, "fp32", lambda c: c == 0)):
+            y = _cuda(y_in, torch.float32)
             th = _cuda(th_np)
             l = torch.empty(N, dtype=torch.float64, device="cuda")
             smc.smc_loglik(ctx, g, y, th, prec, out=l)
             ctx.fp32_shifted_data(reset=True)
             smc.smc_rwmh_move(ctx, g, y, th, l, 0.5, 0.5, seed=5, step=1, prec=prec)
             ctx.check()
-            assert ctx.fp32_shifted_data(reset=True) == want, name
+            got = ctx.fp32_shifted_data(reset=True)
+            assert want(got), (name, got)
     finally:
         ctx.set_slices(0)
+
+
+def _order_keys(v):
+    """Sign-magnitude order keys of FP32 values (the order smc_sort_data defines)."""
+    b = np.ascontiguousarray(v, dtype=np.float32).view(np.int32).astype(np.int64)
+    return np.where(b >= 0, b, b ^ 0x7FFFFFFF)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 100, 4095, 4096, 4097, 10000, 65537, (1 << 20) + 3])
+def test_sort_data_matches_key_order(smc, n):
+    """smc_sort_data gives the bits of numpy's sort of the values' order keys,
+    with NaNs of both signs, infinities, signed zeros and many ties, and leaves
+    the array's neighbours untouched."""
+    announce(f"sort n={n}")
+    rng = np.random.default_rng(n + 17)
+    v = rng.standard_normal(n).astype(np.float32)
+    if n >= 10:
+        v[rng.integers(0, n, n // 10)] = np.float32(1.5)                 # ties
+        special = np.array([np.nan, -np.nan, np.inf, -np.inf, 0.0, -0.0], dtype=np.float32)
+        v[rng.integers(0, n, 6)] = special
+        v[n // 2] = np.frombuffer(np.uint32(0xFFC00001).tobytes(), dtype=np.float32)[0]
+    buf = np.full(n + 8, 7.25, dtype=np.float32)
+    buf[4:4 + n] = v
+    t = _cuda(buf, torch.float32)
+    smc.smc_sort_data(t[4:4 + n])
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    want = np.sort(_order_keys(v), kind="stable")
+    assert np.array_equal(_order_keys(got[4:4 + n]), want)
+    assert np.all(got[:4] == 7.25) and np.all(got[4 + n:] == 7.25)
+
+
+def test_sort_data_rejects_bad_sizes(smc):
+    from paper_0905_2441_amd import _lib
+    lib = _lib.load()
+    assert lib.smc_sort_data(None, -1, None) == _lib.SMC_ERR_INVALID_ARG
+    assert lib.smc_sort_data(None, 5, None) == _lib.SMC_ERR_INVALID_ARG
+    assert lib.smc_sort_data(None, (1 << 30) + 1, None) == _lib.SMC_ERR_INVALID_ARG
+    assert lib.smc_sort_data(None, 0, None) == _lib.SMC_OK
+
+
+def test_samplers_hold_sorted_data(smc, ctx):
+    """The 1-D samplers sort their own device copy of the data (each batched
+    run's data apart); d > 1 data keep their order."""
+    announce("samplers sort data")
+    mu = np.array([-3.0, 0.0, 3.0, 6.0])
+    y = make_mixture_data(777, mu, 0.55, seed=61)
+    g = smc.Gmm.equal_weights(4, 1, 0.55)
+    s = smc.SMCSampler(ctx, g, y, 128, np.linspace(0.0, 1.0, 5), 0.5, 1, 3)
+    s.stream.synchronize()
+    assert np.array_equal(s.y.cpu().numpy(), np.sort(y))
+    assert not np.array_equal(y, np.sort(y))                              # the caller's copy
+    p = smc.PTSampler(ctx, g, y, np.linspace(0.1, 1.0, 8), 0.5, 3)
+    p.stream.synchronize()
+    assert np.array_equal(p.y.cpu().numpy(), np.sort(y))
+    datas = [make_mixture_data(n, mu, 0.55, seed=n) for n in (50, 300, 4100)]
+    b = smc.BatchSampler(ctx, g, datas, [64, 64, 64], [1, 2, 3], np.linspace(0.0, 1.0, 4), 0.5, 1)
+    b.stream.synchronize()
+    assert np.array_equal(b.y.cpu().numpy(), np.concatenate([np.sort(d) for d in datas]))
+    y8 = make_mixture_data(100, 3.0 * np.ones((2, 8)), 1.0, seed=62)
+    s8 = smc.SMCSampler(ctx, smc.Gmm.equal_weights(2, 8, 1.0), y8, 64,
+                        np.linspace(0.0, 1.0, 3), 0.5, 1, 3)
+    s8.stream.synchronize()
+    assert np.array_equal(s8.y.cpu().numpy(), y8)
 
 
 def test_launch_table_selects_slices(smc, ctx):
