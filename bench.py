@@ -166,6 +166,27 @@ def trans_per_eval(k: int, form: str = "pivot") -> int:
     return k - 1 if form == "pivot" else k
 
 
+def form_shares(fc, pairs):
+    """Shares of (observation, tile) pairs by FP32 form from the device form
+    counters, and the pivot form's mean number of other components evaluated
+    per pair (it leaves out those below 2^-25 over a window for the whole
+    wave)."""
+    piv, sh = fc["pivot"] / pairs, fc["shifted"] / pairs
+    return {"pivot": piv, "direct": max(0.0, 1.0 - piv - sh), "shifted": sh,
+            "pivot_terms_mean": fc["pivot_terms"] / fc["pivot"] if fc["pivot"] else 0.0}
+
+
+def ops_mix(k: int, forms, trans: float = TRANS_SLOTS) -> float:
+    """Algorithmic issue slots per evaluation for a measured mix of forms: the
+    pivot form at its measured mean of m other components (per datum m FMAs,
+    m exp2, m - 1 adds and one FMA into the product: (2 + trans) m), the plain
+    direct and shifted forms as in ops_per_eval."""
+    def plain(form):
+        return ops_per_eval(k, form) - (TRANS_SLOTS - trans) * trans_per_eval(k, form)
+    return (forms["pivot"] * (2.0 + trans) * forms["pivot_terms_mean"]
+            + forms["direct"] * plain("direct") + forms["shifted"] * plain("shifted"))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -527,7 +548,7 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     s.stream.synchronize()
     s.init()                               # a fresh run from the prior for the timed steps
     s.stream.synchronize()
-    ctx.fp32_shifted_data(reset=True)
+    ctx.fp32_form_counts(reset=True)
     t0 = time.perf_counter()
     s.advance(steps, graph=True, steps_per_graph=u)
     s.stream.synchronize()
@@ -535,7 +556,7 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     ctx.check(s.stream)
     # the timed steps' moves: (observation, tile) pairs in the shifted form
     step_pairs = steps * cfg.n_moves * ((cfg.N + 63) // 64) * cfg.n
-    shifted_steps = ctx.fp32_shifted_data(reset=True) / step_pairs
+    forms_steps = form_shares(ctx.fp32_form_counts(reset=True), step_pairs)
     res = s.results()          # the timed run's final population (before the kernel timing)
     ms_step = (t1 - t0) * 1e3 / steps
     # the dominant kernel alone: the RW-MH move (proposal + likelihood + accept)
@@ -543,22 +564,21 @@ def time_precision(smc, torch, ctx, cfg, g, y, betas, prec, steps, warmup):
     # runs on (an event pair around every launch would add its own overhead)
     reps = max(10, steps)
     acc = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ctx.fp32_shifted_data(reset=True)
+    ctx.fp32_form_counts(reset=True)
     kern_ms = time_launches(torch, s.stream, lambda i: smc.smc_rwmh_move(
         ctx, g, s.y, s.theta, s.loglik, 1.0, cfg.step_sd, cfg.run_seed, cfg.T + 1 + i, 0, prec,
         n_accept=acc, stream=s.stream), reps)
     ctx.check(s.stream)
     accept_rate = acc.item() / ((reps + 1) * cfg.N)
-    shifted = None
+    forms = None
     if prec == "fp32":
-        # (observation, tile) pairs of the reps + 1 launches (one untimed) that
-        # went through the plain shifted form
+        # the (observation, tile) pairs of the reps + 1 launches (one untimed)
         pairs = (reps + 1) * ((cfg.N + 63) // 64) * cfg.n
-        shifted = ctx.fp32_shifted_data(reset=True) / pairs
+        forms = form_shares(ctx.fp32_form_counts(reset=True), pairs)
     move_steps_ms = moves_of_steps(smc, torch, ctx, cfg, g, s, betas, prec, steps)
-    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, shifted_share=shifted,
+    return dict(ms_per_step=ms_step, kernel_ms=kern_ms, forms=forms,
                 accept_rate=accept_rate, move_steps_ms=move_steps_ms,
-                shifted_share_steps=shifted_steps if prec == "fp32" else None,
+                forms_steps=forms_steps if prec == "fp32" else None,
                 resamples=res["resamples"],
                 accepted=res["accepted"], logZ=res["logZ"], theta=res["theta"], l=res["l"],
                 t=res["t"])
@@ -624,7 +644,8 @@ def main():
         log(f"[bench] fp64 {r64['ms_per_step']:.4f} ms/step, move kernel {r64['kernel_ms']:.4f} ms")
 
     kern_evals = evals_per_step / (r32["kernel_ms"] * 1e-3)
-    achieved = kern_evals * ops_per_eval(cfg.k)
+    ops = ops_mix(cfg.k, r32["forms"])
+    achieved = kern_evals * ops
     roofline = {
         "bound": "alu",
         "achieved": achieved / 1e12,
@@ -636,25 +657,22 @@ def main():
         "traffic_algorithmic": cfg.N * 40.0 * (1.0 + r32["accept_rate"]),
         "traffic_unit": "bytes per launch",
         "kernel": "k_rwmh<4,1,FP32> (proposal + likelihood + accept)",
-        "ops_per_eval": ops_per_eval(cfg.k),
-        "form": "pivot",
-        # the looser bound with exp2 charged one slot (9 slots per evaluation)
-        "frac_exp_one_slot": kern_evals * (ops_per_eval(cfg.k)
-                                           - (TRANS_SLOTS - 1.0) * trans_per_eval(cfg.k))
-                             / PEAK_LANE_OPS,
+        # issue slots per evaluation at the timed launches' measured form mix
+        # (device form counters: pivot form at its mean number of other
+        # components, exp2 at two slots)
+        "ops_per_eval": ops,
+        "forms": r32["forms"],
+        "forms_timed_steps": r32["forms_steps"],
+        # the same launches against the pivot form with all k - 1 other
+        # components (12 slots for k = 4), and with exp2 charged one slot
+        "frac_dense_pivot": kern_evals * ops_per_eval(cfg.k) / PEAK_LANE_OPS,
+        "frac_exp_one_slot": kern_evals * ops_mix(cfg.k, r32["forms"], 1.0) / PEAK_LANE_OPS,
         "valu_busy_measured": move_valu_busy(slices32),
         "counters": {"slices": MOVE_COUNTERS["slices"], "waves": MOVE_COUNTERS["waves"],
                      "apply_to_timed_shape": counters_apply(slices32)},
         "kernel_ms": r32["kernel_ms"],
         "kernel_evals_per_s": kern_evals,
-        # the timed launches' per-datum forms: the share of (observation, tile)
-        # pairs that went through the plain shifted form (device counter; the
-        # rest took the pivot form, or the plain direct form in windows the
-        # pivot form refused; the < 8 observations after the last full block of
-        # 8 of each range the plain forms take are not counted)
         "accept_rate": r32["accept_rate"],
-        "shifted_form_share": r32["shifted_share"],
-        "shifted_form_share_timed_steps": r32["shifted_share_steps"],
         "launch_slices": slices32,
     }
     cpu = oracle_error = None
@@ -807,7 +825,8 @@ def probes(smc, torch, ctx, reps):
     out["loglik_fp32_N1048576_n4096"] = {
         "us": ms * 1e3, "evals_per_s": evals,
         "form": "pivot (prior draws, far from the data; data in ascending order)",
-        "frac_issue_slots": evals * ops_per_eval(4, "pivot") / PEAK_LANE_OPS}
+        # against the pivot form with all 3 other components (12 slots)
+        "frac_issue_slots_dense_pivot": evals * ops_per_eval(4, "pivot") / PEAK_LANE_OPS}
     del th, l
     for logN in (17, 20, 24):
         N = 1 << logN

@@ -431,18 +431,22 @@ int smc_graph_launch(smc_graph g, void* stream);
 int smc_graph_destroy(smc_graph g);
 
 /* [sync] Diagnostic of the FP32 likelihood's per-datum forms (see
- * smc_loglik): *out = the number of (observation, 64-particle tile) pairs that
- * FP32 moves launched one move at a time (smc_rwmh_move, and the moves of
- * smc_step / smc_steps unless a step's several moves run in one launch)
- * evaluated in the plain shifted form since the last reset, summed over every
- * context on the context's device: the data of a wave's slice (d > 1, or
- * slices shorter than 32) or of a window the pivot form refused (d = 1) from
- * where the wave left, or never took, the plain direct form. Not counted: the
- * fewer than 8 observations after the last full block of 8 of each such range,
- * which always take the shifted form. With reset != 0 the count is cleared
- * after the read. Waves that take only the pivot and direct forms do not touch
- * the counter. */
-int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset);
+ * smc_loglik), summed over every context on the context's device since the
+ * last reset, for the FP32 moves launched one move at a time (smc_rwmh_move,
+ * and the moves of smc_step / smc_steps unless a step's several moves run in
+ * one launch), counted in (observation, 64-particle tile) pairs. out[3]:
+ *   out[0]: pairs evaluated in the plain shifted form: the data of a wave's
+ *           slice (d > 1, or slices shorter than 32) or of a window the pivot
+ *           form refused (d = 1) from where the wave left, or never took, the
+ *           plain direct form; not counted: the fewer than 8 observations
+ *           after the last full block of 8 of each such range, which always
+ *           take the shifted form;
+ *   out[1]: pairs evaluated in the pivot form;
+ *   out[2]: the number of components other than the pivot that the pivot
+ *           form evaluated, summed over those pairs (out[2] / out[1] is the
+ *           mean, at most k - 1).
+ * With reset != 0 the counts are cleared after the read. */
+int smc_fp32_form_counts(smc_ctx ctx, uint64_t* out, int32_t reset);
 
 /* Sort n FP32 values of the device array y in place into ascending order
  * (Mixture Modelling section: the data are independent draws, so the

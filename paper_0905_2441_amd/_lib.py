@@ -81,7 +81,7 @@ SIGNATURES = {
     "smc_set_slices": (c_int, [_P, c_int32]),
     "pt_set_single_workgroup": (c_int, [_P, c_int32]),
     "smc_set_launch_table": (c_int, [_P, POINTER(SmcLaunchRule), c_int32]),
-    "smc_fp32_shifted_data": (c_int, [_P, POINTER(c_uint64), c_int32]),
+    "smc_fp32_form_counts": (c_int, [_P, POINTER(c_uint64), c_int32]),
     "smc_loglik": (c_int, [_P, _GP, _P, c_int64, _P, c_int64, c_int, _P, _P]),
     "smc_prior_init": (c_int, [_P, _GP, c_int64, c_uint64, _P, _P]),
     "smc_rwmh_move": (c_int, [_P, _GP, _P, c_int64, _P, _P, c_int64, _P, c_double, c_double,

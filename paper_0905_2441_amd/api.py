@@ -139,12 +139,14 @@ class Context:
         L.check(self._lib.smc_set_launch_table(self.handle, arr, len(rules)))
         self.rules = [dict(r) for r in rules]
 
-    def fp32_shifted_data(self, reset: bool = False) -> int:
-        """(observation, tile) pairs that FP32 single moves on this device took
-        in the shifted form since the last reset (smc_fp32_shifted_data)."""
-        v = ctypes.c_uint64()
-        L.check(self._lib.smc_fp32_shifted_data(self.handle, ctypes.byref(v), int(bool(reset))))
-        return int(v.value)
+    def fp32_form_counts(self, reset: bool = False) -> dict:
+        """Form counts of the FP32 single moves on this device since the last
+        reset (smc_fp32_form_counts), in (observation, tile) pairs: "shifted"
+        (plain shifted form), "pivot" (pivot form) and "pivot_terms" (other
+        components the pivot form evaluated, summed over its pairs)."""
+        v = (ctypes.c_uint64 * 3)()
+        L.check(self._lib.smc_fp32_form_counts(self.handle, v, int(bool(reset))))
+        return {"shifted": int(v[0]), "pivot": int(v[1]), "pivot_terms": int(v[2])}
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -28,7 +28,7 @@ from typing import Dict, Iterable, List, Optional, Sequence
 import numpy as np
 import torch
 
-from .api import Context, Gmm, smc_rwmh_move
+from .api import Context, Gmm, smc_rwmh_move, smc_sort_data
 
 # Slice counts tried: 1..4 for short data, then multiples of 4 so that every
 # SIMD of a CU receives the same number of waves of a workgroup.
@@ -62,14 +62,19 @@ def time_move(ctx: Context, model: Gmm, y, theta, loglik, prec: str, reps: int,
 def tune_shape(ctx: Context, k: int, d: int, n: int, N: int, prec: str = "fp32",
                reps: int = 20, cands: Optional[Sequence[int]] = None, seed: int = 0) -> dict:
     """Time every candidate slice count for one shape; returns
-    {"best": T, "ms": {T: ms}}. Inputs are synthetic (standard-normal data and
-    means): the kernels' time does not depend on the values."""
+    {"best": T, "ms": {T: ms}}. Inputs are synthetic: standard-normal data
+    (1-D data in ascending order, as the samplers hold them, so that the FP32
+    likelihood takes its pivot form) and standard-normal means. The kernels'
+    time depends on the values only through the FP32 form a wave takes and,
+    in the pivot form, through how many components it evaluates."""
     model = Gmm.equal_weights(k, d, 1.0)
     stream = torch.cuda.Stream()
     gen = torch.Generator(device="cuda").manual_seed(seed)
     with torch.cuda.stream(stream):
         y = torch.randn((n, d) if d > 1 else (n,), generator=gen, device="cuda",
                         dtype=torch.float32)
+        if d == 1:
+            smc_sort_data(y, stream=stream)
         theta = torch.randn((k * d, N), generator=gen, device="cuda", dtype=torch.float64)
         loglik = torch.full((N,), -1.0e6, device="cuda", dtype=torch.float64)
     ctx.reserve(N, k * d, n if prec == "bf16x3" else 0)

@@ -1104,13 +1104,13 @@ int smc_graph_destroy(smc_graph g) {
     return SMC_OK;
 }
 
-int smc_fp32_shifted_data(smc_ctx ctx, uint64_t* out, int32_t reset) {
+int smc_fp32_form_counts(smc_ctx ctx, uint64_t* out, int32_t reset) {
     int r = enter(ctx);
     if (r) return r;
     if (!out) return fail(SMC_ERR_INVALID_ARG, "out is NULL");
-    unsigned long long v = 0;
-    SMC_CHECK_HIP(fp32_shifted_data(&v, reset != 0), "reading the form counter");
-    *out = static_cast<uint64_t>(v);
+    unsigned long long v[3] = {0, 0, 0};
+    SMC_CHECK_HIP(fp32_form_counts(v, reset != 0), "reading the form counters");
+    for (int c = 0; c < 3; ++c) out[c] = static_cast<uint64_t>(v[c]);
     return SMC_OK;
 }
 

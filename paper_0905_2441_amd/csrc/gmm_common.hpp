@@ -1,5 +1,7 @@
 // Device helpers shared by the mixture likelihood kernels (VALU and MFMA forms).
 #pragma once
+#include <type_traits>
+
 #include "cdf_search.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
@@ -31,8 +33,13 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 //      dB_i = 2 s^2 (mu_i - mu_p),
 //    and sum_j a_pj over the window follows in FP64 from two sums over the
 //    window's data (of y_j - c and of its square) that every particle shares.
-//    Per datum and particle that is K-1 FMAs, K-1 exp2, K-2 adds and one FMA
-//    into the product. Every factor is at least 1, so the product cannot
+//    Per datum and particle that is at most K-1 FMAs, K-1 exp2, K-2 adds and
+//    one FMA into the product: each particle orders its other components by
+//    the largest t_ij the window can hold, and the wave takes only as many as
+//    its neediest particle has that can reach 2^kPivotSkip (near the data
+//    mostly the one or two nearest neighbours of the pivot; the terms left out
+//    are below the factor's FP32 resolution). Every factor is at least 1, so
+//    the product cannot
 //    underflow; a window is taken when, for every particle of the wave, every
 //    dX_i + |dB_i| h (the largest t_ij the window can hold) is at most
 //    kPivotOverMax, which keeps a block of 8 factors below 2^120. A window
@@ -56,13 +63,17 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // shares (fixed for a given launch shape, population and data order). j0 and
 // j1 must be the same in every lane of the wave, and every lane of the wave
 // must take part (the forms use cross-lane operations, scalar loads and the
-// wave's LDS row). With shifted_ctr set, a wave adds the number of data it
-// took in the shifted form, counted up to the last full block of 8 of each
-// range the plain forms took (a whole slice, or a refused window), to the
-// counter slot shifted_ctr[slot] (one atomic per such wave, slots spread so
-// that waves rarely share one; the fewer than 8 data after such a range's
-// last full block always take the shifted form and are not counted).
+// wave's LDS row). With form_ctr set (kFormCounts arrays of kFormSlots
+// counters), a wave adds to slot `slot` of each array (one atomic per nonzero
+// count, slots spread so that waves rarely share one): [0] the number of data
+// it took in the plain shifted form, counted up to the last full block of 8
+// of each range the plain forms took (a whole slice, or a refused window; the
+// fewer than 8 data after such a range's last full block always take the
+// shifted form and are not counted); [1] the number of data it took in the
+// pivot form; [2] the sum over those data of the number of other components
+// the pivot form evaluated for them.
 constexpr int kFormSlots = 1024;
+constexpr int kFormCounts = 3;
 // Data per window of the pivot form (one per lane).
 constexpr int kPivotWin = kWave;
 // Shortest slice that takes the pivot form (below it the per-window set-up
@@ -72,6 +83,23 @@ constexpr int kPivotMinData = 32;
 // factor is then below 1 + 7 * 2^12 < 2^15 and a block of 8 below 2^120.
 constexpr float kPivotOverMax = 12.0f;
 static_assert(SMC_KMAX <= 8, "kPivotOverMax assumes at most 8 components");
+// A component other than the pivot whose t_ij stays below this in a window
+// for every particle of the wave is left out there: its term is below 2^-25,
+// under half the relative resolution of the product update p (1 + e) it would
+// join (at most 7 such terms, so a datum's log2 factor is short by less than
+// 3.1e-7, of the order of that update's own rounding).
+constexpr float kPivotSkip = -25.0f;
+
+// Calls f(std::integral_constant<int, m>) for a wave-uniform m in [0, M].
+template <int M, class F>
+__device__ __forceinline__ void with_count(int m, F&& f) {
+    if constexpr (M == 0) {
+        f(std::integral_constant<int, 0>{});
+    } else {
+        if (m == M) f(std::integral_constant<int, M>{});
+        else with_count<M - 1>(m, f);
+    }
+}
 
 // A wave's staging for the pivot form: its LDS row of kPivotWin floats
 // (nullptr: plain forms only) and, when `pre` is set, each lane's datum
@@ -94,16 +122,23 @@ __device__ __forceinline__ void slice_bounds(int n, int sl, int nsl, int& j0, in
     j1 = wave_uniform(blocks && sl + 1 < nsl ? b & ~7 : b);
 }
 
+// Data counts of one wave's slice by form (the form counters of partial_fp32).
+struct FormCount {
+    int shifted = 0;           // in the plain shifted form (up to full blocks of 8)
+    int pivot = 0;             // in the pivot form
+    int terms = 0;             // other components evaluated, summed over pivot data
+};
+
 // The pivot form over the 1-D slice [j0, j1) (see partial_fp32): adds the
-// slice's terms to prod, expo and msum and returns the count of data the
-// plain forms took in the shifted form. nms[i] = -s mu_i in FP32; plain(ja, jb)
-// runs the plain forms over [ja, jb) and returns its own such count.
+// slice's terms to prod, expo and msum and its data counts to fc. nms[i] =
+// -s mu_i in FP32; plain(ja, jb) runs the plain forms over [ja, jb) and
+// returns the count of data they took in the shifted form.
 template <int K, class Plain>
-__device__ __forceinline__ int pivot_slice(const float* __restrict__ y, int j0, int j1,
-                                           const double (&mu)[K], const GmmDev& g,
-                                           const float (&nms)[K], const PivotStage& st,
-                                           float& prod, int& expo, double& msum,
-                                           Plain&& plain) {
+__device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0, int j1,
+                                            const double (&mu)[K], const GmmDev& g,
+                                            const float (&nms)[K], const PivotStage& st,
+                                            float& prod, int& expo, double& msum, FormCount& fc,
+                                            Plain&& plain) {
     constexpr double kLog2eD = 1.4426950408889634;
     constexpr int KO = K > 1 ? K - 1 : 1;
     const int lane = lane_id();
@@ -113,7 +148,6 @@ __device__ __forceinline__ int pivot_slice(const float* __restrict__ y, int j0, 
     float beta[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) beta[i] = static_cast<float>(2.0 * s2 * mu[i]);
-    int counted = 0;
     float ycur = st.pre ? st.y0 : (j0 + lane < j1 ? y[j0 + lane] : 0.0f);
     for (int wb = j0; wb < j1; wb += kPivotWin) {
         const int nw = wave_uniform(j1 - wb < kPivotWin ? j1 - wb : kPivotWin);
@@ -150,47 +184,79 @@ __device__ __forceinline__ int pivot_slice(const float* __restrict__ y, int j0, 
         float bp = beta[0];
 #pragma unroll
         for (int i = 1; i < K; ++i) bp = piv == i ? beta[i] : bp;
-        float dX[KO], dB[KO];
+        float dX[KO], dB[KO], ub[KO];         // ub: the largest t_ij in the window
         bool ok = h <= 3.0e38f;               // false for a datum not finite
 #pragma unroll
         for (int o = 0; o + 1 < K; ++o) {
             const bool up = o >= piv;
             dX[o] = (up ? a[o + 1] : a[o]) - best;
             dB[o] = (up ? beta[o + 1] : beta[o]) - bp;
-            ok &= __builtin_fmaf(fabsf(dB[o]), h, dX[o]) <= kPivotOverMax;
+            ub[o] = __builtin_fmaf(fabsf(dB[o]), h, dX[o]);
+            ok &= ub[o] <= kPivotOverMax;
         }
         if (!__all(ok)) {
-            counted += plain(wb, wb + nw);
+            fc.shifted += plain(wb, wb + nw);
             continue;
         }
+        fc.pivot += nw;
         if constexpr (K > 1) {
-            auto factor = [&](float p, float d) {
-                float e = __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[0], dX[0]));
+            // each lane's others in decreasing order of ub (odd-even
+            // transposition network); the wave takes as many of them as its
+            // neediest lane has with ub >= kPivotSkip
 #pragma unroll
-                for (int o = 1; o + 1 < K; ++o)
-                    e += __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[o], dX[o]));
-                return __builtin_fmaf(p, e, p);
-            };
-            int u = 0;
-            for (; u + 8 <= nw; u += 8) {
-                float p = prod;
+            for (int r = 0; r < KO; ++r) {
 #pragma unroll
-                for (int q = 0; q < 8; q += 4) {
-                    const float4 d4 = *reinterpret_cast<const float4*>(row + u + q);
-                    p = factor(p, d4.x);
-                    p = factor(p, d4.y);
-                    p = factor(p, d4.z);
-                    p = factor(p, d4.w);
+                for (int o = r & 1; o + 1 < KO; o += 2) {
+                    const bool sw = ub[o + 1] > ub[o];
+                    const float u0 = ub[o], x0 = dX[o], b0 = dB[o];
+                    ub[o] = sw ? ub[o + 1] : u0;
+                    dX[o] = sw ? dX[o + 1] : x0;
+                    dB[o] = sw ? dB[o + 1] : b0;
+                    ub[o + 1] = sw ? u0 : ub[o + 1];
+                    dX[o + 1] = sw ? x0 : dX[o + 1];
+                    dB[o + 1] = sw ? b0 : dB[o + 1];
                 }
-                expo += __builtin_amdgcn_frexp_expf(p);
-                prod = __builtin_amdgcn_frexp_mantf(p);
             }
-            if (u < nw) {
-                float p = prod;
-                for (; u < nw; ++u) p = factor(p, row[u]);
-                expo += __builtin_amdgcn_frexp_expf(p);
-                prod = __builtin_amdgcn_frexp_mantf(p);
-            }
+            int need = 0;
+#pragma unroll
+            for (int o = 0; o < KO; ++o) need += ub[o] >= kPivotSkip ? 1 : 0;
+            int m = 0;
+#pragma unroll
+            for (int q = 1; q < K; ++q) m = __any(need >= q) ? q : m;
+            m = wave_uniform(m);
+            fc.terms += m * nw;
+            with_count<KO>(m, [&](auto mc) {
+                constexpr int M = decltype(mc)::value;
+                if constexpr (M > 0) {
+                    auto factor = [&](float p, float d) {
+                        float e = __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[0], dX[0]));
+#pragma unroll
+                        for (int o = 1; o < M; ++o)
+                            e += __builtin_amdgcn_exp2f(__builtin_fmaf(d, dB[o], dX[o]));
+                        return __builtin_fmaf(p, e, p);
+                    };
+                    int u = 0;
+                    for (; u + 8 <= nw; u += 8) {
+                        float p = prod;
+#pragma unroll
+                        for (int q = 0; q < 8; q += 4) {
+                            const float4 d4 = *reinterpret_cast<const float4*>(row + u + q);
+                            p = factor(p, d4.x);
+                            p = factor(p, d4.y);
+                            p = factor(p, d4.z);
+                            p = factor(p, d4.w);
+                        }
+                        expo += __builtin_amdgcn_frexp_expf(p);
+                        prod = __builtin_amdgcn_frexp_mantf(p);
+                    }
+                    if (u < nw) {
+                        float p = prod;
+                        for (; u < nw; ++u) p = factor(p, row[u]);
+                        expo += __builtin_amdgcn_frexp_expf(p);
+                        prod = __builtin_amdgcn_frexp_mantf(p);
+                    }
+                }
+            });
         }
         // the pivots' own terms over the window, in FP64
         double mp = mu[0], lwp = g.lw[0];
@@ -204,14 +270,13 @@ __device__ __forceinline__ int pivot_slice(const float* __restrict__ y, int j0, 
                           d * (2.0 * static_cast<double>(S1) + static_cast<double>(nw) * d);
         msum += static_cast<double>(nw) * lwp * kLog2eD - s2 * sq;
     }
-    return counted;
 }
 
 template <int K, int D>
 __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int j0, int j1,
                                                const double (&mu)[K * D], const GmmDev& g,
                                                bool near, const PivotStage& st,
-                                               unsigned long long* shifted_ctr = nullptr) {
+                                               unsigned long long* form_ctr = nullptr) {
     constexpr int UF = 8;            // direct-form block
     constexpr int US = 16;           // shifted-form block
     constexpr float kFloor = 0x1p-100f;
@@ -302,19 +367,23 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
         }
         return counted;
     };
-    int counted;
+    FormCount fc;
     if constexpr (D == 1) {
         if (st.row != nullptr && j1 - j0 >= kPivotMinData)
-            counted = pivot_slice<K>(y, j0, j1, mu, g, nms, st, prod, expo, msum, plain);
+            pivot_slice<K>(y, j0, j1, mu, g, nms, st, prod, expo, msum, fc, plain);
         else
-            counted = plain(j0, j1);
+            fc.shifted = plain(j0, j1);
     } else {
-        counted = plain(j0, j1);
+        fc.shifted = plain(j0, j1);
     }
-    if (shifted_ctr != nullptr && counted > 0 && lane_id() == 0) {
+    if (form_ctr != nullptr && lane_id() == 0) {
         const int slot = (static_cast<int>(blockIdx.x) * (static_cast<int>(blockDim.x) >> 6) +
                           wave_id()) & (kFormSlots - 1);
-        atomicAdd(shifted_ctr + slot, static_cast<unsigned long long>(counted));
+        const int cnt[kFormCounts] = {fc.shifted, fc.pivot, fc.terms};
+#pragma unroll
+        for (int c = 0; c < kFormCounts; ++c)
+            if (cnt[c] > 0)
+                atomicAdd(form_ctr + c * kFormSlots + slot, static_cast<unsigned long long>(cnt[c]));
     }
     return msum + static_cast<double>(expo) + log2(static_cast<double>(prod));
 }
@@ -362,9 +431,9 @@ template <int K, int D, int PREC>
 __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int j0, int j1,
                                                 const double (&pr)[K * D], const GmmDev& g,
                                                 bool near = true, const PivotStage& st = {},
-                                                unsigned long long* shifted_ctr = nullptr) {
+                                                unsigned long long* form_ctr = nullptr) {
     if constexpr (PREC == SMC_PREC_FP32) {
-        return partial_fp32<K, D>(y, j0, j1, pr, g, near, st, shifted_ctr);
+        return partial_fp32<K, D>(y, j0, j1, pr, g, near, st, form_ctr);
     } else {
         return partial_fp64<K, D>(y, j0, j1, pr, g);
     }

@@ -35,6 +35,9 @@
 //
 // FP64 form ("plain"): the same decomposition in FP64 with natural logs, the
 // device library's exp/log for every term and a plain FP64 sum over data.
+#include <algorithm>
+#include <vector>
+
 #include "exchange.hpp"
 #include "gmm_common.hpp"
 #include "reduce.hpp"
@@ -42,11 +45,12 @@
 namespace smc {
 namespace {
 
-// Observations x 64-particle tiles that the FP32 single-move kernel (k_rwmh)
-// evaluated in the shifted form since the last reset, on this device, spread
-// over kFormSlots counters (a diagnostic of which form the moves took; summed
-// by smc_fp32_shifted_data).
-__device__ unsigned long long g_fp32_shifted_data[kFormSlots];
+// Form counts of the FP32 single-move kernel (k_rwmh) since the last reset, on
+// this device (partial_fp32: observation x 64-particle tile pairs in the plain
+// shifted form, pairs in the pivot form, and the pivot form's other components
+// summed over its pairs), each spread over kFormSlots counters (a diagnostic
+// of which forms the moves took; summed by smc_fp32_form_counts).
+__device__ unsigned long long g_fp32_form_ctr[kFormCounts * kFormSlots];
 
 template <int K, int D, int PREC>
 __global__ void __launch_bounds__(1024)
@@ -152,7 +156,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
                         pr);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
-                                             PivotStage{row, y_first, y_pre}, g_fp32_shifted_data);
+                                             PivotStage{row, y_first, y_pre}, g_fp32_form_ctr);
     __syncthreads();
     if (w != 0) return;
 
@@ -1007,20 +1011,23 @@ hipError_t launch_prior(const GmmDev& g, int64_t N, uint64_t seed, double* theta
     return hipErrorInvalidValue;
 }
 
-hipError_t fp32_shifted_data(unsigned long long* out, bool reset) {
-    static_assert(sizeof(g_fp32_shifted_data) == kFormSlots * sizeof(unsigned long long), "");
-    unsigned long long v[kFormSlots];
+hipError_t fp32_form_counts(unsigned long long* out, bool reset) {
+    constexpr int kAll = kFormCounts * kFormSlots;
+    static_assert(sizeof(g_fp32_form_ctr) == kAll * sizeof(unsigned long long), "");
+    std::vector<unsigned long long> v(kAll);
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess)
-        e = hipMemcpyFromSymbol(v, HIP_SYMBOL(g_fp32_shifted_data), sizeof(v), 0,
+        e = hipMemcpyFromSymbol(v.data(), HIP_SYMBOL(g_fp32_form_ctr), kAll * sizeof(v[0]), 0,
                                 hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    unsigned long long sum = 0;
-    for (int i = 0; i < kFormSlots; ++i) sum += v[i];
-    *out = sum;
+    for (int c = 0; c < kFormCounts; ++c) {
+        unsigned long long sum = 0;
+        for (int i = 0; i < kFormSlots; ++i) sum += v[c * kFormSlots + i];
+        out[c] = sum;
+    }
     if (reset) {
-        for (int i = 0; i < kFormSlots; ++i) v[i] = 0ull;
-        e = hipMemcpyToSymbol(HIP_SYMBOL(g_fp32_shifted_data), v, sizeof(v), 0,
+        std::fill(v.begin(), v.end(), 0ull);
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_fp32_form_ctr), v.data(), kAll * sizeof(v[0]), 0,
                               hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipDeviceSynchronize();
     }

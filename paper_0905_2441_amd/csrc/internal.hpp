@@ -187,7 +187,7 @@ hipError_t launch_batch_step(const BatchDev& b, const GmmDev& g, const float* y,
 
 // Read (and with reset, clear) the device's count of observations x tiles that
 // FP32 single moves evaluated in the shifted form (synchronous).
-hipError_t fp32_shifted_data(unsigned long long* out, bool reset);
+hipError_t fp32_form_counts(unsigned long long* out, bool reset);   // out[kFormCounts]
 
 // The text smc_last_error() returns on this thread (set by every failing call).
 void set_last_error(const char* msg);

@@ -292,8 +292,9 @@ def test_fp32_shifted_form_counter(smc, ctx):
     every full block of 8 observations of every wave's slice, and a move of
     particles near a posterior mode stays in the plain direct form. On the
     same data in ascending order the near particles take the pivot form
-    throughout and the prior draws take it in most windows. FP64 moves do not
-    count. (Four slices whose boundaries fall on multiples of 8: 248, 248, 248
+    throughout, with fewer than 2.5 of their three other components on
+    average (the rest fall below 2^-25 over a window), and the prior draws
+    take it in most windows. FP64 moves do not count. (Four slices whose boundaries fall on multiples of 8: 248, 248, 248
     and 256 observations, all in full blocks.)"""
     announce("fp32 form counter")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
@@ -315,11 +316,21 @@ def test_fp32_shifted_form_counter(smc, ctx):
             th = _cuda(th_np)
             l = torch.empty(N, dtype=torch.float64, device="cuda")
             smc.smc_loglik(ctx, g, y, th, prec, out=l)
-            ctx.fp32_shifted_data(reset=True)
+            ctx.fp32_form_counts(reset=True)
             smc.smc_rwmh_move(ctx, g, y, th, l, 0.5, 0.5, seed=5, step=1, prec=prec)
             ctx.check()
-            got = ctx.fp32_shifted_data(reset=True)
-            assert want(got), (name, got)
+            fc = ctx.fp32_form_counts(reset=True)
+            got = fc["shifted"]
+            assert want(got), (name, fc)
+            # every pair of a 1-D FP32 move is in the pivot form, the plain
+            # shifted form or the plain direct form; the pivot form evaluates
+            # at most k - 1 other components per pair
+            assert fc["shifted"] + fc["pivot"] <= tiles * n, (name, fc)
+            assert fc["pivot_terms"] <= 3 * fc["pivot"], (name, fc)
+            if name == "near sorted":
+                assert fc["pivot"] == tiles * n and fc["pivot_terms"] < 2.5 * fc["pivot"], fc
+            if prec == "fp64" or name in ("prior", "near"):
+                assert fc["pivot"] == 0 and fc["pivot_terms"] == 0, (name, fc)
     finally:
         ctx.set_slices(0)
 
