@@ -436,7 +436,7 @@ int smc_graph_destroy(smc_graph g);
  * and the moves of smc_step / smc_steps unless a step's several moves run in
  * one launch), counted in (observation, 64-particle tile) pairs. out[3]:
  *   out[0]: pairs evaluated in the plain shifted form: the data of a wave's
- *           slice (d > 1, or slices shorter than 32) or of a window the pivot
+ *           slice (d > 1, or slices shorter than 128) or of a window the pivot
  *           form refused (d = 1) from where the wave left, or never took, the
  *           plain direct form; not counted: the fewer than 8 observations
  *           after the last full block of 8 of each such range, which always

@@ -233,8 +233,8 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
 @pytest.mark.parametrize("case", ["sorted_near", "sorted_far", "sorted_mixed", "sorted_k1",
                                   "sorted_k2", "sorted_k3", "sorted_k8", "unsorted",
                                   "sorted_outliers", "wide_clusters", "zero_weights",
-                                  "slice_31", "slice_32", "slice_33", "slice_63", "slice_65",
-                                  "slice_129"])
+                                  "slice_63", "slice_65", "slice_127", "slice_128", "slice_129",
+                                  "slice_200"])
 def test_loglik_fp32_pivot_form(smc, ctx, case):
     """The FP32 pivot form (1-D data, windows of 64 data, each particle's
     largest component at the window's midpoint as its pivot) at 4 slices:
@@ -242,9 +242,9 @@ def test_loglik_fp32_pivot_form(smc, ctx, case):
     leaves only the pivot's own terms); unordered data, windows that span
     far-apart clusters or hold a jump to outliers at +40 are refused for some
     or all particles and go through the plain forms; components of zero
-    weight never become pivots; slices of 31 to 129 data sit on either side
-    of the shortest slice the form takes (32) and of a window's length.
-    Every case agrees with the oracle."""
+    weight never become pivots; slices of 63 to 200 data sit on either side
+    of the shortest slice the form takes (128) and of a window's length (64),
+    with partial last windows. Every case agrees with the oracle."""
     announce(f"loglik fp32 pivot {case}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     g = smc.Gmm.equal_weights(4, 1, 0.55)
