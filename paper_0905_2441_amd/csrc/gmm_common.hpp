@@ -459,21 +459,35 @@ __device__ __forceinline__ float* pivot_row() {
 // over the block's nw waves (pair q: Philox block q/2, words 0-1 for even q and
 // 2-3 for odd q, normals 2q and 2q+1) and exchanged through LDS, so no wave
 // repeats another's draws. Cooperative: every thread of the block calls it (it
-// contains one barrier); prs holds KD rows of 64 doubles.
+// contains one barrier); prs holds KD rows of 64 doubles. With hold set, the
+// current state is kept in LDS for the decision as well: hold[c] (KD rows of 64
+// doubles) gets th_src[c, a] and hold_l the current log-likelihood l_src[a]
+// (read by the block's last wave), so the decision after the likelihood does
+// not wait on global loads.
 template <int KD>
 __device__ __forceinline__ void block_proposals(uint64_t seed, uint32_t index, uint32_t step,
                                                 uint32_t move, const double* th_src, int N,
                                                 int a, double sd, int w, int nw,
-                                                double (*prs)[kWave], double (&pr)[KD]) {
+                                                double (*prs)[kWave], double (&pr)[KD],
+                                                double (*hold)[kWave] = nullptr,
+                                                const double* l_src = nullptr,
+                                                double* hold_l = nullptr) {
     const int lane = lane_id();
+    if (hold != nullptr && w == nw - 1) hold_l[lane] = l_src[a];
     for (int q = w; q < (KD + 1) / 2; q += nw) {
+        const int c = 2 * q;
+        const double t0 = th_src[static_cast<size_t>(c) * N + a];
+        const double t1 = c + 1 < KD ? th_src[static_cast<size_t>(c + 1) * N + a] : 0.0;
         const Words4 wd = draw(seed, index, static_cast<uint32_t>(q / 2), step, kProp, move);
         double z0, z1;
         if (q & 1) box_muller(wd.w2, wd.w3, z0, z1);
         else box_muller(wd.w0, wd.w1, z0, z1);
-        const int c = 2 * q;
-        prs[c][lane] = th_src[static_cast<size_t>(c) * N + a] + sd * z0;
-        if (c + 1 < KD) prs[c + 1][lane] = th_src[static_cast<size_t>(c + 1) * N + a] + sd * z1;
+        prs[c][lane] = t0 + sd * z0;
+        if (c + 1 < KD) prs[c + 1][lane] = t1 + sd * z1;
+        if (hold != nullptr) {
+            hold[c][lane] = t0;
+            if (c + 1 < KD) hold[c + 1][lane] = t1;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -611,11 +625,38 @@ __device__ __forceinline__ void move_duties(int p, int N, const MoveStep& ms) {
     else if (rs && ms.reset_logw) ms.logw[p] = 0.0;
 }
 
-// Decision and write-back of particle p of a random-walk move. The current
-// state is column a of (th_src, l_src) (a = p, or p's ancestor after a fused
-// resampling) and is re-read rather than held; pr_at(c) returns coordinate c of
-// the proposal. Rejected particles are copied when the move is out of place.
-// l_new (optional) receives the particle's log-likelihood after the move.
+// Decision and write-back of particle p of a random-walk move, its current
+// state given by cur_at(c) and l_cur; pr_at(c) returns coordinate c of the
+// proposal. Rejected particles are copied when the move is out of place
+// (write_always). l_new (optional) receives the particle's log-likelihood after
+// the move.
+template <int KD, class PropAt, class CurAt>
+__device__ __forceinline__ bool rwmh_accept_state(int p, int N, PropAt pr_at, CurAt cur_at,
+                                                  double l_cur, double l_prop, bool write_always,
+                                                  double* theta, double* l,
+                                                  const double* beta_vec, const StepSrc& src,
+                                                  uint32_t step, uint64_t seed, uint32_t move,
+                                                  const GmmDev& g, int* status,
+                                                  const MoveStep& ms, double* l_new = nullptr) {
+    const bool acc = rwmh_decide<KD>(p, pr_at, cur_at, l_cur, l_prop, beta_vec, src, step, seed,
+                                     move, g);
+    if (acc) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = pr_at(c);
+        l[p] = l_prop;
+    } else if (write_always) {
+#pragma unroll
+        for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = cur_at(c);
+        l[p] = l_cur;
+    }
+    if (l_prop != l_prop) atomicOr(status, kStatusNaN);
+    move_duties(p, N, ms);
+    if (l_new) *l_new = acc ? l_prop : l_cur;
+    return acc;
+}
+
+// rwmh_accept_state with the current state read from column a of (th_src,
+// l_src) (a = p, or p's ancestor after a fused resampling).
 template <int KD, class PropAt>
 __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, double l_prop,
                                             const MoveSource& srcs, double* theta, double* l,
@@ -624,24 +665,10 @@ __device__ __forceinline__ bool rwmh_accept(int p, int a, int N, PropAt pr_at, d
                                             const GmmDev& g, int* status, const MoveStep& ms,
                                             double* l_new = nullptr) {
     const double* th_src = srcs.th;
-    const double l_cur = srcs.l[a];
-    const bool acc = rwmh_decide<KD>(
-        p, pr_at, [&](int c) { return th_src[static_cast<size_t>(c) * N + a]; }, l_cur, l_prop,
-        beta_vec, src, step, seed, move, g);
-    if (acc) {
-#pragma unroll
-        for (int c = 0; c < KD; ++c) theta[static_cast<size_t>(c) * N + p] = pr_at(c);
-        l[p] = l_prop;
-    } else if (srcs.write_always) {
-#pragma unroll
-        for (int c = 0; c < KD; ++c)
-            theta[static_cast<size_t>(c) * N + p] = th_src[static_cast<size_t>(c) * N + a];
-        l[p] = l_cur;
-    }
-    if (l_prop != l_prop) atomicOr(status, kStatusNaN);
-    move_duties(p, N, ms);
-    if (l_new) *l_new = acc ? l_prop : l_cur;
-    return acc;
+    return rwmh_accept_state<KD>(
+        p, N, pr_at, [&](int c) { return th_src[static_cast<size_t>(c) * N + a]; }, srcs.l[a],
+        l_prop, srcs.write_always, theta, l, beta_vec, src, step, seed, move, g, status, ms,
+        l_new);
 }
 
 }  // namespace smc

@@ -117,9 +117,13 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
        double* __restrict__ part, int* __restrict__ anc_out) {
     constexpr int KD = K * D;
     constexpr bool kRows = PREC == SMC_PREC_FP32 && D == 1;
+    // the current state held in LDS for the decision (small k*d)
+    constexpr bool kHold = KD <= 16;
     __shared__ double red[kMaxSlices][kWave];
     __shared__ int anc[kWave];
     __shared__ double prs[KD][kWave];
+    __shared__ double hold[kHold ? KD : 1][kWave];
+    __shared__ double hold_l[kWave];
     // LDS sized by the launch (rwmh_dyn_lds_bytes): for the FP32 1-D form the
     // waves' staging rows [S][kPivotWin] floats, then offh, offl [nch] (nch =
     // ms.nchunks when the move can resample, else 0)
@@ -154,7 +158,7 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
 
     double pr[KD];
     block_proposals<KD>(seed, static_cast<uint32_t>(pc), step, move, srcs.th, N, a, sd, w, S, prs,
-                        pr);
+                        pr, kHold && G == 1 ? hold : nullptr, srcs.l, hold_l);
     red[w][lane] = slice_partial<K, D, PREC>(y, j0, j1, pr, g, near_data(srcs.l[a], n, g),
                                              PivotStage{row, y_first, y_pre}, g_fp32_form_ctr);
     __syncthreads();
@@ -179,9 +183,16 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
         double tot = red[0][lane];
         for (int s = 1; s < S; ++s) tot += red[s][lane];
         const double l_prop = finish_loglik<PREC>(tot, n, g);
-        acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
-                              beta_vec, src, step, seed, move, g, status, ms,
-                              CHAIN ? &l_new : nullptr);
+        if constexpr (kHold) {
+            acc = rwmh_accept_state<KD>(
+                p, N, [&](int c) { return pr[c]; }, [&](int c) { return hold[c][lane]; },
+                hold_l[lane], l_prop, srcs.write_always, theta, l, beta_vec, src, step, seed,
+                move, g, status, ms, CHAIN ? &l_new : nullptr);
+        } else {
+            acc = rwmh_accept<KD>(p, a, N, [&](int c) { return pr[c]; }, l_prop, srcs, theta, l,
+                                  beta_vec, src, step, seed, move, g, status, ms,
+                                  CHAIN ? &l_new : nullptr);
+        }
     }
     const unsigned long long mask = __ballot(acc);
     if (lane == 0 && n_acc != nullptr && mask != 0ull)
