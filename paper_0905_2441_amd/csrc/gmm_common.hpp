@@ -155,8 +155,6 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
         const int nw = wave_uniform(j1 - wb < kPivotWin ? j1 - wb : kPivotWin);
         const bool in = lane < nw;
         const float v = ycur;
-        const int jn = wb + kPivotWin + lane;
-        ycur = jn < j1 ? y[jn] : 0.0f;        // the next window's datum, in flight
         // the window's range and its data sums about the midpoint (all lanes)
         const float lo = wave_min_dpp(in ? v : INFINITY);
         const float hi = wave_max_dpp(in ? v : -INFINITY);
@@ -167,6 +165,10 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
         const float S2 = wave_sum_dpp(dv * dv);
         wave_sync();                          // the previous window's reads come first
         row[lane] = dv;
+        // the next window's datum, in flight while this window is consumed (issued
+        // after this window's datum is used, so that no wait covers it)
+        const int jn = wb + kPivotWin + lane;
+        ycur = jn < j1 ? y[jn] : 0.0f;
         wave_sync();                          // the window is written before it is read
         // the lane's pivot and the others' offsets and slopes
         float a[K];
