@@ -389,7 +389,11 @@ __device__ __forceinline__ double partial_fp32(const float* __restrict__ y, int 
             if (cnt[c] > 0)
                 atomicAdd(form_ctr + c * kFormSlots + slot, static_cast<unsigned long long>(cnt[c]));
     }
-    return msum + static_cast<double>(expo) + log2(static_cast<double>(prod));
+    // the product's mantissa in [0.5, 1): its hardware log2 is within 2^-23 of
+    // the exact value, far below the bound per slice
+    expo += __builtin_amdgcn_frexp_expf(prod);
+    prod = __builtin_amdgcn_frexp_mantf(prod);
+    return msum + static_cast<double>(expo) + static_cast<double>(__builtin_amdgcn_logf(prod));
 }
 
 // Sum over data j in [j0, j1) of ln sum_i w_i exp(-||y_j - mu_i||^2 / (2 sigma2)), FP64.

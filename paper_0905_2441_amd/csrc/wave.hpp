@@ -5,6 +5,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "dd.hpp"
 
 namespace smc {
@@ -45,17 +47,22 @@ __device__ __forceinline__ int float_order_key(float v) {
 __device__ __forceinline__ float float_of_order_key(int k) {
     return __builtin_bit_cast(float, k >= 0 ? k : k ^ 0x7fffffff);
 }
+template <bool MAX, int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_extreme_step(int v) {
+    // a lane whose DPP source is outside its row, or whose row is masked off,
+    // reads the operation's identity (so the DPP move folds into the min/max)
+    constexpr int kId = MAX ? INT_MIN : INT_MAX;
+    const int o = __builtin_amdgcn_update_dpp(kId, v, CTRL, ROW_MASK, 0xf, false);
+    return MAX ? (v > o ? v : o) : (v < o ? v : o);
+}
 template <bool MAX>
 __device__ __forceinline__ int wave_extreme_key(int v) {
-    // a lane whose DPP source is outside its row, or whose row is masked off,
-    // keeps its own value (the operation is idempotent)
-    auto step = [&](int o) { return MAX ? (v > o ? v : o) : (v < o ? v : o); };
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));   // row_shr:1
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));   // row_shr:2
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));   // row_shr:4
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));   // row_shr:8
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
-    v = step(__builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    v = dpp_extreme_step<MAX, 0x111, 0xf>(v);   // row_shr:1
+    v = dpp_extreme_step<MAX, 0x112, 0xf>(v);   // row_shr:2
+    v = dpp_extreme_step<MAX, 0x114, 0xf>(v);   // row_shr:4
+    v = dpp_extreme_step<MAX, 0x118, 0xf>(v);   // row_shr:8
+    v = dpp_extreme_step<MAX, 0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_extreme_step<MAX, 0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
     return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ __forceinline__ float wave_max_dpp(float v) {
