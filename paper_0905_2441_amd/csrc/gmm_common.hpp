@@ -74,8 +74,10 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 // the pivot form evaluated for them.
 constexpr int kFormSlots = 1024;
 constexpr int kFormCounts = 3;
-// Data per window of the pivot form (one per lane).
+// Data per window of the pivot form (one per lane), and the floats of a wave's
+// staging row (two windows).
 constexpr int kPivotWin = kWave;
+constexpr int kPivotRow = 2 * kPivotWin;
 // Shortest slice that takes the pivot form. Short slices come from short data
 // (the paper's runs have 100 observations), whose windows of 64 span most of
 // the data's range: the pivot form refuses nearly all of them, and trying cost
@@ -103,7 +105,7 @@ __device__ __forceinline__ void with_count(int m, F&& f) {
     }
 }
 
-// A wave's staging for the pivot form: its LDS row of kPivotWin floats
+// A wave's staging for the pivot form: its LDS row of kPivotRow floats
 // (nullptr: plain forms only) and, when `pre` is set, each lane's datum
 // y[j0 + lane] of its slice already loaded where j0 + lane < j1 (a caller may
 // issue that load early, ahead of other work).
@@ -150,27 +152,17 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
     float beta[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) beta[i] = static_cast<float>(2.0 * s2 * mu[i]);
+    // each lane's datum of the current window and of the next one, loaded a
+    // window ahead of their use
     float ycur = st.pre ? st.y0 : (j0 + lane < j1 ? y[j0 + lane] : 0.0f);
-    for (int wb = j0; wb < j1; wb += kPivotWin) {
-        const int nw = wave_uniform(j1 - wb < kPivotWin ? j1 - wb : kPivotWin);
-        const bool in = lane < nw;
-        const float v = ycur;
-        // the window's range and its data sums about the midpoint (all lanes)
-        const float lo = wave_min_dpp(in ? v : INFINITY);
-        const float hi = wave_max_dpp(in ? v : -INFINITY);
-        const float c = 0.5f * lo + 0.5f * hi;
-        const float h = 0.5f * hi - 0.5f * lo;
-        const float dv = in ? v - c : 0.0f;
-        const float S1 = wave_sum_dpp(dv);
-        const float S2 = wave_sum_dpp(dv * dv);
-        wave_sync();                          // the previous window's reads come first
-        row[lane] = dv;
-        // the next window's datum, in flight while this window is consumed (issued
-        // after this window's datum is used, so that no wait covers it)
-        const int jn = wb + kPivotWin + lane;
-        ycur = jn < j1 ? y[jn] : 0.0f;
-        wave_sync();                          // the window is written before it is read
-        // the lane's pivot and the others' offsets and slopes
+    float ynext = j0 + kPivotWin + lane < j1 ? y[j0 + kPivotWin + lane] : 0.0f;
+    // the pivot of each lane for a window with midpoint c and half-width h:
+    // the others' offsets dX, slopes dB and largest offsets ub, and the pivot's
+    // mean and log-weight; ok when no lane's ub passes kPivotOverMax (and h is
+    // finite)
+    float dX[KO], dB[KO], ub[KO];
+    double mp = 0.0, lwp = 0.0;
+    auto choose = [&](float c, float h) {
         float a[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -186,9 +178,15 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
             piv = up ? i : piv;
         }
         float bp = beta[0];
+        mp = mu[0];
+        lwp = g.lw[0];
 #pragma unroll
-        for (int i = 1; i < K; ++i) bp = piv == i ? beta[i] : bp;
-        float dX[KO], dB[KO], ub[KO];         // ub: the largest t_ij in the window
+        for (int i = 1; i < K; ++i) {
+            const bool at = piv == i;
+            bp = at ? beta[i] : bp;
+            mp = at ? mu[i] : mp;
+            lwp = at ? g.lw[i] : lwp;
+        }
         bool ok = h <= 3.0e38f;               // false for a datum not finite
 #pragma unroll
         for (int o = 0; o + 1 < K; ++o) {
@@ -198,9 +196,72 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
             ub[o] = __builtin_fmaf(fabsf(dB[o]), h, dX[o]);
             ok &= ub[o] <= kPivotOverMax;
         }
-        if (!__all(ok)) {
-            fc.shifted += plain(wb, wb + nw);
-            continue;
+        return __all(ok);
+    };
+    // while it works, two windows at a time share one choice of pivots
+    bool pairs = true;
+    for (int wb = j0; wb < j1;) {
+        const int left = j1 - wb;
+        const int nw0 = wave_uniform(left < kPivotWin ? left : kPivotWin);
+        const int nw1 = wave_uniform(left > kPivotWin ? (left - kPivotWin < kPivotWin
+                                                             ? left - kPivotWin : kPivotWin) : 0);
+        const float v0 = ycur, v1 = ynext;
+        const bool in0 = lane < nw0, in1 = lane < nw1;
+        int nw = 0;
+        float c = 0.0f, S1 = 0.0f, S2 = 0.0f;
+        if (pairs && nw1 > 0) {
+            // the pair's range and its data sums about its midpoint (all lanes)
+            const int k0 = float_order_key(v0);
+            const int k1 = in1 ? float_order_key(v1) : INT_MAX;
+            const int k1x = in1 ? float_order_key(v1) : INT_MIN;
+            const float lo = float_of_order_key(wave_extreme_key<false>(k0 < k1 ? k0 : k1));
+            const float hi = float_of_order_key(wave_extreme_key<true>(k0 > k1x ? k0 : k1x));
+            c = 0.5f * lo + 0.5f * hi;
+            const float h = 0.5f * hi - 0.5f * lo;
+            if (choose(c, h)) {
+                const float d0 = v0 - c;
+                const float d1 = in1 ? v1 - c : 0.0f;
+                S1 = wave_sum_dpp(d0 + d1);
+                S2 = wave_sum_dpp(__builtin_fmaf(d1, d1, d0 * d0));
+                wave_sync();                  // the previous window's reads come first
+                row[lane] = d0;
+                row[kPivotWin + lane] = d1;
+                // the next two windows' data, in flight while these are consumed
+                // (issued after these are used, so that no wait covers them)
+                const int jn = wb + 2 * kPivotWin + lane;
+                ycur = jn < j1 ? y[jn] : 0.0f;
+                ynext = jn + kPivotWin < j1 ? y[jn + kPivotWin] : 0.0f;
+                wave_sync();                  // the windows are written before they are read
+                nw = nw0 + nw1;
+            } else {
+                pairs = false;
+            }
+        }
+        if (nw == 0) {
+            // one window: its range and data sums about its midpoint
+            const float lo = wave_min_dpp(in0 ? v0 : INFINITY);
+            const float hi = wave_max_dpp(in0 ? v0 : -INFINITY);
+            c = 0.5f * lo + 0.5f * hi;
+            const float h = 0.5f * hi - 0.5f * lo;
+            const bool take = choose(c, h);
+            const float d0 = in0 ? v0 - c : 0.0f;
+            if (take) {
+                S1 = wave_sum_dpp(d0);
+                S2 = wave_sum_dpp(d0 * d0);
+                wave_sync();
+                row[lane] = d0;
+            }
+            // the window after next, in flight
+            const int jn = wb + 2 * kPivotWin + lane;
+            ycur = v1;
+            ynext = jn < j1 ? y[jn] : 0.0f;
+            if (!take) {
+                fc.shifted += plain(wb, wb + nw0);
+                wb += nw0;
+                continue;
+            }
+            wave_sync();
+            nw = nw0;
         }
         fc.pivot += nw;
         if constexpr (K > 1) {
@@ -262,17 +323,12 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
                 }
             });
         }
-        // the pivots' own terms over the window, in FP64
-        double mp = mu[0], lwp = g.lw[0];
-#pragma unroll
-        for (int i = 1; i < K; ++i) {
-            mp = piv == i ? mu[i] : mp;
-            lwp = piv == i ? g.lw[i] : lwp;
-        }
+        // the pivots' own terms over the window(s), in FP64
         const double d = static_cast<double>(c) - mp;
         const double sq = static_cast<double>(S2) +
                           d * (2.0 * static_cast<double>(S1) + static_cast<double>(nw) * d);
         msum += static_cast<double>(nw) * lwp * kLog2eD - s2 * sq;
+        wb += nw;
     }
 }
 
@@ -453,7 +509,7 @@ __device__ __forceinline__ double slice_partial(const float* __restrict__ y, int
 template <int PREC, int D, int W>
 __device__ __forceinline__ float* pivot_row() {
     if constexpr (PREC == SMC_PREC_FP32 && D == 1) {
-        __shared__ __align__(16) float win[W][kPivotWin];
+        __shared__ __align__(16) float win[W][kPivotRow];
         return win[wave_id()];
     } else {
         return nullptr;

@@ -58,14 +58,14 @@ k_loglik(const float* __restrict__ y, int n, const double* __restrict__ theta, i
          GmmDev g, double* __restrict__ out, int* status) {
     constexpr int KD = K * D;
     // LDS sized by the launch (loglik_dyn_lds_bytes): red [S][64] doubles, then
-    // for the FP32 1-D form the waves' staging rows [S][kPivotWin] floats
+    // for the FP32 1-D form the waves' staging rows [S][kPivotRow] floats
     extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     double (*red)[kWave] = reinterpret_cast<double (*)[kWave]>(lds);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
     float* row = (PREC == SMC_PREC_FP32 && D == 1)
-                     ? reinterpret_cast<float*>(lds + S * kWave) + w * kPivotWin
+                     ? reinterpret_cast<float*>(lds + S * kWave) + w * kPivotRow
                      : nullptr;
     const int p = blockIdx.x * kWave + lane;
     const int pc = p < N ? p : N - 1;
@@ -125,16 +125,16 @@ k_rwmh(const float* __restrict__ y, int n, double* theta, double* l, int N,
     __shared__ double hold[kHold ? KD : 1][kWave];
     __shared__ double hold_l[kWave];
     // LDS sized by the launch (rwmh_dyn_lds_bytes): for the FP32 1-D form the
-    // waves' staging rows [S][kPivotWin] floats, then offh, offl [nch] (nch =
+    // waves' staging rows [S][kPivotRow] floats, then offh, offl [nch] (nch =
     // ms.nchunks when the move can resample, else 0)
     extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
-    double* offh = lds + (kRows ? S * (kPivotWin / 2) : 0);
+    double* offh = lds + (kRows ? S * (kPivotRow / 2) : 0);
     double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
-    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotWin : nullptr;
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotRow : nullptr;
     const int tile = static_cast<int>(blockIdx.x) / G;
     const int grp = static_cast<int>(blockIdx.x) - tile * G;
     const int p = tile * kWave + lane;
@@ -222,11 +222,11 @@ k_rwmh_multi(const float* __restrict__ y, int n, double* theta, double* l, int N
     extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int nch = ms.cdf_hi != nullptr ? ms.nchunks : 0;
-    double* offh = lds + (kRows ? S * (kPivotWin / 2) : 0);
+    double* offh = lds + (kRows ? S * (kPivotRow / 2) : 0);
     double* offl = offh + nch;
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
-    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotWin : nullptr;
+    float* row = kRows ? reinterpret_cast<float*>(lds) + w * kPivotRow : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < N ? p : N - 1;
     int j0, j1;
@@ -438,13 +438,13 @@ k_pt_deferred(const float* __restrict__ y, int n, const double* __restrict__ th_
     __shared__ double prs[KD][kWave];
     __shared__ double lcur[kWave];
     // LDS sized by the launch: for the FP32 1-D form the waves' staging rows
-    // [S][kPivotWin] floats
+    // [S][kPivotRow] floats
     extern __shared__ __align__(16) double lds[];
     const int S = wave_uniform(blockDim.x / kWave);
     const int lane = lane_id();
     const int w = wave_uniform(threadIdx.x / kWave);
     float* row = (PREC == SMC_PREC_FP32 && D == 1)
-                     ? reinterpret_cast<float*>(lds) + w * kPivotWin
+                     ? reinterpret_cast<float*>(lds) + w * kPivotRow
                      : nullptr;
     const int p = static_cast<int>(blockIdx.x) * kWave + lane;
     const int pc = p < M ? p : M - 1;
@@ -687,7 +687,7 @@ constexpr size_t kMaxRwmhLds = 24 * 1024;
 
 // LDS bytes of the pivot form's staging rows of `slices` waves (FP32, d = 1).
 size_t rows_lds_bytes(int slices, bool rows) {
-    return rows ? sizeof(float) * slices * kPivotWin : 0;
+    return rows ? sizeof(float) * slices * kPivotRow : 0;
 }
 
 // Dynamic LDS bytes of one k_rwmh / k_rwmh_multi workgroup (the layout at the

@@ -234,7 +234,8 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
                                   "sorted_k2", "sorted_k3", "sorted_k8", "unsorted",
                                   "sorted_outliers", "wide_clusters", "zero_weights",
                                   "slice_63", "slice_65", "slice_127", "slice_128", "slice_129",
-                                  "slice_200"])
+                                  "slice_191", "slice_192", "slice_193", "slice_200", "slice_256",
+                                  "slice_320", "pairs_then_single"])
 def test_loglik_fp32_pivot_form(smc, ctx, case):
     """The FP32 pivot form (1-D data, windows of 64 data, each particle's
     largest component at the window's midpoint as its pivot) at 4 slices:
@@ -242,9 +243,12 @@ def test_loglik_fp32_pivot_form(smc, ctx, case):
     leaves only the pivot's own terms); unordered data, windows that span
     far-apart clusters or hold a jump to outliers at +40 are refused for some
     or all particles and go through the plain forms; components of zero
-    weight never become pivots; slices of 63 to 200 data sit on either side
-    of the shortest slice the form takes (128) and of a window's length (64),
-    with partial last windows. Every case agrees with the oracle."""
+    weight never become pivots; slices of 63 to 320 data sit on either side
+    of the shortest slice the form takes (128), of a window's length (64) and
+    of a pair of windows (two windows share one choice of pivots while no
+    particle's bound over both passes the limit; a wide second window ends the
+    pairs for the rest of the slice), with partial last windows. Every case
+    agrees with the oracle."""
     announce(f"loglik fp32 pivot {case}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     g = smc.Gmm.equal_weights(4, 1, 0.55)
@@ -276,6 +280,11 @@ def test_loglik_fp32_pivot_form(smc, ctx, case):
     elif case.startswith("slice_"):
         per = int(case.split("_")[1])
         y = make_mixture_data(4 * per, mu, 0.55, seed=per)
+    elif case == "pairs_then_single":
+        # 4 slices of 256 sorted data; the fourth slice's last 40 data jump to
+        # +40, so its second pair is refused and its windows go one at a time
+        y = np.sort(make_mixture_data(n, mu, 0.55, seed=53))
+        y[-40:] = 40.0 + np.arange(40, dtype=np.float32) * 0.01
     if case != "unsorted":
         y = np.sort(y)
     ctx.set_slices(4)
