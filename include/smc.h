@@ -175,7 +175,8 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  * particles sit near the data (weights of total mass <= 1) and relative to its
  * largest term otherwise (those maxima added in 16-term FP32 blocks promoted to
  * FP64). For d = 1 a third form, the pivot form, runs first: a wave's slice
- * goes in windows of 64 data; in a window with midpoint c each particle's
+ * goes in windows of 64 data, two at a time sharing one choice of pivots while
+ * the test below holds over both; in a window with midpoint c each particle's
  * component p with the largest exponent at c is its pivot, each other
  * component's exponent difference to it is linear in y (one FMA and one exp2
  * per datum and component), every per-datum factor is at least 1, and the

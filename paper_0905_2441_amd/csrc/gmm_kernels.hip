@@ -17,7 +17,8 @@
 //
 // FP32 forms, in base-2 units, a_i = log2 w_i - s^2 (y - mu_i)^2 with
 // s = sqrt(log2(e)/(2 sigma2)) (partial_fp32):
-//   * pivot (1-D data): per window of 64 data about its midpoint c, each
+//   * pivot (1-D data): per window of 64 data (or pair of windows, while the
+//     pair's range is narrow enough) about its midpoint c, each
 //     particle's component p with the largest a_p(c) is its pivot; the
 //     others enter through t_i = a_i - a_p, which is linear in y (one FMA),
 //     as 2^(t_i) (hardware v_exp_f32), and the pivot's own a_p summed over
