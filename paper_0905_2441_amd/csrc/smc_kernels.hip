@@ -262,10 +262,10 @@ k_cdf_offsets(int nchunks, Scratch sc, ResamplePred pred) {
 // mom_stride per workgroup), workgroup 0 also writes the step's weighted means
 // and standard deviations to moments[(t-1) * 2k ...]. With `chained`, the
 // partials are the per-tile ones of the new weights made by the previous move
-// of a chain of steps (many more than the reweight pass makes): their maximum
-// is formed first so that the loads and exps of different partials do not
-// wait on each other, and the old weights' log-sum-exp is taken from the step
-// state (the previous step's new one, or log N after its resampling).
+// of a chain of steps (many more than the reweight pass makes): they are read
+// in one pass, with the loads of a thread's partials issued together, and the
+// old weights' log-sum-exp is taken from the step state (the previous step's
+// new one, or log N after its resampling).
 __global__ void __launch_bounds__(kRedBlock)
 k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
            double* stats, double ess_frac, const double* __restrict__ logw,
@@ -287,21 +287,12 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
     }
     Lse3 o = lse3_empty(), nw = lse3_empty();
     if (chained) {
-        // kU partials per thread per round, their loads issued together
+        // one pass over the partials: kU of them per thread per round, all
+        // their loads issued together; each thread sums its partials about
+        // its own largest mn (rescaling its running sums when that grows), and
+        // the block log-sum-exp rescales the threads' sums to the block's
         constexpr int kU = 8;
-        double m = -INFINITY;
-        for (int b0 = threadIdx.x; b0 < parts; b0 += kU * kRedBlock) {
-            double v[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int b = b0 + u * kRedBlock;
-                v[u] = b < parts ? part[b].mn : -INFINITY;
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) m = fmax(m, v[u]);
-        }
-        m = block_max(m);
-        double a = 0.0, c = 0.0;
+        double m = -INFINITY, a = 0.0, c = 0.0;
         for (int b0 = threadIdx.x; b0 < parts; b0 += kU * kRedBlock) {
             double vm[kU], v1[kU], v2[kU];
 #pragma unroll
@@ -311,14 +302,21 @@ k_step_mid(int parts, int N, int chunk, StepSrc src, int* t_advance, Scratch sc,
                 v1[u] = b < parts ? part[b].s1 : 0.0;
                 v2[u] = b < parts ? part[b].s2 : 0.0;
             }
+            double mr = m;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) mr = fmax(mr, vm[u]);
+            const double rr = m == -INFINITY ? 0.0 : exp(m - mr);
+            a *= rr;
+            c *= rr * rr;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const double r = vm[u] == -INFINITY ? 0.0 : exp(vm[u] - m);
+                const double r = vm[u] == -INFINITY ? 0.0 : exp(vm[u] - mr);
                 a += v1[u] * r;
                 c += v2[u] * (r * r);
             }
+            m = mr;
         }
-        nw = Lse3{m, block_sum(a), block_sum(c)};
+        nw = block_lse3(Lse3{m, a, c});
     } else {
         for (int b = threadIdx.x; b < parts; b += blockDim.x) {
             const RwPartial q = part[b];
