@@ -235,7 +235,9 @@ def test_loglik_fp32_direct_and_shifted_forms(smc, ctx, case):
                                   "sorted_outliers", "wide_clusters", "zero_weights",
                                   "slice_63", "slice_65", "slice_127", "slice_128", "slice_129",
                                   "slice_191", "slice_192", "slice_193", "slice_200", "slice_256",
-                                  "slice_320", "pairs_then_single"])
+                                  "slice_255", "slice_257", "slice_320", "slice_384",
+                                  "slice_512", "slice_520", "pairs_then_single",
+                                  "clusters_at_crossings"])
 def test_loglik_fp32_pivot_form(smc, ctx, case):
     """The FP32 pivot form (1-D data, windows of 64 data, each particle's
     largest component at the window's midpoint as its pivot) at 4 slices:
@@ -243,12 +245,13 @@ def test_loglik_fp32_pivot_form(smc, ctx, case):
     leaves only the pivot's own terms); unordered data, windows that span
     far-apart clusters or hold a jump to outliers at +40 are refused for some
     or all particles and go through the plain forms; components of zero
-    weight never become pivots; slices of 63 to 320 data sit on either side
+    weight never become pivots; slices of 63 to 520 data sit on either side
     of the shortest slice the form takes (128), of a window's length (64) and
     of a pair of windows (two windows share one choice of pivots while no
     particle's bound over both passes the limit; a wide second window ends the
-    pairs for the rest of the slice), with partial last windows. Every case
-    agrees with the oracle."""
+    pairs for the rest of the slice), with partial last windows and pairs;
+    tight clusters of data straddle the points where two components'
+    densities cross. Every case agrees with the oracle."""
     announce(f"loglik fp32 pivot {case}")
     mu = np.array([-3.0, 0.0, 3.0, 6.0])
     g = smc.Gmm.equal_weights(4, 1, 0.55)
@@ -281,10 +284,19 @@ def test_loglik_fp32_pivot_form(smc, ctx, case):
         per = int(case.split("_")[1])
         y = make_mixture_data(4 * per, mu, 0.55, seed=per)
     elif case == "pairs_then_single":
-        # 4 slices of 256 sorted data; the fourth slice's last 40 data jump to
+        # 4 slices of 250 sorted data; the fourth slice's last 40 data jump to
         # +40, so its second pair is refused and its windows go one at a time
         y = np.sort(make_mixture_data(n, mu, 0.55, seed=53))
         y[-40:] = 40.0 + np.arange(40, dtype=np.float32) * 0.01
+    elif case == "clusters_at_crossings":
+        # 4 slices of 256 sorted data, each two tight clusters of 128 data 5
+        # apart; in the first two slices the clusters straddle the point where
+        # two components' densities cross (-1.5, 4.5), and each pair of
+        # windows holds one cluster
+        rng = np.random.default_rng(54)
+        y = np.concatenate([c + 0.3 * rng.random(128)
+                            for c in (-4.0, 1.0, 2.0, 7.0, 8.0, 13.0, 14.0, 19.0)])
+        y = y.astype(np.float32)
     if case != "unsorted":
         y = np.sort(y)
     ctx.set_slices(4)
