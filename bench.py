@@ -608,7 +608,7 @@ def main():
     STEPS_PER_GRAPH = max(1, int(args.steps_per_graph if args.steps_per_graph is not None
                                  else GRAPH_STEPS.get(args.workload, STEPS_PER_GRAPH)))
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
