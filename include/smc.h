@@ -182,8 +182,9 @@ int smc_set_launch_table(smc_ctx ctx, const smc_launch_rule* rules, int32_t coun
  * per datum and component), every per-datum factor is at least 1, and the
  * pivot's own exponents summed over the window come in FP64 from two data sums
  * the wave forms once for all its particles. A window is taken when none of
- * the wave's particles can see an exponent difference above 12 in it
- * (narrow windows; data in ascending order, see smc_sort_data, give them);
+ * the wave's particles can see a base-2 exponent difference above 14 in it
+ * (13 for k > 4; the bound keeps a block of 8 factors below FP32 overflow;
+ * narrow windows, which data in ascending order give, see smc_sort_data);
  * other windows, and windows holding a datum or parameter that is not finite,
  * go through the plain forms. All forms are within the bound (the form
  * depends on the wave and the data order, fixed for a given launch shape,

@@ -42,7 +42,7 @@ __device__ __forceinline__ double finish_loglik(double acc, int n, const GmmDev&
 //    the product cannot
 //    underflow; a window is taken when, for every particle of the wave, every
 //    dX_i + |dB_i| h (the largest t_ij the window can hold) is at most
-//    kPivotOverMax, which keeps a block of 8 factors below 2^120. A window
+//    pivot_over_max<K>(), which keeps a block of 8 factors below 2^128. A window
 //    that some particle fails (components far apart across a wide window, a
 //    datum or parameter not finite) goes through the plain forms below. On
 //    data in ascending order the windows are narrow and nearly all are
@@ -83,10 +83,16 @@ constexpr int kPivotRow = 2 * kPivotWin;
 // the data's range: the pivot form refuses nearly all of them, and trying cost
 // 5-8% there.
 constexpr int kPivotMinData = 128;
-// Largest t_ij a window of the pivot form may hold: with K <= 8 components a
-// factor is then below 1 + 7 * 2^12 < 2^15 and a block of 8 below 2^120.
-constexpr float kPivotOverMax = 12.0f;
-static_assert(SMC_KMAX <= 8, "kPivotOverMax assumes at most 8 components");
+// Largest t_ij a window of the pivot form may hold with K components: a
+// factor is then below 1 + (K-1) 2^T, and a block of 8 factors times a
+// mantissa below 1 stays below the FP32 overflow at 2^128:
+// (1 + 3 * 2^14)^8 < 2^125 for K <= 4, (1 + 7 * 2^13)^8 < 2^127 for K <= 8.
+template <int K>
+constexpr float pivot_over_max() {
+    static_assert(K <= 8, "pivot_over_max assumes at most 8 components");
+    return K <= 4 ? 14.0f : 13.0f;
+}
+static_assert(SMC_KMAX <= 8, "pivot_over_max assumes at most 8 components");
 // A component other than the pivot whose t_ij stays below this in a window
 // for every particle of the wave is left out there: its term is below 2^-25,
 // under half the relative resolution of the product update p (1 + e) it would
@@ -158,7 +164,7 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
     float ynext = j0 + kPivotWin + lane < j1 ? y[j0 + kPivotWin + lane] : 0.0f;
     // the pivot of each lane for a window with midpoint c and half-width h:
     // the others' offsets dX, slopes dB and largest offsets ub, and the pivot's
-    // mean and log-weight; ok when no lane's ub passes kPivotOverMax (and h is
+    // mean and log-weight; ok when no lane's ub passes pivot_over_max<K>() (and h is
     // finite)
     float dX[KO], dB[KO], ub[KO];
     double mp = 0.0, lwp = 0.0;
@@ -194,7 +200,7 @@ __device__ __forceinline__ void pivot_slice(const float* __restrict__ y, int j0,
             dX[o] = (up ? a[o + 1] : a[o]) - best;
             dB[o] = (up ? beta[o + 1] : beta[o]) - bp;
             ub[o] = __builtin_fmaf(fabsf(dB[o]), h, dX[o]);
-            ok &= ub[o] <= kPivotOverMax;
+            ok &= ub[o] <= pivot_over_max<K>();
         }
         return __all(ok);
     };
